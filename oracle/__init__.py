@@ -1,0 +1,155 @@
+"""CPU oracle for speculative First-Fit colouring -- TEST INFRASTRUCTURE.
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may
+import this package.  The product (``paper_1505_04086_amd``) never does, and
+this package imports nothing from it: the two share no code.
+
+The arithmetic lives in ``oracle.c`` (plain C, compiled with gcc); this file
+only marshals numpy arrays.  Functions:
+
+* :func:`seq_ff` -- sequential First-Fit in natural id order (Section 2.1,
+  Algorithm 1).
+* :func:`rsync`  -- Algorithm 3 (Section 3) as a deterministic
+  round-synchronous schedule: every read in a round sees the colours of the
+  previous barrier; ties go to the lower id by default.
+* :func:`cat`    -- Algorithm 2 (Section 2.2) under the same reading.
+* :func:`check`  -- validity and the First-Fit bound c(v) <= deg(v).
+
+Parity status: seq_ff, rsync (both tie rules) and check are pinned by the
+``-m "not gpu"`` tests (closed forms, hand-derived worked examples, networkx's
+independent greedy colouring, brute-force chromatic numbers, reversal
+symmetry and monotonicity of |L|).  cat is pinned by hand-derived examples and
+invariants only.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lock = threading.Lock()
+_lib = None
+
+TIE_LOWER_KEEPS = 0
+TIE_HIGHER_KEEPS = 1
+TIE_NONE = 2
+_TIES = {"lower": 0, "higher": 1, "none": 2, 0: 0, 1: 1, 2: 2}
+
+ENOCONV = -7
+
+
+def build(force: bool = True, src: str = _SRC, out: str = _LIB) -> str:
+    """Compile ``oracle.c`` (or another copy of it) into a shared library."""
+    if force or not os.path.exists(out):
+        tmp = out + ".tmp%d" % os.getpid()
+        subprocess.run(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-o", tmp, src], check=True)
+        os.replace(tmp, out)
+    return out
+
+
+class OracleLib:
+    """ctypes view of one compiled copy of ``oracle.c`` (the default build, or a
+    test-built variant)."""
+
+    def __init__(self, path: str):
+        lib = ctypes.CDLL(path)
+        p = ctypes.c_void_p
+        i32, i64 = ctypes.c_int32, ctypes.c_int64
+        lib.orc_seq_ff.argtypes = [i32, p, p, p]
+        lib.orc_seq_ff.restype = i32
+        for f in (lib.orc_rsync, lib.orc_cat):
+            f.argtypes = [i32, p, p, i32, i32, p, ctypes.POINTER(i32), ctypes.POINTER(i64), p, i32]
+            f.restype = i32
+        lib.orc_check.argtypes = [i32, p, p, p]
+        lib.orc_check.restype = i64
+        self.lib = lib
+        self.path = path
+
+    def seq_ff(self, row_ptr, col_idx):
+        """Sequential First-Fit (Algorithm 1).  Returns (colors int32[n], K)."""
+        rp, ci, n = _csr(row_ptr, col_idx)
+        col = np.empty(max(n, 1), dtype=np.int32)
+        k = self.lib.orc_seq_ff(n, rp.ctypes.data, ci.ctypes.data, col.ctypes.data)
+        if k < 0:
+            raise RuntimeError("orc_seq_ff failed: %d" % k)
+        return col[:n], int(k)
+
+    def _iterated(self, fn, row_ptr, col_idx, tie, max_rounds, raise_on_noconv):
+        rp, ci, n = _csr(row_ptr, col_idx)
+        col = np.empty(max(n, 1), dtype=np.int32)
+        cap = n + 2
+        Ls = np.zeros(cap, dtype=np.int32)
+        rounds = ctypes.c_int32(0)
+        conflicts = ctypes.c_int64(0)
+        k = fn(n, rp.ctypes.data, ci.ctypes.data, _TIES[tie], int(max_rounds or 0), col.ctypes.data,
+               ctypes.byref(rounds), ctypes.byref(conflicts), Ls.ctypes.data, cap)
+        if k < 0 and (k != ENOCONV or raise_on_noconv):
+            raise RuntimeError("oracle failed: %d" % k)
+        R = int(rounds.value)
+        return {"colors": col[:n], "K": int(k), "rounds": R, "conflicts": int(conflicts.value),
+                "L_sizes": Ls[:min(R, cap)].copy(), "status": 0 if k >= 0 else int(k)}
+
+    def rsync(self, row_ptr, col_idx, tie="lower", max_rounds=None, raise_on_noconv=True):
+        """Deterministic round-synchronous Algorithm 3.
+
+        Returns dict(colors, K, rounds = recolouring rounds R, conflicts = sum |L|,
+        L_sizes = |L| per recolouring round, status)."""
+        return self._iterated(self.lib.orc_rsync, row_ptr, col_idx, tie, max_rounds, raise_on_noconv)
+
+    def cat(self, row_ptr, col_idx, tie="lower", max_rounds=None, raise_on_noconv=True):
+        """Deterministic round-synchronous Algorithm 2 (tentative colouring, barrier,
+        conflict detection, barrier).  rounds = Phase-1 passes; L_sizes = |L| per round."""
+        return self._iterated(self.lib.orc_cat, row_ptr, col_idx, tie, max_rounds, raise_on_noconv)
+
+    def check(self, row_ptr, col_idx, colors) -> int:
+        """0 iff no edge joins equal colours and 0 <= c(v) <= deg(v) for all v."""
+        rp, ci, n = _csr(row_ptr, col_idx)
+        c = np.ascontiguousarray(colors, dtype=np.int32)
+        if n == 0:
+            return 0
+        return int(self.lib.orc_check(n, rp.ctypes.data, ci.ctypes.data, c.ctypes.data))
+
+
+def _csr(row_ptr, col_idx):
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+    if len(ci) == 0:
+        ci = np.zeros(1, dtype=np.int32)
+    return rp, ci, len(rp) - 1
+
+
+def default() -> OracleLib:
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(_LIB):
+                build(force=False)
+            _lib = OracleLib(_LIB)
+    return _lib
+
+
+def seq_ff(row_ptr, col_idx):
+    return default().seq_ff(row_ptr, col_idx)
+
+
+def rsync(row_ptr, col_idx, tie="lower", max_rounds=None, raise_on_noconv=True):
+    return default().rsync(row_ptr, col_idx, tie, max_rounds, raise_on_noconv)
+
+
+def cat(row_ptr, col_idx, tie="lower", max_rounds=None, raise_on_noconv=True):
+    return default().cat(row_ptr, col_idx, tie, max_rounds, raise_on_noconv)
+
+
+def check(row_ptr, col_idx, colors) -> int:
+    return default().check(row_ptr, col_idx, colors)
+
+
+def colour_count(colors) -> int:
+    """K = max + 1 (0 for no vertices)."""
+    return int(colors.max()) + 1 if len(colors) else 0
