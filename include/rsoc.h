@@ -1,0 +1,208 @@
+/*
+ * rsoc.h -- C ABI of librsoc: speculative First-Fit graph colouring on AMD
+ * Instinct MI355X (gfx950).
+ *
+ * Method: Rokos, Gorman, Kelly, "A Fast and Scalable Graph Coloring Algorithm
+ * for Multi-core and Many-core Architectures" (arXiv 1505.04086), Section 3,
+ * Algorithm 3 ("RSOC"): a tentative First-Fit round over every vertex, then
+ * rounds that each inspect the vertices recoloured in the previous round,
+ * recolour the ones that still share a colour with a neighbour they lose to,
+ * and collect them for the next round, with one barrier per round, until a
+ * round recolours nobody.  The First-Fit step gives a vertex the smallest
+ * colour absent among its neighbours (Section 2.1, Algorithm 1).
+ *
+ * Problem statement (Section 2.1): input an undirected graph G(V,E), output a
+ * colour c(v) per vertex such that adjacent vertices differ, plus the number
+ * of colours.
+ *
+ * Conventions shared by every entry point:
+ *  - Graph: symmetric CSR, int32.  row_ptr has n+1 entries, row_ptr[0] == 0,
+ *    non-decreasing, row_ptr[n] = nnz <= 2^31-1; col_idx has nnz entries in
+ *    [0, n).  Both directions of every edge must be present.  Duplicate
+ *    entries are harmless.  Self-loops are rejected when validation is on;
+ *    otherwise they are ignored.  Rows need not be sorted.
+ *  - Colours: int32, 0-based (the paper's palette {1..d+1} shifted down by
+ *    one).  Every colour satisfies 0 <= c(v) <= deg(v), hence at most
+ *    max-degree + 1 colours (Section 2.1).
+ *  - Return value: >= 0 on success (the colour count K = max colour + 1, 0
+ *    for n == 0, or the documented value), < 0 an rsoc_status code.
+ *  - Ownership: the caller owns every buffer it passes in; the library never
+ *    frees or retains caller memory (except pool slots, see below).  A context
+ *    owns its device scratch, grows it on demand and frees it at destroy.
+ *  - Threading: one host thread at a time per context / pool.  No C++
+ *    exception crosses this ABI.
+ *  - Streams: entry points taking `hip_stream` (a hipStream_t; NULL = the
+ *    default stream) enqueue their kernels there and synchronise it before
+ *    returning.
+ */
+#ifndef RSOC_H
+#define RSOC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RSOC_OK = 0,
+    RSOC_EINVAL = -1,     /* null pointer, n < 0, bad option value */
+    RSOC_ECSR = -2,       /* row_ptr[0] != 0, decreasing row_ptr, col_idx out of range */
+    RSOC_ESELFLOOP = -3,  /* a self-loop, with validation on */
+    RSOC_EASYM = -4,      /* an edge stored in one direction only (RSOC_CHECK_SYMMETRY) */
+    RSOC_ENOMEM = -5,     /* device or host allocation failed */
+    RSOC_EHIP = -6,       /* a HIP runtime error (see rsoc_last_error) */
+    RSOC_ENOCONV = -7,    /* the worklist was still non-empty after max_rounds passes */
+    RSOC_EBUDGET = -8,    /* pool admission refused: HBM budget or slot table full */
+    RSOC_ENOTFOUND = -9   /* unknown or unfinished pool slot */
+} rsoc_status;
+
+typedef enum {
+    /* The paper's Algorithm 3 as written: reads see whatever neighbour colours
+     * are in memory (live), writes go straight to the colour array.  Any valid
+     * colouring is a correct result; it may differ from run to run. */
+    RSOC_MODE_OPTIMISTIC = 0,
+    /* Algorithm 3 read round-synchronously: every read of a round sees the
+     * colours of the previous barrier and every write of the round lands at
+     * the next barrier.  Round 0 therefore gives every vertex colour 0.  The
+     * result is unique and bit-reproducible. */
+    RSOC_MODE_DETERMINISTIC = 1,
+    /* Algorithm 2 (Section 2.2, the predecessor scheme): per round a tentative
+     * First-Fit over U, a barrier, conflict detection over U into L, a barrier,
+     * U <- L.  Round-synchronous reads, so the result is unique. */
+    RSOC_MODE_TWO_PHASE = 2
+} rsoc_mode;
+
+typedef enum {
+    RSOC_TIE_LOWER_KEEPS = 0,  /* on a conflict the lower vertex id keeps its colour */
+    RSOC_TIE_HIGHER_KEEPS = 1  /* the paper's test: V_i is defective if a neighbour V_j > V_i shares its colour */
+} rsoc_tie;
+
+enum { RSOC_CHECK_CSR = 1, RSOC_CHECK_SYMMETRY = 2 };
+
+typedef struct {
+    int32_t mode;        /* rsoc_mode (default RSOC_MODE_OPTIMISTIC) */
+    int32_t tie;         /* rsoc_tie (default RSOC_TIE_LOWER_KEEPS) */
+    int32_t max_rounds;  /* bound on inspection passes (rounds >= 1); 0 => n + 1, which no input reaches */
+    int32_t validate;    /* bitmask of RSOC_CHECK_*; symmetry is checked only for host-pointer calls */
+    /* tuning; 0 selects the library default (or the tuned value) */
+    int32_t t_thread;    /* max degree coloured by one thread (<= 63; default 32) */
+    int32_t t_wave;      /* max degree coloured by one wavefront; larger rows use a workgroup (default 2048) */
+    int32_t grid_thread; /* workgroups given to the thread bin per round launch (default 2048) */
+    int32_t grid_wave;   /* workgroups given to the wavefront bin (default 512) */
+    int32_t rounds_per_sync; /* rounds enqueued (as one HIP graph) per host check of the worklist (default 8, even) */
+    int32_t small_cutoff;    /* batch: graphs with n <= this are coloured whole by one workgroup (default 4096; -1 disables) */
+    int32_t timing;      /* 1: record per-kernel HIP events (fills the ms_* fields of rsoc_stats) */
+    int32_t reserved[5]; /* must be zero */
+} rsoc_options;
+
+typedef struct {
+    int32_t rounds;          /* recolouring rounds R: rounds >= 1 that recoloured at least one vertex */
+    int32_t passes;          /* inspection passes executed (R, plus the final pass that finds nothing) */
+    int32_t colors;          /* K = max colour + 1 */
+    int32_t colors_distinct; /* number of distinct colours used (gaps are possible in parallel modes) */
+    int64_t conflicts;       /* sum over rounds of |L| (vertices recoloured after round 0) */
+    int64_t inspected;       /* vertices inspected in rounds >= 1 */
+    int64_t alg_bytes;       /* algorithmic bytes moved by the colouring (model: see the library docs) */
+    double ms;               /* device time from the first round-0 kernel to convergence */
+    double ms_round0;        /* (timing) duration of the round-0 launch */
+    double ms_round1;        /* (timing) duration of the round-1 launch */
+    int64_t bytes_round0;    /* algorithmic bytes of the round-0 launch */
+    int64_t bytes_round1;    /* algorithmic bytes of the round-1 launch */
+    int32_t max_degree;
+    int32_t bin_counts[3];   /* vertices per degree bin: thread, wavefront, workgroup */
+    int32_t *per_round_L;    /* optional caller array: per_round_L[i] = |L| of recolouring round i+1 */
+    int32_t per_round_cap;   /* its length */
+    int32_t reserved[5];
+} rsoc_stats;
+
+typedef struct rsoc_ctx rsoc_ctx;
+typedef struct rsoc_pool rsoc_pool;
+
+/* Fills *opts with the defaults (optimistic mode, lower id keeps). */
+void rsoc_default_options(rsoc_options *opts);
+
+/*
+ * The problem statement as one call (Section 2.1; Algorithm 3 of Section 3):
+ * host arrays in, host colours out, default options, on device 0.  Returns K.
+ * Validates the CSR structure and rejects self-loops.
+ */
+int32_t rsoc_color(const int32_t *row_ptr, const int32_t *col_idx, int32_t n, int32_t *colors_out);
+
+/* Creates a context on HIP device `device`.  Returns RSOC_OK or an error. */
+int32_t rsoc_ctx_create(rsoc_ctx **out, int32_t device);
+void rsoc_ctx_destroy(rsoc_ctx *ctx);
+
+/*
+ * Host-pointer colouring with options and statistics (stats may be NULL).
+ * Copies the CSR to the device, colours it, copies colours_out back.
+ * Returns K.
+ */
+int32_t rsoc_color_ex(rsoc_ctx *ctx, const int32_t *row_ptr, const int32_t *col_idx, int32_t n,
+                      int32_t *colors_out, const rsoc_options *opts, rsoc_stats *stats);
+
+/*
+ * Device-pointer colouring (Algorithm 3 on a device-resident graph).
+ * d_row_ptr[n+1], d_col_idx[nnz], d_colors_out[n] are device pointers owned
+ * by the caller; the kernels run on `hip_stream`, which is synchronised before
+ * returning.  d_colors_out is overwritten.  Returns K.
+ */
+int32_t rsoc_color_device(rsoc_ctx *ctx, const int32_t *d_row_ptr, const int32_t *d_col_idx, int32_t n,
+                          int32_t *d_colors_out, const rsoc_options *opts, rsoc_stats *stats, void *hip_stream);
+
+/*
+ * Batched colouring of G independent graphs in one sequence of fused launches.
+ * Layout (all device pointers except the offset tables):
+ *   vtx_off[G+1], nnz_off[G+1]: host int64 prefix sums of n_g and nnz_g;
+ *   d_row_ptr_cat: graph g's local row_ptr (n_g+1 entries, starting at 0)
+ *                  begins at element vtx_off[g] + g;
+ *   d_col_idx_cat: graph g's local column ids begin at element nnz_off[g];
+ *   d_colors_cat:  graph g's colours begin at element vtx_off[g].
+ * Each graph is coloured exactly as a separate call would colour it (in
+ * deterministic mode bit-identically).  counts_out[g] (host, may be NULL)
+ * receives K_g.  Returns max_g K_g.  Sum of n_g must stay below 2^31.
+ */
+int32_t rsoc_color_batch(rsoc_ctx *ctx, int32_t G, const int64_t *vtx_off, const int64_t *nnz_off,
+                         const int32_t *d_row_ptr_cat, const int32_t *d_col_idx_cat, int32_t *d_colors_cat,
+                         int32_t *counts_out, const rsoc_options *opts, rsoc_stats *stats, void *hip_stream);
+
+/*
+ * Continuous batching.  A pool accepts graphs (already on the device) while
+ * others are being coloured; each rsoc_pool_step runs one fused round over all
+ * live slots (newly admitted slots run their round 0 in the same launch in
+ * which older ones run a later round) and reports the slots that finished.
+ * hbm_budget_bytes bounds the device scratch the pool's slots may hold
+ * (worklists and staging: about 16 bytes per vertex); 0 means unlimited.
+ */
+int32_t rsoc_pool_create(rsoc_ctx *ctx, int64_t hbm_budget_bytes, int32_t max_slots, rsoc_pool **out);
+void rsoc_pool_destroy(rsoc_pool *pool);
+/* Admits a graph; the device pointers must stay valid until rsoc_pool_result.
+ * Returns a slot id >= 0, or RSOC_EBUDGET if its scratch does not fit now. */
+int32_t rsoc_pool_admit(rsoc_pool *pool, const int32_t *d_row_ptr, const int32_t *d_col_idx, int32_t n,
+                        int32_t *d_colors_out, const rsoc_options *opts);
+/* One fused round over all live slots on hip_stream (synchronised).  Writes up
+ * to `cap` finished slot ids to finished_slots.  Returns the number finished
+ * (they stay reserved until rsoc_pool_result). */
+int32_t rsoc_pool_step(rsoc_pool *pool, void *hip_stream, int32_t *finished_slots, int32_t cap);
+/* Number of admitted slots that are not yet released. */
+int32_t rsoc_pool_live(const rsoc_pool *pool);
+/* Scratch bytes currently reserved by admitted slots. */
+int64_t rsoc_pool_reserved_bytes(const rsoc_pool *pool);
+/* Statistics of a finished slot (stats may be NULL); releases the slot and
+ * its budget.  Returns K or RSOC_ENOTFOUND. */
+int32_t rsoc_pool_result(rsoc_pool *pool, int32_t slot, rsoc_stats *stats);
+
+/* Host-side CSR check (flags: RSOC_CHECK_*).  Returns RSOC_OK or the first error found. */
+int32_t rsoc_check_csr(const int32_t *row_ptr, const int32_t *col_idx, int32_t n, int32_t flags);
+
+/* Static string for a status code. */
+const char *rsoc_strerror(int32_t status);
+
+/* Text of the last HIP error seen on this host thread ("" if none). */
+const char *rsoc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RSOC_H */

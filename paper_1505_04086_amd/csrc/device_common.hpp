@@ -1,0 +1,86 @@
+// device_common.hpp -- wavefront helpers and constants shared by the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rsoc {
+
+constexpr int kWave = 64;                 // CDNA wavefront width
+constexpr int kBlock = 256;               // threads per workgroup for every round kernel
+constexpr int kWavesPerBlock = kBlock / kWave;
+constexpr int kWaveWindowBits = 4096;     // forbidden-colour window of a wavefront (512 B of LDS)
+constexpr int kWaveWindowWords = kWaveWindowBits / 32;
+constexpr int kBlockWindowBits = 32768;   // forbidden-colour window of a workgroup (4 KB of LDS)
+constexpr int kBlockWindowWords = kBlockWindowBits / 32;
+constexpr int kLdsWords = (kBlockWindowWords > kWavesPerBlock * kWaveWindowWords) ? kBlockWindowWords
+                                                                                  : kWavesPerBlock * kWaveWindowWords;
+constexpr int kHistCap = 1 << 16;         // per-round |L| history kept on the device
+constexpr int kXcds = 8;                  // MI355X: 8 accelerator complex dies, 32 CUs each
+
+enum Phase : int { kAssign = 0, kRecolor = 1, kDetect = 2 };
+enum Mode : int { kOptimistic = 0, kDeterministic = 1, kTwoPhase = 2 };
+enum Tie : int { kLowerKeeps = 0, kHigherKeeps = 1 };
+enum Bin : int { kBinThread = 0, kBinWave = 1, kBinBlock = 2 };
+
+// v is defective against neighbour u with the same colour iff it loses the tie.
+template <int TIE>
+__device__ __forceinline__ bool loses(int v, int u) {
+    return TIE == kLowerKeeps ? (u < v) : (u > v);
+}
+
+__device__ __forceinline__ int lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0)); }
+
+// number of set bits of m below this lane
+__device__ __forceinline__ int lanes_below(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
+}
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+// Orders this wavefront's LDS accesses across lanes (a compiler barrier; the
+// hardware executes one wavefront's LDS instructions in order).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ void lds_or(uint32_t *p, uint32_t bits) {
+    __hip_atomic_fetch_or(p, bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Appends `v` for every lane with `take` set: one global atomic per wavefront,
+// positions from the lane prefix count.
+__device__ __forceinline__ void wave_append(bool take, int v, int *counter, int *list) {
+    uint64_t m = ballot(take);
+    if (m == 0) return;
+    int leader = __ffsll((unsigned long long)m) - 1;
+    int base = 0;
+    if (lane_id() == leader) base = atomicAdd(counter, __popcll(m));
+    base = __shfl(base, leader);
+    if (take) list[base + lanes_below(m)] = v;
+}
+
+// Wavefront sum of a 64-bit value (result valid in every lane).
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t x) {
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+    return x;
+}
+
+__device__ __forceinline__ int wave_max_i32(int x) {
+    for (int off = 32; off > 0; off >>= 1) x = max(x, __shfl_xor(x, off));
+    return x;
+}
+
+// Block index remapped so that each XCD works on one contiguous range of the
+// section: hardware dispatches consecutive workgroups round-robin over XCDs,
+// so blocks b, b+8, b+16, ... share an L2.  Only a bijection when nblocks is
+// a multiple of kXcds; otherwise returns b unchanged.
+__device__ __forceinline__ int xcd_contiguous(int b, int nblocks) {
+    if (nblocks % kXcds) return b;
+    int per = nblocks / kXcds;
+    return (b % kXcds) * per + b / kXcds;
+}
+
+}  // namespace rsoc

@@ -1,0 +1,115 @@
+// host_common.hpp -- error plumbing and small host utilities for the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <string.h>
+
+#include "rsoc.h"
+
+namespace rsoc {
+
+// Text of the last HIP error on this host thread (rsoc_last_error).
+inline char *last_error_buf() {
+    static thread_local char buf[256] = {0};
+    return buf;
+}
+
+inline int32_t hip_fail(hipError_t e, const char *what, const char *file, int line) {
+    snprintf(last_error_buf(), 256, "%s: %s (%s:%d)", what, hipGetErrorString(e), file, line);
+    return (e == hipErrorOutOfMemory) ? RSOC_ENOMEM : RSOC_EHIP;
+}
+
+#define RSOC_HIP(call)                                                          \
+    do {                                                                        \
+        hipError_t e_ = (call);                                                 \
+        if (e_ != hipSuccess) return ::rsoc::hip_fail(e_, #call, __FILE__, __LINE__); \
+    } while (0)
+
+#define RSOC_TRY(expr)                      \
+    do {                                    \
+        int32_t r_ = (expr);                \
+        if (r_ < 0) return r_;              \
+    } while (0)
+
+#define RSOC_LAUNCH_CHECK() RSOC_HIP(hipGetLastError())
+
+inline int div_up(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+inline int round_up_to(int x, int m) { return ((x + m - 1) / m) * m; }
+
+// Device buffer that only grows.
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    int32_t reserve(size_t want) {
+        if (want <= bytes) return RSOC_OK;
+        if (p) { (void)hipFree(p); p = nullptr; bytes = 0; }
+        size_t b = want < 256 ? 256 : want;
+        RSOC_HIP(hipMalloc(&p, b));
+        bytes = b;
+        return RSOC_OK;
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    template <class T>
+    T *as() const { return static_cast<T *>(p); }
+};
+
+struct HostPinned {
+    void *p = nullptr;
+    size_t bytes = 0;
+    int32_t reserve(size_t want) {
+        if (want <= bytes) return RSOC_OK;
+        if (p) { (void)hipHostFree(p); p = nullptr; bytes = 0; }
+        size_t b = want < 256 ? 256 : want;
+        RSOC_HIP(hipHostMalloc(&p, b, hipHostMallocDefault));
+        bytes = b;
+        return RSOC_OK;
+    }
+    void release() {
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    template <class T>
+    T *as() const { return static_cast<T *>(p); }
+};
+
+struct Options {
+    int mode, tie, max_rounds, validate, t_thread, t_wave, grid_thread, grid_wave, rounds_per_sync, small_cutoff,
+        timing;
+};
+
+inline int32_t resolve_options(const rsoc_options *o, int64_t n, Options &r) {
+    rsoc_options d;
+    memset(&d, 0, sizeof(d));
+    if (o) d = *o;
+    r.mode = d.mode;
+    r.tie = d.tie;
+    if (r.mode < RSOC_MODE_OPTIMISTIC || r.mode > RSOC_MODE_TWO_PHASE) return RSOC_EINVAL;
+    if (r.tie != RSOC_TIE_LOWER_KEEPS && r.tie != RSOC_TIE_HIGHER_KEEPS) return RSOC_EINVAL;
+    if (d.max_rounds < 0 || d.t_thread < 0 || d.t_thread > 63 || d.t_wave < 0 || d.grid_thread < 0 ||
+        d.grid_wave < 0 || d.rounds_per_sync < 0 || d.validate < 0 || d.validate > 3)
+        return RSOC_EINVAL;
+    for (int i = 0; i < 5; ++i)
+        if (d.reserved[i]) return RSOC_EINVAL;
+    r.max_rounds = d.max_rounds ? d.max_rounds : (int)((n + 1 < INT32_MAX) ? n + 1 : INT32_MAX);
+    r.validate = d.validate;
+    r.t_thread = d.t_thread ? d.t_thread : 32;
+    r.t_wave = d.t_wave ? d.t_wave : 2048;
+    if (r.t_wave < r.t_thread) r.t_wave = r.t_thread;
+    r.grid_thread = d.grid_thread ? d.grid_thread : 2048;
+    r.grid_wave = d.grid_wave ? d.grid_wave : 512;
+    r.rounds_per_sync = d.rounds_per_sync ? d.rounds_per_sync : 8;
+    if (r.rounds_per_sync & 1) r.rounds_per_sync += 1;  // worklist buffers alternate: keep it even
+    r.small_cutoff = d.small_cutoff == 0 ? 4096 : (d.small_cutoff < 0 ? -1 : d.small_cutoff);
+    r.timing = d.timing;
+    return RSOC_OK;
+}
+
+}  // namespace rsoc

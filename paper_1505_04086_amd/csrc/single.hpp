@@ -1,0 +1,348 @@
+// single.hpp -- host driver of the single-graph path (rsoc_color_device and friends).
+//
+// Round 0 and round 1 touch every vertex and are launched directly; the later
+// rounds only touch the worklist and are launched as a captured HIP graph of
+// `rounds_per_sync` rounds, after which the host reads the worklist size (one
+// 64-byte copy) and either stops or replays the graph.  ROCm 7.2 has no
+// conditional graph nodes, so every kernel of a captured round first reads the
+// device-side worklist size and returns at once when it is zero.
+#pragma once
+
+#include <map>
+#include <tuple>
+
+#include "host_common.hpp"
+#include "single_kernels.hpp"
+
+struct rsoc_ctx {
+    int device = 0;
+    hipStream_t own = nullptr;    // stream for host-pointer calls
+    hipStream_t cap = nullptr;    // capture stream
+    rsoc::DevBuf wl0, wl1, hubW, hubB, pend, flags;
+    rsoc::DevBuf args, state;     // SingleArgs, SingleState (fixed addresses: graphs point at them)
+    rsoc::HostPinned host;        // pinned staging for small copies
+    rsoc::DevBuf drp, dci, dcol;  // device copies for host-pointer calls
+    std::map<std::tuple<int, int, int, int, int, int>, hipGraphExec_t> graphs;
+    hipEvent_t ev[8] = {};
+    // batched path scratch (batch.hpp)
+    rsoc::DevBuf b_desc, b_wl0, b_wl1, b_pend, b_flags, b_state, b_hub, b_kmax, b_tasks;
+};
+
+namespace rsoc {
+
+constexpr size_t kStateHeader = offsetof(SingleState, hist);
+
+struct HostStaging {
+    SingleArgs args;
+    SingleState head;  // only the header part is ever copied
+    int32_t rp_ends[2];
+};
+
+inline int32_t ctx_init(rsoc_ctx *c, int device) {
+    c->device = device;
+    RSOC_HIP(hipSetDevice(device));
+    RSOC_HIP(hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking));
+    RSOC_HIP(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+    RSOC_TRY(c->args.reserve(sizeof(SingleArgs)));
+    RSOC_TRY(c->state.reserve(sizeof(SingleState)));
+    RSOC_TRY(c->host.reserve(sizeof(HostStaging) + 4096));
+    for (auto &e : c->ev) RSOC_HIP(hipEventCreate(&e));
+    return RSOC_OK;
+}
+
+inline void ctx_free(rsoc_ctx *c) {
+    (void)hipSetDevice(c->device);
+    for (auto &kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+    c->graphs.clear();
+    for (auto &e : c->ev)
+        if (e) (void)hipEventDestroy(e);
+    for (rsoc::DevBuf *b : {&c->wl0, &c->wl1, &c->hubW, &c->hubB, &c->pend, &c->flags, &c->args, &c->state, &c->drp,
+                            &c->dci, &c->dcol, &c->b_desc, &c->b_wl0, &c->b_wl1, &c->b_pend, &c->b_flags,
+                            &c->b_state, &c->b_hub, &c->b_kmax, &c->b_tasks})
+        b->release();
+    c->host.release();
+    if (c->own) (void)hipStreamDestroy(c->own);
+    if (c->cap) (void)hipStreamDestroy(c->cap);
+}
+
+// Launches one worklist round (no sweep) for the given mode.
+template <int MODE, int TIE>
+inline void launch_list_round(rsoc_ctx *c, hipStream_t s, int parity, int gB, int gW, int gT) {
+    const SingleArgs *A = c->args.as<SingleArgs>();
+    SingleState *S = c->state.as<SingleState>();
+    const int grid = gB + gW + gT;
+    if (MODE == kTwoPhase) {
+        k_round<kAssign, kTwoPhase, TIE, false><<<grid, kBlock, 0, s>>>(A, S, parity, gB, gW, gT);
+        k_scatter<false, true><<<gT, kBlock, 0, s>>>(A, S, parity);
+        k_round<kDetect, kTwoPhase, TIE, false><<<grid, kBlock, 0, s>>>(A, S, parity, gB, gW, gT);
+    } else {
+        k_round<kRecolor, MODE, TIE, false><<<grid, kBlock, 0, s>>>(A, S, parity, gB, gW, gT);
+        if (MODE == kDeterministic) k_scatter<false, false><<<gT, kBlock, 0, s>>>(A, S, parity);
+    }
+    k_round_end<MODE, false><<<1, 64, 0, s>>>(A, S);
+}
+
+template <int MODE, int TIE>
+inline void launch_list_rounds(rsoc_ctx *c, hipStream_t s, int K, int gB, int gW, int gT) {
+    for (int r = 0; r < K; ++r) launch_list_round<MODE, TIE>(c, s, r & 1, gB, gW, gT);
+}
+
+inline void launch_list_rounds_dyn(rsoc_ctx *c, hipStream_t s, int mode, int tie, int K, int gB, int gW, int gT) {
+    if (mode == kOptimistic)
+        tie ? launch_list_rounds<kOptimistic, kHigherKeeps>(c, s, K, gB, gW, gT)
+            : launch_list_rounds<kOptimistic, kLowerKeeps>(c, s, K, gB, gW, gT);
+    else if (mode == kDeterministic)
+        tie ? launch_list_rounds<kDeterministic, kHigherKeeps>(c, s, K, gB, gW, gT)
+            : launch_list_rounds<kDeterministic, kLowerKeeps>(c, s, K, gB, gW, gT);
+    else
+        tie ? launch_list_rounds<kTwoPhase, kHigherKeeps>(c, s, K, gB, gW, gT)
+            : launch_list_rounds<kTwoPhase, kLowerKeeps>(c, s, K, gB, gW, gT);
+}
+
+// Captured graph of K worklist rounds, cached per (mode, tie, K, grid split).
+inline int32_t get_round_graph(rsoc_ctx *c, int mode, int tie, int K, int gB, int gW, int gT, hipGraphExec_t *out) {
+    auto key = std::make_tuple(mode, tie, K, gB, gW, gT);
+    auto it = c->graphs.find(key);
+    if (it != c->graphs.end()) { *out = it->second; return RSOC_OK; }
+    hipGraph_t g = nullptr;
+    RSOC_HIP(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+    launch_list_rounds_dyn(c, c->cap, mode, tie, K, gB, gW, gT);
+    hipError_t le = hipGetLastError();
+    hipError_t ee = hipStreamEndCapture(c->cap, &g);
+    if (le != hipSuccess) { if (g) (void)hipGraphDestroy(g); return hip_fail(le, "capture launch", __FILE__, __LINE__); }
+    if (ee != hipSuccess) return hip_fail(ee, "hipStreamEndCapture", __FILE__, __LINE__);
+    hipGraphExec_t ex = nullptr;
+    hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ie != hipSuccess) return hip_fail(ie, "hipGraphInstantiate", __FILE__, __LINE__);
+    c->graphs[key] = ex;
+    *out = ex;
+    return RSOC_OK;
+}
+
+// Rounds 0 and 1 (both cover all of V).  Returns after enqueueing.
+template <int MODE, int TIE>
+inline void launch_sweep_rounds(rsoc_ctx *c, hipStream_t s, int32_t *col, int n, int gB, int gW, int gT, bool timing) {
+    const SingleArgs *A = c->args.as<SingleArgs>();
+    SingleState *S = c->state.as<SingleState>();
+    const int grid = gB + gW + gT;
+    const int fill_grid = std::min(div_up(n, kBlock), 4096);
+    // sweep rounds read no worklist and append into buffer 0 (parity 1)
+    if (timing) (void)hipEventRecord(c->ev[2], s);
+    if (MODE == kDeterministic) {
+        // round 0: against the all-uncoloured snapshot every vertex takes colour 0
+        k_fill<<<fill_grid, kBlock, 0, s>>>(col, n, 0);
+    } else {
+        k_fill<<<fill_grid, kBlock, 0, s>>>(col, n, -1);
+        if (MODE == kOptimistic) {
+            if (timing) (void)hipEventRecord(c->ev[2], s);
+            // round 0: tentative First-Fit over all of V with live reads
+            k_round<kAssign, kOptimistic, TIE, true><<<grid, kBlock, 0, s>>>(A, S, 1, gB, gW, gT);
+        }
+    }
+    if (timing) (void)hipEventRecord(c->ev[3], s);
+    if (MODE == kTwoPhase) {
+        // Algorithm 2, first round: tentative colouring of V, publish, detect
+        k_round<kAssign, kTwoPhase, TIE, true><<<grid, kBlock, 0, s>>>(A, S, 1, gB, gW, gT);
+        k_scatter<true, false><<<fill_grid, kBlock, 0, s>>>(A, S, 1);
+        if (timing) (void)hipEventRecord(c->ev[4], s);
+        k_round<kDetect, kTwoPhase, TIE, true><<<grid, kBlock, 0, s>>>(A, S, 1, gB, gW, gT);
+        if (timing) (void)hipEventRecord(c->ev[5], s);
+    } else {
+        if (timing) (void)hipEventRecord(c->ev[4], s);
+        // round 1: detect-and-recolour over U^0 = V
+        k_round<kRecolor, MODE, TIE, true><<<grid, kBlock, 0, s>>>(A, S, 1, gB, gW, gT);
+        if (timing) (void)hipEventRecord(c->ev[5], s);
+        if (MODE == kDeterministic) k_scatter<false, false><<<std::max(1, gT), kBlock, 0, s>>>(A, S, 1);
+    }
+    k_round_end<MODE, true><<<1, 64, 0, s>>>(A, S);
+}
+
+inline void launch_sweep_dyn(rsoc_ctx *c, hipStream_t s, int mode, int tie, int32_t *col, int n, int gB, int gW,
+                             int gT, bool timing) {
+    if (mode == kOptimistic)
+        tie ? launch_sweep_rounds<kOptimistic, kHigherKeeps>(c, s, col, n, gB, gW, gT, timing)
+            : launch_sweep_rounds<kOptimistic, kLowerKeeps>(c, s, col, n, gB, gW, gT, timing);
+    else if (mode == kDeterministic)
+        tie ? launch_sweep_rounds<kDeterministic, kHigherKeeps>(c, s, col, n, gB, gW, gT, timing)
+            : launch_sweep_rounds<kDeterministic, kLowerKeeps>(c, s, col, n, gB, gW, gT, timing);
+    else
+        tie ? launch_sweep_rounds<kTwoPhase, kHigherKeeps>(c, s, col, n, gB, gW, gT, timing)
+            : launch_sweep_rounds<kTwoPhase, kLowerKeeps>(c, s, col, n, gB, gW, gT, timing);
+}
+
+inline int32_t ensure_single_scratch(rsoc_ctx *c, int64_t n) {
+    const size_t b = sizeof(int32_t) * (size_t)(n + 2);
+    RSOC_TRY(c->wl0.reserve(b));
+    RSOC_TRY(c->wl1.reserve(b));
+    RSOC_TRY(c->hubW.reserve(b));
+    RSOC_TRY(c->hubB.reserve(b));
+    RSOC_TRY(c->pend.reserve(b));
+    RSOC_TRY(c->flags.reserve(b));
+    return RSOC_OK;
+}
+
+inline int32_t status_from_err(int32_t err) {
+    if (err & 1) return RSOC_ECSR;
+    if (err & 2) return RSOC_ESELFLOOP;
+    return RSOC_OK;
+}
+
+// Algorithmic bytes of the colouring (what the method itself must move,
+// counted whether served by cache or HBM):
+//   round 0 (optimistic): row_ptr 4(n+1) + col_idx 4 nnz + neighbour colours
+//     4 nnz + colour writes 4n + static hub lists 4(nW+nB);
+//   round 0 (round-synchronous): the colour fill 4n;
+//   round 1 (sweep): row_ptr 4(n+1) + own colour 4n + 8 nnz + hub lists, plus
+//     per recoloured vertex 8 (colour write + append), or 20 when staged
+//     (stage write, append, then list read, stage read, colour write);
+//   worklist rounds: per inspected vertex 16 (list entry, row_ptr pair, own
+//     colour) + 8 per adjacency entry + the per-recoloured cost above.
+inline void alg_bytes(int mode, int64_t n, int64_t nnz, int64_t nW, int64_t nB, int64_t L1, int64_t conflicts,
+                      uint64_t inspected, uint64_t deg_sum, int64_t &b0, int64_t &b1, int64_t &total) {
+    const int64_t per_rec = (mode == kOptimistic) ? 8 : 20;
+    if (mode == kTwoPhase) {
+        b0 = 4 * n;
+        b1 = (4 * (n + 1) + 8 * nnz + 4 * n + 4 * (nW + nB)) + 12 * n + (4 * (n + 1) + 4 * n + 8 * nnz + 4 * (nW + nB)) +
+             4 * L1;
+        total = b0 + b1 + 44 * (int64_t)inspected + 16 * (int64_t)deg_sum + 4 * (conflicts - L1);
+        return;
+    }
+    b0 = (mode == kOptimistic) ? 4 * (n + 1) + 8 * nnz + 4 * n + 4 * (nW + nB) : 4 * n;
+    b1 = 4 * (n + 1) + 4 * n + 8 * nnz + 4 * (nW + nB) + per_rec * L1;
+    total = b0 + b1 + 16 * (int64_t)inspected + 8 * (int64_t)deg_sum + per_rec * (conflicts - L1);
+}
+
+// The single-graph driver.  All pointers are device pointers.
+inline int32_t run_single(rsoc_ctx *c, const int32_t *rp, const int32_t *ci, int32_t n, int32_t *col,
+                          const Options &o, rsoc_stats *st, hipStream_t s) {
+    HostStaging *h = c->host.as<HostStaging>();
+    SingleState *S = c->state.as<SingleState>();
+    if (st) {
+        int32_t *keep = st->per_round_L;
+        int32_t cap = st->per_round_cap;
+        memset(st, 0, sizeof(*st));
+        st->per_round_L = keep;
+        st->per_round_cap = cap;
+    }
+    if (n == 0) return 0;
+    // nnz and row_ptr[0]
+    RSOC_HIP(hipMemcpyAsync(&h->rp_ends[0], rp, 4, hipMemcpyDeviceToHost, s));
+    RSOC_HIP(hipMemcpyAsync(&h->rp_ends[1], rp + n, 4, hipMemcpyDeviceToHost, s));
+    RSOC_HIP(hipStreamSynchronize(s));
+    if (h->rp_ends[0] != 0 || h->rp_ends[1] < 0) return RSOC_ECSR;
+    const int64_t nnz = h->rp_ends[1];
+    if (nnz > 0 && !ci) return RSOC_EINVAL;
+    RSOC_TRY(ensure_single_scratch(c, n));
+
+    SingleArgs &a = h->args;
+    a.rp = rp;
+    a.ci = ci;
+    a.col = col;
+    a.pend = c->pend.as<int32_t>();
+    a.wl[0] = c->wl0.as<int32_t>();
+    a.wl[1] = c->wl1.as<int32_t>();
+    a.hubW = c->hubW.as<int32_t>();
+    a.hubB = c->hubB.as<int32_t>();
+    a.n = n;
+    a.t_thread = o.t_thread;
+    a.t_wave = o.t_wave;
+    a.max_rounds = o.max_rounds;
+    a.offW = a.offB = 0;
+    RSOC_HIP(hipMemcpyAsync(c->args.p, &a, sizeof(a), hipMemcpyHostToDevice, s));
+    RSOC_HIP(hipMemsetAsync(S, 0, kStateHeader, s));
+    const int vgrid = std::min(div_up(n, kBlock), 4096);
+    if (o.validate & RSOC_CHECK_CSR) {
+        k_validate<<<vgrid, kBlock, 0, s>>>(rp, ci, n, nnz, &S->err);
+        RSOC_LAUNCH_CHECK();
+        RSOC_HIP(hipMemcpyAsync(&h->head, S, kStateHeader, hipMemcpyDeviceToHost, s));
+        RSOC_HIP(hipStreamSynchronize(s));
+        RSOC_TRY(status_from_err(h->head.err));
+    }
+    k_bin<<<vgrid, kBlock, 0, s>>>(c->args.as<SingleArgs>(), S);
+    RSOC_LAUNCH_CHECK();
+    RSOC_HIP(hipMemcpyAsync(&h->head, S, kStateHeader, hipMemcpyDeviceToHost, s));
+    RSOC_HIP(hipStreamSynchronize(s));
+    const int nW = h->head.nW, nB = h->head.nB, maxdeg = h->head.maxdeg;
+    const int nT = n - nW - nB;
+    a.offW = nT;
+    a.offB = nT + nW;
+    RSOC_HIP(hipMemcpyAsync(c->args.p, &a, sizeof(a), hipMemcpyHostToDevice, s));
+
+    // launch shapes
+    const int gB = std::min(nB, 1024);
+    const int gW = std::min(div_up(nW, kWavesPerBlock), o.grid_wave);
+    int gTs = std::min(div_up(n, kBlock), o.grid_thread);
+    if (gTs >= kXcds) gTs -= gTs % kXcds;
+    const int gBl = std::min(nB, 256);
+    const int gWl = std::min(div_up(nW, kWavesPerBlock), o.grid_wave);
+    const int gTl = std::max(1, std::min(div_up(nT, kBlock), o.grid_thread));
+
+    hipGraphExec_t gexec = nullptr;
+    RSOC_TRY(get_round_graph(c, o.mode, o.tie, o.rounds_per_sync, gBl, gWl, gTl, &gexec));
+
+    RSOC_HIP(hipEventRecord(c->ev[0], s));
+    launch_sweep_dyn(c, s, o.mode, o.tie, col, n, gB, gW, gTs, o.timing != 0);
+    RSOC_LAUNCH_CHECK();
+    int32_t status = RSOC_OK;
+    for (;;) {
+        RSOC_HIP(hipGraphLaunch(gexec, s));
+        RSOC_HIP(hipEventRecord(c->ev[1], s));
+        RSOC_HIP(hipMemcpyAsync(&h->head, S, kStateHeader, hipMemcpyDeviceToHost, s));
+        RSOC_HIP(hipStreamSynchronize(s));
+        const int left = h->head.cnt_in[0] + h->head.cnt_in[1] + h->head.cnt_in[2];
+        if (left == 0) break;
+        if (h->head.passes >= o.max_rounds) { status = RSOC_ENOCONV; break; }
+    }
+    // colour count (K = max + 1) and distinct colours; every colour is at most
+    // min(max degree, n - 1) (a First-Fit value over at most that many neighbours)
+    const int clim = std::min(maxdeg, n - 1);
+    RSOC_HIP(hipMemsetAsync(c->flags.p, 0, sizeof(int32_t) * (size_t)(clim + 1), s));
+    k_colour_stats<<<vgrid, kBlock, 0, s>>>(col, n, clim, c->flags.as<int32_t>(), &S->kmax, &S->err);
+    k_count_flags<<<std::min(div_up(clim + 1, kBlock), 1024), kBlock, 0, s>>>(c->flags.as<int32_t>(), clim + 1,
+                                                                               &S->distinct);
+    RSOC_LAUNCH_CHECK();
+    RSOC_HIP(hipMemcpyAsync(&h->head, S, kStateHeader, hipMemcpyDeviceToHost, s));
+    int32_t L1 = 0;
+    RSOC_HIP(hipMemcpyAsync(&L1, &S->hist[0], 4, hipMemcpyDeviceToHost, s));
+    if (st && st->per_round_L && st->per_round_cap > 0) {
+        RSOC_HIP(hipStreamSynchronize(s));
+        const int cnt = std::min(std::min(h->head.rounds, st->per_round_cap), kHistCap);
+        if (cnt > 0)
+            RSOC_HIP(hipMemcpyAsync(st->per_round_L, S->hist, sizeof(int32_t) * cnt, hipMemcpyDeviceToHost, s));
+    }
+    RSOC_HIP(hipStreamSynchronize(s));
+    if (h->head.err & 4) return RSOC_EHIP;  // a colour outside [0, max degree]: never expected
+    if (st) {
+        st->rounds = h->head.rounds;
+        st->passes = h->head.passes;
+        st->colors = h->head.kmax;
+        st->colors_distinct = h->head.distinct;
+        st->conflicts = h->head.conflicts;
+        st->inspected = (int64_t)h->head.inspected + n;
+        st->max_degree = maxdeg;
+        st->bin_counts[0] = nT;
+        st->bin_counts[1] = nW;
+        st->bin_counts[2] = nB;
+        float ms = 0;
+        RSOC_HIP(hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
+        st->ms = ms;
+        if (o.timing) {
+            float m0 = 0, m1 = 0;
+            RSOC_HIP(hipEventElapsedTime(&m0, c->ev[2], c->ev[3]));
+            RSOC_HIP(hipEventElapsedTime(&m1, c->ev[4], c->ev[5]));
+            st->ms_round0 = m0;
+            st->ms_round1 = m1;
+        }
+        int64_t b0, b1, tot;
+        const int64_t l1 = h->head.rounds > 0 ? L1 : 0;
+        alg_bytes(o.mode, n, nnz, nW, nB, l1, h->head.conflicts, h->head.inspected, h->head.deg_sum, b0, b1, tot);
+        st->bytes_round0 = b0;
+        st->bytes_round1 = b1;
+        st->alg_bytes = tot;
+    }
+    if (status < 0) return status;
+    return h->head.kmax;
+}
+
+}  // namespace rsoc
