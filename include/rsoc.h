@@ -86,14 +86,26 @@ typedef struct {
     int32_t max_rounds;  /* bound on inspection passes (rounds >= 1); 0 => n + 1, which no input reaches */
     int32_t validate;    /* bitmask of RSOC_CHECK_*; symmetry is checked only for host-pointer calls */
     /* tuning; 0 selects the library default (or the tuned value) */
-    int32_t t_thread;    /* max degree coloured by one thread (<= 63; default 32) */
+    int32_t t_thread;    /* max degree coloured by a group of 8 lanes (<= 32; default 32) */
     int32_t t_wave;      /* max degree coloured by one wavefront; larger rows use a workgroup (default 2048) */
-    int32_t grid_thread; /* workgroups given to the thread bin per round launch (default 2048) */
+    int32_t grid_thread; /* workgroups given to the thread bin per round launch (default 1024) */
     int32_t grid_wave;   /* workgroups given to the wavefront bin (default 512) */
     int32_t rounds_per_sync; /* rounds enqueued (as one HIP graph) per host check of the worklist (default 8, even) */
     int32_t small_cutoff;    /* batch: graphs with n <= this are coloured whole by one workgroup (default 4096; -1 disables) */
     int32_t timing;      /* 1: record per-kernel HIP events (fills the ms_* fields of rsoc_stats) */
-    int32_t reserved[5]; /* must be zero */
+    /* Optimistic mode only.  0 (default): round 0 gives each vertex the smallest
+     * colour absent among the neighbours it loses a tie to (the ones sequential
+     * First-Fit in tie order would have coloured first) and collects the
+     * vertices that read one of those still uncoloured; round 1 inspects only
+     * them, since no other vertex can be defective after round 0.  1: the literal
+     * reading: round 0 reads all neighbours and round 1 inspects all of V. */
+    int32_t full_sweep;
+    /* Optimistic default flow: round 0 also reads neighbours it wins against
+     * whose id is within this distance (the sweep may have coloured them
+     * already).  0 = library default (16 times the ids one round-0 step covers),
+     * -1 = none. */
+    int32_t lookahead;
+    int32_t reserved[3]; /* must be zero */
 } rsoc_options;
 
 typedef struct {
@@ -113,7 +125,8 @@ typedef struct {
     int32_t bin_counts[3];   /* vertices per degree bin: thread, wavefront, workgroup */
     int32_t *per_round_L;    /* optional caller array: per_round_L[i] = |L| of recolouring round i+1 */
     int32_t per_round_cap;   /* its length */
-    int32_t reserved[5];
+    int32_t worklist0;       /* |U^0|: vertices round 1 inspects */
+    int32_t reserved[4];
 } rsoc_stats;
 
 typedef struct rsoc_ctx rsoc_ctx;

@@ -60,7 +60,8 @@ class rsoc_options(ctypes.Structure):
                 ("validate", ctypes.c_int32), ("t_thread", ctypes.c_int32), ("t_wave", ctypes.c_int32),
                 ("grid_thread", ctypes.c_int32), ("grid_wave", ctypes.c_int32),
                 ("rounds_per_sync", ctypes.c_int32), ("small_cutoff", ctypes.c_int32),
-                ("timing", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+                ("timing", ctypes.c_int32), ("full_sweep", ctypes.c_int32), ("lookahead", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 3)]
 
 
 class rsoc_stats(ctypes.Structure):
@@ -70,7 +71,7 @@ class rsoc_stats(ctypes.Structure):
                 ("ms_round1", ctypes.c_double), ("bytes_round0", ctypes.c_int64), ("bytes_round1", ctypes.c_int64),
                 ("max_degree", ctypes.c_int32), ("bin_counts", ctypes.c_int32 * 3),
                 ("per_round_L", ctypes.POINTER(ctypes.c_int32)), ("per_round_cap", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 5)]
+                ("worklist0", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
 
 
 _p = ctypes.c_void_p

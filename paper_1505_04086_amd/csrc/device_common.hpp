@@ -6,6 +6,15 @@
 
 namespace rsoc {
 
+// Global-memory (address space 1) views of plain pointers: loads through them
+// compile to global_load_* instead of flat loads (pointers read from device
+// memory would otherwise stay generic).
+#define RSOC_GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ const RSOC_GLOBAL T *gro(const T *p) { return (const RSOC_GLOBAL T *)p; }
+template <class T>
+__device__ __forceinline__ RSOC_GLOBAL T *grw(T *p) { return (RSOC_GLOBAL T *)p; }
+
 constexpr int kWave = 64;                 // CDNA wavefront width
 constexpr int kBlock = 256;               // threads per workgroup for every round kernel
 constexpr int kWavesPerBlock = kBlock / kWave;
@@ -17,6 +26,10 @@ constexpr int kLdsWords = (kBlockWindowWords > kWavesPerBlock * kWaveWindowWords
                                                                                   : kWavesPerBlock * kWaveWindowWords;
 constexpr int kHistCap = 1 << 16;         // per-round |L| history kept on the device
 constexpr int kXcds = 8;                  // MI355X: 8 accelerator complex dies, 32 CUs each
+constexpr int kGroup = 8;                 // lanes per vertex in the thread bin
+constexpr int kGroupSlots = 4;            // row entries each lane holds: thread-bin degree <= 32
+constexpr int kThreadBinMax = kGroup * kGroupSlots;
+constexpr int kQueueCap = 1024;           // per-workgroup append queue (LDS) of the thread bin
 
 enum Phase : int { kAssign = 0, kRecolor = 1, kDetect = 2 };
 enum Mode : int { kOptimistic = 0, kDeterministic = 1, kTwoPhase = 2 };
@@ -37,6 +50,25 @@ __device__ __forceinline__ int lanes_below(uint64_t m) {
 }
 
 __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+// OR of a predicate over the G-lane group this lane belongs to (G divides 64).
+template <int G>
+__device__ __forceinline__ bool group_any(bool p) {
+    const uint64_t m = ballot(p);
+    const int g0 = lane_id() & ~(G - 1);
+    return ((m >> g0) & ((G == 64) ? ~0ull : ((1ull << G) - 1))) != 0;
+}
+
+// OR of a 64-bit value over the G-lane group (butterfly).
+template <int G>
+__device__ __forceinline__ uint64_t group_or64(uint64_t x) {
+#pragma unroll
+    for (int off = 1; off < G; off <<= 1) {
+        const uint32_t lo = __shfl_xor((uint32_t)x, off), hi = __shfl_xor((uint32_t)(x >> 32), off);
+        x |= ((uint64_t)hi << 32) | lo;
+    }
+    return x;
+}
 
 // Orders this wavefront's LDS accesses across lanes (a compiler barrier; the
 // hardware executes one wavefront's LDS instructions in order).

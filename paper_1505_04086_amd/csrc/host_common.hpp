@@ -82,7 +82,7 @@ struct HostPinned {
 
 struct Options {
     int mode, tie, max_rounds, validate, t_thread, t_wave, grid_thread, grid_wave, rounds_per_sync, small_cutoff,
-        timing;
+        timing, full_sweep, lookahead;
 };
 
 inline int32_t resolve_options(const rsoc_options *o, int64_t n, Options &r) {
@@ -93,17 +93,21 @@ inline int32_t resolve_options(const rsoc_options *o, int64_t n, Options &r) {
     r.tie = d.tie;
     if (r.mode < RSOC_MODE_OPTIMISTIC || r.mode > RSOC_MODE_TWO_PHASE) return RSOC_EINVAL;
     if (r.tie != RSOC_TIE_LOWER_KEEPS && r.tie != RSOC_TIE_HIGHER_KEEPS) return RSOC_EINVAL;
-    if (d.max_rounds < 0 || d.t_thread < 0 || d.t_thread > 63 || d.t_wave < 0 || d.grid_thread < 0 ||
+    if (d.max_rounds < 0 || d.t_thread < 0 || d.t_thread > 32 || d.t_wave < 0 || d.grid_thread < 0 ||
         d.grid_wave < 0 || d.rounds_per_sync < 0 || d.validate < 0 || d.validate > 3)
         return RSOC_EINVAL;
-    for (int i = 0; i < 5; ++i)
+    for (int i = 0; i < 3; ++i)
         if (d.reserved[i]) return RSOC_EINVAL;
+    if (d.lookahead < -1) return RSOC_EINVAL;
+    r.lookahead = d.lookahead;
+    if (d.full_sweep < 0 || d.full_sweep > 1) return RSOC_EINVAL;
+    r.full_sweep = d.full_sweep;
     r.max_rounds = d.max_rounds ? d.max_rounds : (int)((n + 1 < INT32_MAX) ? n + 1 : INT32_MAX);
     r.validate = d.validate;
     r.t_thread = d.t_thread ? d.t_thread : 32;
     r.t_wave = d.t_wave ? d.t_wave : 2048;
     if (r.t_wave < r.t_thread) r.t_wave = r.t_thread;
-    r.grid_thread = d.grid_thread ? d.grid_thread : 2048;
+    r.grid_thread = d.grid_thread ? d.grid_thread : 1024;
     r.grid_wave = d.grid_wave ? d.grid_wave : 512;
     r.rounds_per_sync = d.rounds_per_sync ? d.rounds_per_sync : 8;
     if (r.rounds_per_sync & 1) r.rounds_per_sync += 1;  // worklist buffers alternate: keep it even

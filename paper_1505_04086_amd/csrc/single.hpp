@@ -18,7 +18,7 @@ struct rsoc_ctx {
     int device = 0;
     hipStream_t own = nullptr;    // stream for host-pointer calls
     hipStream_t cap = nullptr;    // capture stream
-    rsoc::DevBuf wl0, wl1, hubW, hubB, pend, flags;
+    rsoc::DevBuf wl0, wl1, hubW, hubB, pend, flags, col8;
     rsoc::DevBuf args, state;     // SingleArgs, SingleState (fixed addresses: graphs point at them)
     rsoc::HostPinned host;        // pinned staging for small copies
     rsoc::DevBuf drp, dci, dcol;  // device copies for host-pointer calls
@@ -56,7 +56,7 @@ inline void ctx_free(rsoc_ctx *c) {
     c->graphs.clear();
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);
-    for (rsoc::DevBuf *b : {&c->wl0, &c->wl1, &c->hubW, &c->hubB, &c->pend, &c->flags, &c->args, &c->state, &c->drp,
+    for (rsoc::DevBuf *b : {&c->col8, &c->wl0, &c->wl1, &c->hubW, &c->hubB, &c->pend, &c->flags, &c->args, &c->state, &c->drp,
                             &c->dci, &c->dcol, &c->b_desc, &c->b_wl0, &c->b_wl1, &c->b_pend, &c->b_flags,
                             &c->b_state, &c->b_hub, &c->b_kmax, &c->b_tasks})
         b->release();
@@ -122,7 +122,8 @@ inline int32_t get_round_graph(rsoc_ctx *c, int mode, int tie, int K, int gB, in
 
 // Rounds 0 and 1 (both cover all of V).  Returns after enqueueing.
 template <int MODE, int TIE>
-inline void launch_sweep_rounds(rsoc_ctx *c, hipStream_t s, int32_t *col, int n, int gB, int gW, int gT, bool timing) {
+inline void launch_sweep_rounds(rsoc_ctx *c, hipStream_t s, int32_t *col, int n, int gB, int gW, int gT, bool timing,
+                                bool full_sweep) {
     const SingleArgs *A = c->args.as<SingleArgs>();
     SingleState *S = c->state.as<SingleState>();
     const int grid = gB + gW + gT;
@@ -131,13 +132,22 @@ inline void launch_sweep_rounds(rsoc_ctx *c, hipStream_t s, int32_t *col, int n,
     if (timing) (void)hipEventRecord(c->ev[2], s);
     if (MODE == kDeterministic) {
         // round 0: against the all-uncoloured snapshot every vertex takes colour 0
-        k_fill<<<fill_grid, kBlock, 0, s>>>(col, n, 0);
+        k_fill<<<fill_grid, kBlock, 0, s>>>(col, c->col8.as<uint8_t>(), n, 0);
     } else {
-        k_fill<<<fill_grid, kBlock, 0, s>>>(col, n, -1);
+        k_fill<<<fill_grid, kBlock, 0, s>>>(col, c->col8.as<uint8_t>(), n, -1);
         if (MODE == kOptimistic) {
             if (timing) (void)hipEventRecord(c->ev[2], s);
             // round 0: tentative First-Fit over all of V with live reads
-            k_round<kAssign, kOptimistic, TIE, true><<<grid, kBlock, 0, s>>>(A, S, 1, gB, gW, gT);
+            if (full_sweep) {
+                k_round<kAssign, kOptimistic, TIE, true, 0><<<grid, kBlock, 0, s>>>(A, S, 1, gB, gW, gT);
+            } else {
+                // ... over the neighbours each vertex loses to, collecting the
+                // only vertices that can end the round defective as U^0
+                k_round<kAssign, kOptimistic, TIE, true, 1><<<grid, kBlock, 0, s>>>(A, S, 1, gB, gW, gT);
+                if (timing) (void)hipEventRecord(c->ev[3], s);
+                k_round_end<MODE, true, true><<<1, 64, 0, s>>>(A, S);
+                return;  // round 1 is the first worklist round
+            }
         }
     }
     if (timing) (void)hipEventRecord(c->ev[3], s);
@@ -159,16 +169,16 @@ inline void launch_sweep_rounds(rsoc_ctx *c, hipStream_t s, int32_t *col, int n,
 }
 
 inline void launch_sweep_dyn(rsoc_ctx *c, hipStream_t s, int mode, int tie, int32_t *col, int n, int gB, int gW,
-                             int gT, bool timing) {
+                             int gT, bool timing, bool full) {
     if (mode == kOptimistic)
-        tie ? launch_sweep_rounds<kOptimistic, kHigherKeeps>(c, s, col, n, gB, gW, gT, timing)
-            : launch_sweep_rounds<kOptimistic, kLowerKeeps>(c, s, col, n, gB, gW, gT, timing);
+        tie ? launch_sweep_rounds<kOptimistic, kHigherKeeps>(c, s, col, n, gB, gW, gT, timing, full)
+            : launch_sweep_rounds<kOptimistic, kLowerKeeps>(c, s, col, n, gB, gW, gT, timing, full);
     else if (mode == kDeterministic)
-        tie ? launch_sweep_rounds<kDeterministic, kHigherKeeps>(c, s, col, n, gB, gW, gT, timing)
-            : launch_sweep_rounds<kDeterministic, kLowerKeeps>(c, s, col, n, gB, gW, gT, timing);
+        tie ? launch_sweep_rounds<kDeterministic, kHigherKeeps>(c, s, col, n, gB, gW, gT, timing, full)
+            : launch_sweep_rounds<kDeterministic, kLowerKeeps>(c, s, col, n, gB, gW, gT, timing, full);
     else
-        tie ? launch_sweep_rounds<kTwoPhase, kHigherKeeps>(c, s, col, n, gB, gW, gT, timing)
-            : launch_sweep_rounds<kTwoPhase, kLowerKeeps>(c, s, col, n, gB, gW, gT, timing);
+        tie ? launch_sweep_rounds<kTwoPhase, kHigherKeeps>(c, s, col, n, gB, gW, gT, timing, full)
+            : launch_sweep_rounds<kTwoPhase, kLowerKeeps>(c, s, col, n, gB, gW, gT, timing, full);
 }
 
 inline int32_t ensure_single_scratch(rsoc_ctx *c, int64_t n) {
@@ -179,6 +189,7 @@ inline int32_t ensure_single_scratch(rsoc_ctx *c, int64_t n) {
     RSOC_TRY(c->hubB.reserve(b));
     RSOC_TRY(c->pend.reserve(b));
     RSOC_TRY(c->flags.reserve(b));
+    RSOC_TRY(c->col8.reserve((size_t)n + 64));
     return RSOC_OK;
 }
 
@@ -190,22 +201,32 @@ inline int32_t status_from_err(int32_t err) {
 
 // Algorithmic bytes of the colouring (what the method itself must move,
 // counted whether served by cache or HBM):
-//   round 0 (optimistic): row_ptr 4(n+1) + col_idx 4 nnz + neighbour colours
-//     4 nnz + colour writes 4n + static hub lists 4(nW+nB);
-//   round 0 (round-synchronous): the colour fill 4n;
-//   round 1 (sweep): row_ptr 4(n+1) + own colour 4n + 8 nnz + hub lists, plus
-//     per recoloured vertex 8 (colour write + append), or 20 when staged
+//   round 0, optimistic, literal (full_sweep): row_ptr 4(n+1) + col_idx 4 nnz
+//     + neighbour colours 4 nnz + colour writes 4n + hub lists 4(nW+nB);
+//   round 0, optimistic, default: the same but neighbour colours only for the
+//     neighbours a vertex loses to (4 nnz/2 on a symmetric graph without
+//     self-loops) plus 4 |U^0| for collecting U^0;
+//   round 0, round-synchronous: the colour fill 4n;
+//   round 1 as a sweep: row_ptr 4(n+1) + own colour 4n + 8 nnz + hub lists,
+//     plus per recoloured vertex 8 (colour write + append), or 20 when staged
 //     (stage write, append, then list read, stage read, colour write);
 //   worklist rounds: per inspected vertex 16 (list entry, row_ptr pair, own
 //     colour) + 8 per adjacency entry + the per-recoloured cost above.
-inline void alg_bytes(int mode, int64_t n, int64_t nnz, int64_t nW, int64_t nB, int64_t L1, int64_t conflicts,
-                      uint64_t inspected, uint64_t deg_sum, int64_t &b0, int64_t &b1, int64_t &total) {
+inline void alg_bytes(int mode, bool full_sweep, int64_t n, int64_t nnz, int64_t nW, int64_t nB, int64_t u0,
+                      int64_t L1, int64_t conflicts, uint64_t inspected, uint64_t deg_sum, int64_t &b0, int64_t &b1,
+                      int64_t &total) {
     const int64_t per_rec = (mode == kOptimistic) ? 8 : 20;
     if (mode == kTwoPhase) {
         b0 = 4 * n;
         b1 = (4 * (n + 1) + 8 * nnz + 4 * n + 4 * (nW + nB)) + 12 * n + (4 * (n + 1) + 4 * n + 8 * nnz + 4 * (nW + nB)) +
              4 * L1;
         total = b0 + b1 + 44 * (int64_t)inspected + 16 * (int64_t)deg_sum + 4 * (conflicts - L1);
+        return;
+    }
+    if (mode == kOptimistic && !full_sweep) {
+        b0 = 4 * (n + 1) + 4 * nnz + 4 * (nnz / 2) + 4 * n + 4 * (nW + nB) + 4 * u0;
+        b1 = 0;
+        total = b0 + 16 * (int64_t)inspected + 8 * (int64_t)deg_sum + per_rec * conflicts;
         return;
     }
     b0 = (mode == kOptimistic) ? 4 * (n + 1) + 8 * nnz + 4 * n + 4 * (nW + nB) : 4 * n;
@@ -239,6 +260,7 @@ inline int32_t run_single(rsoc_ctx *c, const int32_t *rp, const int32_t *ci, int
     a.rp = rp;
     a.ci = ci;
     a.col = col;
+    a.col8 = c->col8.as<uint8_t>();
     a.pend = c->pend.as<int32_t>();
     a.wl[0] = c->wl0.as<int32_t>();
     a.wl[1] = c->wl1.as<int32_t>();
@@ -249,6 +271,7 @@ inline int32_t run_single(rsoc_ctx *c, const int32_t *rp, const int32_t *ci, int
     a.t_wave = o.t_wave;
     a.max_rounds = o.max_rounds;
     a.offW = a.offB = 0;
+    a.look = 0;
     RSOC_HIP(hipMemcpyAsync(c->args.p, &a, sizeof(a), hipMemcpyHostToDevice, s));
     RSOC_HIP(hipMemsetAsync(S, 0, kStateHeader, s));
     const int vgrid = std::min(div_up(n, kBlock), 4096);
@@ -267,22 +290,25 @@ inline int32_t run_single(rsoc_ctx *c, const int32_t *rp, const int32_t *ci, int
     const int nT = n - nW - nB;
     a.offW = nT;
     a.offB = nT + nW;
-    RSOC_HIP(hipMemcpyAsync(c->args.p, &a, sizeof(a), hipMemcpyHostToDevice, s));
 
     // launch shapes
+    constexpr int kVpb = 2 * kBlock / kGroup;  // thread-bin vertices per workgroup step
     const int gB = std::min(nB, 1024);
     const int gW = std::min(div_up(nW, kWavesPerBlock), o.grid_wave);
-    int gTs = std::min(div_up(n, kBlock), o.grid_thread);
+    int gTs = std::min(div_up(n, kVpb), o.grid_thread);
     if (gTs >= kXcds) gTs -= gTs % kXcds;
+    const int64_t look = o.lookahead == -1 ? 0 : (o.lookahead > 0 ? o.lookahead : 16ll * gTs * kVpb);
+    a.look = (int)std::min<int64_t>(look, INT32_MAX);
+    RSOC_HIP(hipMemcpyAsync(c->args.p, &a, sizeof(a), hipMemcpyHostToDevice, s));
     const int gBl = std::min(nB, 256);
     const int gWl = std::min(div_up(nW, kWavesPerBlock), o.grid_wave);
-    const int gTl = std::max(1, std::min(div_up(nT, kBlock), o.grid_thread));
+    const int gTl = std::max(1, std::min(div_up(nT, kVpb), o.grid_thread));
 
     hipGraphExec_t gexec = nullptr;
     RSOC_TRY(get_round_graph(c, o.mode, o.tie, o.rounds_per_sync, gBl, gWl, gTl, &gexec));
 
     RSOC_HIP(hipEventRecord(c->ev[0], s));
-    launch_sweep_dyn(c, s, o.mode, o.tie, col, n, gB, gW, gTs, o.timing != 0);
+    launch_sweep_dyn(c, s, o.mode, o.tie, col, n, gB, gW, gTs, o.timing != 0, o.full_sweep != 0);
     RSOC_LAUNCH_CHECK();
     int32_t status = RSOC_OK;
     for (;;) {
@@ -319,7 +345,8 @@ inline int32_t run_single(rsoc_ctx *c, const int32_t *rp, const int32_t *ci, int
         st->colors = h->head.kmax;
         st->colors_distinct = h->head.distinct;
         st->conflicts = h->head.conflicts;
-        st->inspected = (int64_t)h->head.inspected + n;
+        const bool sweep1 = !(o.mode == kOptimistic && !o.full_sweep);
+        st->inspected = (int64_t)h->head.inspected + (sweep1 ? n : 0);
         st->max_degree = maxdeg;
         st->bin_counts[0] = nT;
         st->bin_counts[1] = nW;
@@ -330,14 +357,16 @@ inline int32_t run_single(rsoc_ctx *c, const int32_t *rp, const int32_t *ci, int
         if (o.timing) {
             float m0 = 0, m1 = 0;
             RSOC_HIP(hipEventElapsedTime(&m0, c->ev[2], c->ev[3]));
-            RSOC_HIP(hipEventElapsedTime(&m1, c->ev[4], c->ev[5]));
+            if (sweep1) RSOC_HIP(hipEventElapsedTime(&m1, c->ev[4], c->ev[5]));
             st->ms_round0 = m0;
             st->ms_round1 = m1;
         }
         int64_t b0, b1, tot;
         const int64_t l1 = h->head.rounds > 0 ? L1 : 0;
-        alg_bytes(o.mode, n, nnz, nW, nB, l1, h->head.conflicts, h->head.inspected, h->head.deg_sum, b0, b1, tot);
+        alg_bytes(o.mode, o.full_sweep != 0, n, nnz, nW, nB, h->head.u0, l1, h->head.conflicts, h->head.inspected,
+                  h->head.deg_sum, b0, b1, tot);
         st->bytes_round0 = b0;
+        st->worklist0 = sweep1 ? n : h->head.u0;
         st->bytes_round1 = b1;
         st->alg_bytes = tot;
     }

@@ -20,6 +20,7 @@ struct SingleArgs {
     const int32_t *rp;   // row_ptr[n+1]
     const int32_t *ci;   // col_idx[nnz]
     int32_t *col;        // colours[n]
+    uint8_t *col8;       // byte shadow of the colours: min(colour, 255), 255 when uncoloured
     int32_t *pend;       // staged colours (round-synchronous modes), indexed by vertex
     int32_t *wl[2];      // worklist buffers; bin segments start at 0, offW, offB
     int32_t *hubW;       // static list of wavefront-bin vertices
@@ -29,6 +30,7 @@ struct SingleArgs {
     int32_t t_wave;
     int32_t max_rounds;  // bound on inspection passes
     int32_t offW, offB;  // segment offsets inside wl buffers
+    int32_t look;        // round-0 lookahead (ids within `look` of v are read even when v wins against them)
 };
 
 // Device-side round state.
@@ -45,14 +47,19 @@ struct SingleState {
     int64_t conflicts;    // sum of |L|
     uint64_t inspected;   // vertices inspected by worklist rounds
     uint64_t deg_sum;     // their degree sum
-    int32_t pad[2];
+    int32_t u0;           // |U^0| when round 0 collects it (optimistic, default flow)
+    int32_t pad;
     int32_t hist[kHistCap];  // |L| of recolouring round i+1
 };
 
+__device__ __forceinline__ uint8_t shadow_of(int c) { return (uint8_t)((unsigned)c < 255u ? c : 255); }
+
 // ------------------------------------------------------------------ fill --
-__global__ void k_fill(int32_t *p, int64_t n, int32_t value) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+__global__ void k_fill(int32_t *p, uint8_t *p8, int64_t n, int32_t value) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         p[i] = value;
+        if (p8) p8[i] = shadow_of(value);
+    }
 }
 
 // ------------------------------------------------------------- validate --
@@ -70,26 +77,71 @@ __global__ void k_validate(const int32_t *__restrict__ rp, const int32_t *__rest
             else if (u == (int)v) flags |= 2;
         }
     }
-    if (flags) atomicOr(err, flags);
+    if (ballot(flags != 0)) {
+        // one atomic per wavefront with a finding
+        int f = flags;
+        for (int off = 32; off > 0; off >>= 1) f |= __shfl_xor(f, off);
+        if (lane_id() == 0) atomicOr(err, f);
+    }
+}
+
+// Workgroup max of an int; the result is valid in thread 0.
+__device__ __forceinline__ int block_max(int x, int *sh) {
+    x = wave_max_i32(x);
+    if (lane_id() == 0) sh[threadIdx.x / kWave] = x;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int w = 1; w < kWavesPerBlock; ++w) x = max(x, sh[w]);
+    return x;
 }
 
 // ------------------------------------------------------------------ bin --
 // Splits V by degree: deg <= t_thread stays implicit (thread bin); larger rows
 // go to the static wavefront / workgroup lists.  Also finds the max degree.
 __global__ __launch_bounds__(kBlock) void k_bin(const SingleArgs *__restrict__ A, SingleState *S) {
+    __shared__ int sh[kWavesPerBlock];
     const SingleArgs a = *A;
+    const RSOC_GLOBAL int32_t *rp = gro(a.rp);
     int md = 0;
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     for (int64_t base = (int64_t)blockIdx.x * kBlock; base < a.n; base += stride) {
         const int v = (int)(base + threadIdx.x);
         int d = -1;
-        if (v < a.n) d = a.rp[v + 1] - a.rp[v];
+        if (v < a.n) d = rp[v + 1] - rp[v];
         md = max(md, d);
         wave_append(d > a.t_wave, v, &S->nB, a.hubB);
         wave_append(d > a.t_thread && d <= a.t_wave, v, &S->nW, a.hubW);
     }
-    md = wave_max_i32(md);
-    if (lane_id() == 0) atomicMax(&S->maxdeg, md);
+    md = block_max(md, sh);
+    // most workgroups find nothing larger than what is already published
+    if (threadIdx.x == 0 && md > __hip_atomic_load(&S->maxdeg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+        atomicMax(&S->maxdeg, md);
+}
+
+// Appends v for every lane with `take` into the workgroup's LDS queue.  Called
+// by every thread of the workgroup in lockstep (the loop is workgroup-uniform).
+__device__ __forceinline__ void queue_push(bool take, int v, int *q, int *qn) {
+    const uint64_t m = ballot(take);
+    if (m == 0) return;
+    const int leader = __ffsll((unsigned long long)m) - 1;
+    int base = 0;
+    if (lane_id() == leader) base = atomicAdd(qn, __popcll(m));
+    base = __shfl(base, leader);
+    if (take) q[base + lanes_below(m)] = v;
+}
+
+// Moves the queue to the global list (one global atomic per flush).
+__device__ __forceinline__ void queue_flush(int *q, int *qn, int *qbase, int *counter, int32_t *out) {
+    __syncthreads();
+    const int cnt = *qn;
+    if (cnt == 0) return;
+    if (threadIdx.x == 0) *qbase = atomicAdd(counter, cnt);
+    __syncthreads();
+    const int base = *qbase;
+    for (int i = threadIdx.x; i < cnt; i += kBlock) out[base + i] = q[i];
+    __syncthreads();
+    if (threadIdx.x == 0) *qn = 0;
+    __syncthreads();
 }
 
 // ---------------------------------------------------------------- round --
@@ -99,25 +151,38 @@ __global__ __launch_bounds__(kBlock) void k_bin(const SingleArgs *__restrict__ A
 // SWEEP: the round covers all of V (rounds 0 and 1): the thread bin walks
 //        vertex ids directly, the other bins read the static lists; otherwise
 //        the round reads worklist buffer `parity` and appends to parity^1.
-// Sections: blocks [0,gB) workgroup bin, [gB,gB+gW) wavefront bin, rest thread bin.
-template <int PHASE, int MODE, int TIE, bool SWEEP>
+// Sections: blocks [0,gB) workgroup bin, [gB,gB+gW) wavefront bin, rest
+// thread bin (kGroup lanes per vertex).
+// ROUND0 (kAssign only): 0 = First-Fit over all neighbours, no appends;
+// 1 = First-Fit over the neighbours v loses to, sweeping in the order that
+// visits them first, and v is appended to the next worklist iff one of them
+// was still uncoloured when read (only such v can end round 0 defective).
+template <int PHASE, int MODE, int TIE, bool SWEEP, int ROUND0 = 0>
 __global__ __launch_bounds__(kBlock) void k_round(const SingleArgs *__restrict__ A, SingleState *S, int parity,
                                                   int gB, int gW, int gT) {
     __shared__ uint32_t lds[kLdsWords];
-    __shared__ int sh_min;
+    __shared__ int q[kQueueCap];
+    __shared__ int sh_min, qn, qbase;
     __shared__ unsigned long long sh_acc[2];
     const SingleArgs a = *A;
     if (!SWEEP && S->passes >= a.max_rounds) return;  // guard: the round may not run
     const int cT = SWEEP ? a.n : S->cnt_in[kBinThread];
     const int cW = SWEEP ? S->nW : S->cnt_in[kBinWave];
     const int cB = SWEEP ? S->nB : S->cnt_in[kBinBlock];
-    const int32_t *inT = a.wl[parity];
-    const int32_t *inW = SWEEP ? a.hubW : a.wl[parity] + a.offW;
-    const int32_t *inB = SWEEP ? a.hubB : a.wl[parity] + a.offB;
-    int32_t *out = a.wl[parity ^ 1];
-    int32_t *wcol = (MODE == kOptimistic) ? a.col : a.pend;
-    const int32_t *rcol = a.col;
-    constexpr bool kAppend = PHASE != kAssign;
+    int32_t *const in = parity ? a.wl[1] : a.wl[0];
+    int32_t *const out = parity ? a.wl[0] : a.wl[1];
+    const RSOC_GLOBAL int32_t *inT = gro(in);
+    const RSOC_GLOBAL int32_t *inW = gro(SWEEP ? a.hubW : in + a.offW);
+    const RSOC_GLOBAL int32_t *inB = gro(SWEEP ? a.hubB : in + a.offB);
+    const RSOC_GLOBAL int32_t *rp = gro(a.rp);
+    const RSOC_GLOBAL int32_t *ci = gro(a.ci);
+    const RSOC_GLOBAL int32_t *rcol = gro(a.col);
+    const RSOC_GLOBAL uint8_t *rcol8 = gro(a.col8);
+    RSOC_GLOBAL int32_t *wcol = grw((MODE == kOptimistic) ? a.col : a.pend);
+    RSOC_GLOBAL uint8_t *wcol8 = grw(a.col8);
+    constexpr bool kFlagAppend = PHASE == kAssign && ROUND0 == 1;
+    constexpr bool kWinOnly = kFlagAppend;
+    constexpr bool kAppend = PHASE != kAssign || kFlagAppend;
     constexpr bool kWrite = PHASE != kDetect;
     constexpr bool kAcct = PHASE != kAssign && !SWEEP;  // worklist rounds count their inspections
     uint64_t items = 0, degs = 0;
@@ -125,14 +190,19 @@ __global__ __launch_bounds__(kBlock) void k_round(const SingleArgs *__restrict__
     if (bid < gB) {
         for (int i = bid; i < cB; i += gB) {
             const int v = inB[i];
-            const int b = a.rp[v], e = a.rp[v + 1];
+            const int b = rp[v], e = rp[v + 1];
             int nc = 0;
-            const bool act = block_vertex<PHASE, TIE>(v, b, e, a.ci, rcol, lds, &sh_min, nc);
+            bool unc = false;
+            const bool act = block_vertex<PHASE, TIE, kWinOnly>(v, b, e, ci, rcol, lds, &sh_min, a.look, nc, unc);
             if (threadIdx.x == 0) {
                 items += 1;
                 degs += (uint64_t)(e - b);
-                if (act && kWrite) wcol[v] = nc;
-                if (act && kAppend) out[a.offB + atomicAdd(&S->cnt_out[kBinBlock], 1)] = v;
+                if (act && kWrite) {
+                    wcol[v] = nc;
+                    if (MODE == kOptimistic) wcol8[v] = shadow_of(nc);
+                }
+                const bool take = kFlagAppend ? unc : act;
+                if (take && kAppend) out[a.offB + atomicAdd(&S->cnt_out[kBinBlock], 1)] = v;
             }
         }
     } else if (bid < gB + gW) {
@@ -142,36 +212,78 @@ __global__ __launch_bounds__(kBlock) void k_round(const SingleArgs *__restrict__
         uint32_t *bm = lds + wv * kWaveWindowWords;
         for (int i = w; i < cW; i += nw) {
             const int v = inW[i];
-            const int b = a.rp[v], e = a.rp[v + 1];
+            const int b = rp[v], e = rp[v + 1];
             int nc = 0;
-            const bool act = wave_vertex<PHASE, TIE>(v, b, e, a.ci, rcol, bm, nc);
+            bool unc = false;
+            const bool act = wave_vertex<PHASE, TIE, kWinOnly>(v, b, e, ci, rcol, bm, a.look, nc, unc);
             if (lane_id() == 0) {
                 items += 1;
                 degs += (uint64_t)(e - b);
-                if (act && kWrite) wcol[v] = nc;
-                if (act && kAppend) out[a.offW + atomicAdd(&S->cnt_out[kBinWave], 1)] = v;
+                if (act && kWrite) {
+                    wcol[v] = nc;
+                    if (MODE == kOptimistic) wcol8[v] = shadow_of(nc);
+                }
+                const bool take = kFlagAppend ? unc : act;
+                if (take && kAppend) out[a.offW + atomicAdd(&S->cnt_out[kBinWave], 1)] = v;
             }
         }
     } else {
         int tb = bid - gB - gW;
-        if (SWEEP) tb = xcd_contiguous(tb, gT);
-        const int64_t stride = (int64_t)gT * kBlock;
-        for (int64_t base = (int64_t)tb * kBlock; base < cT; base += stride) {
-            const int i = (int)(base + threadIdx.x);
-            bool act = false;
-            int v = 0, nc = 0;
-            if (i < cT) {
-                v = SWEEP ? i : inT[i];
-                const int b = a.rp[v], e = a.rp[v + 1];
-                if (!SWEEP || e - b <= a.t_thread) {
-                    act = thread_vertex<PHASE, TIE>(v, b, e, a.ci, rcol, nc);
-                    items += 1;
-                    degs += (uint64_t)(e - b);
+        // worklist-free sweeps that need no particular order keep each XCD on
+        // one id range (neighbouring ids share its L2); round 0 sweeps in order
+        if (SWEEP && PHASE != kAssign) tb = xcd_contiguous(tb, gT);
+        constexpr int kNV = 2;                       // vertices per lane group per step
+        constexpr int kVpb = kNV * kBlock / kGroup;  // vertices per workgroup step
+        const int gi = threadIdx.x / kGroup;
+        const bool leader = (threadIdx.x & (kGroup - 1)) == 0;
+        if (kAppend) {
+            if (threadIdx.x == 0) qn = 0;
+            __syncthreads();
+        }
+        const int64_t stride = (int64_t)gT * kVpb;
+        for (int64_t base = (int64_t)tb * kVpb; base < cT; base += stride) {
+            int v[kNV], b[kNV], e[kNV], cv[kNV], nc[kNV];
+            bool act[kNV], unc[kNV] = {};
+#pragma unroll
+            for (int i = 0; i < kNV; ++i) {
+                const int64_t idx = base + gi + i * (kBlock / kGroup);
+                v[i] = -1;
+                b[i] = e[i] = 0;
+                if (idx < cT) {
+                    v[i] = SWEEP ? ((kFlagAppend && TIE == kHigherKeeps) ? (int)(cT - 1 - idx) : (int)idx) : inT[idx];
                 }
             }
-            if (act && kWrite) wcol[v] = nc;
-            if (kAppend) wave_append(act, v, &S->cnt_out[kBinThread], out);
+#pragma unroll
+            for (int i = 0; i < kNV; ++i) {
+                if (v[i] >= 0) {
+                    b[i] = rp[v[i]];
+                    e[i] = rp[v[i] + 1];
+                    if (SWEEP && e[i] - b[i] > a.t_thread) e[i] = b[i] = 0, v[i] = -1;  // another bin's vertex
+                }
+                cv[i] = (PHASE != kAssign && v[i] >= 0) ? (int)rcol8[v[i]] : 255;
+            }
+            group_vertices<PHASE, TIE, kGroup, kGroupSlots, kWinOnly, kNV>(v, b, e, ci, rcol8, cv, a.look, nc, act,
+                                                                           unc);
+#pragma unroll
+            for (int i = 0; i < kNV; ++i) {
+                if (v[i] < 0) act[i] = unc[i] = false;
+                if (leader && v[i] >= 0) {
+                    items += 1;
+                    degs += (uint64_t)(e[i] - b[i]);
+                    if (act[i] && kWrite) {
+                        wcol[v[i]] = nc[i];
+                        if (MODE == kOptimistic) wcol8[v[i]] = (uint8_t)nc[i];
+                    }
+                }
+            }
+            if (kAppend) {
+#pragma unroll
+                for (int i = 0; i < kNV; ++i) queue_push((kFlagAppend ? unc[i] : act[i]) && leader, v[i], q, &qn);
+                __syncthreads();
+                if (qn > kQueueCap - kVpb) queue_flush(q, &qn, &qbase, &S->cnt_out[kBinThread], out);
+            }
         }
+        if (kAppend) queue_flush(q, &qn, &qbase, &S->cnt_out[kBinThread], out);
     }
     if (kAcct) {
         if (threadIdx.x == 0) { sh_acc[0] = 0; sh_acc[1] = 0; }
@@ -199,19 +311,29 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const SingleArgs *__restrict
     const SingleArgs a = *A;
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     const int64_t t0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    RSOC_GLOBAL int32_t *col = grw(a.col);
+    RSOC_GLOBAL uint8_t *col8 = grw(a.col8);
+    const RSOC_GLOBAL int32_t *pend = gro(a.pend);
     if (SWEEP) {
-        for (int64_t v = t0; v < a.n; v += stride) a.col[v] = a.pend[v];
+        for (int64_t v = t0; v < a.n; v += stride) {
+            const int c = pend[v];
+            col[v] = c;
+            col8[v] = shadow_of(c);
+        }
         return;
     }
     if (S->passes >= a.max_rounds) return;
-    const int32_t *lst = a.wl[USE_IN ? parity : (parity ^ 1)];
+    const bool use_wl1 = USE_IN ? (parity != 0) : (parity == 0);
+    const RSOC_GLOBAL int32_t *lst = gro(use_wl1 ? a.wl[1] : a.wl[0]);
     const int32_t *cnt = USE_IN ? S->cnt_in : S->cnt_out;
-    const int off[3] = {0, a.offW, a.offB};
     for (int bin = 0; bin < 3; ++bin) {
         const int c = cnt[bin];
+        const int off = bin == 0 ? 0 : (bin == 1 ? a.offW : a.offB);
         for (int64_t i = t0; i < c; i += stride) {
-            const int v = lst[off[bin] + i];
-            a.col[v] = a.pend[v];
+            const int v = lst[off + i];
+            const int cc = pend[v];
+            col[v] = cc;
+            col8[v] = shadow_of(cc);
         }
     }
 }
@@ -219,9 +341,18 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const SingleArgs *__restrict
 // ------------------------------------------------------------ round end --
 // Runs after a round (single thread): counts the pass, records |L|, makes the
 // appended list the next worklist and clears the append counters.
-template <int MODE, bool SWEEP>
+// PUBLISH_ONLY: after round 0 (no pass to count): only publish the appended list.
+template <int MODE, bool SWEEP, bool PUBLISH_ONLY = false>
 __global__ void k_round_end(const SingleArgs *__restrict__ A, SingleState *S) {
     if (threadIdx.x != 0) return;
+    if (PUBLISH_ONLY) {
+        S->u0 = S->cnt_out[0] + S->cnt_out[1] + S->cnt_out[2];
+        for (int b = 0; b < 3; ++b) {
+            S->cnt_in[b] = S->cnt_out[b];
+            S->cnt_out[b] = 0;
+        }
+        return;
+    }
     if (!SWEEP && S->passes >= A->max_rounds) return;  // the guarded round did nothing
     const int in_total = SWEEP ? A->n : (S->cnt_in[0] + S->cnt_in[1] + S->cnt_in[2]);
     const int out_total = S->cnt_out[0] + S->cnt_out[1] + S->cnt_out[2];
@@ -246,19 +377,22 @@ __global__ void k_round_end(const SingleArgs *__restrict__ A, SingleState *S) {
 // --------------------------------------------------------- colour stats --
 // K = max colour + 1; marks used colours (flags[0..maxdeg]) for the distinct
 // count; flags an error if any colour is outside [0, maxdeg].
-__global__ __launch_bounds__(kBlock) void k_colour_stats(const int32_t *__restrict__ col, int64_t n, int32_t maxdeg,
+__global__ __launch_bounds__(kBlock) void k_colour_stats(const int32_t *__restrict__ colp, int64_t n, int32_t maxdeg,
                                                          int32_t *flags, int32_t *kmax, int32_t *err) {
+    __shared__ int sh[kWavesPerBlock];
+    const RSOC_GLOBAL int32_t *col = gro(colp);
     int m = -1;
     bool bad = false;
     for (int64_t v = blockIdx.x * (int64_t)kBlock + threadIdx.x; v < n; v += (int64_t)gridDim.x * kBlock) {
         const int c = col[v];
         if (c < 0 || c > maxdeg) { bad = true; continue; }
         m = max(m, c);
-        flags[c] = 1;
+        if (flags[c] == 0) flags[c] = 1;  // racy but idempotent; the read keeps most writes away
     }
-    m = wave_max_i32(m);
-    if (lane_id() == 0) atomicMax(kmax, m + 1);
     if (ballot(bad) && lane_id() == 0) atomicOr(err, 4);
+    m = block_max(m, sh);
+    if (threadIdx.x == 0 && m + 1 > __hip_atomic_load(kmax, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+        atomicMax(kmax, m + 1);
 }
 
 __global__ __launch_bounds__(kBlock) void k_count_flags(const int32_t *__restrict__ flags, int64_t len, int32_t *out) {

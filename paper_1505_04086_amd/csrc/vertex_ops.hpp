@@ -1,9 +1,10 @@
 // vertex_ops.hpp -- the per-vertex work of a colouring round, in three shapes
-// chosen by degree: one thread, one wavefront, or one workgroup per vertex.
+// chosen by degree: a group of kGroup lanes, one wavefront, or one workgroup
+// per vertex.
 //
 // Every shape computes, for vertex v with row [b, e) of col_idx:
-//   * detection (Algorithm 3's test, Section 3): does a neighbour u != v that
-//     v loses to (by the tie rule) hold v's colour?
+//   * detection (the test of Algorithm 3, Section 3): does a neighbour u != v
+//     that v loses to (by the tie rule) hold v's colour?
 //   * First-Fit (Algorithm 1, Section 2.1): the smallest colour absent among
 //     all neighbours u != v.  Colours < 0 (uncoloured) are ignored.  Since v
 //     has at most e-b neighbours, the answer is at most e-b, so a window of
@@ -18,46 +19,115 @@
 
 namespace rsoc {
 
-// ---------------------------------------------------------------- thread --
-// Rows of at most 63 neighbours: the forbidden set of colours 0..63 is one
-// 64-bit register mask and the answer is its lowest clear bit.
-template <int PHASE, int TIE>
-__device__ __forceinline__ bool thread_vertex(int v, int b, int e, const int32_t *__restrict__ ci,
-                                              const int32_t *col, int &newc) {
-    const int cv = (PHASE == kAssign) ? -1 : col[v];
-    uint64_t mask = 0;
-    bool conflict = false;
-    for (int j = b; j < e; ++j) {
-        const int u = __builtin_nontemporal_load(ci + j);
-        if (u == v) continue;
-        const int cu = col[u];
-        if (PHASE != kAssign) conflict |= (cu == cv) && loses<TIE>(v, u);
-        if (PHASE != kDetect) mask |= ((unsigned)cu < 64u) ? (1ull << cu) : 0ull;
+// ------------------------------------------------------------ lane group --
+// Rows of at most kThreadBinMax entries.  The G lanes of a group first load
+// the whole row (S entries per lane, all loads issued before any is used),
+// then gather neighbour colours from the byte-wide colour shadow col8
+// (min(colour, 255); 255 also marks "uncoloured").  A thread-bin vertex has a
+// colour <= its degree < 64, so only shadow values < 64 can equal it or block
+// its First-Fit, and the byte shadow loses nothing.  In detect phases only
+// the neighbours v loses to are gathered first; the rest only when v turns out
+// defective.  The forbidden set is one 64-bit mask OR-reduced over the group.
+// Every lane of the group gets the same result.
+// NV vertices per group are handled together so that their loads overlap.
+// In kAssign, WIN_ONLY restricts First-Fit to the neighbours v loses to plus
+// the neighbours it wins against whose id lies within `look` of v's (those
+// the sweep may already have coloured); unc[i] reports whether a neighbour v
+// loses to was still uncoloured when read.
+template <int PHASE, int TIE, int G, int S, bool WIN_ONLY, int NV>
+__device__ __forceinline__ void group_vertices(const int (&v)[NV], const int (&b)[NV], const int (&e)[NV],
+                                               const RSOC_GLOBAL int32_t *ci, const RSOC_GLOBAL uint8_t *col8,
+                                               const int (&cv)[NV], int look, int (&newc)[NV], bool (&act)[NV],
+                                               bool (&unc)[NV]) {
+    const int k = lane_id() & (G - 1);
+    int u[NV][S];
+    int cu[NV][S];
+#pragma unroll
+    for (int i = 0; i < NV; ++i)
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const int j = b[i] + k + s * G;
+            u[i][s] = (j < e[i]) ? __builtin_nontemporal_load(ci + j) : v[i];
+        }
+    if (PHASE != kAssign) {
+        bool def[NV];
+#pragma unroll
+        for (int i = 0; i < NV; ++i)
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                const bool w = (u[i][s] != v[i]) && loses<TIE>(v[i], u[i][s]);
+                cu[i][s] = w ? (int)col8[u[i][s]] : 255;
+            }
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            bool c = false;
+#pragma unroll
+            for (int s = 0; s < S; ++s) c |= (cu[i][s] == cv[i]);
+            def[i] = group_any<G>(c);
+            act[i] = def[i];
+        }
+        if (PHASE == kDetect) return;
+#pragma unroll
+        for (int i = 0; i < NV; ++i)
+#pragma unroll
+            for (int s = 0; s < S; ++s)
+                if (def[i] && u[i][s] != v[i] && !loses<TIE>(v[i], u[i][s])) cu[i][s] = col8[u[i][s]];
+    } else {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            bool un = false;
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                const bool win = (u[i][s] != v[i]) && loses<TIE>(v[i], u[i][s]);
+                const int dist = u[i][s] > v[i] ? u[i][s] - v[i] : v[i] - u[i][s];
+                const bool take = WIN_ONLY ? (win || (u[i][s] != v[i] && dist < look)) : (u[i][s] != v[i]);
+                cu[i][s] = take ? (int)col8[u[i][s]] : 255;
+                un |= win && cu[i][s] == 255;
+            }
+            unc[i] = group_any<G>(un);
+            act[i] = true;
+        }
     }
-    newc = (int)__builtin_ctzll(~mask);
-    return PHASE == kAssign ? true : conflict;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        uint64_t mask = 0;
+#pragma unroll
+        for (int s = 0; s < S; ++s) mask |= (cu[i][s] < 64) ? (1ull << cu[i][s]) : 0ull;
+        mask = group_or64<G>(mask);
+        newc[i] = (int)__builtin_ctzll(~mask);
+    }
 }
 
 // -------------------------------------------------------------- wavefront --
-// One wavefront per vertex: lanes stride the row (coalesced), the conflict
-// flag is a ballot, and the forbidden colours go into a per-wavefront LDS
-// bitmap window of kWaveWindowBits bits, scanned for its first clear bit with
-// ballots.  Returns the same value in every lane; newc valid in every lane.
-template <int PHASE, int TIE>
-__device__ __forceinline__ bool wave_vertex(int v, int b, int e, const int32_t *__restrict__ ci, const int32_t *col,
-                                            uint32_t *bm, int &newc) {
+// One wavefront per vertex: lanes stride the row (coalesced, four chunks of 64
+// entries in flight per ballot), the conflict flag is a ballot, and the
+// forbidden colours go into a per-wavefront LDS bitmap window of
+// kWaveWindowBits bits, scanned for its first clear bit with ballots.
+// Returns the same value in every lane; newc valid in every lane.
+template <int PHASE, int TIE, bool WIN_ONLY>
+__device__ __forceinline__ bool wave_vertex(int v, int b, int e, const RSOC_GLOBAL int32_t *ci,
+                                            const RSOC_GLOBAL int32_t *col, uint32_t *bm, int look, int &newc,
+                                            bool &unc_win) {
     const int lane = lane_id();
+    constexpr int U = 4;
+    bool unc = false;
     if (PHASE != kAssign) {
         const int cv = col[v];
         bool any = false;
-        for (int j0 = b; j0 < e; j0 += kWave) {
-            const int j = j0 + lane;
-            bool c = false;
-            if (j < e) {
-                const int u = ci[j];
-                c = (u != v) && loses<TIE>(v, u) && (col[u] == cv);
+        for (int j0 = b; j0 < e && !any; j0 += U * kWave) {
+            int u[U];
+#pragma unroll
+            for (int s = 0; s < U; ++s) {
+                const int j = j0 + s * kWave + lane;
+                u[s] = (j < e) ? ci[j] : v;
             }
-            if (ballot(c)) { any = true; break; }
+            bool c = false;
+#pragma unroll
+            for (int s = 0; s < U; ++s) {
+                const bool w = (u[s] != v) && loses<TIE>(v, u[s]);
+                c |= w && (col[u[s]] == cv);
+            }
+            any = ballot(c) != 0;
         }
         if (!any) return false;
         if (PHASE == kDetect) return true;
@@ -65,12 +135,29 @@ __device__ __forceinline__ bool wave_vertex(int v, int b, int e, const int32_t *
     for (int base = 0;; base += kWaveWindowBits) {
         for (int w = lane; w < kWaveWindowWords; w += kWave) bm[w] = 0u;
         wave_lds_sync();
-        for (int j = b + lane; j < e; j += kWave) {
-            const int u = ci[j];
-            if (u == v) continue;
-            const int rel = col[u] - base;
-            if ((unsigned)rel < (unsigned)kWaveWindowBits) lds_or(&bm[rel >> 5], 1u << (rel & 31));
+        for (int j0 = b; j0 < e; j0 += U * kWave) {
+            int u[U];
+#pragma unroll
+            for (int s = 0; s < U; ++s) {
+                const int j = j0 + s * kWave + lane;
+                u[s] = (j < e) ? ci[j] : v;
+            }
+            int c[U];
+#pragma unroll
+            for (int s = 0; s < U; ++s) {
+                const bool win = (u[s] != v) && loses<TIE>(v, u[s]);
+                const int dist = u[s] > v ? u[s] - v : v - u[s];
+                const bool take = (PHASE == kAssign && WIN_ONLY) ? (win || (u[s] != v && dist < look)) : (u[s] != v);
+                c[s] = take ? col[u[s]] : -1;
+                if (PHASE == kAssign) unc |= win && c[s] < 0;
+            }
+#pragma unroll
+            for (int s = 0; s < U; ++s) {
+                const int rel = c[s] - base;
+                if (c[s] >= 0 && (unsigned)rel < (unsigned)kWaveWindowBits) lds_or(&bm[rel >> 5], 1u << (rel & 31));
+            }
         }
+        if (PHASE == kAssign) unc_win = ballot(unc) != 0;
         wave_lds_sync();
         for (int w0 = 0; w0 < kWaveWindowWords; w0 += kWave) {
             const uint32_t word = bm[w0 + lane];
@@ -92,19 +179,28 @@ __device__ __forceinline__ bool wave_vertex(int v, int b, int e, const int32_t *
 // is a workgroup OR, forbidden colours go into an LDS bitmap window of
 // kBlockWindowBits bits; the first clear word is found with an LDS atomicMin.
 // Must be called by the whole workgroup; newc valid in every thread.
-template <int PHASE, int TIE>
-__device__ __forceinline__ bool block_vertex(int v, int b, int e, const int32_t *__restrict__ ci, const int32_t *col,
-                                             uint32_t *bm, int *sh_min, int &newc) {
+template <int PHASE, int TIE, bool WIN_ONLY>
+__device__ __forceinline__ bool block_vertex(int v, int b, int e, const RSOC_GLOBAL int32_t *ci,
+                                             const RSOC_GLOBAL int32_t *col, uint32_t *bm, int *sh_min, int look,
+                                             int &newc, bool &unc_win) {
     const int t = threadIdx.x;
+    constexpr int U = 4;
+    bool unc = false;
     if (PHASE != kAssign) {
         const int cv = col[v];
         int any = 0;
-        for (int j0 = b; j0 < e; j0 += kBlock * 8) {
+        for (int j0 = b; j0 < e; j0 += kBlock * U * 4) {
             bool c = false;
-            const int j1 = min(e, j0 + kBlock * 8);
-            for (int j = j0 + t; j < j1; j += kBlock) {
-                const int u = ci[j];
-                c |= (u != v) && loses<TIE>(v, u) && (col[u] == cv);
+            const int j1 = min(e, j0 + kBlock * U * 4);
+            for (int jj = j0; jj < j1; jj += kBlock * U) {
+                int u[U];
+#pragma unroll
+                for (int s = 0; s < U; ++s) {
+                    const int j = jj + s * kBlock + t;
+                    u[s] = (j < j1) ? ci[j] : v;
+                }
+#pragma unroll
+                for (int s = 0; s < U; ++s) c |= (u[s] != v) && loses<TIE>(v, u[s]) && (col[u[s]] == cv);
             }
             any = __syncthreads_or(c);
             if (any) break;
@@ -116,12 +212,29 @@ __device__ __forceinline__ bool block_vertex(int v, int b, int e, const int32_t 
         for (int w = t; w < kBlockWindowWords; w += kBlock) bm[w] = 0u;
         if (t == 0) *sh_min = INT_MAX;
         __syncthreads();
-        for (int j = b + t; j < e; j += kBlock) {
-            const int u = ci[j];
-            if (u == v) continue;
-            const int rel = col[u] - base;
-            if ((unsigned)rel < (unsigned)kBlockWindowBits) lds_or(&bm[rel >> 5], 1u << (rel & 31));
+        for (int j0 = b; j0 < e; j0 += kBlock * U) {
+            int u[U];
+#pragma unroll
+            for (int s = 0; s < U; ++s) {
+                const int j = j0 + s * kBlock + t;
+                u[s] = (j < e) ? ci[j] : v;
+            }
+            int c[U];
+#pragma unroll
+            for (int s = 0; s < U; ++s) {
+                const bool win = (u[s] != v) && loses<TIE>(v, u[s]);
+                const int dist = u[s] > v ? u[s] - v : v - u[s];
+                const bool take = (PHASE == kAssign && WIN_ONLY) ? (win || (u[s] != v && dist < look)) : (u[s] != v);
+                c[s] = take ? col[u[s]] : -1;
+                if (PHASE == kAssign) unc |= win && c[s] < 0;
+            }
+#pragma unroll
+            for (int s = 0; s < U; ++s) {
+                const int rel = c[s] - base;
+                if (c[s] >= 0 && (unsigned)rel < (unsigned)kBlockWindowBits) lds_or(&bm[rel >> 5], 1u << (rel & 31));
+            }
         }
+        if (PHASE == kAssign) unc_win = __syncthreads_or(unc) != 0;
         __syncthreads();
         for (int w = t; w < kBlockWindowWords; w += kBlock)
             if (bm[w] != 0xffffffffu) { atomicMin(sh_min, w); break; }

@@ -86,13 +86,14 @@ def test_two_phase_matches_oracle(lib, ctx, name, tie, split):
     assert list(st["L_sizes"]) == list(want["L_sizes"])
 
 
+@pytest.mark.parametrize("full_sweep", [0, 1])
 @pytest.mark.parametrize("split", sorted(BIN_SPLITS))
 @pytest.mark.parametrize("tie", ["lower", "higher"])
 @pytest.mark.parametrize("name", sorted(CASES))
-def test_optimistic_valid(lib, ctx, name, tie, split):
+def test_optimistic_valid(lib, ctx, name, tie, split, full_sweep):
     rp, ci = CASES[name]
     d_rp, d_ci, d_col, n = _dev(lib, rp, ci)
-    o = lib.make_options("optimistic", tie, **BIN_SPLITS[split])
+    o = lib.make_options("optimistic", tie, full_sweep=full_sweep, **BIN_SPLITS[split])
     k, st = lib.rsoc_color_device(ctx, d_rp, d_ci, n, d_col, o)
     got = d_col.cpu().numpy()[:n]
     assert oracle.check(rp, ci, got) == 0
