@@ -1,11 +1,281 @@
-// batch.hpp -- batched colouring of many graphs (placeholder until the fused path lands).
+// batch.hpp -- host driver of rsoc_color_batch: G independent graphs coloured
+// by one sequence of fused launches (round 0, then captured worklist rounds),
+// with the same round structure as the single-graph driver.
 #pragma once
+
+#include <vector>
+
+#include "batch_kernels.hpp"
 #include "single.hpp"
+
+namespace rsoc {
+
+template <int MODE, int TIE>
+inline void launch_blist_round(rsoc_ctx *c, hipStream_t s, int parity, int gB, int gW, int gT) {
+    const BatchArgs *A = c->b_args.as<BatchArgs>();
+    SingleState *S = c->b_state.as<SingleState>();
+    const int grid = gB + gW + gT;
+    if (MODE == kTwoPhase) {
+        k_bround<kAssign, kTwoPhase, TIE, false><<<grid, kBlock, 0, s>>>(A, S, parity, gB, gW, gT);
+        k_bscatter<false, true><<<gT, kBlock, 0, s>>>(A, S, parity);
+        k_bround<kDetect, kTwoPhase, TIE, false><<<grid, kBlock, 0, s>>>(A, S, parity, gB, gW, gT);
+    } else {
+        k_bround<kRecolor, MODE, TIE, false><<<grid, kBlock, 0, s>>>(A, S, parity, gB, gW, gT);
+        if (MODE == kDeterministic) k_bscatter<false, false><<<gT, kBlock, 0, s>>>(A, S, parity);
+    }
+    k_bround_end<MODE, false><<<1, 64, 0, s>>>(A, S);
+}
+
+inline void launch_blist_rounds_dyn(rsoc_ctx *c, hipStream_t s, int mode, int tie, int K, int gB, int gW, int gT) {
+    for (int r = 0; r < K; ++r) {
+        const int p = r & 1;
+        if (mode == kOptimistic)
+            tie ? launch_blist_round<kOptimistic, kHigherKeeps>(c, s, p, gB, gW, gT)
+                : launch_blist_round<kOptimistic, kLowerKeeps>(c, s, p, gB, gW, gT);
+        else if (mode == kDeterministic)
+            tie ? launch_blist_round<kDeterministic, kHigherKeeps>(c, s, p, gB, gW, gT)
+                : launch_blist_round<kDeterministic, kLowerKeeps>(c, s, p, gB, gW, gT);
+        else
+            tie ? launch_blist_round<kTwoPhase, kHigherKeeps>(c, s, p, gB, gW, gT)
+                : launch_blist_round<kTwoPhase, kLowerKeeps>(c, s, p, gB, gW, gT);
+    }
+}
+
+inline int32_t get_batch_graph(rsoc_ctx *c, int mode, int tie, int K, int gB, int gW, int gT, hipGraphExec_t *out) {
+    auto key = std::make_tuple(100 + mode, tie, K, gB, gW, gT);
+    auto it = c->graphs.find(key);
+    if (it != c->graphs.end()) { *out = it->second; return RSOC_OK; }
+    hipGraph_t g = nullptr;
+    RSOC_HIP(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+    launch_blist_rounds_dyn(c, c->cap, mode, tie, K, gB, gW, gT);
+    hipError_t le = hipGetLastError();
+    hipError_t ee = hipStreamEndCapture(c->cap, &g);
+    if (le != hipSuccess) { if (g) (void)hipGraphDestroy(g); return hip_fail(le, "capture launch", __FILE__, __LINE__); }
+    if (ee != hipSuccess) return hip_fail(ee, "hipStreamEndCapture", __FILE__, __LINE__);
+    hipGraphExec_t ex = nullptr;
+    hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ie != hipSuccess) return hip_fail(ie, "hipGraphInstantiate", __FILE__, __LINE__);
+    c->graphs[key] = ex;
+    *out = ex;
+    return RSOC_OK;
+}
+
+template <int MODE, int TIE>
+inline void launch_bsweep(rsoc_ctx *c, hipStream_t s, int64_t nV, int gB, int gW, int gT, bool full_sweep) {
+    const BatchArgs *A = c->b_args.as<BatchArgs>();
+    SingleState *S = c->b_state.as<SingleState>();
+    const int grid = gB + gW + gT;
+    const int fill_grid = (int)std::min<int64_t>(div_up(nV, kBlock), 8192);
+    int32_t *col = c->b_colp;
+    uint8_t *col8 = c->b_col8.as<uint8_t>();
+    if (MODE == kDeterministic) {
+        k_fill<<<fill_grid, kBlock, 0, s>>>(col, col8, nV, 0);
+    } else {
+        k_fill<<<fill_grid, kBlock, 0, s>>>(col, col8, nV, -1);
+        if (MODE == kOptimistic) {
+            if (!full_sweep) {
+                k_bround<kAssign, kOptimistic, TIE, true, 1><<<grid, kBlock, 0, s>>>(A, S, 1, gB, gW, gT);
+                k_bround_end<MODE, true, true><<<1, 64, 0, s>>>(A, S);
+                return;
+            }
+            k_bround<kAssign, kOptimistic, TIE, true, 0><<<grid, kBlock, 0, s>>>(A, S, 1, gB, gW, gT);
+        }
+    }
+    if (MODE == kTwoPhase) {
+        k_bround<kAssign, kTwoPhase, TIE, true><<<grid, kBlock, 0, s>>>(A, S, 1, gB, gW, gT);
+        k_bscatter<true, false><<<fill_grid, kBlock, 0, s>>>(A, S, 1);
+        k_bround<kDetect, kTwoPhase, TIE, true><<<grid, kBlock, 0, s>>>(A, S, 1, gB, gW, gT);
+    } else {
+        k_bround<kRecolor, MODE, TIE, true><<<grid, kBlock, 0, s>>>(A, S, 1, gB, gW, gT);
+        if (MODE == kDeterministic) k_bscatter<false, false><<<std::max(1, gT), kBlock, 0, s>>>(A, S, 1);
+    }
+    k_bround_end<MODE, true><<<1, 64, 0, s>>>(A, S);
+}
+
+inline void launch_bsweep_dyn(rsoc_ctx *c, hipStream_t s, int mode, int tie, int64_t nV, int gB, int gW, int gT,
+                              bool full) {
+    if (mode == kOptimistic)
+        tie ? launch_bsweep<kOptimistic, kHigherKeeps>(c, s, nV, gB, gW, gT, full)
+            : launch_bsweep<kOptimistic, kLowerKeeps>(c, s, nV, gB, gW, gT, full);
+    else if (mode == kDeterministic)
+        tie ? launch_bsweep<kDeterministic, kHigherKeeps>(c, s, nV, gB, gW, gT, full)
+            : launch_bsweep<kDeterministic, kLowerKeeps>(c, s, nV, gB, gW, gT, full);
+    else
+        tie ? launch_bsweep<kTwoPhase, kHigherKeeps>(c, s, nV, gB, gW, gT, full)
+            : launch_bsweep<kTwoPhase, kLowerKeeps>(c, s, nV, gB, gW, gT, full);
+}
+
+struct BatchHost {
+    BatchArgs args;
+    SingleState head;
+};
+static_assert(sizeof(BatchArgs) <= 1024, "b_args holds one BatchArgs");
+static_assert(sizeof(BatchHost) <= sizeof(HostStaging) + 4096, "pinned staging holds one BatchHost");
+
+inline int32_t run_batch(rsoc_ctx *c, int32_t G, const int64_t *vtx_off, const int64_t *nnz_off, const int32_t *rp,
+                         const int32_t *ci, int32_t *col, int32_t *counts_out, const Options &o, rsoc_stats *st,
+                         hipStream_t s) {
+    if (st) {
+        int32_t *keep = st->per_round_L;
+        int32_t cap = st->per_round_cap;
+        memset(st, 0, sizeof(*st));
+        st->per_round_L = keep;
+        st->per_round_cap = cap;
+    }
+    if (vtx_off[0] != 0 || nnz_off[0] != 0) return RSOC_ECSR;
+    for (int g = 0; g < G; ++g) {
+        if (vtx_off[g + 1] < vtx_off[g] || nnz_off[g + 1] < nnz_off[g]) return RSOC_ECSR;
+        if (vtx_off[g + 1] - vtx_off[g] > INT32_MAX - 1 || nnz_off[g + 1] - nnz_off[g] > INT32_MAX) return RSOC_EINVAL;
+    }
+    const int64_t nV = vtx_off[G];
+    if (nV >= INT32_MAX) return RSOC_EINVAL;
+    if (G == 0 || nV == 0) {
+        for (int g = 0; g < G; ++g)
+            if (counts_out) counts_out[g] = 0;
+        return 0;
+    }
+    // sweep tasks: (graph, first vertex) chunks of kTaskLen vertices, in graph order
+    std::vector<int64_t> tasks;
+    tasks.reserve((size_t)(nV / kTaskLen + G + 1));
+    for (int g = 0; g < G; ++g)
+        for (int64_t st0 = 0; st0 < vtx_off[g + 1] - vtx_off[g]; st0 += kTaskLen)
+            tasks.push_back(((int64_t)g << 32) | (uint32_t)st0);
+    if (tasks.size() > (size_t)INT32_MAX) return RSOC_EINVAL;
+    const int ntasks = (int)tasks.size();
+    RSOC_TRY(c->b_desc.reserve(sizeof(int64_t) * 2 * (size_t)(G + 1)));
+    RSOC_TRY(c->b_tasks.reserve(sizeof(int64_t) * (size_t)ntasks));
+    RSOC_TRY(c->b_col8.reserve((size_t)nV + 64));
+    if (o.mode != kOptimistic) RSOC_TRY(c->b_pend.reserve(sizeof(int32_t) * (size_t)nV));
+    RSOC_TRY(c->b_wl0.reserve(sizeof(int64_t) * (size_t)(nV + 1)));
+    RSOC_TRY(c->b_wl1.reserve(sizeof(int64_t) * (size_t)(nV + 1)));
+    RSOC_TRY(c->b_hub.reserve(sizeof(int64_t) * (size_t)(nV + 1)));
+    RSOC_TRY(c->b_kmax.reserve(sizeof(int32_t) * (size_t)G));
+    int64_t *d_voff = c->b_desc.as<int64_t>();
+    int64_t *d_noff = d_voff + (G + 1);
+    RSOC_HIP(hipMemcpyAsync(d_voff, vtx_off, sizeof(int64_t) * (size_t)(G + 1), hipMemcpyHostToDevice, s));
+    RSOC_HIP(hipMemcpyAsync(d_noff, nnz_off, sizeof(int64_t) * (size_t)(G + 1), hipMemcpyHostToDevice, s));
+    RSOC_HIP(hipMemcpyAsync(c->b_tasks.p, tasks.data(), sizeof(int64_t) * (size_t)ntasks, hipMemcpyHostToDevice, s));
+    c->b_colp = col;
+
+    BatchHost *h = c->host.as<BatchHost>();
+    BatchArgs &a = h->args;
+    a.voff = d_voff;
+    a.noff = d_noff;
+    a.rp = rp;
+    a.ci = ci;
+    a.col = col;
+    a.col8 = c->b_col8.as<uint8_t>();
+    a.pend = c->b_pend.as<int32_t>();
+    a.wl[0] = c->b_wl0.as<int64_t>();
+    a.wl[1] = c->b_wl1.as<int64_t>();
+    a.hub = c->b_hub.as<int64_t>();
+    a.tasks = c->b_tasks.as<int64_t>();
+    a.kg = c->b_kmax.as<int32_t>();
+    a.nV = nV;
+    a.hub_cap = nV + 1;
+    a.offW = a.offB = 0;
+    a.G = G;
+    a.ntasks = ntasks;
+    a.t_thread = o.t_thread;
+    a.t_wave = o.t_wave;
+    a.max_rounds = o.max_rounds;
+    a.look = 0;
+    SingleState *S = c->b_state.as<SingleState>();
+    RSOC_HIP(hipMemcpyAsync(c->b_args.p, &a, sizeof(a), hipMemcpyHostToDevice, s));
+    RSOC_HIP(hipMemsetAsync(S, 0, kStateHeader, s));
+    RSOC_HIP(hipMemsetAsync(c->b_kmax.p, 0, sizeof(int32_t) * (size_t)G, s));
+    const int tgrid = std::min(ntasks, 8192);
+    if (o.validate & RSOC_CHECK_CSR) {
+        k_bvalidate<<<tgrid, kBlock, 0, s>>>(c->b_args.as<BatchArgs>(), &S->err);
+        RSOC_LAUNCH_CHECK();
+    }
+    k_bbin<<<tgrid, kBlock, 0, s>>>(c->b_args.as<BatchArgs>(), S);
+    RSOC_LAUNCH_CHECK();
+    RSOC_HIP(hipMemcpyAsync(&h->head, S, kStateHeader, hipMemcpyDeviceToHost, s));
+    RSOC_HIP(hipStreamSynchronize(s));
+    RSOC_TRY(status_from_err(h->head.err));
+    const int nW = h->head.nW, nB = h->head.nB;
+    const int64_t nT = nV - nW - nB;
+    a.offW = nT;
+    a.offB = nT + nW;
+    constexpr int kVpb = 2 * kBlock / kGroup;
+    const int gB = std::min(nB, 1024);
+    const int gW = std::min(div_up(nW, kWavesPerBlock), o.grid_wave);
+    const int gTs = std::max(1, std::min(ntasks, o.grid_thread));
+    const int64_t look = o.lookahead == -1 ? 0 : (o.lookahead > 0 ? o.lookahead : 16ll * gTs * kVpb);
+    a.look = (int)std::min<int64_t>(look, INT32_MAX);
+    RSOC_HIP(hipMemcpyAsync(c->b_args.p, &a, sizeof(a), hipMemcpyHostToDevice, s));
+    const int gBl = std::min(nB, 256);
+    const int gWl = std::min(div_up(nW, kWavesPerBlock), o.grid_wave);
+    const int gTl = (int)std::max<int64_t>(1, std::min<int64_t>(div_up(nT, kVpb), o.grid_thread));
+    hipGraphExec_t gexec = nullptr;
+    RSOC_TRY(get_batch_graph(c, o.mode, o.tie, o.rounds_per_sync, gBl, gWl, gTl, &gexec));
+
+    RSOC_HIP(hipEventRecord(c->ev[0], s));
+    launch_bsweep_dyn(c, s, o.mode, o.tie, nV, gB, gW, gTs, o.full_sweep != 0);
+    RSOC_LAUNCH_CHECK();
+    int32_t status = RSOC_OK;
+    for (;;) {
+        RSOC_HIP(hipGraphLaunch(gexec, s));
+        RSOC_HIP(hipEventRecord(c->ev[1], s));
+        RSOC_HIP(hipMemcpyAsync(&h->head, S, kStateHeader, hipMemcpyDeviceToHost, s));
+        RSOC_HIP(hipStreamSynchronize(s));
+        const int left = h->head.cnt_in[0] + h->head.cnt_in[1] + h->head.cnt_in[2];
+        if (left == 0) break;
+        if (h->head.passes >= o.max_rounds) { status = RSOC_ENOCONV; break; }
+    }
+    k_bcount<<<tgrid, kBlock, 0, s>>>(c->b_args.as<BatchArgs>(), &S->err);
+    RSOC_LAUNCH_CHECK();
+    RSOC_HIP(hipMemcpyAsync(&h->head, S, kStateHeader, hipMemcpyDeviceToHost, s));
+    std::vector<int32_t> kg((size_t)G);
+    RSOC_HIP(hipMemcpyAsync(kg.data(), c->b_kmax.p, sizeof(int32_t) * (size_t)G, hipMemcpyDeviceToHost, s));
+    if (st && st->per_round_L && st->per_round_cap > 0) {
+        RSOC_HIP(hipStreamSynchronize(s));
+        const int cnt = std::min(std::min(h->head.rounds, st->per_round_cap), kHistCap);
+        if (cnt > 0)
+            RSOC_HIP(hipMemcpyAsync(st->per_round_L, S->hist, sizeof(int32_t) * cnt, hipMemcpyDeviceToHost, s));
+    }
+    RSOC_HIP(hipStreamSynchronize(s));
+    if (h->head.err & 4) return RSOC_EHIP;
+    int32_t kmax = 0;
+    for (int g = 0; g < G; ++g) {
+        if (counts_out) counts_out[g] = kg[g];
+        kmax = std::max(kmax, kg[g]);
+    }
+    if (st) {
+        st->rounds = h->head.rounds;
+        st->passes = h->head.passes;
+        st->colors = kmax;
+        st->colors_distinct = -1;
+        st->conflicts = h->head.conflicts;
+        st->inspected = (int64_t)h->head.inspected;
+        st->max_degree = h->head.maxdeg;
+        st->bin_counts[0] = (int32_t)nT;
+        st->bin_counts[1] = nW;
+        st->bin_counts[2] = nB;
+        st->worklist0 = h->head.u0;
+        float ms = 0;
+        RSOC_HIP(hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
+        st->ms = ms;
+    }
+    if (status < 0) return status;
+    return kmax;
+}
+
+}  // namespace rsoc
 
 extern "C" int32_t rsoc_color_batch(rsoc_ctx *ctx, int32_t G, const int64_t *vtx_off, const int64_t *nnz_off,
                                     const int32_t *d_row_ptr_cat, const int32_t *d_col_idx_cat, int32_t *d_colors_cat,
-                                    int32_t *counts_out, const rsoc_options *opts, rsoc_stats *stats, void *hip_stream) {
-    (void)ctx; (void)G; (void)vtx_off; (void)nnz_off; (void)d_row_ptr_cat; (void)d_col_idx_cat; (void)d_colors_cat;
-    (void)counts_out; (void)opts; (void)stats; (void)hip_stream;
-    return RSOC_EINVAL;
+                                    int32_t *counts_out, const rsoc_options *opts, rsoc_stats *stats,
+                                    void *hip_stream) {
+    using namespace rsoc;
+    if (!ctx || G < 0 || (G > 0 && (!vtx_off || !nnz_off))) return RSOC_EINVAL;
+    if (G > 0 && vtx_off[G] > 0 && (!d_row_ptr_cat || !d_colors_cat)) return RSOC_EINVAL;
+    if (G > 0 && nnz_off[G] > 0 && !d_col_idx_cat) return RSOC_EINVAL;
+    Options o;
+    RSOC_TRY(resolve_options(opts, G > 0 ? vtx_off[G] : 0, o));
+    RSOC_HIP(hipSetDevice(ctx->device));
+    return run_batch(ctx, G, vtx_off, nnz_off, d_row_ptr_cat, d_col_idx_cat, d_colors_cat, counts_out, o, stats,
+                     (hipStream_t)hip_stream);
 }

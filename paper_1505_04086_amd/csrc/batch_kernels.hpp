@@ -1,0 +1,418 @@
+// batch_kernels.hpp -- kernels of the batched path: many independent graphs
+// coloured by the same fused launches.
+//
+// The batch is a concatenation of G local-id CSR graphs with int64 offset
+// tables.  A round of Algorithm 3 (Section 3) over the whole batch is one
+// launch: round-0 and sweep rounds walk a task table of (graph, first vertex)
+// chunks; worklist rounds walk packed (graph << 32 | local id) entries.  Every
+// vertex only ever meets neighbours of its own graph and ties are decided on
+// local ids, so each graph is coloured exactly as a separate call colours it
+// (bit-identically in the round-synchronous modes).
+#pragma once
+
+#include "single_kernels.hpp"
+
+namespace rsoc {
+
+constexpr int kTaskLen = 512;  // vertices per sweep task
+
+struct BatchArgs {
+    const int64_t *voff;  // [G+1] vertex offsets of the graphs
+    const int64_t *noff;  // [G+1] adjacency offsets of the graphs
+    const int32_t *rp;    // concatenated local row_ptr arrays (graph g at voff[g] + g)
+    const int32_t *ci;    // concatenated local column ids (graph g at noff[g])
+    int32_t *col;         // concatenated colours (graph g at voff[g])
+    uint8_t *col8;        // byte shadow of col
+    int32_t *pend;        // staged colours (round-synchronous modes)
+    int64_t *wl[2];       // packed worklists; bin segments start at 0, offW, offB
+    int64_t *hub;         // static hub lists: wavefront bin from the front, workgroup bin from the back
+    const int64_t *tasks; // packed (graph << 32 | first local vertex) sweep tasks
+    int32_t *kg;          // [G] per-graph max colour + 1
+    int64_t nV;           // total vertices (< 2^31)
+    int64_t hub_cap;      // entries of hub
+    int64_t offW, offB;   // worklist segment offsets
+    int32_t G, ntasks;
+    int32_t t_thread, t_wave, max_rounds, look;
+};
+
+__device__ __forceinline__ int64_t pack_item(int g, int v) { return ((int64_t)g << 32) | (uint32_t)v; }
+__device__ __forceinline__ int item_graph(int64_t x) { return (int)(x >> 32); }
+__device__ __forceinline__ int item_vertex(int64_t x) { return (int)(uint32_t)x; }
+
+// Base pointers of one graph of the batch.
+struct GraphView {
+    const RSOC_GLOBAL int32_t *rp;
+    const RSOC_GLOBAL int32_t *ci;
+    const RSOC_GLOBAL int32_t *col;
+    const RSOC_GLOBAL uint8_t *col8;
+    int64_t voff;
+    int n;
+};
+
+__device__ __forceinline__ GraphView graph_view(const BatchArgs &a, int g) {
+    GraphView w;
+    const int64_t vo = a.voff[g];
+    w.voff = vo;
+    w.n = (int)(a.voff[g + 1] - vo);
+    w.rp = gro(a.rp + vo + g);
+    w.ci = gro(a.ci + a.noff[g]);
+    w.col = gro(a.col + vo);
+    w.col8 = gro(a.col8 + vo);
+    return w;
+}
+
+__device__ __forceinline__ void wave_append64(bool take, int64_t x, int *counter, int64_t *list, bool from_back,
+                                              int64_t cap) {
+    uint64_t m = ballot(take);
+    if (m == 0) return;
+    int leader = __ffsll((unsigned long long)m) - 1;
+    int base = 0;
+    if (lane_id() == leader) base = atomicAdd(counter, __popcll(m));
+    base = __shfl(base, leader);
+    if (take) {
+        const int64_t pos = base + lanes_below(m);
+        list[from_back ? cap - 1 - pos : pos] = x;
+    }
+}
+
+// --------------------------------------------------------------- binning --
+__global__ __launch_bounds__(kBlock) void k_bbin(const BatchArgs *__restrict__ A, SingleState *S) {
+    __shared__ int sh[kWavesPerBlock];
+    const BatchArgs a = *A;
+    int md = 0;
+    for (int t = blockIdx.x; t < a.ntasks; t += gridDim.x) {
+        const int64_t task = a.tasks[t];
+        const int g = item_graph(task), start = item_vertex(task);
+        const GraphView w = graph_view(a, g);
+        const int end = min(w.n, start + kTaskLen);
+        for (int base = start; base < end; base += kBlock) {
+            const int v = base + threadIdx.x;
+            int d = -1;
+            if (v < end) d = w.rp[v + 1] - w.rp[v];
+            md = max(md, d);
+            wave_append64(d > a.t_wave, pack_item(g, v), &S->nB, a.hub, true, a.hub_cap);
+            wave_append64(d > a.t_thread && d <= a.t_wave, pack_item(g, v), &S->nW, a.hub, false, a.hub_cap);
+        }
+    }
+    md = block_max(md, sh);
+    if (threadIdx.x == 0 && md > __hip_atomic_load(&S->maxdeg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+        atomicMax(&S->maxdeg, md);
+}
+
+__global__ __launch_bounds__(kBlock) void k_bvalidate(const BatchArgs *__restrict__ A, int32_t *err) {
+    const BatchArgs a = *A;
+    int flags = 0;
+    for (int t = blockIdx.x; t < a.ntasks; t += gridDim.x) {
+        const int64_t task = a.tasks[t];
+        const int g = item_graph(task), start = item_vertex(task);
+        const GraphView w = graph_view(a, g);
+        const int end = min(w.n, start + kTaskLen);
+        const int64_t nnz = a.noff[g + 1] - a.noff[g];
+        if (start == 0 && threadIdx.x == 0 && w.rp[0] != 0) flags |= 1;
+        for (int v = start + threadIdx.x; v < end; v += kBlock) {
+            const int b = w.rp[v], e = w.rp[v + 1];
+            if (b > e || b < 0 || (int64_t)e > nnz) { flags |= 1; continue; }
+            for (int j = b; j < e; ++j) {
+                const int u = w.ci[j];
+                if ((unsigned)u >= (unsigned)w.n) flags |= 1;
+                else if (u == v) flags |= 2;
+            }
+        }
+    }
+    if (ballot(flags != 0)) {
+        int f = flags;
+        for (int off = 32; off > 0; off >>= 1) f |= __shfl_xor(f, off);
+        if (lane_id() == 0) atomicOr(err, f);
+    }
+}
+
+// Appends packed items into the workgroup's LDS queue / flushes it.
+__device__ __forceinline__ void queue_push64(bool take, int64_t x, int64_t *q, int *qn) {
+    const uint64_t m = ballot(take);
+    if (m == 0) return;
+    const int leader = __ffsll((unsigned long long)m) - 1;
+    int base = 0;
+    if (lane_id() == leader) base = atomicAdd(qn, __popcll(m));
+    base = __shfl(base, leader);
+    if (take) q[base + lanes_below(m)] = x;
+}
+
+__device__ __forceinline__ void queue_flush64(int64_t *q, int *qn, int *qbase, int *counter, int64_t *out) {
+    __syncthreads();
+    const int cnt = *qn;
+    if (cnt == 0) return;
+    if (threadIdx.x == 0) *qbase = atomicAdd(counter, cnt);
+    __syncthreads();
+    const int base = *qbase;
+    for (int i = threadIdx.x; i < cnt; i += kBlock) out[base + i] = q[i];
+    __syncthreads();
+    if (threadIdx.x == 0) *qn = 0;
+    __syncthreads();
+}
+
+// ----------------------------------------------------------------- round --
+// Same contract as k_round (PHASE, MODE, TIE, SWEEP, ROUND0), over the batch.
+template <int PHASE, int MODE, int TIE, bool SWEEP, int ROUND0 = 0>
+__global__ __launch_bounds__(kBlock) void k_bround(const BatchArgs *__restrict__ A, SingleState *S, int parity,
+                                                   int gB, int gW, int gT) {
+    __shared__ uint32_t lds[kLdsWords];
+    __shared__ int64_t q[kQueueCap];
+    __shared__ int sh_min, qn, qbase;
+    __shared__ unsigned long long sh_acc[2];
+    const BatchArgs a = *A;
+    if (!SWEEP && S->passes >= a.max_rounds) return;
+    const int cT = SWEEP ? a.ntasks : S->cnt_in[kBinThread];
+    const int cW = SWEEP ? S->nW : S->cnt_in[kBinWave];
+    const int cB = SWEEP ? S->nB : S->cnt_in[kBinBlock];
+    int64_t *const in = parity ? a.wl[1] : a.wl[0];
+    int64_t *const out = parity ? a.wl[0] : a.wl[1];
+    constexpr bool kFlagAppend = PHASE == kAssign && ROUND0 == 1;
+    constexpr bool kWinOnly = kFlagAppend;
+    constexpr bool kAppend = PHASE != kAssign || kFlagAppend;
+    constexpr bool kWrite = PHASE != kDetect;
+    constexpr bool kAcct = PHASE != kAssign && !SWEEP;
+    RSOC_GLOBAL int32_t *wcolg = grw((MODE == kOptimistic) ? a.col : a.pend);
+    RSOC_GLOBAL uint8_t *wcol8g = grw(a.col8);
+    uint64_t items = 0, degs = 0;
+    const int bid = blockIdx.x;
+    if (bid < gB) {
+        for (int i = bid; i < cB; i += gB) {
+            const int64_t it = SWEEP ? a.hub[a.hub_cap - 1 - i] : in[a.offB + i];
+            const int g = item_graph(it), v = item_vertex(it);
+            const GraphView w = graph_view(a, g);
+            const int b = w.rp[v], e = w.rp[v + 1];
+            int nc = 0;
+            bool unc = false;
+            const bool act = block_vertex<PHASE, TIE, kWinOnly>(v, b, e, w.ci, w.col, lds, &sh_min, a.look, nc, unc);
+            if (threadIdx.x == 0) {
+                items += 1;
+                degs += (uint64_t)(e - b);
+                if (act && kWrite) {
+                    wcolg[w.voff + v] = nc;
+                    if (MODE == kOptimistic) wcol8g[w.voff + v] = shadow_of(nc);
+                }
+                const bool take = kFlagAppend ? unc : act;
+                if (take && kAppend) out[a.offB + atomicAdd(&S->cnt_out[kBinBlock], 1)] = it;
+            }
+        }
+    } else if (bid < gB + gW) {
+        const int wv = threadIdx.x / kWave;
+        const int wi = (bid - gB) * kWavesPerBlock + wv;
+        const int nw = gW * kWavesPerBlock;
+        uint32_t *bm = lds + wv * kWaveWindowWords;
+        for (int i = wi; i < cW; i += nw) {
+            const int64_t it = SWEEP ? a.hub[i] : in[a.offW + i];
+            const int g = item_graph(it), v = item_vertex(it);
+            const GraphView w = graph_view(a, g);
+            const int b = w.rp[v], e = w.rp[v + 1];
+            int nc = 0;
+            bool unc = false;
+            const bool act = wave_vertex<PHASE, TIE, kWinOnly>(v, b, e, w.ci, w.col, bm, a.look, nc, unc);
+            if (lane_id() == 0) {
+                items += 1;
+                degs += (uint64_t)(e - b);
+                if (act && kWrite) {
+                    wcolg[w.voff + v] = nc;
+                    if (MODE == kOptimistic) wcol8g[w.voff + v] = shadow_of(nc);
+                }
+                const bool take = kFlagAppend ? unc : act;
+                if (take && kAppend) out[a.offW + atomicAdd(&S->cnt_out[kBinWave], 1)] = it;
+            }
+        }
+    } else {
+        const int tb = bid - gB - gW;
+        constexpr int kNV = 2;
+        constexpr int kGpb = kBlock / kGroup;  // lane groups per workgroup
+        constexpr int kVpb = kNV * kGpb;
+        const int gi = threadIdx.x / kGroup;
+        const bool leader = (threadIdx.x & (kGroup - 1)) == 0;
+        if (kAppend) {
+            if (threadIdx.x == 0) qn = 0;
+            __syncthreads();
+        }
+        // SWEEP: one task (a chunk of one graph) per workgroup step group;
+        // worklist rounds: kVpb packed items per step.
+        const int64_t nsteps = SWEEP ? (int64_t)cT : ((int64_t)cT + kVpb - 1) / kVpb;
+        for (int64_t step = tb; step < nsteps; step += gT) {
+            int tg = 0, tstart = 0, tlen = 0;
+            GraphView tw;
+            if (SWEEP) {
+                const int t = (kFlagAppend && TIE == kHigherKeeps) ? (int)(nsteps - 1 - step) : (int)step;
+                const int64_t task = a.tasks[t];
+                tg = item_graph(task);
+                tstart = item_vertex(task);
+                tw = graph_view(a, tg);
+                tlen = min(kTaskLen, tw.n - tstart);
+            }
+            const int inner = SWEEP ? (tlen + kVpb - 1) / kVpb : 1;
+            for (int r = 0; r < inner; ++r) {
+                int v[kNV], b[kNV], e[kNV], cv[kNV], nc[kNV], gg[kNV];
+                bool act[kNV], unc[kNV] = {};
+                const RSOC_GLOBAL int32_t *cis[kNV];
+                const RSOC_GLOBAL uint8_t *c8s[kNV];
+                int64_t vo[kNV];
+#pragma unroll
+                for (int i = 0; i < kNV; ++i) {
+                    v[i] = -1;
+                    b[i] = e[i] = 0;
+                    gg[i] = 0;
+                    if (SWEEP) {
+                        const int li = r * kVpb + gi + i * kGpb;
+                        if (li < tlen) v[i] = (kFlagAppend && TIE == kHigherKeeps) ? tstart + tlen - 1 - li : tstart + li;
+                        gg[i] = tg;
+                        cis[i] = tw.ci;
+                        c8s[i] = tw.col8;
+                        vo[i] = tw.voff;
+                        if (v[i] >= 0) {
+                            b[i] = tw.rp[v[i]];
+                            e[i] = tw.rp[v[i] + 1];
+                        }
+                    } else {
+                        const int64_t idx = step * kVpb + gi + i * kGpb;
+                        cis[i] = gro(a.ci);
+                        c8s[i] = gro(a.col8);
+                        vo[i] = 0;
+                        if (idx < cT) {
+                            const int64_t it = in[idx];
+                            gg[i] = item_graph(it);
+                            v[i] = item_vertex(it);
+                            const GraphView w = graph_view(a, gg[i]);
+                            cis[i] = w.ci;
+                            c8s[i] = w.col8;
+                            vo[i] = w.voff;
+                            b[i] = w.rp[v[i]];
+                            e[i] = w.rp[v[i] + 1];
+                        }
+                    }
+                    if (SWEEP && v[i] >= 0 && e[i] - b[i] > a.t_thread) e[i] = b[i] = 0, v[i] = -1;
+                    cv[i] = (PHASE != kAssign && v[i] >= 0) ? (int)c8s[i][v[i]] : 255;
+                }
+                group_vertices<PHASE, TIE, kGroup, kGroupSlots, kWinOnly, kNV>(v, b, e, cis, c8s, cv, a.look, nc,
+                                                                               act, unc);
+#pragma unroll
+                for (int i = 0; i < kNV; ++i) {
+                    if (v[i] < 0) act[i] = unc[i] = false;
+                    if (leader && v[i] >= 0) {
+                        items += 1;
+                        degs += (uint64_t)(e[i] - b[i]);
+                        if (act[i] && kWrite) {
+                            wcolg[vo[i] + v[i]] = nc[i];
+                            if (MODE == kOptimistic) wcol8g[vo[i] + v[i]] = (uint8_t)nc[i];
+                        }
+                    }
+                }
+                if (kAppend) {
+#pragma unroll
+                    for (int i = 0; i < kNV; ++i)
+                        queue_push64((kFlagAppend ? unc[i] : act[i]) && leader, pack_item(gg[i], v[i]), q, &qn);
+                    __syncthreads();
+                    if (qn > kQueueCap - kVpb) queue_flush64(q, &qn, &qbase, &S->cnt_out[kBinThread], out);
+                }
+            }
+        }
+        if (kAppend) queue_flush64(q, &qn, &qbase, &S->cnt_out[kBinThread], out);
+    }
+    if (kAcct) {
+        if (threadIdx.x == 0) { sh_acc[0] = 0; sh_acc[1] = 0; }
+        __syncthreads();
+        items = wave_sum_u64(items);
+        degs = wave_sum_u64(degs);
+        if (lane_id() == 0 && items) {
+            atomicAdd(&sh_acc[0], (unsigned long long)items);
+            atomicAdd(&sh_acc[1], (unsigned long long)degs);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0 && sh_acc[0]) {
+            atomicAdd((unsigned long long *)&S->inspected, sh_acc[0]);
+            atomicAdd((unsigned long long *)&S->deg_sum, sh_acc[1]);
+        }
+    }
+}
+
+// --------------------------------------------------------------- scatter --
+template <bool SWEEP, bool USE_IN>
+__global__ __launch_bounds__(kBlock) void k_bscatter(const BatchArgs *__restrict__ A, SingleState *S, int parity) {
+    const BatchArgs a = *A;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    const int64_t t0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    RSOC_GLOBAL int32_t *col = grw(a.col);
+    RSOC_GLOBAL uint8_t *col8 = grw(a.col8);
+    const RSOC_GLOBAL int32_t *pend = gro(a.pend);
+    if (SWEEP) {
+        for (int64_t x = t0; x < a.nV; x += stride) {
+            const int c = pend[x];
+            col[x] = c;
+            col8[x] = shadow_of(c);
+        }
+        return;
+    }
+    if (S->passes >= a.max_rounds) return;
+    const bool use_wl1 = USE_IN ? (parity != 0) : (parity == 0);
+    const int64_t *lst = use_wl1 ? a.wl[1] : a.wl[0];
+    const int32_t *cnt = USE_IN ? S->cnt_in : S->cnt_out;
+    for (int bin = 0; bin < 3; ++bin) {
+        const int c = cnt[bin];
+        const int64_t off = bin == 0 ? 0 : (bin == 1 ? a.offW : a.offB);
+        for (int64_t i = t0; i < c; i += stride) {
+            const int64_t it = lst[off + i];
+            const int64_t x = a.voff[item_graph(it)] + item_vertex(it);
+            const int cc = pend[x];
+            col[x] = cc;
+            col8[x] = shadow_of(cc);
+        }
+    }
+}
+
+template <int MODE, bool SWEEP, bool PUBLISH_ONLY = false>
+__global__ void k_bround_end(const BatchArgs *__restrict__ A, SingleState *S) {
+    if (threadIdx.x != 0) return;
+    if (PUBLISH_ONLY) {
+        S->u0 = S->cnt_out[0] + S->cnt_out[1] + S->cnt_out[2];
+        for (int b = 0; b < 3; ++b) {
+            S->cnt_in[b] = S->cnt_out[b];
+            S->cnt_out[b] = 0;
+        }
+        return;
+    }
+    if (!SWEEP && S->passes >= A->max_rounds) return;
+    const int in_total = SWEEP ? (int)A->nV : (S->cnt_in[0] + S->cnt_in[1] + S->cnt_in[2]);
+    const int out_total = S->cnt_out[0] + S->cnt_out[1] + S->cnt_out[2];
+    if (in_total > 0) {
+        S->passes += 1;
+        if (MODE == kTwoPhase || out_total > 0) {
+            if (S->rounds < kHistCap) S->hist[S->rounds] = out_total;
+            S->rounds += 1;
+            S->conflicts += out_total;
+        }
+    }
+    for (int b = 0; b < 3; ++b) {
+        S->cnt_in[b] = S->cnt_out[b];
+        S->cnt_out[b] = 0;
+    }
+}
+
+// Per-graph colour count: kg[g] = max colour + 1; flags colours outside [0, n_g).
+__global__ __launch_bounds__(kBlock) void k_bcount(const BatchArgs *__restrict__ A, int32_t *err) {
+    __shared__ int sh[kWavesPerBlock];
+    const BatchArgs a = *A;
+    for (int t = blockIdx.x; t < a.ntasks; t += gridDim.x) {
+        const int64_t task = a.tasks[t];
+        const int g = item_graph(task), start = item_vertex(task);
+        const GraphView w = graph_view(a, g);
+        const int end = min(w.n, start + kTaskLen);
+        int m = -1;
+        bool bad = false;
+        for (int v = start + threadIdx.x; v < end; v += kBlock) {
+            const int c = w.col[v];
+            bad |= (c < 0 || c >= w.n);
+            m = max(m, c);
+        }
+        if (ballot(bad) && lane_id() == 0) atomicOr(err, 4);
+        m = block_max(m, sh);
+        if (threadIdx.x == 0 && m + 1 > __hip_atomic_load(&a.kg[g], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            atomicMax(&a.kg[g], m + 1);
+        __syncthreads();
+    }
+}
+
+}  // namespace rsoc

@@ -25,7 +25,8 @@ struct rsoc_ctx {
     std::map<std::tuple<int, int, int, int, int, int>, hipGraphExec_t> graphs;
     hipEvent_t ev[8] = {};
     // batched path scratch (batch.hpp)
-    rsoc::DevBuf b_desc, b_wl0, b_wl1, b_pend, b_flags, b_state, b_hub, b_kmax, b_tasks;
+    rsoc::DevBuf b_desc, b_wl0, b_wl1, b_pend, b_flags, b_state, b_hub, b_kmax, b_tasks, b_args, b_col8;
+    int32_t *b_colp = nullptr;
 };
 
 namespace rsoc {
@@ -46,6 +47,8 @@ inline int32_t ctx_init(rsoc_ctx *c, int device) {
     RSOC_TRY(c->args.reserve(sizeof(SingleArgs)));
     RSOC_TRY(c->state.reserve(sizeof(SingleState)));
     RSOC_TRY(c->host.reserve(sizeof(HostStaging) + 4096));
+    RSOC_TRY(c->b_args.reserve(1024));  // holds a BatchArgs (fixed address: captured graphs use it)
+    RSOC_TRY(c->b_state.reserve(sizeof(SingleState)));
     for (auto &e : c->ev) RSOC_HIP(hipEventCreate(&e));
     return RSOC_OK;
 }
@@ -58,7 +61,7 @@ inline void ctx_free(rsoc_ctx *c) {
         if (e) (void)hipEventDestroy(e);
     for (rsoc::DevBuf *b : {&c->col8, &c->wl0, &c->wl1, &c->hubW, &c->hubB, &c->pend, &c->flags, &c->args, &c->state, &c->drp,
                             &c->dci, &c->dcol, &c->b_desc, &c->b_wl0, &c->b_wl1, &c->b_pend, &c->b_flags,
-                            &c->b_state, &c->b_hub, &c->b_kmax, &c->b_tasks})
+                            &c->b_state, &c->b_hub, &c->b_kmax, &c->b_tasks, &c->b_args, &c->b_col8})
         b->release();
     c->host.release();
     if (c->own) (void)hipStreamDestroy(c->own);

@@ -262,7 +262,9 @@ __global__ __launch_bounds__(kBlock) void k_round(const SingleArgs *__restrict__
                 }
                 cv[i] = (PHASE != kAssign && v[i] >= 0) ? (int)rcol8[v[i]] : 255;
             }
-            group_vertices<PHASE, TIE, kGroup, kGroupSlots, kWinOnly, kNV>(v, b, e, ci, rcol8, cv, a.look, nc, act,
+            const RSOC_GLOBAL int32_t *const cis[kNV] = {ci, ci};
+            const RSOC_GLOBAL uint8_t *const c8s[kNV] = {rcol8, rcol8};
+            group_vertices<PHASE, TIE, kGroup, kGroupSlots, kWinOnly, kNV>(v, b, e, cis, c8s, cv, a.look, nc, act,
                                                                            unc);
 #pragma unroll
             for (int i = 0; i < kNV; ++i) {

@@ -34,11 +34,12 @@ namespace rsoc {
 // the neighbours it wins against whose id lies within `look` of v's (those
 // the sweep may already have coloured); unc[i] reports whether a neighbour v
 // loses to was still uncoloured when read.
+// ci[i] / col8[i] are the (per-graph) bases vertex i's ids refer to.
 template <int PHASE, int TIE, int G, int S, bool WIN_ONLY, int NV>
 __device__ __forceinline__ void group_vertices(const int (&v)[NV], const int (&b)[NV], const int (&e)[NV],
-                                               const RSOC_GLOBAL int32_t *ci, const RSOC_GLOBAL uint8_t *col8,
-                                               const int (&cv)[NV], int look, int (&newc)[NV], bool (&act)[NV],
-                                               bool (&unc)[NV]) {
+                                               const RSOC_GLOBAL int32_t *const (&ci)[NV],
+                                               const RSOC_GLOBAL uint8_t *const (&col8)[NV], const int (&cv)[NV],
+                                               int look, int (&newc)[NV], bool (&act)[NV], bool (&unc)[NV]) {
     const int k = lane_id() & (G - 1);
     int u[NV][S];
     int cu[NV][S];
@@ -47,7 +48,7 @@ __device__ __forceinline__ void group_vertices(const int (&v)[NV], const int (&b
 #pragma unroll
         for (int s = 0; s < S; ++s) {
             const int j = b[i] + k + s * G;
-            u[i][s] = (j < e[i]) ? __builtin_nontemporal_load(ci + j) : v[i];
+            u[i][s] = (j < e[i]) ? __builtin_nontemporal_load(ci[i] + j) : v[i];
         }
     if (PHASE != kAssign) {
         bool def[NV];
@@ -56,7 +57,7 @@ __device__ __forceinline__ void group_vertices(const int (&v)[NV], const int (&b
 #pragma unroll
             for (int s = 0; s < S; ++s) {
                 const bool w = (u[i][s] != v[i]) && loses<TIE>(v[i], u[i][s]);
-                cu[i][s] = w ? (int)col8[u[i][s]] : 255;
+                cu[i][s] = w ? (int)col8[i][u[i][s]] : 255;
             }
 #pragma unroll
         for (int i = 0; i < NV; ++i) {
@@ -71,7 +72,7 @@ __device__ __forceinline__ void group_vertices(const int (&v)[NV], const int (&b
         for (int i = 0; i < NV; ++i)
 #pragma unroll
             for (int s = 0; s < S; ++s)
-                if (def[i] && u[i][s] != v[i] && !loses<TIE>(v[i], u[i][s])) cu[i][s] = col8[u[i][s]];
+                if (def[i] && u[i][s] != v[i] && !loses<TIE>(v[i], u[i][s])) cu[i][s] = col8[i][u[i][s]];
     } else {
 #pragma unroll
         for (int i = 0; i < NV; ++i) {
@@ -81,7 +82,7 @@ __device__ __forceinline__ void group_vertices(const int (&v)[NV], const int (&b
                 const bool win = (u[i][s] != v[i]) && loses<TIE>(v[i], u[i][s]);
                 const int dist = u[i][s] > v[i] ? u[i][s] - v[i] : v[i] - u[i][s];
                 const bool take = WIN_ONLY ? (win || (u[i][s] != v[i] && dist < look)) : (u[i][s] != v[i]);
-                cu[i][s] = take ? (int)col8[u[i][s]] : 255;
+                cu[i][s] = take ? (int)col8[i][u[i][s]] : 255;
                 un |= win && cu[i][s] == 255;
             }
             unc[i] = group_any<G>(un);

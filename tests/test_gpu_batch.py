@@ -1,0 +1,111 @@
+"""Batched colouring on the GPU: every graph of a batch must come out exactly as
+the oracle colours it alone (round-synchronous modes: element by element;
+optimistic mode: valid with 0 <= c(v) <= deg(v)), and exactly as a separate
+single-graph call colours it."""
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx(lib):
+    c = lib.Context(0)
+    yield c
+    c.close()
+
+
+def _mixed_batch():
+    graphs = [gg.path(7), gg.cycle(5), (np.zeros(1, np.int32), np.zeros(0, np.int32)), gg.complete(40),
+              gg.star(300), gg.tri_grid(30, 17), gg.tri_grid(25, 25, permute_seed=3), gg.rmat(9, 8, seed=4, shuffle_seed=5),
+              (np.zeros(4, np.int32), np.zeros(0, np.int32)), gg.rgg(2500, seed=6), gg.complete_bipartite(20, 70)]
+    b = gg.batch(20, seed=77, nmin=50, nmax=4000)
+    graphs += [gg.batch_member(b, g) for g in range(20)]
+    return graphs
+
+
+GRAPHS = _mixed_batch()
+BATCH = gg.concat(GRAPHS)
+SPLITS = {"default": {}, "allbins": {"t_thread": 3, "t_wave": 8}}
+
+
+def _upload(lib, b):
+    import torch
+    d = torch.device("cuda:0")
+    rp = torch.from_numpy(b["row_ptr_cat"]).to(d)
+    ci = torch.from_numpy(b["col_idx_cat"] if len(b["col_idx_cat"]) else np.zeros(1, np.int32)).to(d)
+    col = torch.full((max(int(b["vtx_off"][-1]), 1),), -5, dtype=torch.int32, device=d)
+    return rp, ci, col
+
+
+def _member_colours(col, b, g):
+    return col[int(b["vtx_off"][g]): int(b["vtx_off"][g + 1])]
+
+
+@pytest.mark.parametrize("split", sorted(SPLITS))
+@pytest.mark.parametrize("tie", ["lower", "higher"])
+@pytest.mark.parametrize("mode", ["deterministic", "two_phase"])
+def test_batch_round_synchronous_matches_oracle(lib, ctx, mode, tie, split):
+    rp, ci, col = _upload(lib, BATCH)
+    counts, kmax, st = lib.rsoc_color_batch(ctx, BATCH["vtx_off"], BATCH["nnz_off"], rp, ci, col,
+                                            lib.make_options(mode, tie, **SPLITS[split]))
+    got = col.cpu().numpy()
+    fn = oracle.rsync if mode == "deterministic" else oracle.cat
+    for g, (grp, gci) in enumerate(GRAPHS):
+        want = fn(grp, gci, tie=tie)
+        assert np.array_equal(_member_colours(got, BATCH, g), want["colors"]), (mode, tie, g)
+        assert counts[g] == want["K"], g
+    assert kmax == max(counts)
+
+
+@pytest.mark.parametrize("split", sorted(SPLITS))
+@pytest.mark.parametrize("full_sweep", [0, 1])
+@pytest.mark.parametrize("tie", ["lower", "higher"])
+def test_batch_optimistic_valid(lib, ctx, tie, full_sweep, split):
+    rp, ci, col = _upload(lib, BATCH)
+    counts, kmax, st = lib.rsoc_color_batch(ctx, BATCH["vtx_off"], BATCH["nnz_off"], rp, ci, col,
+                                            lib.make_options("optimistic", tie, full_sweep=full_sweep,
+                                                             **SPLITS[split]))
+    got = col.cpu().numpy()
+    for g, (grp, gci) in enumerate(GRAPHS):
+        c = _member_colours(got, BATCH, g)
+        assert oracle.check(grp, gci, c) == 0, g
+        assert counts[g] == oracle.colour_count(c)
+
+
+def test_batch_equals_single_calls(lib, ctx):
+    """Deterministic: each graph's colours in the batch equal a separate call's."""
+    import torch
+    rp, ci, col = _upload(lib, BATCH)
+    lib.rsoc_color_batch(ctx, BATCH["vtx_off"], BATCH["nnz_off"], rp, ci, col, lib.make_options("deterministic"))
+    got = col.cpu().numpy()
+    d = torch.device("cuda:0")
+    for g, (grp, gci) in enumerate(GRAPHS):
+        n = len(grp) - 1
+        if n == 0:
+            continue
+        d_rp = torch.from_numpy(grp).to(d)
+        d_ci = torch.from_numpy(gci if len(gci) else np.zeros(1, np.int32)).to(d)
+        d_col = torch.empty(n, dtype=torch.int32, device=d)
+        lib.rsoc_color_device(ctx, d_rp, d_ci, n, d_col, lib.make_options("deterministic"))
+        assert np.array_equal(d_col.cpu().numpy(), _member_colours(got, BATCH, g)), g
+
+
+def test_batch_validation_and_empty(lib, ctx):
+    import torch
+    d = torch.device("cuda:0")
+    z = torch.zeros(1, dtype=torch.int32, device=d)
+    counts, k, st = lib.rsoc_color_batch(ctx, np.zeros(1, np.int64), np.zeros(1, np.int64), z, z, z)
+    assert k == 0 and len(counts) == 0
+    b = gg.concat([gg.cycle(5), gg.path(4)])
+    bad = b["col_idx_cat"].copy()
+    bad[2] = 9  # out of range for graph 0
+    rp = torch.from_numpy(b["row_ptr_cat"]).to(d)
+    ci = torch.from_numpy(bad).to(d)
+    col = torch.empty(9, dtype=torch.int32, device=d)
+    with pytest.raises(lib.RsocError) as e:
+        lib.rsoc_color_batch(ctx, b["vtx_off"], b["nnz_off"], rp, ci, col, lib.make_options(validate=1))
+    assert e.value.code == lib.RSOC_ECSR
