@@ -1,15 +1,344 @@
-// pool.hpp -- continuous batching (placeholder until the pool lands).
+// pool.hpp -- continuous batching: graphs are admitted into slots while others
+// are being coloured; every rsoc_pool_step is one fused round over all live
+// slots.  Slot scratch (worklists, hub lists, colour shadow, staging) comes
+// from an arena sized by the HBM budget; admission is refused with
+// RSOC_EBUDGET when it does not fit.
 #pragma once
+
+#include <map>
+#include <vector>
+
+#include "pool_kernels.hpp"
 #include "single.hpp"
 
-struct rsoc_pool { int dummy; };
+struct rsoc_pool {
+    rsoc_ctx *ctx = nullptr;
+    int64_t budget = 0;    // 0: unlimited (per-slot hipMalloc)
+    int64_t reserved = 0;  // scratch bytes held by admitted slots
+    int max_slots = 0;
+    rsoc::DevBuf slots_dev, tasks_dev, active_dev, arena;
+    rsoc::HostPinned mirror, tasks_host, active_host;
+    std::map<int64_t, int64_t> free_blocks;  // arena offset -> size
+    struct Alloc {
+        int64_t off = -1, bytes = 0;
+        void *own = nullptr;  // per-slot allocation when the pool has no arena
+    };
+    std::vector<Alloc> allocs;
+    std::vector<char> reported;  // finished slot already returned by a step
+};
+
+namespace rsoc {
+
+constexpr int64_t kPoolAlign = 256;
+
+inline int64_t align_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+
+inline int64_t pool_slot_bytes(int64_t n, int mode) {
+    const int64_t l = align_up(4 * (n + 1), kPoolAlign);
+    return 4 * l + align_up(n + 64, kPoolAlign) + (mode == kOptimistic ? 0 : l);
+}
+
+inline int64_t arena_alloc(rsoc_pool *p, int64_t bytes) {
+    for (auto it = p->free_blocks.begin(); it != p->free_blocks.end(); ++it) {
+        if (it->second >= bytes) {
+            const int64_t off = it->first, sz = it->second;
+            p->free_blocks.erase(it);
+            if (sz > bytes) p->free_blocks[off + bytes] = sz - bytes;
+            return off;
+        }
+    }
+    return -1;
+}
+
+inline void arena_free(rsoc_pool *p, int64_t off, int64_t bytes) {
+    auto it = p->free_blocks.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != p->free_blocks.end() && it->first + it->second == nx->first) {
+        it->second += nx->second;
+        p->free_blocks.erase(nx);
+    }
+    if (it != p->free_blocks.begin()) {
+        auto pv = std::prev(it);
+        if (pv->first + pv->second == it->first) {
+            pv->second += it->second;
+            p->free_blocks.erase(it);
+        }
+    }
+}
+
+inline PoolSlot *pool_mirror(rsoc_pool *p) { return p->mirror.as<PoolSlot>(); }
+
+inline int32_t pool_upload_slot(rsoc_pool *p, int slot, hipStream_t s) {
+    RSOC_HIP(hipMemcpyAsync(p->slots_dev.as<PoolSlot>() + slot, pool_mirror(p) + slot, sizeof(PoolSlot),
+                            hipMemcpyHostToDevice, s));
+    return RSOC_OK;
+}
+
+inline int32_t pool_download_slot(rsoc_pool *p, int slot, hipStream_t s) {
+    RSOC_HIP(hipMemcpyAsync(pool_mirror(p) + slot, p->slots_dev.as<PoolSlot>() + slot, sizeof(PoolSlot),
+                            hipMemcpyDeviceToHost, s));
+    return RSOC_OK;
+}
+
+inline void pool_release(rsoc_pool *p, int slot) {
+    rsoc_pool::Alloc &a = p->allocs[slot];
+    if (a.own) (void)hipFree(a.own);
+    if (a.off >= 0) arena_free(p, a.off, a.bytes);
+    p->reserved -= a.bytes;
+    a = rsoc_pool::Alloc();
+    PoolSlot &m = pool_mirror(p)[slot];
+    memset(&m, 0, sizeof(m));
+    m.phase = kSlotFree;
+}
+
+}  // namespace rsoc
 
 extern "C" {
-int32_t rsoc_pool_create(rsoc_ctx *, int64_t, int32_t, rsoc_pool **out) { if (out) *out = nullptr; return RSOC_EINVAL; }
-void rsoc_pool_destroy(rsoc_pool *) {}
-int32_t rsoc_pool_admit(rsoc_pool *, const int32_t *, const int32_t *, int32_t, int32_t *, const rsoc_options *) { return RSOC_EINVAL; }
-int32_t rsoc_pool_step(rsoc_pool *, void *, int32_t *, int32_t) { return RSOC_EINVAL; }
-int32_t rsoc_pool_live(const rsoc_pool *) { return 0; }
-int64_t rsoc_pool_reserved_bytes(const rsoc_pool *) { return 0; }
-int32_t rsoc_pool_result(rsoc_pool *, int32_t, rsoc_stats *) { return RSOC_ENOTFOUND; }
+
+int32_t rsoc_pool_create(rsoc_ctx *ctx, int64_t hbm_budget_bytes, int32_t max_slots, rsoc_pool **out) {
+    using namespace rsoc;
+    if (!out) return RSOC_EINVAL;
+    *out = nullptr;
+    if (!ctx || hbm_budget_bytes < 0 || max_slots <= 0 || max_slots > 65536) return RSOC_EINVAL;
+    RSOC_HIP(hipSetDevice(ctx->device));
+    rsoc_pool *p = new (std::nothrow) rsoc_pool();
+    if (!p) return RSOC_ENOMEM;
+    p->ctx = ctx;
+    p->budget = hbm_budget_bytes;
+    p->max_slots = max_slots;
+    p->allocs.resize((size_t)max_slots);
+    p->reported.assign((size_t)max_slots, 0);
+    int32_t r = RSOC_OK;
+    if ((r = p->slots_dev.reserve(sizeof(PoolSlot) * (size_t)max_slots)) < 0 ||
+        (r = p->mirror.reserve(sizeof(PoolSlot) * (size_t)max_slots)) < 0 ||
+        (r = p->active_dev.reserve(sizeof(int32_t) * (size_t)max_slots)) < 0 ||
+        (r = p->active_host.reserve(sizeof(int32_t) * (size_t)max_slots)) < 0 ||
+        (hbm_budget_bytes > 0 && (r = p->arena.reserve((size_t)hbm_budget_bytes)) < 0)) {
+        rsoc_pool_destroy(p);
+        return r;
+    }
+    memset(p->mirror.p, 0, sizeof(PoolSlot) * (size_t)max_slots);
+    if (hbm_budget_bytes > 0) p->free_blocks[0] = hbm_budget_bytes;
+    hipError_t e = hipMemcpy(p->slots_dev.p, p->mirror.p, sizeof(PoolSlot) * (size_t)max_slots, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        rsoc_pool_destroy(p);
+        return hip_fail(e, "hipMemcpy", __FILE__, __LINE__);
+    }
+    *out = p;
+    return RSOC_OK;
 }
+
+void rsoc_pool_destroy(rsoc_pool *p) {
+    if (!p) return;
+    (void)hipSetDevice(p->ctx->device);
+    for (auto &a : p->allocs)
+        if (a.own) (void)hipFree(a.own);
+    for (rsoc::DevBuf *b : {&p->slots_dev, &p->tasks_dev, &p->active_dev, &p->arena}) b->release();
+    for (rsoc::HostPinned *b : {&p->mirror, &p->tasks_host, &p->active_host}) b->release();
+    delete p;
+}
+
+int32_t rsoc_pool_admit(rsoc_pool *p, const int32_t *d_row_ptr, const int32_t *d_col_idx, int32_t n,
+                        int32_t *d_colors_out, const rsoc_options *opts) {
+    using namespace rsoc;
+    if (!p || n < 0 || (n > 0 && (!d_row_ptr || !d_colors_out))) return RSOC_EINVAL;
+    Options o;
+    RSOC_TRY(resolve_options(opts, n, o));
+    if (o.mode == RSOC_MODE_TWO_PHASE) return RSOC_EINVAL;  // the pool runs Algorithm 3 only
+    rsoc_ctx *c = p->ctx;
+    RSOC_HIP(hipSetDevice(c->device));
+    int slot = -1;
+    for (int i = 0; i < p->max_slots; ++i)
+        if (pool_mirror(p)[i].phase == kSlotFree) { slot = i; break; }
+    if (slot < 0) return RSOC_EBUDGET;
+    const int64_t bytes = pool_slot_bytes(n, o.mode);
+    rsoc_pool::Alloc al;
+    al.bytes = bytes;
+    char *base = nullptr;
+    if (p->budget > 0) {
+        if (p->reserved + bytes > p->budget) return RSOC_EBUDGET;
+        al.off = arena_alloc(p, bytes);
+        if (al.off < 0) return RSOC_EBUDGET;  // fragmented: wait for releases
+        base = p->arena.as<char>() + al.off;
+    } else {
+        hipError_t e = hipMalloc(&al.own, (size_t)bytes);
+        if (e != hipSuccess) return hip_fail(e, "hipMalloc", __FILE__, __LINE__);
+        base = static_cast<char *>(al.own);
+    }
+    p->allocs[slot] = al;
+    p->reserved += bytes;
+    hipStream_t s = c->own;
+    HostStaging *h = c->host.as<HostStaging>();
+    int32_t r = RSOC_OK;
+    int64_t nnz = 0;
+    if (n > 0) {
+        hipError_t e = hipMemcpyAsync(&h->rp_ends[1], d_row_ptr + n, 4, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) r = hip_fail(e, "read nnz", __FILE__, __LINE__);
+        nnz = h->rp_ends[1];
+        if (r == RSOC_OK && (nnz < 0 || (nnz > 0 && !d_col_idx))) r = RSOC_EINVAL;
+    }
+    if (r < 0) {
+        pool_release(p, slot);
+        return r;
+    }
+    const int64_t l = align_up(4 * (int64_t)(n + 1), kPoolAlign);
+    PoolSlot &m = pool_mirror(p)[slot];
+    memset(&m, 0, sizeof(m));
+    m.rp = d_row_ptr;
+    m.ci = d_col_idx;
+    m.col = d_colors_out;
+    m.wl[0] = reinterpret_cast<int32_t *>(base);
+    m.wl[1] = reinterpret_cast<int32_t *>(base + l);
+    m.hubW = reinterpret_cast<int32_t *>(base + 2 * l);
+    m.hubB = reinterpret_cast<int32_t *>(base + 3 * l);
+    m.col8 = reinterpret_cast<uint8_t *>(base + 4 * l);
+    m.pend = o.mode == kOptimistic ? nullptr : reinterpret_cast<int32_t *>(base + 4 * l + align_up(n + 64, kPoolAlign));
+    m.nnz = nnz;
+    m.n = n;
+    m.mode = o.mode;
+    m.tie = o.tie;
+    m.max_rounds = o.max_rounds;
+    m.t_thread = o.t_thread;
+    m.t_wave = o.t_wave;
+    m.look = o.lookahead == -1 ? 0 : (o.lookahead > 0 ? o.lookahead : (1 << 20));
+    m.phase = kSlotNew;
+    p->reported[slot] = 0;
+    if ((r = pool_upload_slot(p, slot, s)) < 0) { pool_release(p, slot); return r; }
+    if (n > 0) {
+        // fill the colours (round 0 of the round-synchronous mode) and bin by degree
+        k_pinit<<<std::min(div_up(n, kBlock), 1024), kBlock, 0, s>>>(p->slots_dev.as<PoolSlot>(), slot);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) { pool_release(p, slot); return hip_fail(e, "k_pinit", __FILE__, __LINE__); }
+        if ((r = pool_download_slot(p, slot, s)) < 0) { pool_release(p, slot); return r; }
+        e = hipStreamSynchronize(s);
+        if (e != hipSuccess) { pool_release(p, slot); return hip_fail(e, "admit sync", __FILE__, __LINE__); }
+        m.offW = n - m.nW - m.nB;
+        m.offB = n - m.nB;
+    } else {
+        m.phase = kSlotDone;  // nothing to colour
+    }
+    if ((r = pool_upload_slot(p, slot, s)) < 0) { pool_release(p, slot); return r; }
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) { pool_release(p, slot); return hip_fail(e, "admit sync", __FILE__, __LINE__); }
+    return slot;
+}
+
+int32_t rsoc_pool_step(rsoc_pool *p, void *hip_stream, int32_t *finished_slots, int32_t cap) {
+    using namespace rsoc;
+    if (!p || cap < 0 || (cap > 0 && !finished_slots)) return RSOC_EINVAL;
+    rsoc_ctx *c = p->ctx;
+    RSOC_HIP(hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)hip_stream;
+    PoolSlot *m = pool_mirror(p);
+    // task table: workgroup-bin tasks, then wavefront-bin, then thread-bin
+    std::vector<PoolTask> tb, tw, tt;
+    int nact = 0;
+    int32_t *act = p->active_host.as<int32_t>();
+    for (int i = 0; i < p->max_slots; ++i) {
+        const PoolSlot &sl = m[i];
+        if (sl.phase != kSlotNew && sl.phase != kSlotRunning) continue;
+        int kind, cT, cW, cB;
+        if (sl.phase == kSlotNew) {
+            kind = sl.mode == kOptimistic ? kAssignSweep : kRecolorSweep;
+            cT = sl.n;  // the sweep skips the other bins' vertices
+            cW = sl.nW;
+            cB = sl.nB;
+        } else {
+            kind = kRecolorList;
+            cT = sl.cnt_in[0];
+            cW = sl.cnt_in[1];
+            cB = sl.cnt_in[2];
+        }
+        for (int b = 0; b < cB; b += kPoolTaskB) tb.push_back({i, kind, b, std::min(cB, b + kPoolTaskB)});
+        for (int b = 0; b < cW; b += kPoolTaskW) tw.push_back({i, kind, b, std::min(cW, b + kPoolTaskW)});
+        for (int b = 0; b < cT; b += kPoolTaskT) tt.push_back({i, kind, b, std::min(cT, b + kPoolTaskT)});
+        act[nact++] = i;
+    }
+    int nfin = 0;
+    if (nact > 0) {
+        const size_t ntask = tb.size() + tw.size() + tt.size();
+        RSOC_TRY(p->tasks_dev.reserve(sizeof(PoolTask) * std::max<size_t>(ntask, 1)));
+        RSOC_TRY(p->tasks_host.reserve(sizeof(PoolTask) * std::max<size_t>(ntask, 1)));
+        PoolTask *th = p->tasks_host.as<PoolTask>();
+        std::copy(tb.begin(), tb.end(), th);
+        std::copy(tw.begin(), tw.end(), th + tb.size());
+        std::copy(tt.begin(), tt.end(), th + tb.size() + tw.size());
+        RSOC_HIP(hipMemcpyAsync(p->tasks_dev.p, th, sizeof(PoolTask) * ntask, hipMemcpyHostToDevice, s));
+        RSOC_HIP(hipMemcpyAsync(p->active_dev.p, act, sizeof(int32_t) * nact, hipMemcpyHostToDevice, s));
+        const int gB = (int)std::min<size_t>(tb.size(), 256);
+        const int gW = (int)std::min<size_t>(tw.size(), 512);
+        const int gT = (int)std::min<size_t>(tt.size(), 2048);
+        if (gB + gW + gT > 0)
+            k_pstep<<<gB + gW + gT, kBlock, 0, s>>>(p->slots_dev.as<PoolSlot>(), p->tasks_dev.as<PoolTask>(),
+                                                    (int)tb.size(), (int)tw.size(), (int)tt.size(), gB, gW, gT);
+        bool any_staged = false;
+        for (int k = 0; k < nact; ++k) any_staged |= m[act[k]].mode != kOptimistic;
+        if (any_staged)
+            k_pscatter<<<dim3(64, std::min(nact, 64)), kBlock, 0, s>>>(p->slots_dev.as<PoolSlot>(),
+                                                                      p->active_dev.as<int32_t>(), nact);
+        k_pround_end<<<1, 256, 0, s>>>(p->slots_dev.as<PoolSlot>(), p->active_dev.as<int32_t>(), nact);
+        RSOC_LAUNCH_CHECK();
+        RSOC_HIP(hipMemcpyAsync(m, p->slots_dev.p, sizeof(PoolSlot) * (size_t)p->max_slots, hipMemcpyDeviceToHost, s));
+        RSOC_HIP(hipStreamSynchronize(s));
+    }
+    // report finished slots (including ones a previous step could not fit in `cap`)
+    for (int i = 0; i < p->max_slots && nfin < cap; ++i) {
+        if (m[i].phase == kSlotDone && !p->reported[i]) {
+            p->reported[i] = 1;
+            finished_slots[nfin++] = i;
+        }
+    }
+    return nfin;
+}
+
+int32_t rsoc_pool_live(const rsoc_pool *p) {
+    if (!p) return RSOC_EINVAL;
+    const rsoc::PoolSlot *m = p->mirror.as<rsoc::PoolSlot>();
+    int live = 0;
+    for (int i = 0; i < p->max_slots; ++i) live += m[i].phase != rsoc::kSlotFree;
+    return live;
+}
+
+int64_t rsoc_pool_reserved_bytes(const rsoc_pool *p) { return p ? p->reserved : RSOC_EINVAL; }
+
+int32_t rsoc_pool_result(rsoc_pool *p, int32_t slot, rsoc_stats *stats) {
+    using namespace rsoc;
+    if (!p || slot < 0 || slot >= p->max_slots) return RSOC_ENOTFOUND;
+    PoolSlot &m = pool_mirror(p)[slot];
+    if (m.phase != kSlotDone) return RSOC_ENOTFOUND;
+    rsoc_ctx *c = p->ctx;
+    RSOC_HIP(hipSetDevice(c->device));
+    hipStream_t s = c->own;
+    if (m.n > 0) {
+        k_pcount<<<std::min(div_up(m.n, kBlock), 1024), kBlock, 0, s>>>(p->slots_dev.as<PoolSlot>(), slot);
+        RSOC_LAUNCH_CHECK();
+        RSOC_TRY(pool_download_slot(p, slot, s));
+        RSOC_HIP(hipStreamSynchronize(s));
+    }
+    if (stats) {
+        int32_t *keep = stats->per_round_L;
+        int32_t cap = stats->per_round_cap;
+        memset(stats, 0, sizeof(*stats));
+        stats->per_round_L = keep;
+        stats->per_round_cap = cap;
+        stats->rounds = m.rounds;
+        stats->passes = m.passes;
+        stats->colors = m.kmax;
+        stats->colors_distinct = -1;
+        stats->conflicts = m.conflicts;
+        stats->max_degree = m.maxdeg;
+        stats->bin_counts[0] = m.n - m.nW - m.nB;
+        stats->bin_counts[1] = m.nW;
+        stats->bin_counts[2] = m.nB;
+        stats->worklist0 = m.mode == kOptimistic ? m.u0 : m.n;
+    }
+    const int32_t k = (m.err & 4) ? RSOC_EHIP : (m.status < 0 ? m.status : m.kmax);
+    pool_release(p, slot);
+    int32_t r = pool_upload_slot(p, slot, s);
+    if (r < 0) return r;
+    RSOC_HIP(hipStreamSynchronize(s));
+    return k;
+}
+
+}  // extern "C"

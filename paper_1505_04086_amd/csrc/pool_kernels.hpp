@@ -1,0 +1,284 @@
+// pool_kernels.hpp -- kernels of the continuous-batching pool.
+//
+// A pool slot is one admitted graph with its own worklists.  One pool step is
+// one fused launch over a task table whose tasks belong to different slots
+// and different rounds: a slot admitted since the last step runs its round 0
+// (optimistic) or round 1 (round-synchronous) in the same launch in which
+// older slots run a later worklist round.  Mode and tie rule are per slot.
+#pragma once
+
+#include "single_kernels.hpp"
+
+namespace rsoc {
+
+enum PoolPhase : int { kSlotFree = 0, kSlotNew = 1, kSlotRunning = 2, kSlotDone = 3 };
+enum PoolTaskKind : int { kAssignSweep = 0, kRecolorSweep = 1, kRecolorList = 2 };
+constexpr int kPoolTaskT = 512;  // thread-bin items per task
+constexpr int kPoolTaskW = 32;   // wavefront-bin items per task
+constexpr int kPoolTaskB = 2;    // workgroup-bin items per task
+
+struct PoolSlot {
+    const int32_t *rp, *ci;
+    int32_t *col;
+    uint8_t *col8;
+    int32_t *pend;
+    int32_t *wl[2];
+    int32_t *hubW, *hubB;
+    int64_t nnz;
+    int64_t conflicts;
+    int32_t n, mode, tie, max_rounds, t_thread, t_wave, look, parity;
+    int32_t offW, offB;
+    int32_t cnt_in[4], cnt_out[4];
+    int32_t nW, nB, maxdeg, passes, rounds, kmax, err, phase, u0, status;
+    int32_t pad[2];
+};
+
+struct PoolTask {
+    int32_t slot, kind, begin, end;
+};
+
+__global__ __launch_bounds__(kBlock) void k_pinit(PoolSlot *slots, int slot) {
+    __shared__ int sh[kWavesPerBlock];
+    PoolSlot *sp = slots + slot;
+    const RSOC_GLOBAL int32_t *rp = gro(sp->rp);
+    const int n = sp->n;
+    const int fillc = sp->mode == kOptimistic ? -1 : 0;
+    int md = 0;
+    for (int64_t base = (int64_t)blockIdx.x * kBlock; base < n; base += (int64_t)gridDim.x * kBlock) {
+        const int v = (int)(base + threadIdx.x);
+        int d = -1;
+        if (v < n) {
+            d = rp[v + 1] - rp[v];
+            sp->col[v] = fillc;
+            sp->col8[v] = shadow_of(fillc);
+        }
+        md = max(md, d);
+        wave_append(d > sp->t_wave, v, &sp->nB, sp->hubB);
+        wave_append(d > sp->t_thread && d <= sp->t_wave, v, &sp->nW, sp->hubW);
+    }
+    md = block_max(md, sh);
+    if (threadIdx.x == 0) atomicMax(&sp->maxdeg, md);
+}
+
+template <int TIE, int KIND>
+__device__ __forceinline__ void pool_thread_task(PoolSlot *sp, const PoolSlot &s, const PoolTask &tk, int *q, int *qn,
+                                                 int *qbase) {
+    constexpr int PHASE = KIND == kAssignSweep ? kAssign : kRecolor;
+    constexpr bool SWEEP = KIND != kRecolorList;
+    constexpr bool kWinOnly = KIND == kAssignSweep;
+    constexpr int kNV = 2;
+    constexpr int kGpb = kBlock / kGroup;
+    constexpr int kVpb = kNV * kGpb;
+    const RSOC_GLOBAL int32_t *rp = gro(s.rp);
+    const RSOC_GLOBAL int32_t *ci = gro(s.ci);
+    const RSOC_GLOBAL uint8_t *c8 = gro(s.col8);
+    const bool opt = s.mode == kOptimistic;
+    RSOC_GLOBAL int32_t *wcol = grw(opt ? s.col : s.pend);
+    RSOC_GLOBAL uint8_t *wcol8 = grw(s.col8);
+    const int32_t *in = s.parity ? s.wl[1] : s.wl[0];
+    int32_t *out = s.parity ? s.wl[0] : s.wl[1];
+    const int gi = threadIdx.x / kGroup;
+    const bool leader = (threadIdx.x & (kGroup - 1)) == 0;
+    for (int base = tk.begin; base < tk.end; base += kVpb) {
+        int v[kNV], b[kNV], e[kNV], cv[kNV], nc[kNV];
+        bool act[kNV], unc[kNV] = {};
+#pragma unroll
+        for (int i = 0; i < kNV; ++i) {
+            const int idx = base + gi + i * kGpb;
+            v[i] = -1;
+            b[i] = e[i] = 0;
+            if (idx < tk.end) {
+                if (SWEEP) v[i] = (KIND == kAssignSweep && TIE == kHigherKeeps) ? s.n - 1 - idx : idx;
+                else v[i] = in[idx];
+                b[i] = rp[v[i]];
+                e[i] = rp[v[i] + 1];
+                if (SWEEP && e[i] - b[i] > s.t_thread) e[i] = b[i] = 0, v[i] = -1;
+            }
+            cv[i] = (PHASE != kAssign && v[i] >= 0) ? (int)c8[v[i]] : 255;
+        }
+        const RSOC_GLOBAL int32_t *const cis[kNV] = {ci, ci};
+        const RSOC_GLOBAL uint8_t *const c8s[kNV] = {c8, c8};
+        group_vertices<PHASE, TIE, kGroup, kGroupSlots, kWinOnly, kNV>(v, b, e, cis, c8s, cv, s.look, nc, act, unc);
+#pragma unroll
+        for (int i = 0; i < kNV; ++i) {
+            if (v[i] < 0) act[i] = unc[i] = false;
+            if (leader && act[i]) {
+                wcol[v[i]] = nc[i];
+                if (opt) wcol8[v[i]] = (uint8_t)nc[i];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < kNV; ++i) queue_push((KIND == kAssignSweep ? unc[i] : act[i]) && leader, v[i], q, qn);
+        __syncthreads();
+        if (*qn > kQueueCap - kVpb) queue_flush(q, qn, qbase, &sp->cnt_out[kBinThread], out);
+    }
+    queue_flush(q, qn, qbase, &sp->cnt_out[kBinThread], out);
+}
+
+template <int TIE, int KIND>
+__device__ __forceinline__ void pool_wave_task(PoolSlot *sp, const PoolSlot &s, const PoolTask &tk, uint32_t *lds) {
+    constexpr int PHASE = KIND == kAssignSweep ? kAssign : kRecolor;
+    constexpr bool kWinOnly = KIND == kAssignSweep;
+    const int wv = threadIdx.x / kWave;
+    uint32_t *bm = lds + wv * kWaveWindowWords;
+    const bool opt = s.mode == kOptimistic;
+    const int32_t *in = (KIND == kRecolorList) ? (s.parity ? s.wl[1] : s.wl[0]) + s.offW : s.hubW;
+    int32_t *out = (s.parity ? s.wl[0] : s.wl[1]) + s.offW;
+    for (int i = tk.begin + wv; i < tk.end; i += kWavesPerBlock) {
+        const int v = in[i];
+        const int b = s.rp[v], e = s.rp[v + 1];
+        int nc = 0;
+        bool unc = false;
+        const bool act = wave_vertex<PHASE, TIE, kWinOnly>(v, b, e, gro(s.ci), gro(s.col), bm, s.look, nc, unc);
+        if (lane_id() == 0) {
+            if (act) {
+                (opt ? s.col : s.pend)[v] = nc;
+                if (opt) s.col8[v] = shadow_of(nc);
+            }
+            if (KIND == kAssignSweep ? unc : act) out[atomicAdd(&sp->cnt_out[kBinWave], 1)] = v;
+        }
+    }
+}
+
+template <int TIE, int KIND>
+__device__ __forceinline__ void pool_block_task(PoolSlot *sp, const PoolSlot &s, const PoolTask &tk, uint32_t *lds,
+                                                int *sh_min) {
+    constexpr int PHASE = KIND == kAssignSweep ? kAssign : kRecolor;
+    constexpr bool kWinOnly = KIND == kAssignSweep;
+    const bool opt = s.mode == kOptimistic;
+    const int32_t *in = (KIND == kRecolorList) ? (s.parity ? s.wl[1] : s.wl[0]) + s.offB : s.hubB;
+    int32_t *out = (s.parity ? s.wl[0] : s.wl[1]) + s.offB;
+    for (int i = tk.begin; i < tk.end; ++i) {
+        const int v = in[i];
+        const int b = s.rp[v], e = s.rp[v + 1];
+        int nc = 0;
+        bool unc = false;
+        const bool act = block_vertex<PHASE, TIE, kWinOnly>(v, b, e, gro(s.ci), gro(s.col), lds, sh_min, s.look, nc,
+                                                              unc);
+        if (threadIdx.x == 0) {
+            if (act) {
+                (opt ? s.col : s.pend)[v] = nc;
+                if (opt) s.col8[v] = shadow_of(nc);
+            }
+            if (KIND == kAssignSweep ? unc : act) out[atomicAdd(&sp->cnt_out[kBinBlock], 1)] = v;
+        }
+    }
+}
+
+// One fused pool round.  Blocks [0,gB) take workgroup-bin tasks, [gB,gB+gW)
+// wavefront-bin tasks, the rest thread-bin tasks (grid-stride over each).
+__global__ __launch_bounds__(kBlock) void k_pstep(PoolSlot *slots, const PoolTask *__restrict__ tasks, int ntB,
+                                                  int ntW, int ntT, int gB, int gW, int gT) {
+    __shared__ uint32_t lds[kLdsWords];
+    __shared__ int q[kQueueCap];
+    __shared__ int sh_min, qn, qbase;
+    const int bid = blockIdx.x;
+    if (threadIdx.x == 0) qn = 0;
+    __syncthreads();
+    int first, count, stride, self;
+    if (bid < gB) { first = 0; count = ntB; stride = gB; self = bid; }
+    else if (bid < gB + gW) { first = ntB; count = ntW; stride = gW; self = bid - gB; }
+    else { first = ntB + ntW; count = ntT; stride = gT; self = bid - gB - gW; }
+    for (int t = self; t < count; t += stride) {
+        const PoolTask tk = tasks[first + t];
+        PoolSlot *sp = slots + tk.slot;
+        const PoolSlot s = *sp;
+        const int sel = tk.kind * 2 + s.tie;
+        if (bid < gB) {
+            switch (sel) {
+                case 0: pool_block_task<kLowerKeeps, kAssignSweep>(sp, s, tk, lds, &sh_min); break;
+                case 1: pool_block_task<kHigherKeeps, kAssignSweep>(sp, s, tk, lds, &sh_min); break;
+                case 2: pool_block_task<kLowerKeeps, kRecolorSweep>(sp, s, tk, lds, &sh_min); break;
+                case 3: pool_block_task<kHigherKeeps, kRecolorSweep>(sp, s, tk, lds, &sh_min); break;
+                case 4: pool_block_task<kLowerKeeps, kRecolorList>(sp, s, tk, lds, &sh_min); break;
+                default: pool_block_task<kHigherKeeps, kRecolorList>(sp, s, tk, lds, &sh_min); break;
+            }
+        } else if (bid < gB + gW) {
+            switch (sel) {
+                case 0: pool_wave_task<kLowerKeeps, kAssignSweep>(sp, s, tk, lds); break;
+                case 1: pool_wave_task<kHigherKeeps, kAssignSweep>(sp, s, tk, lds); break;
+                case 2: pool_wave_task<kLowerKeeps, kRecolorSweep>(sp, s, tk, lds); break;
+                case 3: pool_wave_task<kHigherKeeps, kRecolorSweep>(sp, s, tk, lds); break;
+                case 4: pool_wave_task<kLowerKeeps, kRecolorList>(sp, s, tk, lds); break;
+                default: pool_wave_task<kHigherKeeps, kRecolorList>(sp, s, tk, lds); break;
+            }
+        } else {
+            switch (sel) {
+                case 0: pool_thread_task<kLowerKeeps, kAssignSweep>(sp, s, tk, q, &qn, &qbase); break;
+                case 1: pool_thread_task<kHigherKeeps, kAssignSweep>(sp, s, tk, q, &qn, &qbase); break;
+                case 2: pool_thread_task<kLowerKeeps, kRecolorSweep>(sp, s, tk, q, &qn, &qbase); break;
+                case 3: pool_thread_task<kHigherKeeps, kRecolorSweep>(sp, s, tk, q, &qn, &qbase); break;
+                case 4: pool_thread_task<kLowerKeeps, kRecolorList>(sp, s, tk, q, &qn, &qbase); break;
+                default: pool_thread_task<kHigherKeeps, kRecolorList>(sp, s, tk, q, &qn, &qbase); break;
+            }
+        }
+    }
+}
+
+// Round-synchronous slots publish their staged colours (col = pend for L).
+__global__ __launch_bounds__(kBlock) void k_pscatter(PoolSlot *slots, const int32_t *__restrict__ active, int nact) {
+    for (int k = blockIdx.y; k < nact; k += gridDim.y) {
+        PoolSlot *sp = slots + active[k];
+        if (sp->mode == kOptimistic) continue;
+        const int32_t *lst = sp->wl[sp->parity ^ 1];
+        for (int bin = 0; bin < 3; ++bin) {
+            const int c = sp->cnt_out[bin];
+            const int off = bin == 0 ? 0 : (bin == 1 ? sp->offW : sp->offB);
+            for (int i = blockIdx.x * kBlock + threadIdx.x; i < c; i += gridDim.x * kBlock) {
+                const int v = lst[off + i];
+                const int cc = sp->pend[v];
+                sp->col[v] = cc;
+                sp->col8[v] = shadow_of(cc);
+            }
+        }
+    }
+}
+
+// Per-slot round end: counts the pass, publishes the appended list, flips the
+// worklist parity, and marks the slot done when its worklist is empty (or
+// the pass bound is reached).
+__global__ void k_pround_end(PoolSlot *slots, const int32_t *__restrict__ active, int nact) {
+    for (int k = threadIdx.x; k < nact; k += blockDim.x) {
+        PoolSlot *sp = slots + active[k];
+        const int out_total = sp->cnt_out[0] + sp->cnt_out[1] + sp->cnt_out[2];
+        const bool round0 = sp->phase == kSlotNew && sp->mode == kOptimistic;
+        if (round0) {
+            sp->u0 = out_total;
+        } else {
+            sp->passes += 1;
+            if (out_total > 0) {
+                sp->rounds += 1;
+                sp->conflicts += out_total;
+            }
+        }
+        for (int b = 0; b < 3; ++b) {
+            sp->cnt_in[b] = sp->cnt_out[b];
+            sp->cnt_out[b] = 0;
+        }
+        sp->parity ^= 1;
+        sp->phase = kSlotRunning;
+        if (out_total == 0) {
+            sp->phase = kSlotDone;
+        } else if (!round0 && sp->passes >= sp->max_rounds) {
+            sp->phase = kSlotDone;
+            sp->status = -7;  // RSOC_ENOCONV
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_pcount(PoolSlot *slots, int slot) {
+    __shared__ int sh[kWavesPerBlock];
+    PoolSlot *sp = slots + slot;
+    int m = -1;
+    bool bad = false;
+    for (int v = blockIdx.x * kBlock + threadIdx.x; v < sp->n; v += gridDim.x * kBlock) {
+        const int c = sp->col[v];
+        bad |= (c < 0 || c >= sp->n);
+        m = max(m, c);
+    }
+    if (ballot(bad) && lane_id() == 0) atomicOr(&sp->err, 4);
+    m = block_max(m, sh);
+    if (threadIdx.x == 0) atomicMax(&sp->kmax, m + 1);
+}
+
+}  // namespace rsoc

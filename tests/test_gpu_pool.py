@@ -1,0 +1,117 @@
+"""Continuous-batching pool on the GPU: graphs admitted at different times and
+coloured by shared fused rounds must come out as they do alone (round-
+synchronous mode: identical to the oracle; optimistic: valid)."""
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx(lib):
+    c = lib.Context(0)
+    yield c
+    c.close()
+
+
+def _dev(rp, ci):
+    import torch
+    d = torch.device("cuda:0")
+    n = len(rp) - 1
+    return (torch.from_numpy(np.ascontiguousarray(rp)).to(d),
+            torch.from_numpy(np.ascontiguousarray(ci) if len(ci) else np.zeros(1, np.int32)).to(d),
+            torch.full((max(n, 1),), -5, dtype=torch.int32, device=d), n)
+
+
+GRAPHS = [gg.path(9), gg.cycle(7), gg.complete(30), gg.star(500), gg.tri_grid(40, 23), gg.tri_grid(31, 31, permute_seed=8),
+          gg.rmat(11, 8, seed=9, shuffle_seed=10), gg.rgg(4000, seed=11), (np.zeros(1, np.int32), np.zeros(0, np.int32)),
+          gg.complete_bipartite(33, 65), gg.grid4(50, 20)]
+MODES = [("deterministic", "lower"), ("optimistic", "lower"), ("deterministic", "higher"), ("optimistic", "higher")]
+
+
+def _check(lib, g, mode, tie, col, k):
+    rp, ci = GRAPHS[g]
+    n = len(rp) - 1
+    got = col.cpu().numpy()[:n]
+    if mode == "deterministic":
+        want = oracle.rsync(rp, ci, tie=tie)
+        assert np.array_equal(got, want["colors"]) and k == want["K"], (g, mode, tie)
+    else:
+        assert oracle.check(rp, ci, got) == 0 and k == oracle.colour_count(got), (g, mode, tie)
+
+
+@pytest.mark.parametrize("split", [{}, {"t_thread": 3, "t_wave": 8}])
+def test_pool_staggered_admission(lib, ctx, split):
+    pool = lib.Pool(ctx, 0, 64)
+    pending = [(g, MODES[(g + i) % 4]) for i in range(2) for g in range(len(GRAPHS))]
+    live = {}
+    done = 0
+    steps = 0
+    while pending or live:
+        # admit two new graphs per step while older ones are mid-way
+        for _ in range(2):
+            if pending:
+                g, (mode, tie) = pending.pop(0)
+                d_rp, d_ci, d_col, n = _dev(*GRAPHS[g])
+                slot = pool.admit(d_rp, d_ci, n, d_col, lib.make_options(mode, tie, **split))
+                live[slot] = (g, mode, tie, d_rp, d_ci, d_col)
+        for slot in pool.step():
+            g, mode, tie, d_rp, d_ci, d_col = live.pop(slot)
+            k, st = pool.result(slot)
+            _check(lib, g, mode, tie, d_col, k)
+            done += 1
+        steps += 1
+        assert steps < 5000
+    assert done == 2 * len(GRAPHS) and pool.live() == 0 and pool.reserved_bytes() == 0
+    pool.close()
+
+
+def test_pool_budget_and_slots(lib, ctx):
+    rp, ci = gg.tri_grid(64, 64)
+    n = len(rp) - 1
+    per = 4 * (((4 * (n + 1) + 255) // 256) * 256) + ((n + 64 + 255) // 256) * 256  # optimistic slot scratch
+    pool = lib.Pool(ctx, per + per // 2, 8)
+    a = _dev(rp, ci)
+    b = _dev(rp, ci)
+    s0 = pool.admit(a[0], a[1], n, a[2])
+    assert pool.reserved_bytes() == per
+    assert pool.try_admit(b[0], b[1], n, b[2]) == lib.RSOC_EBUDGET  # does not fit next to the first
+    fin = []
+    while not fin:
+        fin = pool.step()
+    assert fin == [s0]
+    k, st = pool.result(s0)
+    _check_valid = oracle.check(rp, ci, a[2].cpu().numpy())
+    assert _check_valid == 0
+    assert pool.reserved_bytes() == 0
+    s1 = pool.admit(b[0], b[1], n, b[2])  # fits once the first is released
+    while not pool.step():
+        pass
+    pool.result(s1)
+    with pytest.raises(lib.RsocError) as e:
+        pool.result(s1)
+    assert e.value.code == lib.RSOC_ENOTFOUND
+    pool.close()
+    small = lib.Pool(ctx, 0, 2)
+    p, q, r = _dev(*gg.path(5)), _dev(*gg.path(5)), _dev(*gg.path(5))
+    small.admit(p[0], p[1], 5, p[2])
+    small.admit(q[0], q[1], 5, q[2])
+    assert small.try_admit(r[0], r[1], 5, r[2]) == lib.RSOC_EBUDGET  # slot table full
+    small.close()
+
+
+def test_pool_max_rounds_guard(lib, ctx):
+    pool = lib.Pool(ctx, 0, 4)
+    d = _dev(*gg.path(6))
+    slot = pool.admit(d[0], d[1], 6, d[2], lib.make_options("deterministic", max_rounds=2))
+    while not pool.step():
+        pass
+    with pytest.raises(lib.RsocError) as e:
+        pool.result(slot)
+    assert e.value.code == lib.RSOC_ENOCONV
+    want = oracle.rsync(*gg.path(6), max_rounds=2, raise_on_noconv=False)
+    assert np.array_equal(d[2].cpu().numpy()[:6], want["colors"])
+    pool.close()
