@@ -162,6 +162,7 @@ def bench_single(args):
                    "max_degree": st["max_degree"]},
         "colors": st["colors"],
         "colors_distinct": st["colors_distinct"],
+        "chunk": st["chunk"],
         "rounds": st["rounds"],
         "conflicts": st["conflicts"],
         "worklist0": st["worklist0"],
@@ -205,6 +206,265 @@ def bench_single(args):
     return out
 
 
+def _pinned(a):
+    import torch
+    return torch.from_numpy(a).pin_memory()
+
+
+def bench_batched(args):
+    """Config: many independent grids / random geometric graphs in one batch;
+    batched fused launches vs one call per graph on the same device-resident data."""
+    import numpy as np
+    import torch
+
+    import graphgen as gg
+    import oracle
+    import paper_1505_04086_amd as rsoc
+
+    dev = torch.device("cuda:0")
+    t = time.perf_counter()
+    b = gg.batch(args.batch_graphs, seed=args.seed, nmin=1e3, nmax=1e6, mean_degree=12.0)
+    G = args.batch_graphs
+    vo, no = b["vtx_off"], b["nnz_off"]
+    E = int(no[-1]) // 2
+    print("[bench] batch of %d graphs: %d vertices, %d edges (generated in %.1f s)"
+          % (G, int(vo[-1]), E, time.perf_counter() - t), file=sys.stderr, flush=True)
+    d_rp = torch.from_numpy(b["row_ptr_cat"]).to(dev)
+    d_ci = torch.from_numpy(b["col_idx_cat"]).to(dev)
+    d_col = torch.empty(int(vo[-1]), dtype=torch.int32, device=dev)
+    torch.cuda.synchronize()
+    ctx = rsoc.Context(0)
+    stream = torch.cuda.current_stream()
+    tune_info = None
+    if args.tune:
+        # autotune on a smaller batch drawn from the same distribution (another seed)
+        from paper_1505_04086_amd import tune
+        tb = gg.batch(args.tune_graphs, seed=args.seed + 1, nmin=1e3, nmax=1e6, mean_degree=12.0)
+        t_rp = torch.from_numpy(tb["row_ptr_cat"]).to(dev)
+        t_ci = torch.from_numpy(tb["col_idx_cat"]).to(dev)
+        t_col = torch.empty(int(tb["vtx_off"][-1]), dtype=torch.int32, device=dev)
+        tt = time.perf_counter()
+        space = {k: tune.SPACE[k] for k in ("chunk", "grid_thread", "t_thread", "lookahead", "rounds_per_sync")}
+        best, best_t, trials = tune.coordinate_descent(
+            lambda o: tune._timer(lambda: rsoc.rsoc_color_batch(ctx, tb["vtx_off"], tb["nnz_off"], t_rp, t_ci, t_col,
+                                                                rsoc.make_options(args.mode, **o)), 3),
+            space=space, sweeps=1)
+        args.tuned = best
+        tune_info = {"graphs": args.tune_graphs, "seconds": time.perf_counter() - tt, "trials": len(trials),
+                     "best_ms": best_t * 1e3, "default_ms": trials[0][1] * 1e3, "options": best}
+        print("[bench] tuned %s" % json.dumps(tune_info), file=sys.stderr, flush=True)
+        del t_rp, t_ci, t_col
+    opts = rsoc.make_options(args.mode, "lower", timing=1, **(args.tuned or {}))
+    for _ in range(args.warmup):
+        rsoc.rsoc_color_batch(ctx, vo, no, d_rp, d_ci, d_col, opts, stream=stream)
+    torch.cuda.synchronize()
+    stats = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        counts, kmax, st = rsoc.rsoc_color_batch(ctx, vo, no, d_rp, d_ci, d_col, opts, stream=stream)
+        stats.append(st)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    col = d_col.cpu().numpy()
+    # validity of every graph (oracle checker on the host)
+    bad = 0
+    for g in range(G):
+        rp, ci = gg.batch_member(b, g)
+        bad += oracle.check(rp, ci, col[int(vo[g]):int(vo[g + 1])]) != 0
+    if bad:
+        raise SystemExit("bench: %d invalid graphs in the batch" % bad)
+    # plain form: one rsoc_color_device call per graph, same device-resident data
+    plain_opts = rsoc.make_options(args.mode, "lower")
+    rp_off = vo + np.arange(G + 1)
+
+    def plain_pass():
+        for g in range(G):
+            n = int(vo[g + 1] - vo[g])
+            rsoc.rsoc_color_device(ctx, d_rp[int(rp_off[g]):int(rp_off[g]) + n + 1], d_ci[int(no[g]):int(no[g + 1])],
+                                   n, d_col[int(vo[g]):int(vo[g + 1])], plain_opts, stream=stream)
+
+    plain_pass()
+    torch.cuda.synchronize()
+    tp = time.perf_counter()
+    for _ in range(args.plain_reps):
+        plain_pass()
+    torch.cuda.synchronize()
+    tp = (time.perf_counter() - tp) / args.plain_reps
+    st = stats[-1]
+    kms = float(np.mean([x["ms_round0"] for x in stats]))
+    kbytes = st["bytes_round0"]
+    achieved = kbytes / (kms * 1e-3) / 1e9 if kms > 0 else None
+    value = E * args.steps / elapsed / 1e9
+    out = {
+        "metric": "edges colored/s (GE/s) + colors used; batched vs plain",
+        "value": value, "unit": "GE/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": "batch of %d triangulated grids / random geometric graphs, 1e3..1e6 vertices "
+                               "log-uniform, mean degree 12 (seed %d)" % (G, args.seed),
+                   "graphs": G, "vertices": int(vo[-1]), "edges": E, "nnz": int(no[-1]), "mode": args.mode,
+                   "tuned": args.tuned or {}},
+        "colors_max": int(kmax), "rounds": st["rounds"], "conflicts": st["conflicts"], "chunk": st["chunk"],
+        "autotune": tune_info,
+        "plain": {"GEps": E / tp / 1e9, "ms_per_pass": tp * 1e3, "calls_per_pass": G},
+        "batched_over_plain": value / (E / tp / 1e9),
+        "roofline": {"bound": "hbm", "kernel": "batched_round0_first_fit", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": None if achieved is None else achieved / HBM_PEAK_GBS,
+                     "traffic": load_traffic("batched", "batched_round0_first_fit"), "kernel_ms": kms,
+                     "alg_bytes_per_launch": kbytes},
+    }
+    ctx.close()
+    return out
+
+
+def make_requests(N: int, seed: int):
+    """Served workload: sizes log-uniform in [1e4, 4e6] vertices; 35% 2D
+    triangulated grids (natural ids), 35% 3D 26-stencil lattices (ids
+    permuted), 30% R-MAT scale 14..20, edge factor 16 (ids shuffled)."""
+    import concurrent.futures as cf
+
+    import numpy as np
+
+    import graphgen as gg
+    rng = np.random.default_rng(seed)
+    specs = []
+    for i in range(N):
+        u = rng.random()
+        n = float(np.exp(rng.uniform(np.log(1e4), np.log(4e6))))
+        if u < 0.35:
+            specs.append(("mesh2d", max(2, int(round(np.sqrt(n)))), i))
+        elif u < 0.70:
+            specs.append(("mesh3d", max(2, int(round(n ** (1 / 3)))), i))
+        else:
+            specs.append(("rmat", int(rng.integers(14, 21)), i))
+
+    def gen(sp):
+        kind, p, i = sp
+        if kind == "mesh2d":
+            return gg.tri_grid(p)
+        if kind == "mesh3d":
+            return gg.lattice26(p, permute_seed=seed * 1000 + i)
+        return gg.rmat(p, 16, seed=seed * 1000 + i, shuffle_seed=seed * 1000 + i + 7)
+
+    with cf.ThreadPoolExecutor(8) as ex:
+        graphs = list(ex.map(gen, specs))
+    return specs, graphs
+
+
+def _lat_ms(lat):
+    import numpy as np
+    lat = np.asarray(lat)
+    return {"p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+            "mean_ms": float(lat.mean() * 1e3), "max_ms": float(lat.max() * 1e3)}
+
+
+def bench_served(args):
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_1505_04086_amd as rsoc
+    from paper_1505_04086_amd import serve
+
+    t = time.perf_counter()
+    specs, graphs = make_requests(args.requests, args.seed)
+    E_tot = sum(len(ci) // 2 for _, ci in graphs)
+    V_tot = sum(len(rp) - 1 for rp, _ in graphs)
+    dev = torch.device("cuda:0")
+    # the timed runs start with every request's CSR resident in HBM; the
+    # PCIe-inclusive variant (host arrays copied in, colours copied out) is
+    # measured once at saturation beside it
+    resident = [(torch.from_numpy(rp).to(dev), torch.from_numpy(ci if len(ci) else np.zeros(1, np.int32)).to(dev))
+                for rp, ci in graphs]
+    torch.cuda.synchronize()
+    print("[bench] %d requests: %d vertices, %d edges (generated in %.1f s)"
+          % (len(graphs), V_tot, E_tot, time.perf_counter() - t), file=sys.stderr, flush=True)
+    ctx = rsoc.Context(0)
+    opts = rsoc.make_options(args.mode, "lower")
+    src = {"resident": resident}
+
+    def reqs(arrivals, kind="resident"):
+        data = src[kind]
+        return [serve.Request(i, data[i][0], data[i][1], float(arrivals[i]), options=opts)
+                for i in range(len(graphs))]
+
+    zero = np.zeros(len(graphs))
+    # warm both paths (graph capture, allocator)
+    serve.PlainServer(ctx, opts).run(reqs(zero)[:4])
+    sv = serve.Server(ctx, args.hbm_budget, options=opts)
+    sv.run(reqs(zero)[:4])
+    sv.close()
+
+    def run_plain(arr):
+        t0 = time.monotonic()
+        out = serve.PlainServer(ctx, opts).run(reqs(arr), clock0=t0)
+        return out, max(r.done for r in out) - t0
+
+    def run_served(arr):
+        s = serve.Server(ctx, args.hbm_budget, options=opts)
+        t0 = time.monotonic()
+        out = s.run(reqs(arr), clock0=t0)
+        steps = s.steps
+        s.close()
+        return out, max(r.done for r in out) - t0, steps
+
+    plain_out, plain_span = run_plain(zero)
+    served_out, served_span, served_steps = run_served(zero)
+    print("[bench] saturation: plain %.3f s, served %.3f s (%d steps)" % (plain_span, served_span, served_steps),
+          file=sys.stderr, flush=True)
+    for r in served_out:
+        rp, ci = graphs[r.rid]
+        if r.k < 0 or oracle.check(rp, ci, r.colors.cpu().numpy()) != 0:
+            raise SystemExit("bench: invalid served colouring for request %d" % r.rid)
+    served_out = [dict(rid=r.rid, latency=r.latency, k=r.k) for r in served_out]  # drop result tensors
+    # PCIe-inclusive variant at saturation (pinned host arrays)
+    src["host"] = [(_pinned(rp), _pinned(ci)) for rp, ci in graphs]
+    t0 = time.monotonic()
+    h_plain = serve.PlainServer(ctx, opts).run(reqs(zero, "host"), clock0=t0)
+    h_plain_span = max(r.done for r in h_plain) - t0
+    hs = serve.Server(ctx, args.hbm_budget, options=opts)
+    t0 = time.monotonic()
+    h_served = hs.run(reqs(zero, "host"), clock0=t0)
+    h_served_span = max(r.done for r in h_served) - t0
+    hs.close()
+    del src["host"], h_plain, h_served
+    cap_rps = len(graphs) / plain_span
+    rates = {}
+    rng = np.random.default_rng(args.seed + 99)
+    for f in args.rate_factors:
+        lam = f * cap_rps
+        arr = np.cumsum(rng.exponential(1.0 / lam, size=len(graphs)))
+        arr -= arr[0]
+        po, pspan = run_plain(arr)
+        so, sspan, _ = run_served(arr)
+        rates["%.2gx" % f] = {"rate_rps": lam, "plain": dict(serve.latency_summary(po), GEps=E_tot / pspan / 1e9),
+                              "served": dict(serve.latency_summary(so), GEps=E_tot / sspan / 1e9)}
+        print("[bench] rate %.2gx: %s" % (f, json.dumps(rates["%.2gx" % f])), file=sys.stderr, flush=True)
+    value = E_tot / served_span / 1e9
+    plain_ge = E_tot / plain_span / 1e9
+    out = {
+        "metric": "edges colored/s (GE/s) + colors used; served vs plain, p50/p99 latency",
+        "value": value, "unit": "GE/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": served_span * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int32", "data": "synthetic",
+        "config": {"workload": "%d requests, sizes 1e4..4e6 log-uniform; 35%% 2D grids, 35%% 3D lattices, 30%% R-MAT "
+                               "scale 14..20 (seed %d)" % (len(graphs), args.seed),
+                   "requests": len(graphs), "vertices": V_tot, "edges": E_tot, "mode": args.mode,
+                   "hbm_budget": args.hbm_budget},
+        "saturation": {"served_GEps": value, "plain_GEps": plain_ge, "served_over_plain": value / plain_ge,
+                       "served_steps": served_steps,
+                       "served_latency": _lat_ms([r["latency"] for r in served_out]),
+                       "plain_latency": serve.latency_summary(plain_out)},
+        "pcie_inclusive_saturation": {"served_GEps": E_tot / h_served_span / 1e9,
+                                      "plain_GEps": E_tot / h_plain_span / 1e9,
+                                      "served_over_plain": h_plain_span / h_served_span},
+        "poisson": rates,
+        "colors_max": int(max(r["k"] for r in served_out)),
+    }
+    ctx.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -216,14 +476,36 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--det-too", action="store_true", help="also time deterministic mode once")
+    ap.add_argument("--batch-graphs", type=int, default=4096)
+    ap.add_argument("--plain-reps", type=int, default=1)
+    ap.add_argument("--requests", type=int, default=160)
+    ap.add_argument("--hbm-budget", type=int, default=16 << 30)
+    ap.add_argument("--rate-factors", type=float, nargs="*", default=[0.5, 1.0, 2.0])
+    ap.add_argument("--tune", action="store_true", help="autotune launch options first (batched workload)")
+    ap.add_argument("--tune-graphs", type=int, default=256)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 1 GiB device copy (calibrates rocprofv3 FETCH_SIZE/WRITE_SIZE)")
     args = ap.parse_args()
+    args.tuned = None
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build measures one GPU only (--gpus 1); multi-GPU runs are not supported",
               file=sys.stderr)
         sys.exit(2)
-    if args.workload in ("batched", "served"):
-        raise SystemExit("bench.py: workload %s not available yet" % args.workload)
-    out = bench_single(args)
+    if args.copy_probe:
+        import torch
+        x = torch.ones(1 << 28, dtype=torch.int32, device="cuda:0")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": x.numel() * 4, "launches": 3}), flush=True)
+        return
+    if args.workload == "batched":
+        out = bench_batched(args)
+    elif args.workload == "served":
+        out = bench_served(args)
+    else:
+        out = bench_single(args)
     print(json.dumps(out), flush=True)
 
 

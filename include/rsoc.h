@@ -102,10 +102,15 @@ typedef struct {
     int32_t full_sweep;
     /* Optimistic default flow: round 0 also reads neighbours it wins against
      * whose id is within this distance (the sweep may have coloured them
-     * already).  0 = library default (16 times the ids one round-0 step covers),
+     * already).  0 = library default (twice the ids all workgroups cover in one step),
      * -1 = none. */
     int32_t lookahead;
-    int32_t reserved[3]; /* must be zero */
+    /* Run of consecutive vertex ids one 8-lane group colours one after the
+     * other in sweeps (1, 2, 4 or 8).  0 = chosen per graph from a sample of
+     * its rows: 8 when ids carry locality (natural-order meshes, where
+     * neighbours coloured at the same instant would conflict), else 1. */
+    int32_t chunk;
+    int32_t reserved[2]; /* must be zero */
 } rsoc_options;
 
 typedef struct {
@@ -126,7 +131,8 @@ typedef struct {
     int32_t *per_round_L;    /* optional caller array: per_round_L[i] = |L| of recolouring round i+1 */
     int32_t per_round_cap;   /* its length */
     int32_t worklist0;       /* |U^0|: vertices round 1 inspects */
-    int32_t reserved[4];
+    int32_t chunk;           /* run length used by the sweeps */
+    int32_t reserved[3];
 } rsoc_stats;
 
 typedef struct rsoc_ctx rsoc_ctx;

@@ -61,7 +61,7 @@ class rsoc_options(ctypes.Structure):
                 ("grid_thread", ctypes.c_int32), ("grid_wave", ctypes.c_int32),
                 ("rounds_per_sync", ctypes.c_int32), ("small_cutoff", ctypes.c_int32),
                 ("timing", ctypes.c_int32), ("full_sweep", ctypes.c_int32), ("lookahead", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 3)]
+                ("chunk", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
 
 
 class rsoc_stats(ctypes.Structure):
@@ -71,7 +71,7 @@ class rsoc_stats(ctypes.Structure):
                 ("ms_round1", ctypes.c_double), ("bytes_round0", ctypes.c_int64), ("bytes_round1", ctypes.c_int64),
                 ("max_degree", ctypes.c_int32), ("bin_counts", ctypes.c_int32 * 3),
                 ("per_round_L", ctypes.POINTER(ctypes.c_int32)), ("per_round_cap", ctypes.c_int32),
-                ("worklist0", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+                ("worklist0", ctypes.c_int32), ("chunk", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 _p = ctypes.c_void_p

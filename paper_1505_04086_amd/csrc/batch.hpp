@@ -62,7 +62,8 @@ inline int32_t get_batch_graph(rsoc_ctx *c, int mode, int tie, int K, int gB, in
 }
 
 template <int MODE, int TIE>
-inline void launch_bsweep(rsoc_ctx *c, hipStream_t s, int64_t nV, int gB, int gW, int gT, bool full_sweep) {
+inline void launch_bsweep(rsoc_ctx *c, hipStream_t s, int64_t nV, int gB, int gW, int gT, bool full_sweep,
+                          bool timing) {
     const BatchArgs *A = c->b_args.as<BatchArgs>();
     SingleState *S = c->b_state.as<SingleState>();
     const int grid = gB + gW + gT;
@@ -74,12 +75,15 @@ inline void launch_bsweep(rsoc_ctx *c, hipStream_t s, int64_t nV, int gB, int gW
     } else {
         k_fill<<<fill_grid, kBlock, 0, s>>>(col, col8, nV, -1);
         if (MODE == kOptimistic) {
+            if (timing) (void)hipEventRecord(c->ev[2], s);
             if (!full_sweep) {
                 k_bround<kAssign, kOptimistic, TIE, true, 1><<<grid, kBlock, 0, s>>>(A, S, 1, gB, gW, gT);
+                if (timing) (void)hipEventRecord(c->ev[3], s);
                 k_bround_end<MODE, true, true><<<1, 64, 0, s>>>(A, S);
                 return;
             }
             k_bround<kAssign, kOptimistic, TIE, true, 0><<<grid, kBlock, 0, s>>>(A, S, 1, gB, gW, gT);
+            if (timing) (void)hipEventRecord(c->ev[3], s);
         }
     }
     if (MODE == kTwoPhase) {
@@ -94,16 +98,16 @@ inline void launch_bsweep(rsoc_ctx *c, hipStream_t s, int64_t nV, int gB, int gW
 }
 
 inline void launch_bsweep_dyn(rsoc_ctx *c, hipStream_t s, int mode, int tie, int64_t nV, int gB, int gW, int gT,
-                              bool full) {
+                              bool full, bool timing) {
     if (mode == kOptimistic)
-        tie ? launch_bsweep<kOptimistic, kHigherKeeps>(c, s, nV, gB, gW, gT, full)
-            : launch_bsweep<kOptimistic, kLowerKeeps>(c, s, nV, gB, gW, gT, full);
+        tie ? launch_bsweep<kOptimistic, kHigherKeeps>(c, s, nV, gB, gW, gT, full, timing)
+            : launch_bsweep<kOptimistic, kLowerKeeps>(c, s, nV, gB, gW, gT, full, timing);
     else if (mode == kDeterministic)
-        tie ? launch_bsweep<kDeterministic, kHigherKeeps>(c, s, nV, gB, gW, gT, full)
-            : launch_bsweep<kDeterministic, kLowerKeeps>(c, s, nV, gB, gW, gT, full);
+        tie ? launch_bsweep<kDeterministic, kHigherKeeps>(c, s, nV, gB, gW, gT, full, timing)
+            : launch_bsweep<kDeterministic, kLowerKeeps>(c, s, nV, gB, gW, gT, full, timing);
     else
-        tie ? launch_bsweep<kTwoPhase, kHigherKeeps>(c, s, nV, gB, gW, gT, full)
-            : launch_bsweep<kTwoPhase, kLowerKeeps>(c, s, nV, gB, gW, gT, full);
+        tie ? launch_bsweep<kTwoPhase, kHigherKeeps>(c, s, nV, gB, gW, gT, full, timing)
+            : launch_bsweep<kTwoPhase, kLowerKeeps>(c, s, nV, gB, gW, gT, full, timing);
 }
 
 struct BatchHost {
@@ -181,6 +185,7 @@ inline int32_t run_batch(rsoc_ctx *c, int32_t G, const int64_t *vtx_off, const i
     a.t_wave = o.t_wave;
     a.max_rounds = o.max_rounds;
     a.look = 0;
+    a.chunk = 1;
     SingleState *S = c->b_state.as<SingleState>();
     RSOC_HIP(hipMemcpyAsync(c->b_args.p, &a, sizeof(a), hipMemcpyHostToDevice, s));
     RSOC_HIP(hipMemsetAsync(S, 0, kStateHeader, s));
@@ -191,6 +196,10 @@ inline int32_t run_batch(rsoc_ctx *c, int32_t G, const int64_t *vtx_off, const i
         RSOC_LAUNCH_CHECK();
     }
     k_bbin<<<tgrid, kBlock, 0, s>>>(c->b_args.as<BatchArgs>(), S);
+    if (o.chunk == 0) {
+        const int ns = std::min(ntasks, 16384);
+        k_blocality<<<div_up(ns, kBlock), kBlock, 0, s>>>(c->b_args.as<BatchArgs>(), ns, S);
+    }
     RSOC_LAUNCH_CHECK();
     RSOC_HIP(hipMemcpyAsync(&h->head, S, kStateHeader, hipMemcpyDeviceToHost, s));
     RSOC_HIP(hipStreamSynchronize(s));
@@ -199,21 +208,22 @@ inline int32_t run_batch(rsoc_ctx *c, int32_t G, const int64_t *vtx_off, const i
     const int64_t nT = nV - nW - nB;
     a.offW = nT;
     a.offB = nT + nW;
-    constexpr int kVpb = 2 * kBlock / kGroup;
     const int gB = std::min(nB, 1024);
     const int gW = std::min(div_up(nW, kWavesPerBlock), o.grid_wave);
     const int gTs = std::max(1, std::min(ntasks, o.grid_thread));
-    const int64_t look = o.lookahead == -1 ? 0 : (o.lookahead > 0 ? o.lookahead : 16ll * gTs * kVpb);
+    const int64_t look = o.lookahead == -1 ? 0 : (o.lookahead > 0 ? o.lookahead : 2ll * gTs * kStep);
     a.look = (int)std::min<int64_t>(look, INT32_MAX);
+    a.chunk = pick_chunk(o.chunk, h->head.near, h->head.sampled);
     RSOC_HIP(hipMemcpyAsync(c->b_args.p, &a, sizeof(a), hipMemcpyHostToDevice, s));
     const int gBl = std::min(nB, 256);
     const int gWl = std::min(div_up(nW, kWavesPerBlock), o.grid_wave);
-    const int gTl = (int)std::max<int64_t>(1, std::min<int64_t>(div_up(nT, kVpb), o.grid_thread));
+    const int gTl = (int)std::max<int64_t>(1, std::min<int64_t>(div_up(nT, kStep), o.grid_thread));
     hipGraphExec_t gexec = nullptr;
     RSOC_TRY(get_batch_graph(c, o.mode, o.tie, o.rounds_per_sync, gBl, gWl, gTl, &gexec));
 
     RSOC_HIP(hipEventRecord(c->ev[0], s));
-    launch_bsweep_dyn(c, s, o.mode, o.tie, nV, gB, gW, gTs, o.full_sweep != 0);
+    const bool timing = o.timing && o.mode == kOptimistic;
+    launch_bsweep_dyn(c, s, o.mode, o.tie, nV, gB, gW, gTs, o.full_sweep != 0, timing);
     RSOC_LAUNCH_CHECK();
     int32_t status = RSOC_OK;
     for (;;) {
@@ -255,9 +265,23 @@ inline int32_t run_batch(rsoc_ctx *c, int32_t G, const int64_t *vtx_off, const i
         st->bin_counts[1] = nW;
         st->bin_counts[2] = nB;
         st->worklist0 = h->head.u0;
+        st->chunk = a.chunk;
         float ms = 0;
         RSOC_HIP(hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
         st->ms = ms;
+        const int64_t nnzT = nnz_off[G];
+        if (timing) {
+            float m0 = 0;
+            RSOC_HIP(hipEventElapsedTime(&m0, c->ev[2], c->ev[3]));
+            st->ms_round0 = m0;
+        }
+        // round 0 (optimistic): task table 8/task, row_ptr 4(n+G), col_idx 4 nnz,
+        // colours of the neighbours a vertex loses to (4 nnz/2), colour
+        // writes 4n, hub lists 8(nW+nB), U^0 appends 8|U^0|
+        if (o.mode == kOptimistic)
+            st->bytes_round0 = 8 * (int64_t)ntasks + 4 * (nV + G) + 4 * nnzT +
+                               (o.full_sweep ? 4 * nnzT : 4 * (nnzT / 2)) + 4 * nV + 8 * (int64_t)(nW + nB) +
+                               (o.full_sweep ? 0 : 8 * (int64_t)h->head.u0);
     }
     if (status < 0) return status;
     return kmax;

@@ -14,7 +14,7 @@
 
 namespace rsoc {
 
-constexpr int kTaskLen = 512;  // vertices per sweep task
+constexpr int kTaskLen = kStep;  // vertices per sweep task (one workgroup step)
 
 struct BatchArgs {
     const int64_t *voff;  // [G+1] vertex offsets of the graphs
@@ -33,6 +33,8 @@ struct BatchArgs {
     int64_t offW, offB;   // worklist segment offsets
     int32_t G, ntasks;
     int32_t t_thread, t_wave, max_rounds, look;
+    int32_t chunk;        // run of consecutive ids one lane group walks
+    int32_t pad;
 };
 
 __device__ __forceinline__ int64_t pack_item(int g, int v) { return ((int64_t)g << 32) | (uint32_t)v; }
@@ -76,10 +78,35 @@ __device__ __forceinline__ void wave_append64(bool take, int64_t x, int *counter
 }
 
 // --------------------------------------------------------------- binning --
+__device__ __forceinline__ void queue_push64(bool take, int64_t x, int64_t *q, int *qn);
+
+// Flushes a workgroup queue into the static hub list (workgroup bin: written
+// from the back of the list).
+__device__ __forceinline__ void hub_flush(int64_t *q, int *qn, int *qbase, int *counter, int64_t *hub, bool from_back,
+                                          int64_t cap) {
+    __syncthreads();
+    const int cnt = *qn;
+    if (cnt == 0) return;
+    if (threadIdx.x == 0) *qbase = atomicAdd(counter, cnt);
+    __syncthreads();
+    const int base = *qbase;
+    for (int i = threadIdx.x; i < cnt; i += kBlock) {
+        const int64_t pos = base + i;
+        hub[from_back ? cap - 1 - pos : pos] = q[i];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) *qn = 0;
+    __syncthreads();
+}
+
 __global__ __launch_bounds__(kBlock) void k_bbin(const BatchArgs *__restrict__ A, SingleState *S) {
     __shared__ int sh[kWavesPerBlock];
+    __shared__ int64_t qW[kQueueCap / 2], qB[kQueueCap / 2];
+    __shared__ int nqW, nqB, qbase;
     const BatchArgs a = *A;
     int md = 0;
+    if (threadIdx.x == 0) nqW = nqB = 0;
+    __syncthreads();
     for (int t = blockIdx.x; t < a.ntasks; t += gridDim.x) {
         const int64_t task = a.tasks[t];
         const int g = item_graph(task), start = item_vertex(task);
@@ -90,13 +117,37 @@ __global__ __launch_bounds__(kBlock) void k_bbin(const BatchArgs *__restrict__ A
             int d = -1;
             if (v < end) d = w.rp[v + 1] - w.rp[v];
             md = max(md, d);
-            wave_append64(d > a.t_wave, pack_item(g, v), &S->nB, a.hub, true, a.hub_cap);
-            wave_append64(d > a.t_thread && d <= a.t_wave, pack_item(g, v), &S->nW, a.hub, false, a.hub_cap);
+            queue_push64(d > a.t_wave, pack_item(g, v), qB, &nqB);
+            queue_push64(d > a.t_thread && d <= a.t_wave, pack_item(g, v), qW, &nqW);
+            __syncthreads();
+            if (nqB > kQueueCap / 2 - kBlock) hub_flush(qB, &nqB, &qbase, &S->nB, a.hub, true, a.hub_cap);
+            if (nqW > kQueueCap / 2 - kBlock) hub_flush(qW, &nqW, &qbase, &S->nW, a.hub, false, a.hub_cap);
         }
     }
+    hub_flush(qB, &nqB, &qbase, &S->nB, a.hub, true, a.hub_cap);
+    hub_flush(qW, &nqW, &qbase, &S->nW, a.hub, false, a.hub_cap);
     md = block_max(md, sh);
     if (threadIdx.x == 0 && md > __hip_atomic_load(&S->maxdeg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
         atomicMax(&S->maxdeg, md);
+}
+
+// Id-locality sample over the batch: the first vertex of ns tasks spread
+// evenly over the task table.
+__global__ __launch_bounds__(kBlock) void k_blocality(const BatchArgs *__restrict__ A, int ns, SingleState *S) {
+    const BatchArgs a = *A;
+    uint64_t near = 0, sampled = 0;
+    const int k = blockIdx.x * kBlock + threadIdx.x;
+    if (k < ns) {
+        const int64_t task = a.tasks[(int)((int64_t)k * a.ntasks / ns)];
+        const GraphView w = graph_view(a, item_graph(task));
+        locality_row(w.rp, w.ci, item_vertex(task), near, sampled);
+    }
+    near = wave_sum_u64(near);
+    sampled = wave_sum_u64(sampled);
+    if (lane_id() == 0 && sampled) {
+        atomicAdd((unsigned long long *)&S->near, (unsigned long long)near);
+        atomicAdd((unsigned long long *)&S->sampled, (unsigned long long)sampled);
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_bvalidate(const BatchArgs *__restrict__ A, int32_t *err) {
@@ -159,6 +210,8 @@ __global__ __launch_bounds__(kBlock) void k_bround(const BatchArgs *__restrict__
     __shared__ int64_t q[kQueueCap];
     __shared__ int sh_min, qn, qbase;
     __shared__ unsigned long long sh_acc[2];
+    __shared__ int64_t wbuf[kWavesPerBlock][kWaveBuf];
+    __shared__ int wbn[kWavesPerBlock];
     const BatchArgs a = *A;
     if (!SWEEP && S->passes >= a.max_rounds) return;
     const int cT = SWEEP ? a.ntasks : S->cnt_in[kBinThread];
@@ -176,6 +229,8 @@ __global__ __launch_bounds__(kBlock) void k_bround(const BatchArgs *__restrict__
     uint64_t items = 0, degs = 0;
     const int bid = blockIdx.x;
     if (bid < gB) {
+        if (threadIdx.x == 0) qn = 0;
+        __syncthreads();
         for (int i = bid; i < cB; i += gB) {
             const int64_t it = SWEEP ? a.hub[a.hub_cap - 1 - i] : in[a.offB + i];
             const int g = item_graph(it), v = item_vertex(it);
@@ -184,6 +239,7 @@ __global__ __launch_bounds__(kBlock) void k_bround(const BatchArgs *__restrict__
             int nc = 0;
             bool unc = false;
             const bool act = block_vertex<PHASE, TIE, kWinOnly>(v, b, e, w.ci, w.col, lds, &sh_min, a.look, nc, unc);
+            const bool take = (kFlagAppend ? unc : act) && kAppend;
             if (threadIdx.x == 0) {
                 items += 1;
                 degs += (uint64_t)(e - b);
@@ -191,15 +247,19 @@ __global__ __launch_bounds__(kBlock) void k_bround(const BatchArgs *__restrict__
                     wcolg[w.voff + v] = nc;
                     if (MODE == kOptimistic) wcol8g[w.voff + v] = shadow_of(nc);
                 }
-                const bool take = kFlagAppend ? unc : act;
-                if (take && kAppend) out[a.offB + atomicAdd(&S->cnt_out[kBinBlock], 1)] = it;
+                if (take) q[qn++] = it;
             }
+            __syncthreads();
+            if (qn == kQueueCap) queue_flush64(q, &qn, &qbase, &S->cnt_out[kBinBlock], out + a.offB);
         }
+        if (kAppend) queue_flush64(q, &qn, &qbase, &S->cnt_out[kBinBlock], out + a.offB);
     } else if (bid < gB + gW) {
         const int wv = threadIdx.x / kWave;
         const int wi = (bid - gB) * kWavesPerBlock + wv;
         const int nw = gW * kWavesPerBlock;
         uint32_t *bm = lds + wv * kWaveWindowWords;
+        if (lane_id() == 0) wbn[wv] = 0;
+        wave_lds_sync();
         for (int i = wi; i < cW; i += nw) {
             const int64_t it = SWEEP ? a.hub[i] : in[a.offW + i];
             const int g = item_graph(it), v = item_vertex(it);
@@ -215,27 +275,25 @@ __global__ __launch_bounds__(kBlock) void k_bround(const BatchArgs *__restrict__
                     wcolg[w.voff + v] = nc;
                     if (MODE == kOptimistic) wcol8g[w.voff + v] = shadow_of(nc);
                 }
-                const bool take = kFlagAppend ? unc : act;
-                if (take && kAppend) out[a.offW + atomicAdd(&S->cnt_out[kBinWave], 1)] = it;
             }
+            if (kAppend) wave_buf_push<int64_t>((kFlagAppend ? unc : act), it, wbuf[wv], &wbn[wv],
+                                                &S->cnt_out[kBinWave], out + a.offW);
         }
+        if (kAppend) wave_buf_flush<int64_t>(wbuf[wv], &wbn[wv], &S->cnt_out[kBinWave], out + a.offW);
     } else {
         const int tb = bid - gB - gW;
-        constexpr int kNV = 2;
-        constexpr int kGpb = kBlock / kGroup;  // lane groups per workgroup
-        constexpr int kVpb = kNV * kGpb;
         const int gi = threadIdx.x / kGroup;
         const bool leader = (threadIdx.x & (kGroup - 1)) == 0;
         if (kAppend) {
             if (threadIdx.x == 0) qn = 0;
             __syncthreads();
         }
-        // SWEEP: one task (a chunk of one graph) per workgroup step group;
-        // worklist rounds: kVpb packed items per step.
-        const int64_t nsteps = SWEEP ? (int64_t)cT : ((int64_t)cT + kVpb - 1) / kVpb;
+        // SWEEP: one task (a chunk of one graph) per workgroup step;
+        // worklist rounds: kStep packed items per step.
+        const int64_t nsteps = SWEEP ? (int64_t)cT : ((int64_t)cT + kStep - 1) / kStep;
         for (int64_t step = tb; step < nsteps; step += gT) {
             int tg = 0, tstart = 0, tlen = 0;
-            GraphView tw;
+            GraphView tw = {};
             if (SWEEP) {
                 const int t = (kFlagAppend && TIE == kHigherKeeps) ? (int)(nsteps - 1 - step) : (int)step;
                 const int64_t task = a.tasks[t];
@@ -244,8 +302,7 @@ __global__ __launch_bounds__(kBlock) void k_bround(const BatchArgs *__restrict__
                 tw = graph_view(a, tg);
                 tlen = min(kTaskLen, tw.n - tstart);
             }
-            const int inner = SWEEP ? (tlen + kVpb - 1) / kVpb : 1;
-            for (int r = 0; r < inner; ++r) {
+            for (int r = 0; r < kChunk; ++r) {
                 int v[kNV], b[kNV], e[kNV], cv[kNV], nc[kNV], gg[kNV];
                 bool act[kNV], unc[kNV] = {};
                 const RSOC_GLOBAL int32_t *cis[kNV];
@@ -256,8 +313,8 @@ __global__ __launch_bounds__(kBlock) void k_bround(const BatchArgs *__restrict__
                     v[i] = -1;
                     b[i] = e[i] = 0;
                     gg[i] = 0;
+                    const int li = step_offset(r, i, gi, a.chunk);
                     if (SWEEP) {
-                        const int li = r * kVpb + gi + i * kGpb;
                         if (li < tlen) v[i] = (kFlagAppend && TIE == kHigherKeeps) ? tstart + tlen - 1 - li : tstart + li;
                         gg[i] = tg;
                         cis[i] = tw.ci;
@@ -268,7 +325,7 @@ __global__ __launch_bounds__(kBlock) void k_bround(const BatchArgs *__restrict__
                             e[i] = tw.rp[v[i] + 1];
                         }
                     } else {
-                        const int64_t idx = step * kVpb + gi + i * kGpb;
+                        const int64_t idx = step * kStep + li;
                         cis[i] = gro(a.ci);
                         c8s[i] = gro(a.col8);
                         vo[i] = 0;
@@ -306,7 +363,7 @@ __global__ __launch_bounds__(kBlock) void k_bround(const BatchArgs *__restrict__
                     for (int i = 0; i < kNV; ++i)
                         queue_push64((kFlagAppend ? unc[i] : act[i]) && leader, pack_item(gg[i], v[i]), q, &qn);
                     __syncthreads();
-                    if (qn > kQueueCap - kVpb) queue_flush64(q, &qn, &qbase, &S->cnt_out[kBinThread], out);
+                    if (qn > kQueueCap - kSub) queue_flush64(q, &qn, &qbase, &S->cnt_out[kBinThread], out);
                 }
             }
         }

@@ -30,6 +30,23 @@ constexpr int kGroup = 8;                 // lanes per vertex in the thread bin
 constexpr int kGroupSlots = 4;            // row entries each lane holds: thread-bin degree <= 32
 constexpr int kThreadBinMax = kGroup * kGroupSlots;
 constexpr int kQueueCap = 1024;           // per-workgroup append queue (LDS) of the thread bin
+// Thread-bin walk: each lane group takes kNV runs of kChunk consecutive
+// vertex ids and walks them one id at a time (both runs side by side), so
+// ids that are adjacent in a natural-order mesh are coloured one after the
+// other by the same lanes, as a CPU thread walks its block of ids.
+constexpr int kNV = 2;                              // vertices per lane group per sub-step
+constexpr int kGpb = kBlock / kGroup;               // lane groups per workgroup
+constexpr int kChunk = 8;                           // consecutive ids per run
+constexpr int kSub = kNV * kGpb;                    // vertices per sub-step
+constexpr int kStep = kSub * kChunk;                // vertices per workgroup step
+
+// Position inside a workgroup step of sub-step r (0..kChunk-1), run i, lane
+// group gi, when each group walks runs of c consecutive ids (c a power of two
+// dividing kChunk; c = 1 puts consecutive ids in neighbouring groups, which
+// streams rows best when ids carry no locality).
+__host__ __device__ constexpr int step_offset(int r, int i, int gi, int c) {
+    return (r / c) * (kSub * c) + (i * kGpb + gi) * c + (r % c);
+}
 
 enum Phase : int { kAssign = 0, kRecolor = 1, kDetect = 2 };
 enum Mode : int { kOptimistic = 0, kDeterministic = 1, kTwoPhase = 2 };

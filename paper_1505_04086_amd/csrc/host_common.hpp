@@ -35,6 +35,15 @@ inline int32_t hip_fail(hipError_t e, const char *what, const char *file, int li
 
 #define RSOC_LAUNCH_CHECK() RSOC_HIP(hipGetLastError())
 
+// Run length of consecutive ids per lane group: the option when given, else 8
+// when at least 2% of sampled row entries join ids less than 8 apart (a
+// natural-order mesh: walking runs keeps those neighbours out of the same
+// instant), else 1 (scrambled ids: neighbouring groups stream neighbouring rows).
+inline int pick_chunk(int option, uint64_t near, uint64_t sampled) {
+    if (option) return option;
+    return (sampled > 0 && near * 50 >= sampled) ? 8 : 1;
+}
+
 inline int div_up(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
 inline int round_up_to(int x, int m) { return ((x + m - 1) / m) * m; }
@@ -82,7 +91,7 @@ struct HostPinned {
 
 struct Options {
     int mode, tie, max_rounds, validate, t_thread, t_wave, grid_thread, grid_wave, rounds_per_sync, small_cutoff,
-        timing, full_sweep, lookahead;
+        timing, full_sweep, lookahead, chunk;
 };
 
 inline int32_t resolve_options(const rsoc_options *o, int64_t n, Options &r) {
@@ -96,8 +105,10 @@ inline int32_t resolve_options(const rsoc_options *o, int64_t n, Options &r) {
     if (d.max_rounds < 0 || d.t_thread < 0 || d.t_thread > 32 || d.t_wave < 0 || d.grid_thread < 0 ||
         d.grid_wave < 0 || d.rounds_per_sync < 0 || d.validate < 0 || d.validate > 3)
         return RSOC_EINVAL;
-    for (int i = 0; i < 3; ++i)
+    for (int i = 0; i < 2; ++i)
         if (d.reserved[i]) return RSOC_EINVAL;
+    if (d.chunk != 0 && d.chunk != 1 && d.chunk != 2 && d.chunk != 4 && d.chunk != 8) return RSOC_EINVAL;
+    r.chunk = d.chunk;
     if (d.lookahead < -1) return RSOC_EINVAL;
     r.lookahead = d.lookahead;
     if (d.full_sweep < 0 || d.full_sweep > 1) return RSOC_EINVAL;

@@ -203,6 +203,7 @@ int32_t rsoc_pool_admit(rsoc_pool *p, const int32_t *d_row_ptr, const int32_t *d
     m.t_wave = o.t_wave;
     m.look = o.lookahead == -1 ? 0 : (o.lookahead > 0 ? o.lookahead : (1 << 20));
     m.phase = kSlotNew;
+    m.chunk = 1;
     p->reported[slot] = 0;
     if ((r = pool_upload_slot(p, slot, s)) < 0) { pool_release(p, slot); return r; }
     if (n > 0) {
@@ -215,6 +216,7 @@ int32_t rsoc_pool_admit(rsoc_pool *p, const int32_t *d_row_ptr, const int32_t *d
         if (e != hipSuccess) { pool_release(p, slot); return hip_fail(e, "admit sync", __FILE__, __LINE__); }
         m.offW = n - m.nW - m.nB;
         m.offB = n - m.nB;
+        m.chunk = pick_chunk(o.chunk, m.near, m.sampled);
     } else {
         m.phase = kSlotDone;  // nothing to colour
     }
@@ -332,6 +334,7 @@ int32_t rsoc_pool_result(rsoc_pool *p, int32_t slot, rsoc_stats *stats) {
         stats->bin_counts[1] = m.nW;
         stats->bin_counts[2] = m.nB;
         stats->worklist0 = m.mode == kOptimistic ? m.u0 : m.n;
+        stats->chunk = m.chunk;
     }
     const int32_t k = (m.err & 4) ? RSOC_EHIP : (m.status < 0 ? m.status : m.kmax);
     pool_release(p, slot);

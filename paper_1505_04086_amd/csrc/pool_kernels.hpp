@@ -13,7 +13,7 @@ namespace rsoc {
 
 enum PoolPhase : int { kSlotFree = 0, kSlotNew = 1, kSlotRunning = 2, kSlotDone = 3 };
 enum PoolTaskKind : int { kAssignSweep = 0, kRecolorSweep = 1, kRecolorList = 2 };
-constexpr int kPoolTaskT = 512;  // thread-bin items per task
+constexpr int kPoolTaskT = kStep;  // thread-bin items per task (one workgroup step)
 constexpr int kPoolTaskW = 32;   // wavefront-bin items per task
 constexpr int kPoolTaskB = 2;    // workgroup-bin items per task
 
@@ -30,7 +30,8 @@ struct PoolSlot {
     int32_t offW, offB;
     int32_t cnt_in[4], cnt_out[4];
     int32_t nW, nB, maxdeg, passes, rounds, kmax, err, phase, u0, status;
-    int32_t pad[2];
+    int32_t chunk, pad;
+    uint64_t near, sampled;  // id locality sample (admission)
 };
 
 struct PoolTask {
@@ -39,11 +40,17 @@ struct PoolTask {
 
 __global__ __launch_bounds__(kBlock) void k_pinit(PoolSlot *slots, int slot) {
     __shared__ int sh[kWavesPerBlock];
+    __shared__ int qW[kQueueCap], qB[kQueueCap];
+    __shared__ int nqW, nqB, qbase;
+    if (threadIdx.x == 0) nqW = nqB = 0;
+    __syncthreads();
     PoolSlot *sp = slots + slot;
     const RSOC_GLOBAL int32_t *rp = gro(sp->rp);
     const int n = sp->n;
     const int fillc = sp->mode == kOptimistic ? -1 : 0;
+    const RSOC_GLOBAL int32_t *ci = gro(sp->ci);
     int md = 0;
+    uint64_t near = 0, sampled = 0;
     for (int64_t base = (int64_t)blockIdx.x * kBlock; base < n; base += (int64_t)gridDim.x * kBlock) {
         const int v = (int)(base + threadIdx.x);
         int d = -1;
@@ -51,10 +58,22 @@ __global__ __launch_bounds__(kBlock) void k_pinit(PoolSlot *slots, int slot) {
             d = rp[v + 1] - rp[v];
             sp->col[v] = fillc;
             sp->col8[v] = shadow_of(fillc);
+            if ((v & 255) == 0) locality_row(rp, ci, v, near, sampled);  // id-locality sample
         }
         md = max(md, d);
-        wave_append(d > sp->t_wave, v, &sp->nB, sp->hubB);
-        wave_append(d > sp->t_thread && d <= sp->t_wave, v, &sp->nW, sp->hubW);
+        queue_push(d > sp->t_wave, v, qB, &nqB);
+        queue_push(d > sp->t_thread && d <= sp->t_wave, v, qW, &nqW);
+        __syncthreads();
+        if (nqB > kQueueCap - kBlock) queue_flush(qB, &nqB, &qbase, &sp->nB, sp->hubB);
+        if (nqW > kQueueCap - kBlock) queue_flush(qW, &nqW, &qbase, &sp->nW, sp->hubW);
+    }
+    queue_flush(qB, &nqB, &qbase, &sp->nB, sp->hubB);
+    queue_flush(qW, &nqW, &qbase, &sp->nW, sp->hubW);
+    near = wave_sum_u64(near);
+    sampled = wave_sum_u64(sampled);
+    if (lane_id() == 0 && sampled) {
+        atomicAdd((unsigned long long *)&sp->near, (unsigned long long)near);
+        atomicAdd((unsigned long long *)&sp->sampled, (unsigned long long)sampled);
     }
     md = block_max(md, sh);
     if (threadIdx.x == 0) atomicMax(&sp->maxdeg, md);
@@ -66,9 +85,6 @@ __device__ __forceinline__ void pool_thread_task(PoolSlot *sp, const PoolSlot &s
     constexpr int PHASE = KIND == kAssignSweep ? kAssign : kRecolor;
     constexpr bool SWEEP = KIND != kRecolorList;
     constexpr bool kWinOnly = KIND == kAssignSweep;
-    constexpr int kNV = 2;
-    constexpr int kGpb = kBlock / kGroup;
-    constexpr int kVpb = kNV * kGpb;
     const RSOC_GLOBAL int32_t *rp = gro(s.rp);
     const RSOC_GLOBAL int32_t *ci = gro(s.ci);
     const RSOC_GLOBAL uint8_t *c8 = gro(s.col8);
@@ -79,44 +95,49 @@ __device__ __forceinline__ void pool_thread_task(PoolSlot *sp, const PoolSlot &s
     int32_t *out = s.parity ? s.wl[0] : s.wl[1];
     const int gi = threadIdx.x / kGroup;
     const bool leader = (threadIdx.x & (kGroup - 1)) == 0;
-    for (int base = tk.begin; base < tk.end; base += kVpb) {
-        int v[kNV], b[kNV], e[kNV], cv[kNV], nc[kNV];
-        bool act[kNV], unc[kNV] = {};
+    for (int base = tk.begin; base < tk.end; base += kStep) {
+        for (int r = 0; r < kChunk; ++r) {
+            int v[kNV], b[kNV], e[kNV], cv[kNV], nc[kNV];
+            bool act[kNV], unc[kNV] = {};
 #pragma unroll
-        for (int i = 0; i < kNV; ++i) {
-            const int idx = base + gi + i * kGpb;
-            v[i] = -1;
-            b[i] = e[i] = 0;
-            if (idx < tk.end) {
-                if (SWEEP) v[i] = (KIND == kAssignSweep && TIE == kHigherKeeps) ? s.n - 1 - idx : idx;
-                else v[i] = in[idx];
-                b[i] = rp[v[i]];
-                e[i] = rp[v[i] + 1];
-                if (SWEEP && e[i] - b[i] > s.t_thread) e[i] = b[i] = 0, v[i] = -1;
+            for (int i = 0; i < kNV; ++i) {
+                const int idx = base + step_offset(r, i, gi, s.chunk);
+                v[i] = -1;
+                b[i] = e[i] = 0;
+                if (idx < tk.end) {
+                    if (SWEEP) v[i] = (KIND == kAssignSweep && TIE == kHigherKeeps) ? s.n - 1 - idx : idx;
+                    else v[i] = in[idx];
+                    b[i] = rp[v[i]];
+                    e[i] = rp[v[i] + 1];
+                    if (SWEEP && e[i] - b[i] > s.t_thread) e[i] = b[i] = 0, v[i] = -1;
+                }
+                cv[i] = (PHASE != kAssign && v[i] >= 0) ? (int)c8[v[i]] : 255;
             }
-            cv[i] = (PHASE != kAssign && v[i] >= 0) ? (int)c8[v[i]] : 255;
-        }
-        const RSOC_GLOBAL int32_t *const cis[kNV] = {ci, ci};
-        const RSOC_GLOBAL uint8_t *const c8s[kNV] = {c8, c8};
-        group_vertices<PHASE, TIE, kGroup, kGroupSlots, kWinOnly, kNV>(v, b, e, cis, c8s, cv, s.look, nc, act, unc);
+            const RSOC_GLOBAL int32_t *const cis[kNV] = {ci, ci};
+            const RSOC_GLOBAL uint8_t *const c8s[kNV] = {c8, c8};
+            group_vertices<PHASE, TIE, kGroup, kGroupSlots, kWinOnly, kNV>(v, b, e, cis, c8s, cv, s.look, nc, act,
+                                                                           unc);
 #pragma unroll
-        for (int i = 0; i < kNV; ++i) {
-            if (v[i] < 0) act[i] = unc[i] = false;
-            if (leader && act[i]) {
-                wcol[v[i]] = nc[i];
-                if (opt) wcol8[v[i]] = (uint8_t)nc[i];
+            for (int i = 0; i < kNV; ++i) {
+                if (v[i] < 0) act[i] = unc[i] = false;
+                if (leader && act[i]) {
+                    wcol[v[i]] = nc[i];
+                    if (opt) wcol8[v[i]] = (uint8_t)nc[i];
+                }
             }
-        }
 #pragma unroll
-        for (int i = 0; i < kNV; ++i) queue_push((KIND == kAssignSweep ? unc[i] : act[i]) && leader, v[i], q, qn);
-        __syncthreads();
-        if (*qn > kQueueCap - kVpb) queue_flush(q, qn, qbase, &sp->cnt_out[kBinThread], out);
+            for (int i = 0; i < kNV; ++i)
+                queue_push((KIND == kAssignSweep ? unc[i] : act[i]) && leader, v[i], q, qn);
+            __syncthreads();
+            if (*qn > kQueueCap - kSub) queue_flush(q, qn, qbase, &sp->cnt_out[kBinThread], out);
+        }
     }
     queue_flush(q, qn, qbase, &sp->cnt_out[kBinThread], out);
 }
 
 template <int TIE, int KIND>
-__device__ __forceinline__ void pool_wave_task(PoolSlot *sp, const PoolSlot &s, const PoolTask &tk, uint32_t *lds) {
+__device__ __forceinline__ void pool_wave_task(PoolSlot *sp, const PoolSlot &s, const PoolTask &tk, uint32_t *lds,
+                                               int *wbuf, int *wbn) {
     constexpr int PHASE = KIND == kAssignSweep ? kAssign : kRecolor;
     constexpr bool kWinOnly = KIND == kAssignSweep;
     const int wv = threadIdx.x / kWave;
@@ -124,20 +145,21 @@ __device__ __forceinline__ void pool_wave_task(PoolSlot *sp, const PoolSlot &s, 
     const bool opt = s.mode == kOptimistic;
     const int32_t *in = (KIND == kRecolorList) ? (s.parity ? s.wl[1] : s.wl[0]) + s.offW : s.hubW;
     int32_t *out = (s.parity ? s.wl[0] : s.wl[1]) + s.offW;
+    if (lane_id() == 0) *wbn = 0;
+    wave_lds_sync();
     for (int i = tk.begin + wv; i < tk.end; i += kWavesPerBlock) {
         const int v = in[i];
         const int b = s.rp[v], e = s.rp[v + 1];
         int nc = 0;
         bool unc = false;
         const bool act = wave_vertex<PHASE, TIE, kWinOnly>(v, b, e, gro(s.ci), gro(s.col), bm, s.look, nc, unc);
-        if (lane_id() == 0) {
-            if (act) {
-                (opt ? s.col : s.pend)[v] = nc;
-                if (opt) s.col8[v] = shadow_of(nc);
-            }
-            if (KIND == kAssignSweep ? unc : act) out[atomicAdd(&sp->cnt_out[kBinWave], 1)] = v;
+        if (lane_id() == 0 && act) {
+            (opt ? s.col : s.pend)[v] = nc;
+            if (opt) s.col8[v] = shadow_of(nc);
         }
+        wave_buf_push(KIND == kAssignSweep ? unc : act, v, wbuf, wbn, &sp->cnt_out[kBinWave], out);
     }
+    wave_buf_flush(wbuf, wbn, &sp->cnt_out[kBinWave], out);
 }
 
 template <int TIE, int KIND>
@@ -172,6 +194,8 @@ __global__ __launch_bounds__(kBlock) void k_pstep(PoolSlot *slots, const PoolTas
     __shared__ uint32_t lds[kLdsWords];
     __shared__ int q[kQueueCap];
     __shared__ int sh_min, qn, qbase;
+    __shared__ int wbuf[kWavesPerBlock][kWaveBuf];
+    __shared__ int wbn[kWavesPerBlock];
     const int bid = blockIdx.x;
     if (threadIdx.x == 0) qn = 0;
     __syncthreads();
@@ -195,12 +219,12 @@ __global__ __launch_bounds__(kBlock) void k_pstep(PoolSlot *slots, const PoolTas
             }
         } else if (bid < gB + gW) {
             switch (sel) {
-                case 0: pool_wave_task<kLowerKeeps, kAssignSweep>(sp, s, tk, lds); break;
-                case 1: pool_wave_task<kHigherKeeps, kAssignSweep>(sp, s, tk, lds); break;
-                case 2: pool_wave_task<kLowerKeeps, kRecolorSweep>(sp, s, tk, lds); break;
-                case 3: pool_wave_task<kHigherKeeps, kRecolorSweep>(sp, s, tk, lds); break;
-                case 4: pool_wave_task<kLowerKeeps, kRecolorList>(sp, s, tk, lds); break;
-                default: pool_wave_task<kHigherKeeps, kRecolorList>(sp, s, tk, lds); break;
+                case 0: pool_wave_task<kLowerKeeps, kAssignSweep>(sp, s, tk, lds, wbuf[threadIdx.x / kWave], &wbn[threadIdx.x / kWave]); break;
+                case 1: pool_wave_task<kHigherKeeps, kAssignSweep>(sp, s, tk, lds, wbuf[threadIdx.x / kWave], &wbn[threadIdx.x / kWave]); break;
+                case 2: pool_wave_task<kLowerKeeps, kRecolorSweep>(sp, s, tk, lds, wbuf[threadIdx.x / kWave], &wbn[threadIdx.x / kWave]); break;
+                case 3: pool_wave_task<kHigherKeeps, kRecolorSweep>(sp, s, tk, lds, wbuf[threadIdx.x / kWave], &wbn[threadIdx.x / kWave]); break;
+                case 4: pool_wave_task<kLowerKeeps, kRecolorList>(sp, s, tk, lds, wbuf[threadIdx.x / kWave], &wbn[threadIdx.x / kWave]); break;
+                default: pool_wave_task<kHigherKeeps, kRecolorList>(sp, s, tk, lds, wbuf[threadIdx.x / kWave], &wbn[threadIdx.x / kWave]); break;
             }
         } else {
             switch (sel) {

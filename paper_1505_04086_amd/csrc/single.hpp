@@ -275,6 +275,7 @@ inline int32_t run_single(rsoc_ctx *c, const int32_t *rp, const int32_t *ci, int
     a.max_rounds = o.max_rounds;
     a.offW = a.offB = 0;
     a.look = 0;
+    a.chunk = 1;
     RSOC_HIP(hipMemcpyAsync(c->args.p, &a, sizeof(a), hipMemcpyHostToDevice, s));
     RSOC_HIP(hipMemsetAsync(S, 0, kStateHeader, s));
     const int vgrid = std::min(div_up(n, kBlock), 4096);
@@ -286,6 +287,10 @@ inline int32_t run_single(rsoc_ctx *c, const int32_t *rp, const int32_t *ci, int
         RSOC_TRY(status_from_err(h->head.err));
     }
     k_bin<<<vgrid, kBlock, 0, s>>>(c->args.as<SingleArgs>(), S);
+    if (o.chunk == 0 && nnz > 0) {
+        const int ns = std::min(n, 16384);
+        k_locality<<<div_up(ns, kBlock), kBlock, 0, s>>>(rp, ci, n, ns, S);
+    }
     RSOC_LAUNCH_CHECK();
     RSOC_HIP(hipMemcpyAsync(&h->head, S, kStateHeader, hipMemcpyDeviceToHost, s));
     RSOC_HIP(hipStreamSynchronize(s));
@@ -295,17 +300,17 @@ inline int32_t run_single(rsoc_ctx *c, const int32_t *rp, const int32_t *ci, int
     a.offB = nT + nW;
 
     // launch shapes
-    constexpr int kVpb = 2 * kBlock / kGroup;  // thread-bin vertices per workgroup step
     const int gB = std::min(nB, 1024);
     const int gW = std::min(div_up(nW, kWavesPerBlock), o.grid_wave);
-    int gTs = std::min(div_up(n, kVpb), o.grid_thread);
+    int gTs = std::min(div_up(n, kStep), o.grid_thread);
     if (gTs >= kXcds) gTs -= gTs % kXcds;
-    const int64_t look = o.lookahead == -1 ? 0 : (o.lookahead > 0 ? o.lookahead : 16ll * gTs * kVpb);
+    const int64_t look = o.lookahead == -1 ? 0 : (o.lookahead > 0 ? o.lookahead : 2ll * gTs * kStep);
     a.look = (int)std::min<int64_t>(look, INT32_MAX);
+    a.chunk = pick_chunk(o.chunk, h->head.near, h->head.sampled);
     RSOC_HIP(hipMemcpyAsync(c->args.p, &a, sizeof(a), hipMemcpyHostToDevice, s));
     const int gBl = std::min(nB, 256);
     const int gWl = std::min(div_up(nW, kWavesPerBlock), o.grid_wave);
-    const int gTl = std::max(1, std::min(div_up(nT, kVpb), o.grid_thread));
+    const int gTl = std::max(1, std::min(div_up(nT, kStep), o.grid_thread));
 
     hipGraphExec_t gexec = nullptr;
     RSOC_TRY(get_round_graph(c, o.mode, o.tie, o.rounds_per_sync, gBl, gWl, gTl, &gexec));
@@ -370,6 +375,7 @@ inline int32_t run_single(rsoc_ctx *c, const int32_t *rp, const int32_t *ci, int
                   h->head.deg_sum, b0, b1, tot);
         st->bytes_round0 = b0;
         st->worklist0 = sweep1 ? n : h->head.u0;
+        st->chunk = a.chunk;
         st->bytes_round1 = b1;
         st->alg_bytes = tot;
     }

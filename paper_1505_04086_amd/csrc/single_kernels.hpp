@@ -31,6 +31,7 @@ struct SingleArgs {
     int32_t max_rounds;  // bound on inspection passes
     int32_t offW, offB;  // segment offsets inside wl buffers
     int32_t look;        // round-0 lookahead (ids within `look` of v are read even when v wins against them)
+    int32_t chunk;       // run of consecutive ids one lane group walks (1, 2, 4 or 8)
 };
 
 // Device-side round state.
@@ -49,6 +50,7 @@ struct SingleState {
     uint64_t deg_sum;     // their degree sum
     int32_t u0;           // |U^0| when round 0 collects it (optimistic, default flow)
     int32_t pad;
+    uint64_t near, sampled;  // id locality sample: row entries with |u - v| < kChunk, entries sampled
     int32_t hist[kHistCap];  // |L| of recolouring round i+1
 };
 
@@ -98,24 +100,95 @@ __device__ __forceinline__ int block_max(int x, int *sh) {
 // ------------------------------------------------------------------ bin --
 // Splits V by degree: deg <= t_thread stays implicit (thread bin); larger rows
 // go to the static wavefront / workgroup lists.  Also finds the max degree.
+__device__ __forceinline__ void queue_push(bool take, int v, int *q, int *qn);
+__device__ __forceinline__ void queue_flush(int *q, int *qn, int *qbase, int *counter, int32_t *out);
+
 __global__ __launch_bounds__(kBlock) void k_bin(const SingleArgs *__restrict__ A, SingleState *S) {
     __shared__ int sh[kWavesPerBlock];
+    __shared__ int qW[kQueueCap], qB[kQueueCap];
+    __shared__ int nqW, nqB, qbase;
     const SingleArgs a = *A;
     const RSOC_GLOBAL int32_t *rp = gro(a.rp);
     int md = 0;
+    if (threadIdx.x == 0) nqW = nqB = 0;
+    __syncthreads();
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     for (int64_t base = (int64_t)blockIdx.x * kBlock; base < a.n; base += stride) {
         const int v = (int)(base + threadIdx.x);
         int d = -1;
         if (v < a.n) d = rp[v + 1] - rp[v];
         md = max(md, d);
-        wave_append(d > a.t_wave, v, &S->nB, a.hubB);
-        wave_append(d > a.t_thread && d <= a.t_wave, v, &S->nW, a.hubW);
+        // workgroup queues: one global atomic per flush, not per wavefront
+        queue_push(d > a.t_wave, v, qB, &nqB);
+        queue_push(d > a.t_thread && d <= a.t_wave, v, qW, &nqW);
+        __syncthreads();
+        if (nqB > kQueueCap - kBlock) queue_flush(qB, &nqB, &qbase, &S->nB, a.hubB);
+        if (nqW > kQueueCap - kBlock) queue_flush(qW, &nqW, &qbase, &S->nW, a.hubW);
     }
+    queue_flush(qB, &nqB, &qbase, &S->nB, a.hubB);
+    queue_flush(qW, &nqW, &qbase, &S->nW, a.hubW);
     md = block_max(md, sh);
     // most workgroups find nothing larger than what is already published
     if (threadIdx.x == 0 && md > __hip_atomic_load(&S->maxdeg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
         atomicMax(&S->maxdeg, md);
+}
+
+// Id-locality sample: rows of `ns` vertices spread evenly over [0, n) (rows
+// longer than the thread bin skipped); counts entries joining ids less than
+// kChunk apart.  One vertex per thread, its row read eight entries at a time.
+__device__ __forceinline__ void locality_row(const RSOC_GLOBAL int32_t *rp, const RSOC_GLOBAL int32_t *ci, int v,
+                                             uint64_t &near, uint64_t &sampled) {
+    const int b = rp[v], e = rp[v + 1];
+    if (e - b > kThreadBinMax) return;
+    for (int j0 = b; j0 < e; j0 += 8) {
+        int u[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) u[k] = (j0 + k < e) ? ci[j0 + k] : INT_MIN / 2;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) near += (uint64_t)(abs(u[k] - v) < kChunk);
+    }
+    sampled += (uint64_t)(e - b);
+}
+
+__global__ __launch_bounds__(kBlock) void k_locality(const int32_t *__restrict__ rpp, const int32_t *__restrict__ cip,
+                                                     int32_t n, int32_t ns, SingleState *S) {
+    const RSOC_GLOBAL int32_t *rp = gro(rpp);
+    const RSOC_GLOBAL int32_t *ci = gro(cip);
+    uint64_t near = 0, sampled = 0;
+    const int k = blockIdx.x * kBlock + threadIdx.x;
+    if (k < ns) locality_row(rp, ci, (int)((int64_t)k * n / ns), near, sampled);
+    near = wave_sum_u64(near);
+    sampled = wave_sum_u64(sampled);
+    if (lane_id() == 0 && sampled) {
+        atomicAdd((unsigned long long *)&S->near, (unsigned long long)near);
+        atomicAdd((unsigned long long *)&S->sampled, (unsigned long long)sampled);
+    }
+}
+
+// Per-wavefront append buffer in LDS (wavefront-bin vertices are appended one
+// at a time by lane 0; one global atomic per kWaveBuf entries).
+constexpr int kWaveBuf = 64;
+
+template <class T>
+__device__ __forceinline__ void wave_buf_flush(T *buf, int *bn, int *counter, T *out) {
+    wave_lds_sync();
+    const int cnt = *bn;
+    if (cnt == 0) return;
+    int base = 0;
+    if (lane_id() == 0) base = atomicAdd(counter, cnt);
+    base = __shfl(base, 0);
+    if (lane_id() < cnt) out[base + lane_id()] = buf[lane_id()];
+    wave_lds_sync();
+    if (lane_id() == 0) *bn = 0;
+    wave_lds_sync();
+}
+
+// Lane 0 pushes x when take; the whole wavefront calls this (flushes when full).
+template <class T>
+__device__ __forceinline__ void wave_buf_push(bool take, T x, T *buf, int *bn, int *counter, T *out) {
+    if (lane_id() == 0 && take) buf[(*bn)++] = x;
+    wave_lds_sync();
+    if (*bn == kWaveBuf) wave_buf_flush(buf, bn, counter, out);
 }
 
 // Appends v for every lane with `take` into the workgroup's LDS queue.  Called
@@ -164,6 +237,8 @@ __global__ __launch_bounds__(kBlock) void k_round(const SingleArgs *__restrict__
     __shared__ int q[kQueueCap];
     __shared__ int sh_min, qn, qbase;
     __shared__ unsigned long long sh_acc[2];
+    __shared__ int wbuf[kWavesPerBlock][kWaveBuf];
+    __shared__ int wbn[kWavesPerBlock];
     const SingleArgs a = *A;
     if (!SWEEP && S->passes >= a.max_rounds) return;  // guard: the round may not run
     const int cT = SWEEP ? a.n : S->cnt_in[kBinThread];
@@ -188,12 +263,15 @@ __global__ __launch_bounds__(kBlock) void k_round(const SingleArgs *__restrict__
     uint64_t items = 0, degs = 0;
     const int bid = blockIdx.x;
     if (bid < gB) {
+        if (threadIdx.x == 0) qn = 0;
+        __syncthreads();
         for (int i = bid; i < cB; i += gB) {
             const int v = inB[i];
             const int b = rp[v], e = rp[v + 1];
             int nc = 0;
             bool unc = false;
             const bool act = block_vertex<PHASE, TIE, kWinOnly>(v, b, e, ci, rcol, lds, &sh_min, a.look, nc, unc);
+            const bool take = (kFlagAppend ? unc : act) && kAppend;
             if (threadIdx.x == 0) {
                 items += 1;
                 degs += (uint64_t)(e - b);
@@ -201,15 +279,19 @@ __global__ __launch_bounds__(kBlock) void k_round(const SingleArgs *__restrict__
                     wcol[v] = nc;
                     if (MODE == kOptimistic) wcol8[v] = shadow_of(nc);
                 }
-                const bool take = kFlagAppend ? unc : act;
-                if (take && kAppend) out[a.offB + atomicAdd(&S->cnt_out[kBinBlock], 1)] = v;
+                if (take) q[qn++] = v;
             }
+            __syncthreads();
+            if (qn == kQueueCap) queue_flush(q, &qn, &qbase, &S->cnt_out[kBinBlock], out + a.offB);
         }
+        if (kAppend) queue_flush(q, &qn, &qbase, &S->cnt_out[kBinBlock], out + a.offB);
     } else if (bid < gB + gW) {
         const int wv = threadIdx.x / kWave;
         const int w = (bid - gB) * kWavesPerBlock + wv;
         const int nw = gW * kWavesPerBlock;
         uint32_t *bm = lds + wv * kWaveWindowWords;
+        if (lane_id() == 0) wbn[wv] = 0;
+        wave_lds_sync();
         for (int i = w; i < cW; i += nw) {
             const int v = inW[i];
             const int b = rp[v], e = rp[v + 1];
@@ -223,66 +305,69 @@ __global__ __launch_bounds__(kBlock) void k_round(const SingleArgs *__restrict__
                     wcol[v] = nc;
                     if (MODE == kOptimistic) wcol8[v] = shadow_of(nc);
                 }
-                const bool take = kFlagAppend ? unc : act;
-                if (take && kAppend) out[a.offW + atomicAdd(&S->cnt_out[kBinWave], 1)] = v;
             }
+            if (kAppend) wave_buf_push((kFlagAppend ? unc : act), v, wbuf[wv], &wbn[wv], &S->cnt_out[kBinWave],
+                                       out + a.offW);
         }
+        if (kAppend) wave_buf_flush(wbuf[wv], &wbn[wv], &S->cnt_out[kBinWave], out + a.offW);
     } else {
         int tb = bid - gB - gW;
         // worklist-free sweeps that need no particular order keep each XCD on
         // one id range (neighbouring ids share its L2); round 0 sweeps in order
         if (SWEEP && PHASE != kAssign) tb = xcd_contiguous(tb, gT);
-        constexpr int kNV = 2;                       // vertices per lane group per step
-        constexpr int kVpb = kNV * kBlock / kGroup;  // vertices per workgroup step
         const int gi = threadIdx.x / kGroup;
         const bool leader = (threadIdx.x & (kGroup - 1)) == 0;
         if (kAppend) {
             if (threadIdx.x == 0) qn = 0;
             __syncthreads();
         }
-        const int64_t stride = (int64_t)gT * kVpb;
-        for (int64_t base = (int64_t)tb * kVpb; base < cT; base += stride) {
-            int v[kNV], b[kNV], e[kNV], cv[kNV], nc[kNV];
-            bool act[kNV], unc[kNV] = {};
+        const int64_t stride = (int64_t)gT * kStep;
+        for (int64_t base = (int64_t)tb * kStep; base < cT; base += stride) {
+            for (int r = 0; r < kChunk; ++r) {
+                int v[kNV], b[kNV], e[kNV], cv[kNV], nc[kNV];
+                bool act[kNV], unc[kNV] = {};
 #pragma unroll
-            for (int i = 0; i < kNV; ++i) {
-                const int64_t idx = base + gi + i * (kBlock / kGroup);
-                v[i] = -1;
-                b[i] = e[i] = 0;
-                if (idx < cT) {
-                    v[i] = SWEEP ? ((kFlagAppend && TIE == kHigherKeeps) ? (int)(cT - 1 - idx) : (int)idx) : inT[idx];
-                }
-            }
-#pragma unroll
-            for (int i = 0; i < kNV; ++i) {
-                if (v[i] >= 0) {
-                    b[i] = rp[v[i]];
-                    e[i] = rp[v[i] + 1];
-                    if (SWEEP && e[i] - b[i] > a.t_thread) e[i] = b[i] = 0, v[i] = -1;  // another bin's vertex
-                }
-                cv[i] = (PHASE != kAssign && v[i] >= 0) ? (int)rcol8[v[i]] : 255;
-            }
-            const RSOC_GLOBAL int32_t *const cis[kNV] = {ci, ci};
-            const RSOC_GLOBAL uint8_t *const c8s[kNV] = {rcol8, rcol8};
-            group_vertices<PHASE, TIE, kGroup, kGroupSlots, kWinOnly, kNV>(v, b, e, cis, c8s, cv, a.look, nc, act,
-                                                                           unc);
-#pragma unroll
-            for (int i = 0; i < kNV; ++i) {
-                if (v[i] < 0) act[i] = unc[i] = false;
-                if (leader && v[i] >= 0) {
-                    items += 1;
-                    degs += (uint64_t)(e[i] - b[i]);
-                    if (act[i] && kWrite) {
-                        wcol[v[i]] = nc[i];
-                        if (MODE == kOptimistic) wcol8[v[i]] = (uint8_t)nc[i];
+                for (int i = 0; i < kNV; ++i) {
+                    const int64_t idx = base + step_offset(r, i, gi, a.chunk);
+                    v[i] = -1;
+                    b[i] = e[i] = 0;
+                    if (idx < cT) {
+                        v[i] = SWEEP ? ((kFlagAppend && TIE == kHigherKeeps) ? (int)(cT - 1 - idx) : (int)idx)
+                                     : inT[idx];
                     }
                 }
-            }
-            if (kAppend) {
 #pragma unroll
-                for (int i = 0; i < kNV; ++i) queue_push((kFlagAppend ? unc[i] : act[i]) && leader, v[i], q, &qn);
-                __syncthreads();
-                if (qn > kQueueCap - kVpb) queue_flush(q, &qn, &qbase, &S->cnt_out[kBinThread], out);
+                for (int i = 0; i < kNV; ++i) {
+                    if (v[i] >= 0) {
+                        b[i] = rp[v[i]];
+                        e[i] = rp[v[i] + 1];
+                        if (SWEEP && e[i] - b[i] > a.t_thread) e[i] = b[i] = 0, v[i] = -1;  // another bin's vertex
+                    }
+                    cv[i] = (PHASE != kAssign && v[i] >= 0) ? (int)rcol8[v[i]] : 255;
+                }
+                const RSOC_GLOBAL int32_t *const cis[kNV] = {ci, ci};
+                const RSOC_GLOBAL uint8_t *const c8s[kNV] = {rcol8, rcol8};
+                group_vertices<PHASE, TIE, kGroup, kGroupSlots, kWinOnly, kNV>(v, b, e, cis, c8s, cv, a.look, nc, act,
+                                                                               unc);
+#pragma unroll
+                for (int i = 0; i < kNV; ++i) {
+                    if (v[i] < 0) act[i] = unc[i] = false;
+                    if (leader && v[i] >= 0) {
+                        items += 1;
+                        degs += (uint64_t)(e[i] - b[i]);
+                        if (act[i] && kWrite) {
+                            wcol[v[i]] = nc[i];
+                            if (MODE == kOptimistic) wcol8[v[i]] = (uint8_t)nc[i];
+                        }
+                    }
+                }
+                if (kAppend) {
+#pragma unroll
+                    for (int i = 0; i < kNV; ++i)
+                        queue_push((kFlagAppend ? unc[i] : act[i]) && leader, v[i], q, &qn);
+                    __syncthreads();
+                    if (qn > kQueueCap - kSub) queue_flush(q, &qn, &qbase, &S->cnt_out[kBinThread], out);
+                }
             }
         }
         if (kAppend) queue_flush(q, &qn, &qbase, &S->cnt_out[kBinThread], out);

@@ -29,7 +29,8 @@ def _mixed_batch():
 
 GRAPHS = _mixed_batch()
 BATCH = gg.concat(GRAPHS)
-SPLITS = {"default": {}, "allbins": {"t_thread": 3, "t_wave": 8}}
+SPLITS = {"default": {}, "allbins": {"t_thread": 3, "t_wave": 8}, "runs1": {"chunk": 1, "grid_thread": 7},
+          "runs8": {"chunk": 8, "grid_thread": 3}}
 
 
 def _upload(lib, b):

@@ -1,0 +1,79 @@
+"""The request loop on the GPU: each request's result is the same alone (one
+call per request) and in the mix (continuous batching under a tight HBM
+budget, staggered arrivals).
+
+Tolerance: round-synchronous (deterministic) requests must be identical to
+the oracle both ways; optimistic requests must be valid colourings with
+0 <= c(v) <= deg(v) both ways, and their colour counts may differ by at most
+max(2, 10%) between the two runs (speculation order differs)."""
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def _graphs():
+    gs = [gg.tri_grid(120, 90), gg.lattice26(18, permute_seed=3), gg.rmat(12, 16, seed=4, shuffle_seed=5),
+          gg.tri_grid(40, 40, permute_seed=6), gg.rgg(20000, seed=7), gg.lattice26(25, permute_seed=8),
+          gg.rmat(13, 16, seed=9, shuffle_seed=10), gg.path(1000), gg.complete(60),
+          (np.zeros(1, np.int32), np.zeros(0, np.int32))]
+    return gs
+
+
+GRAPHS = _graphs()
+
+
+def test_alone_equals_mix(lib):
+    import torch
+    from paper_1505_04086_amd import serve
+    ctx = lib.Context(0)
+    det = lib.make_options("deterministic")
+    opt = lib.make_options("optimistic")
+    reqs_spec = [(i, det if i % 2 == 0 else opt) for i in range(len(GRAPHS))] * 2
+
+    def make(arrivals):
+        return [serve.Request(k, torch.from_numpy(GRAPHS[g][0]).pin_memory(), torch.from_numpy(GRAPHS[g][1]).pin_memory(),
+                              float(arrivals[k]), options=o) for k, (g, o) in enumerate(reqs_spec)]
+
+    alone = serve.PlainServer(ctx).run(make(np.zeros(len(reqs_spec))))
+    # budget for roughly three of the larger graphs at a time: admission must wait for releases
+    largest = max(serve.csr_bytes(len(rp) - 1, len(ci)) for rp, ci in GRAPHS)
+    sv = serve.Server(ctx, hbm_budget=int(3 * largest / 0.65), scratch_share=0.35, max_slots=8)
+    arrivals = np.cumsum(np.full(len(reqs_spec), 0.0005))
+    mix = sv.run(make(arrivals))
+    sv.close()
+    assert len(mix) == len(alone) == len(reqs_spec)
+    by_id = {r.rid: r for r in mix}
+    for a in alone:
+        m = by_id[a.rid]
+        g, o = reqs_spec[a.rid]
+        rp, ci = GRAPHS[g]
+        if o.mode == lib.RSOC_MODE_DETERMINISTIC:
+            want = oracle.rsync(rp, ci)
+            assert np.array_equal(a.colors, want["colors"]) and np.array_equal(m.colors, want["colors"]), a.rid
+            assert a.k == m.k == want["K"]
+        else:
+            assert oracle.check(rp, ci, a.colors) == 0 and oracle.check(rp, ci, m.colors) == 0, a.rid
+            assert abs(a.k - m.k) <= max(2, 0.1 * a.k), (a.k, m.k)
+        assert m.latency >= 0
+    assert sv.ledger.used == 0
+    # device-resident requests (CSR already in HBM, colours left on the device)
+    dev = torch.device("cuda:0")
+    res = [(torch.from_numpy(rp).to(dev), torch.from_numpy(ci if len(ci) else np.zeros(1, np.int32)).to(dev))
+           for rp, ci in GRAPHS]
+    sv = serve.Server(ctx, hbm_budget=int(3 * largest / 0.65), scratch_share=0.35, max_slots=8)
+    mix2 = sv.run([serve.Request(k, res[g][0], res[g][1], float(arrivals[k]), options=o)
+                   for k, (g, o) in enumerate(reqs_spec)])
+    sv.close()
+    for m in mix2:
+        g, o = reqs_spec[m.rid]
+        rp, ci = GRAPHS[g]
+        got = m.colors.cpu().numpy()
+        if o.mode == lib.RSOC_MODE_DETERMINISTIC:
+            assert np.array_equal(got, oracle.rsync(rp, ci)["colors"]), m.rid
+        else:
+            assert oracle.check(rp, ci, got) == 0, m.rid
+    ctx.close()

@@ -51,7 +51,8 @@ def _small_cases():
 CASES = _small_cases()
 # degree-bin thresholds small enough to route small graphs through every bin
 BIN_SPLITS = {"default": {}, "allbins": {"t_thread": 3, "t_wave": 8}, "wave_only": {"t_thread": 1, "t_wave": 100000},
-              "block_only": {"t_thread": 1, "t_wave": 1}}
+              "block_only": {"t_thread": 1, "t_wave": 1}, "runs1": {"chunk": 1, "grid_thread": 3},
+              "runs8": {"chunk": 8, "grid_thread": 5}, "runs2": {"chunk": 2, "t_thread": 16}}
 
 
 @pytest.mark.parametrize("split", sorted(BIN_SPLITS))
