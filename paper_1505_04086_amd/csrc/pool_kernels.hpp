@@ -113,8 +113,10 @@ __device__ __forceinline__ void pool_thread_task(PoolSlot *sp, const PoolSlot &s
                 }
                 cv[i] = (PHASE != kAssign && v[i] >= 0) ? (int)c8[v[i]] : 255;
             }
-            const RSOC_GLOBAL int32_t *const cis[kNV] = {ci, ci};
-            const RSOC_GLOBAL uint8_t *const c8s[kNV] = {c8, c8};
+            const RSOC_GLOBAL int32_t *cis[kNV];
+            const RSOC_GLOBAL uint8_t *c8s[kNV];
+#pragma unroll
+            for (int i = 0; i < kNV; ++i) cis[i] = ci, c8s[i] = c8;
             group_vertices<PHASE, TIE, kGroup, kGroupSlots, kWinOnly, kNV>(v, b, e, cis, c8s, cv, s.look, nc, act,
                                                                            unc);
 #pragma unroll

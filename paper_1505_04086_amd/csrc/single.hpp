@@ -18,7 +18,7 @@ struct rsoc_ctx {
     int device = 0;
     hipStream_t own = nullptr;    // stream for host-pointer calls
     hipStream_t cap = nullptr;    // capture stream
-    rsoc::DevBuf wl0, wl1, hubW, hubB, pend, flags, col8;
+    rsoc::DevBuf wl0, wl1, hubW, hubB, pend, flags, col8, col4;
     rsoc::DevBuf args, state;     // SingleArgs, SingleState (fixed addresses: graphs point at them)
     rsoc::HostPinned host;        // pinned staging for small copies
     rsoc::DevBuf drp, dci, dcol;  // device copies for host-pointer calls
@@ -59,7 +59,7 @@ inline void ctx_free(rsoc_ctx *c) {
     c->graphs.clear();
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);
-    for (rsoc::DevBuf *b : {&c->col8, &c->wl0, &c->wl1, &c->hubW, &c->hubB, &c->pend, &c->flags, &c->args, &c->state, &c->drp,
+    for (rsoc::DevBuf *b : {&c->col8, &c->col4, &c->wl0, &c->wl1, &c->hubW, &c->hubB, &c->pend, &c->flags, &c->args, &c->state, &c->drp,
                             &c->dci, &c->dcol, &c->b_desc, &c->b_wl0, &c->b_wl1, &c->b_pend, &c->b_flags,
                             &c->b_state, &c->b_hub, &c->b_kmax, &c->b_tasks, &c->b_args, &c->b_col8})
         b->release();
@@ -139,6 +139,9 @@ inline void launch_sweep_rounds(rsoc_ctx *c, hipStream_t s, int32_t *col, int n,
     } else {
         k_fill<<<fill_grid, kBlock, 0, s>>>(col, c->col8.as<uint8_t>(), n, -1);
         if (MODE == kOptimistic) {
+            // every nibble 15: nothing published yet
+            k_fill<<<std::min(div_up(n / 8 + 1, kBlock), 4096), kBlock, 0, s>>>(
+                reinterpret_cast<int32_t *>(c->col4.p), nullptr, n / 8 + 1, -1);
             if (timing) (void)hipEventRecord(c->ev[2], s);
             // round 0: tentative First-Fit over all of V with live reads
             if (full_sweep) {
@@ -193,6 +196,7 @@ inline int32_t ensure_single_scratch(rsoc_ctx *c, int64_t n) {
     RSOC_TRY(c->pend.reserve(b));
     RSOC_TRY(c->flags.reserve(b));
     RSOC_TRY(c->col8.reserve((size_t)n + 64));
+    RSOC_TRY(c->col4.reserve(sizeof(uint32_t) * (size_t)(n / 8 + 2)));
     return RSOC_OK;
 }
 
@@ -264,6 +268,7 @@ inline int32_t run_single(rsoc_ctx *c, const int32_t *rp, const int32_t *ci, int
     a.ci = ci;
     a.col = col;
     a.col8 = c->col8.as<uint8_t>();
+    a.col4 = c->col4.as<uint32_t>();
     a.pend = c->pend.as<int32_t>();
     a.wl[0] = c->wl0.as<int32_t>();
     a.wl[1] = c->wl1.as<int32_t>();

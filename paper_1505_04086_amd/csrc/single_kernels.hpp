@@ -21,6 +21,7 @@ struct SingleArgs {
     const int32_t *ci;   // col_idx[nnz]
     int32_t *col;        // colours[n]
     uint8_t *col8;       // byte shadow of the colours: min(colour, 255), 255 when uncoloured
+    uint32_t *col4;      // 4-bit shadow (8 per word): min(colour, 15); 15 = consult col8 (optimistic mode)
     int32_t *pend;       // staged colours (round-synchronous modes), indexed by vertex
     int32_t *wl[2];      // worklist buffers; bin segments start at 0, offW, offB
     int32_t *hubW;       // static list of wavefront-bin vertices
@@ -255,6 +256,13 @@ __global__ __launch_bounds__(kBlock) void k_round(const SingleArgs *__restrict__
     const RSOC_GLOBAL uint8_t *rcol8 = gro(a.col8);
     RSOC_GLOBAL int32_t *wcol = grw((MODE == kOptimistic) ? a.col : a.pend);
     RSOC_GLOBAL uint8_t *wcol8 = grw(a.col8);
+    // The 4-bit shadow is used by the optimistic, lower-keeps path (its sweeps
+    // run in ascending id order, so each 8-vertex word is finished by one
+    // wavefront inside one workgroup step and published with a plain store).
+    constexpr bool kNib = MODE == kOptimistic && TIE == kLowerKeeps;
+    constexpr bool kPublish = kNib && PHASE == kAssign && SWEEP;
+    const RSOC_GLOBAL uint32_t *rcol4 = gro(a.col4);
+    RSOC_GLOBAL uint32_t *wcol4 = grw(a.col4);
     constexpr bool kFlagAppend = PHASE == kAssign && ROUND0 == 1;
     constexpr bool kWinOnly = kFlagAppend;
     constexpr bool kAppend = PHASE != kAssign || kFlagAppend;
@@ -321,8 +329,12 @@ __global__ __launch_bounds__(kBlock) void k_round(const SingleArgs *__restrict__
             if (threadIdx.x == 0) qn = 0;
             __syncthreads();
         }
+        const int c = a.chunk;
         const int64_t stride = (int64_t)gT * kStep;
         for (int64_t base = (int64_t)tb * kStep; base < cT; base += stride) {
+            uint32_t acc[kNV];  // nibbles of the words being finished (kPublish)
+#pragma unroll
+            for (int i = 0; i < kNV; ++i) acc[i] = ~0u;
             for (int r = 0; r < kChunk; ++r) {
                 int v[kNV], b[kNV], e[kNV], cv[kNV], nc[kNV];
                 bool act[kNV], unc[kNV] = {};
@@ -345,10 +357,13 @@ __global__ __launch_bounds__(kBlock) void k_round(const SingleArgs *__restrict__
                     }
                     cv[i] = (PHASE != kAssign && v[i] >= 0) ? (int)rcol8[v[i]] : 255;
                 }
-                const RSOC_GLOBAL int32_t *const cis[kNV] = {ci, ci};
-                const RSOC_GLOBAL uint8_t *const c8s[kNV] = {rcol8, rcol8};
-                group_vertices<PHASE, TIE, kGroup, kGroupSlots, kWinOnly, kNV>(v, b, e, cis, c8s, cv, a.look, nc, act,
-                                                                               unc);
+                const RSOC_GLOBAL int32_t *cis[kNV];
+                const RSOC_GLOBAL uint8_t *c8s[kNV];
+                const RSOC_GLOBAL uint32_t *c4s[kNV];
+#pragma unroll
+                for (int i = 0; i < kNV; ++i) cis[i] = ci, c8s[i] = rcol8, c4s[i] = rcol4;
+                group_vertices<PHASE, TIE, kGroup, kGroupSlots, kWinOnly, kNV, kNib>(v, b, e, cis, c8s, cv, a.look, nc,
+                                                                                     act, unc, c4s);
 #pragma unroll
                 for (int i = 0; i < kNV; ++i) {
                     if (v[i] < 0) act[i] = unc[i] = false;
@@ -358,6 +373,31 @@ __global__ __launch_bounds__(kBlock) void k_round(const SingleArgs *__restrict__
                         if (act[i] && kWrite) {
                             wcol[v[i]] = nc[i];
                             if (MODE == kOptimistic) wcol8[v[i]] = (uint8_t)nc[i];
+                            // a recoloured vertex's nibble becomes 15: readers then use col8
+                            if (kNib && !kPublish) atomicOr((uint32_t *)&wcol4[v[i] >> 3], 0xfu << ((v[i] & 7) << 2));
+                        }
+                    }
+                }
+                if (kPublish) {
+                    // nibble of each vertex coloured here; a word of 8 ids is
+                    // covered by 8/c groups of one wavefront over c sub-steps
+#pragma unroll
+                    for (int i = 0; i < kNV; ++i)
+                        if (v[i] >= 0) {
+                            const int sh = (v[i] & 7) << 2;
+                            acc[i] = (acc[i] & ~(0xfu << sh)) | ((uint32_t)min(nc[i], 15) << sh);
+                        }
+                    if ((r & (c - 1)) == c - 1) {
+                        const int span = 8 / c;  // lane groups sharing one word
+#pragma unroll
+                        for (int i = 0; i < kNV; ++i) {
+                            uint32_t x = acc[i];
+                            for (int off = kGroup; off < kGroup * span; off <<= 1) x &= __shfl_xor(x, off);
+                            if ((threadIdx.x & (kGroup * span - 1)) == 0) {
+                                const int64_t pos = base + step_offset(r - (c - 1), i, gi, c);
+                                if (pos < cT) wcol4[pos >> 3] = x;
+                            }
+                            acc[i] = ~0u;
                         }
                     }
                 }

@@ -34,12 +34,40 @@ namespace rsoc {
 // the neighbours it wins against whose id lies within `look` of v's (those
 // the sweep may already have coloured); unc[i] reports whether a neighbour v
 // loses to was still uncoloured when read.
-// ci[i] / col8[i] are the (per-graph) bases vertex i's ids refer to.
-template <int PHASE, int TIE, int G, int S, bool WIN_ONLY, int NV>
+// ci[i] / col8[i] / col4[i] are the (per-graph) bases vertex i's ids refer to.
+//
+// NIB: colours are first read from a 4-bit shadow (eight vertices per 32-bit
+// word, value min(colour, 15)); a nibble of 15 ("15 or more, or uncoloured")
+// falls back to the byte shadow.  The 4-bit array is half the size of the
+// byte one, so far more of it stays in each XCD's L2 under random gathers.
+template <bool NIB, int S>
+__device__ __forceinline__ void gather_colours(const int (&u)[S], const bool (&take)[S],
+                                               const RSOC_GLOBAL uint8_t *col8, const RSOC_GLOBAL uint32_t *col4,
+                                               int (&out)[S]) {
+    if (!NIB) {
+#pragma unroll
+        for (int s = 0; s < S; ++s) out[s] = take[s] ? (int)col8[u[s]] : 255;
+        return;
+    }
+    uint32_t w[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) w[s] = take[s] ? col4[u[s] >> 3] : 0xffffffffu;
+#pragma unroll
+    for (int s = 0; s < S; ++s) out[s] = (int)((w[s] >> ((u[s] & 7) << 2)) & 15u);
+#pragma unroll
+    for (int s = 0; s < S; ++s)
+        if (take[s] && out[s] == 15) out[s] = col8[u[s]];
+#pragma unroll
+    for (int s = 0; s < S; ++s)
+        if (!take[s]) out[s] = 255;
+}
+
+template <int PHASE, int TIE, int G, int S, bool WIN_ONLY, int NV, bool NIB = false>
 __device__ __forceinline__ void group_vertices(const int (&v)[NV], const int (&b)[NV], const int (&e)[NV],
                                                const RSOC_GLOBAL int32_t *const (&ci)[NV],
                                                const RSOC_GLOBAL uint8_t *const (&col8)[NV], const int (&cv)[NV],
-                                               int look, int (&newc)[NV], bool (&act)[NV], bool (&unc)[NV]) {
+                                               int look, int (&newc)[NV], bool (&act)[NV], bool (&unc)[NV],
+                                               const RSOC_GLOBAL uint32_t *const *col4 = nullptr) {
     const int k = lane_id() & (G - 1);
     int u[NV][S];
     int cu[NV][S];
@@ -53,12 +81,12 @@ __device__ __forceinline__ void group_vertices(const int (&v)[NV], const int (&b
     if (PHASE != kAssign) {
         bool def[NV];
 #pragma unroll
-        for (int i = 0; i < NV; ++i)
+        for (int i = 0; i < NV; ++i) {
+            bool w[S];
 #pragma unroll
-            for (int s = 0; s < S; ++s) {
-                const bool w = (u[i][s] != v[i]) && loses<TIE>(v[i], u[i][s]);
-                cu[i][s] = w ? (int)col8[i][u[i][s]] : 255;
-            }
+            for (int s = 0; s < S; ++s) w[s] = (u[i][s] != v[i]) && loses<TIE>(v[i], u[i][s]);
+            gather_colours<NIB, S>(u[i], w, col8[i], NIB ? col4[i] : nullptr, cu[i]);
+        }
 #pragma unroll
         for (int i = 0; i < NV; ++i) {
             bool c = false;
@@ -69,22 +97,30 @@ __device__ __forceinline__ void group_vertices(const int (&v)[NV], const int (&b
         }
         if (PHASE == kDetect) return;
 #pragma unroll
-        for (int i = 0; i < NV; ++i)
+        for (int i = 0; i < NV; ++i) {
+            bool rest[S];
+            int c2[S];
+#pragma unroll
+            for (int s = 0; s < S; ++s) rest[s] = def[i] && u[i][s] != v[i] && !loses<TIE>(v[i], u[i][s]);
+            gather_colours<NIB, S>(u[i], rest, col8[i], NIB ? col4[i] : nullptr, c2);
 #pragma unroll
             for (int s = 0; s < S; ++s)
-                if (def[i] && u[i][s] != v[i] && !loses<TIE>(v[i], u[i][s])) cu[i][s] = col8[i][u[i][s]];
+                if (rest[s]) cu[i][s] = c2[s];
+        }
     } else {
 #pragma unroll
         for (int i = 0; i < NV; ++i) {
-            bool un = false;
+            bool take[S], win[S];
 #pragma unroll
             for (int s = 0; s < S; ++s) {
-                const bool win = (u[i][s] != v[i]) && loses<TIE>(v[i], u[i][s]);
+                win[s] = (u[i][s] != v[i]) && loses<TIE>(v[i], u[i][s]);
                 const int dist = u[i][s] > v[i] ? u[i][s] - v[i] : v[i] - u[i][s];
-                const bool take = WIN_ONLY ? (win || (u[i][s] != v[i] && dist < look)) : (u[i][s] != v[i]);
-                cu[i][s] = take ? (int)col8[i][u[i][s]] : 255;
-                un |= win && cu[i][s] == 255;
+                take[s] = WIN_ONLY ? (win[s] || (u[i][s] != v[i] && dist < look)) : (u[i][s] != v[i]);
             }
+            gather_colours<NIB, S>(u[i], take, col8[i], NIB ? col4[i] : nullptr, cu[i]);
+            bool un = false;
+#pragma unroll
+            for (int s = 0; s < S; ++s) un |= win[s] && cu[i][s] == 255;
             unc[i] = group_any<G>(un);
             act[i] = true;
         }
