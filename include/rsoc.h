@@ -110,7 +110,12 @@ typedef struct {
      * its rows: 8 when ids carry locality (natural-order meshes, where
      * neighbours coloured at the same instant would conflict), else 1. */
     int32_t chunk;
-    int32_t reserved[2]; /* must be zero */
+    /* Workgroups given to the thread bin of worklist rounds (rounds >= 1 over
+     * a list; default 2048).  Those rounds are latency-bound chains of
+     * dependent loads (list entry, row, neighbour colours), so they want more
+     * workgroups in flight than the sweeps. */
+    int32_t grid_list;
+    int32_t reserved[1]; /* must be zero */
 } rsoc_options;
 
 typedef struct {

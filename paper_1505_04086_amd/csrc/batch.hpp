@@ -217,7 +217,7 @@ inline int32_t run_batch(rsoc_ctx *c, int32_t G, const int64_t *vtx_off, const i
     RSOC_HIP(hipMemcpyAsync(c->b_args.p, &a, sizeof(a), hipMemcpyHostToDevice, s));
     const int gBl = std::min(nB, 256);
     const int gWl = std::min(div_up(nW, kWavesPerBlock), o.grid_wave);
-    const int gTl = (int)std::max<int64_t>(1, std::min<int64_t>(div_up(nT, kStep), o.grid_thread));
+    const int gTl = (int)std::max<int64_t>(1, std::min<int64_t>(div_up(nT, kStep), o.grid_list));
     hipGraphExec_t gexec = nullptr;
     RSOC_TRY(get_batch_graph(c, o.mode, o.tie, o.rounds_per_sync, gBl, gWl, gTl, &gexec));
 

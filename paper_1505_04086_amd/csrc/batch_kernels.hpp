@@ -304,7 +304,8 @@ __global__ __launch_bounds__(kBlock) void k_bround(const BatchArgs *__restrict__
             }
             for (int r = 0; r < kChunk; ++r) {
                 int v[kNV], b[kNV], e[kNV], cv[kNV], nc[kNV], gg[kNV];
-                bool act[kNV], unc[kNV] = {};
+                bool act[kNV];
+                uint32_t unc[kNV] = {};
                 const RSOC_GLOBAL int32_t *cis[kNV];
                 const RSOC_GLOBAL uint8_t *c8s[kNV];
                 int64_t vo[kNV];
@@ -348,7 +349,10 @@ __global__ __launch_bounds__(kBlock) void k_bround(const BatchArgs *__restrict__
                                                                                act, unc);
 #pragma unroll
                 for (int i = 0; i < kNV; ++i) {
-                    if (v[i] < 0) act[i] = unc[i] = false;
+                    if (v[i] < 0) {
+                        act[i] = false;
+                        unc[i] = 0;
+                    }
                     if (leader && v[i] >= 0) {
                         items += 1;
                         degs += (uint64_t)(e[i] - b[i]);
@@ -361,7 +365,7 @@ __global__ __launch_bounds__(kBlock) void k_bround(const BatchArgs *__restrict__
                 if (kAppend) {
 #pragma unroll
                     for (int i = 0; i < kNV; ++i)
-                        queue_push64((kFlagAppend ? unc[i] : act[i]) && leader, pack_item(gg[i], v[i]), q, &qn);
+                        queue_push64((kFlagAppend ? unc[i] != 0 : act[i]) && leader, pack_item(gg[i], v[i]), q, &qn);
                     __syncthreads();
                     if (qn > kQueueCap - kSub) queue_flush64(q, &qn, &qbase, &S->cnt_out[kBinThread], out);
                 }

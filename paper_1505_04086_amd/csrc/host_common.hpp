@@ -91,7 +91,7 @@ struct HostPinned {
 
 struct Options {
     int mode, tie, max_rounds, validate, t_thread, t_wave, grid_thread, grid_wave, rounds_per_sync, small_cutoff,
-        timing, full_sweep, lookahead, chunk;
+        timing, full_sweep, lookahead, chunk, grid_list;
 };
 
 inline int32_t resolve_options(const rsoc_options *o, int64_t n, Options &r) {
@@ -103,9 +103,9 @@ inline int32_t resolve_options(const rsoc_options *o, int64_t n, Options &r) {
     if (r.mode < RSOC_MODE_OPTIMISTIC || r.mode > RSOC_MODE_TWO_PHASE) return RSOC_EINVAL;
     if (r.tie != RSOC_TIE_LOWER_KEEPS && r.tie != RSOC_TIE_HIGHER_KEEPS) return RSOC_EINVAL;
     if (d.max_rounds < 0 || d.t_thread < 0 || d.t_thread > 32 || d.t_wave < 0 || d.grid_thread < 0 ||
-        d.grid_wave < 0 || d.rounds_per_sync < 0 || d.validate < 0 || d.validate > 3)
+        d.grid_wave < 0 || d.rounds_per_sync < 0 || d.validate < 0 || d.validate > 3 || d.grid_list < 0)
         return RSOC_EINVAL;
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < 1; ++i)
         if (d.reserved[i]) return RSOC_EINVAL;
     if (d.chunk != 0 && d.chunk != 1 && d.chunk != 2 && d.chunk != 4 && d.chunk != 8) return RSOC_EINVAL;
     r.chunk = d.chunk;
@@ -120,6 +120,7 @@ inline int32_t resolve_options(const rsoc_options *o, int64_t n, Options &r) {
     if (r.t_wave < r.t_thread) r.t_wave = r.t_thread;
     r.grid_thread = d.grid_thread ? d.grid_thread : 1024;
     r.grid_wave = d.grid_wave ? d.grid_wave : 512;
+    r.grid_list = d.grid_list ? d.grid_list : 2048;
     r.rounds_per_sync = d.rounds_per_sync ? d.rounds_per_sync : 8;
     if (r.rounds_per_sync & 1) r.rounds_per_sync += 1;  // worklist buffers alternate: keep it even
     r.small_cutoff = d.small_cutoff == 0 ? 4096 : (d.small_cutoff < 0 ? -1 : d.small_cutoff);

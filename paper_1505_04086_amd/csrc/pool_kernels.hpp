@@ -98,7 +98,8 @@ __device__ __forceinline__ void pool_thread_task(PoolSlot *sp, const PoolSlot &s
     for (int base = tk.begin; base < tk.end; base += kStep) {
         for (int r = 0; r < kChunk; ++r) {
             int v[kNV], b[kNV], e[kNV], cv[kNV], nc[kNV];
-            bool act[kNV], unc[kNV] = {};
+            bool act[kNV];
+            uint32_t unc[kNV] = {};
 #pragma unroll
             for (int i = 0; i < kNV; ++i) {
                 const int idx = base + step_offset(r, i, gi, s.chunk);
@@ -121,7 +122,10 @@ __device__ __forceinline__ void pool_thread_task(PoolSlot *sp, const PoolSlot &s
                                                                            unc);
 #pragma unroll
             for (int i = 0; i < kNV; ++i) {
-                if (v[i] < 0) act[i] = unc[i] = false;
+                if (v[i] < 0) {
+                    act[i] = false;
+                    unc[i] = 0;
+                }
                 if (leader && act[i]) {
                     wcol[v[i]] = nc[i];
                     if (opt) wcol8[v[i]] = (uint8_t)nc[i];
@@ -129,7 +133,7 @@ __device__ __forceinline__ void pool_thread_task(PoolSlot *sp, const PoolSlot &s
             }
 #pragma unroll
             for (int i = 0; i < kNV; ++i)
-                queue_push((KIND == kAssignSweep ? unc[i] : act[i]) && leader, v[i], q, qn);
+                queue_push((KIND == kAssignSweep ? unc[i] != 0 : act[i]) && leader, v[i], q, qn);
             __syncthreads();
             if (*qn > kQueueCap - kSub) queue_flush(q, qn, qbase, &sp->cnt_out[kBinThread], out);
         }

@@ -1,7 +1,8 @@
 // single.hpp -- host driver of the single-graph path (rsoc_color_device and friends).
 //
-// Round 0 and round 1 touch every vertex and are launched directly; the later
-// rounds only touch the worklist and are launched as a captured HIP graph of
+// Round 0 and round 1 are launched directly (both cover all of V, except in
+// the default optimistic flow, where round 1 is the masked pass over U^0);
+// the later rounds only touch the worklist and are launched as a captured HIP graph of
 // `rounds_per_sync` rounds, after which the host reads the worklist size (one
 // 64-byte copy) and either stops or replays the graph.  ROCm 7.2 has no
 // conditional graph nodes, so every kernel of a captured round first reads the
@@ -18,7 +19,7 @@ struct rsoc_ctx {
     int device = 0;
     hipStream_t own = nullptr;    // stream for host-pointer calls
     hipStream_t cap = nullptr;    // capture stream
-    rsoc::DevBuf wl0, wl1, hubW, hubB, pend, flags, col8, col4;
+    rsoc::DevBuf wl0, wl1, hubW, hubB, pend, flags, col8, col4, aux;
     rsoc::DevBuf args, state;     // SingleArgs, SingleState (fixed addresses: graphs point at them)
     rsoc::HostPinned host;        // pinned staging for small copies
     rsoc::DevBuf drp, dci, dcol;  // device copies for host-pointer calls
@@ -59,7 +60,7 @@ inline void ctx_free(rsoc_ctx *c) {
     c->graphs.clear();
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);
-    for (rsoc::DevBuf *b : {&c->col8, &c->col4, &c->wl0, &c->wl1, &c->hubW, &c->hubB, &c->pend, &c->flags, &c->args, &c->state, &c->drp,
+    for (rsoc::DevBuf *b : {&c->col8, &c->col4, &c->aux, &c->wl0, &c->wl1, &c->hubW, &c->hubB, &c->pend, &c->flags, &c->args, &c->state, &c->drp,
                             &c->dci, &c->dcol, &c->b_desc, &c->b_wl0, &c->b_wl1, &c->b_pend, &c->b_flags,
                             &c->b_state, &c->b_hub, &c->b_kmax, &c->b_tasks, &c->b_args, &c->b_col8})
         b->release();
@@ -123,10 +124,11 @@ inline int32_t get_round_graph(rsoc_ctx *c, int mode, int tie, int K, int gB, in
     return RSOC_OK;
 }
 
-// Rounds 0 and 1 (both cover all of V).  Returns after enqueueing.
+// Rounds 0 and 1.  gB/gW/gT split the sweep grid, gBl/gWl/gTl the worklist
+// grid.  Returns after enqueueing; the next round reads worklist buffer 0.
 template <int MODE, int TIE>
-inline void launch_sweep_rounds(rsoc_ctx *c, hipStream_t s, int32_t *col, int n, int gB, int gW, int gT, bool timing,
-                                bool full_sweep) {
+inline void launch_sweep_rounds(rsoc_ctx *c, hipStream_t s, int32_t *col, int n, int gB, int gW, int gT, int gBl,
+                                int gWl, int gTl, bool timing, bool full_sweep) {
     const SingleArgs *A = c->args.as<SingleArgs>();
     SingleState *S = c->state.as<SingleState>();
     const int grid = gB + gW + gT;
@@ -148,11 +150,19 @@ inline void launch_sweep_rounds(rsoc_ctx *c, hipStream_t s, int32_t *col, int n,
                 k_round<kAssign, kOptimistic, TIE, true, 0><<<grid, kBlock, 0, s>>>(A, S, 1, gB, gW, gT);
             } else {
                 // ... over the neighbours each vertex loses to, collecting the
-                // only vertices that can end the round defective as U^0
-                k_round<kAssign, kOptimistic, TIE, true, 1><<<grid, kBlock, 0, s>>>(A, S, 1, gB, gW, gT);
+                // only vertices that can end the round defective as U^0 (into
+                // buffer 1, with their position masks)
+                k_round<kAssign, kOptimistic, TIE, true, 1><<<grid, kBlock, 0, s>>>(A, S, 0, gB, gW, gT);
                 if (timing) (void)hipEventRecord(c->ev[3], s);
                 k_round_end<MODE, true, true><<<1, 64, 0, s>>>(A, S);
-                return;  // round 1 is the first worklist round
+                // round 1: detect-and-recolour over U^0, testing only the
+                // masked neighbours of thread-bin vertices; appends to buffer 0
+                if (timing) (void)hipEventRecord(c->ev[4], s);
+                k_round<kRecolor, kOptimistic, TIE, false, 2><<<gBl + gWl + gTl, kBlock, 0, s>>>(A, S, 1, gBl, gWl,
+                                                                                                  gTl);
+                if (timing) (void)hipEventRecord(c->ev[5], s);
+                k_round_end<MODE, false><<<1, 64, 0, s>>>(A, S);
+                return;
             }
         }
     }
@@ -175,19 +185,18 @@ inline void launch_sweep_rounds(rsoc_ctx *c, hipStream_t s, int32_t *col, int n,
 }
 
 inline void launch_sweep_dyn(rsoc_ctx *c, hipStream_t s, int mode, int tie, int32_t *col, int n, int gB, int gW,
-                             int gT, bool timing, bool full) {
+                             int gT, int gBl, int gWl, int gTl, bool timing, bool full) {
+#define RSOC_SWEEP(M, T) launch_sweep_rounds<M, T>(c, s, col, n, gB, gW, gT, gBl, gWl, gTl, timing, full)
     if (mode == kOptimistic)
-        tie ? launch_sweep_rounds<kOptimistic, kHigherKeeps>(c, s, col, n, gB, gW, gT, timing, full)
-            : launch_sweep_rounds<kOptimistic, kLowerKeeps>(c, s, col, n, gB, gW, gT, timing, full);
+        tie ? RSOC_SWEEP(kOptimistic, kHigherKeeps) : RSOC_SWEEP(kOptimistic, kLowerKeeps);
     else if (mode == kDeterministic)
-        tie ? launch_sweep_rounds<kDeterministic, kHigherKeeps>(c, s, col, n, gB, gW, gT, timing, full)
-            : launch_sweep_rounds<kDeterministic, kLowerKeeps>(c, s, col, n, gB, gW, gT, timing, full);
+        tie ? RSOC_SWEEP(kDeterministic, kHigherKeeps) : RSOC_SWEEP(kDeterministic, kLowerKeeps);
     else
-        tie ? launch_sweep_rounds<kTwoPhase, kHigherKeeps>(c, s, col, n, gB, gW, gT, timing, full)
-            : launch_sweep_rounds<kTwoPhase, kLowerKeeps>(c, s, col, n, gB, gW, gT, timing, full);
+        tie ? RSOC_SWEEP(kTwoPhase, kHigherKeeps) : RSOC_SWEEP(kTwoPhase, kLowerKeeps);
+#undef RSOC_SWEEP
 }
 
-inline int32_t ensure_single_scratch(rsoc_ctx *c, int64_t n) {
+inline int32_t ensure_single_scratch(rsoc_ctx *c, int64_t n, bool need_aux) {
     const size_t b = sizeof(int32_t) * (size_t)(n + 2);
     RSOC_TRY(c->wl0.reserve(b));
     RSOC_TRY(c->wl1.reserve(b));
@@ -197,6 +206,7 @@ inline int32_t ensure_single_scratch(rsoc_ctx *c, int64_t n) {
     RSOC_TRY(c->flags.reserve(b));
     RSOC_TRY(c->col8.reserve((size_t)n + 64));
     RSOC_TRY(c->col4.reserve(sizeof(uint32_t) * (size_t)(n / 8 + 2)));
+    if (need_aux) RSOC_TRY(c->aux.reserve(sizeof(int4) * (size_t)(n + 2)));
     return RSOC_OK;
 }
 
@@ -212,16 +222,20 @@ inline int32_t status_from_err(int32_t err) {
 //     + neighbour colours 4 nnz + colour writes 4n + hub lists 4(nW+nB);
 //   round 0, optimistic, default: the same but neighbour colours only for the
 //     neighbours a vertex loses to (4 nnz/2 on a symmetric graph without
-//     self-loops) plus 4 |U^0| for collecting U^0;
+//     self-loops) plus 8 |U^0| for collecting U^0 with its position masks
+//     (read back, 4 |U^0|, by round 1);
 //   round 0, round-synchronous: the colour fill 4n;
 //   round 1 as a sweep: row_ptr 4(n+1) + own colour 4n + 8 nnz + hub lists,
 //     plus per recoloured vertex 8 (colour write + append), or 20 when staged
 //     (stage write, append, then list read, stage read, colour write);
+//   round 1 over U^0 (default optimistic flow): the masks 4 |U^0| plus the
+//     worklist-round cost below of its own inspections;
 //   worklist rounds: per inspected vertex 16 (list entry, row_ptr pair, own
-//     colour) + 8 per adjacency entry + the per-recoloured cost above.
+//     colour) + 8 per adjacency entry read (the masked round 1 reads only the
+//     masked entries of a vertex it keeps) + the per-recoloured cost above.
 inline void alg_bytes(int mode, bool full_sweep, int64_t n, int64_t nnz, int64_t nW, int64_t nB, int64_t u0,
-                      int64_t L1, int64_t conflicts, uint64_t inspected, uint64_t deg_sum, int64_t &b0, int64_t &b1,
-                      int64_t &total) {
+                      int64_t L1, int64_t conflicts, uint64_t inspected, uint64_t deg_sum, uint64_t inspected1,
+                      uint64_t deg_sum1, int64_t &b0, int64_t &b1, int64_t &total) {
     const int64_t per_rec = (mode == kOptimistic) ? 8 : 20;
     if (mode == kTwoPhase) {
         b0 = 4 * n;
@@ -231,9 +245,9 @@ inline void alg_bytes(int mode, bool full_sweep, int64_t n, int64_t nnz, int64_t
         return;
     }
     if (mode == kOptimistic && !full_sweep) {
-        b0 = 4 * (n + 1) + 4 * nnz + 4 * (nnz / 2) + 4 * n + 4 * (nW + nB) + 4 * u0;
-        b1 = 0;
-        total = b0 + 16 * (int64_t)inspected + 8 * (int64_t)deg_sum + per_rec * conflicts;
+        b0 = 4 * (n + 1) + 4 * nnz + 4 * (nnz / 2) + 4 * n + 4 * (nW + nB) + 8 * u0;
+        b1 = 4 * u0 + 16 * (int64_t)inspected1 + 8 * (int64_t)deg_sum1 + per_rec * L1;
+        total = b0 + 4 * u0 + 16 * (int64_t)inspected + 8 * (int64_t)deg_sum + per_rec * conflicts;
         return;
     }
     b0 = (mode == kOptimistic) ? 4 * (n + 1) + 8 * nnz + 4 * n + 4 * (nW + nB) : 4 * n;
@@ -261,7 +275,7 @@ inline int32_t run_single(rsoc_ctx *c, const int32_t *rp, const int32_t *ci, int
     if (h->rp_ends[0] != 0 || h->rp_ends[1] < 0) return RSOC_ECSR;
     const int64_t nnz = h->rp_ends[1];
     if (nnz > 0 && !ci) return RSOC_EINVAL;
-    RSOC_TRY(ensure_single_scratch(c, n));
+    RSOC_TRY(ensure_single_scratch(c, n, o.mode == kOptimistic && !o.full_sweep));
 
     SingleArgs &a = h->args;
     a.rp = rp;
@@ -270,6 +284,7 @@ inline int32_t run_single(rsoc_ctx *c, const int32_t *rp, const int32_t *ci, int
     a.col8 = c->col8.as<uint8_t>();
     a.col4 = c->col4.as<uint32_t>();
     a.pend = c->pend.as<int32_t>();
+    a.aux = c->aux.as<int4>();
     a.wl[0] = c->wl0.as<int32_t>();
     a.wl[1] = c->wl1.as<int32_t>();
     a.hubW = c->hubW.as<int32_t>();
@@ -315,13 +330,13 @@ inline int32_t run_single(rsoc_ctx *c, const int32_t *rp, const int32_t *ci, int
     RSOC_HIP(hipMemcpyAsync(c->args.p, &a, sizeof(a), hipMemcpyHostToDevice, s));
     const int gBl = std::min(nB, 256);
     const int gWl = std::min(div_up(nW, kWavesPerBlock), o.grid_wave);
-    const int gTl = std::max(1, std::min(div_up(nT, kStep), o.grid_thread));
+    const int gTl = std::max(1, std::min(div_up(nT, kStep), o.grid_list));
 
     hipGraphExec_t gexec = nullptr;
     RSOC_TRY(get_round_graph(c, o.mode, o.tie, o.rounds_per_sync, gBl, gWl, gTl, &gexec));
 
     RSOC_HIP(hipEventRecord(c->ev[0], s));
-    launch_sweep_dyn(c, s, o.mode, o.tie, col, n, gB, gW, gTs, o.timing != 0, o.full_sweep != 0);
+    launch_sweep_dyn(c, s, o.mode, o.tie, col, n, gB, gW, gTs, gBl, gWl, gTl, o.timing != 0, o.full_sweep != 0);
     RSOC_LAUNCH_CHECK();
     int32_t status = RSOC_OK;
     for (;;) {
@@ -370,14 +385,14 @@ inline int32_t run_single(rsoc_ctx *c, const int32_t *rp, const int32_t *ci, int
         if (o.timing) {
             float m0 = 0, m1 = 0;
             RSOC_HIP(hipEventElapsedTime(&m0, c->ev[2], c->ev[3]));
-            if (sweep1) RSOC_HIP(hipEventElapsedTime(&m1, c->ev[4], c->ev[5]));
+            RSOC_HIP(hipEventElapsedTime(&m1, c->ev[4], c->ev[5]));
             st->ms_round0 = m0;
             st->ms_round1 = m1;
         }
         int64_t b0, b1, tot;
         const int64_t l1 = h->head.rounds > 0 ? L1 : 0;
         alg_bytes(o.mode, o.full_sweep != 0, n, nnz, nW, nB, h->head.u0, l1, h->head.conflicts, h->head.inspected,
-                  h->head.deg_sum, b0, b1, tot);
+                  h->head.deg_sum, h->head.inspected1, h->head.deg_sum1, b0, b1, tot);
         st->bytes_round0 = b0;
         st->worklist0 = sweep1 ? n : h->head.u0;
         st->chunk = a.chunk;

@@ -23,6 +23,8 @@ struct SingleArgs {
     uint8_t *col8;       // byte shadow of the colours: min(colour, 255), 255 when uncoloured
     uint32_t *col4;      // 4-bit shadow (8 per word): min(colour, 15); 15 = consult col8 (optimistic mode)
     int32_t *pend;       // staged colours (round-synchronous modes), indexed by vertex
+    int4 *aux;           // optimistic mode: what round 0 kept for U^0's thread-bin entries (parallel
+                         // to that part of the list): up to three neighbour ids, position mask
     int32_t *wl[2];      // worklist buffers; bin segments start at 0, offW, offB
     int32_t *hubW;       // static list of wavefront-bin vertices
     int32_t *hubB;       // static list of workgroup-bin vertices
@@ -51,6 +53,7 @@ struct SingleState {
     uint64_t deg_sum;     // their degree sum
     int32_t u0;           // |U^0| when round 0 collects it (optimistic, default flow)
     int32_t pad;
+    uint64_t inspected1, deg_sum1;  // inspected / deg_sum as they stood after the first worklist round
     uint64_t near, sampled;  // id locality sample: row entries with |u - v| < kChunk, entries sampled
     int32_t hist[kHistCap];  // |L| of recolouring round i+1
 };
@@ -101,8 +104,11 @@ __device__ __forceinline__ int block_max(int x, int *sh) {
 // ------------------------------------------------------------------ bin --
 // Splits V by degree: deg <= t_thread stays implicit (thread bin); larger rows
 // go to the static wavefront / workgroup lists.  Also finds the max degree.
-__device__ __forceinline__ void queue_push(bool take, int v, int *q, int *qn);
-__device__ __forceinline__ void queue_flush(int *q, int *qn, int *qbase, int *counter, int32_t *out);
+template <class T = int>
+__device__ __forceinline__ void queue_push(bool take, int v, int *q, int *qn, T *qx = nullptr, T x = T());
+template <class T = int>
+__device__ __forceinline__ void queue_flush(int *q, int *qn, int *qbase, int *counter, int32_t *out,
+                                            const T *qx = nullptr, T *outx = nullptr);
 
 __global__ __launch_bounds__(kBlock) void k_bin(const SingleArgs *__restrict__ A, SingleState *S) {
     __shared__ int sh[kWavesPerBlock];
@@ -169,6 +175,8 @@ __global__ __launch_bounds__(kBlock) void k_locality(const int32_t *__restrict__
 // Per-wavefront append buffer in LDS (wavefront-bin vertices are appended one
 // at a time by lane 0; one global atomic per kWaveBuf entries).
 constexpr int kWaveBuf = 64;
+constexpr int kMaskedBuf = 512;  // flushed when fewer than a wavefront's worth of slots are left
+constexpr int kAuxCap = 1024;    // round-0 queue length when U^0 entries carry their kept neighbours
 
 template <class T>
 __device__ __forceinline__ void wave_buf_flush(T *buf, int *bn, int *counter, T *out) {
@@ -178,7 +186,7 @@ __device__ __forceinline__ void wave_buf_flush(T *buf, int *bn, int *counter, T 
     int base = 0;
     if (lane_id() == 0) base = atomicAdd(counter, cnt);
     base = __shfl(base, 0);
-    if (lane_id() < cnt) out[base + lane_id()] = buf[lane_id()];
+    for (int i = lane_id(); i < cnt; i += kWave) out[base + i] = buf[i];
     wave_lds_sync();
     if (lane_id() == 0) *bn = 0;
     wave_lds_sync();
@@ -192,30 +200,90 @@ __device__ __forceinline__ void wave_buf_push(bool take, T x, T *buf, int *bn, i
     if (*bn == kWaveBuf) wave_buf_flush(buf, bn, counter, out);
 }
 
-// Appends v for every lane with `take` into the workgroup's LDS queue.  Called
-// by every thread of the workgroup in lockstep (the loop is workgroup-uniform).
-__device__ __forceinline__ void queue_push(bool take, int v, int *q, int *qn) {
+// Appends v for every lane with `take` into the workgroup's LDS queue (and,
+// when qx is given, x beside it).  Called by every thread of the workgroup in
+// lockstep (the loop is workgroup-uniform).
+template <class T>
+__device__ __forceinline__ void queue_push(bool take, int v, int *q, int *qn, T *qx, T x) {
     const uint64_t m = ballot(take);
     if (m == 0) return;
     const int leader = __ffsll((unsigned long long)m) - 1;
     int base = 0;
     if (lane_id() == leader) base = atomicAdd(qn, __popcll(m));
     base = __shfl(base, leader);
-    if (take) q[base + lanes_below(m)] = v;
+    if (take) {
+        q[base + lanes_below(m)] = v;
+        if (qx) qx[base + lanes_below(m)] = x;
+    }
 }
 
-// Moves the queue to the global list (one global atomic per flush).
-__device__ __forceinline__ void queue_flush(int *q, int *qn, int *qbase, int *counter, int32_t *out) {
+// Moves the queue to the global list (one global atomic per flush); the side
+// entries qx, when given, go to the same positions of outx.
+template <class T>
+__device__ __forceinline__ void queue_flush(int *q, int *qn, int *qbase, int *counter, int32_t *out, const T *qx,
+                                            T *outx) {
     __syncthreads();
     const int cnt = *qn;
     if (cnt == 0) return;
     if (threadIdx.x == 0) *qbase = atomicAdd(counter, cnt);
     __syncthreads();
     const int base = *qbase;
-    for (int i = threadIdx.x; i < cnt; i += kBlock) out[base + i] = q[i];
+    for (int i = threadIdx.x; i < cnt; i += kBlock) {
+        out[base + i] = q[i];
+        if (qx) outx[base + i] = qx[i];
+    }
     __syncthreads();
     if (threadIdx.x == 0) *qn = 0;
     __syncthreads();
+}
+
+// Masked round: the entries of this wavefront selected by sel (bit = lane,
+// vertex v of that lane) are staged in the wavefront's LDS slots ms and
+// handled kGroup lanes each: PH = kAssign gives a vertex known to be defective
+// First-Fit over all neighbours; PH = kRecolor detects first.  Recoloured
+// vertices are written (colour, byte shadow, nibble invalidated) and added to
+// the wavefront's append buffer mb (*mbn entries).
+template <int PH, int TIE, bool NIB>
+__device__ __forceinline__ void wave_recolour_selected(uint64_t sel, int v, int *ms, int *mb, int *mbn,
+                                                       const RSOC_GLOBAL int32_t *rp, const RSOC_GLOBAL int32_t *ci,
+                                                       const RSOC_GLOBAL uint8_t *col8,
+                                                       const RSOC_GLOBAL uint32_t *col4, RSOC_GLOBAL int32_t *wcol,
+                                                       RSOC_GLOBAL uint8_t *wcol8, RSOC_GLOBAL uint32_t *wcol4,
+                                                       int look, uint64_t &degs) {
+    if (sel & (1ull << lane_id())) ms[lanes_below(sel)] = v;
+    wave_lds_sync();
+    const int nd = __popcll(sel);
+    const int gi = lane_id() / kGroup;
+    const bool leader = (lane_id() & (kGroup - 1)) == 0;
+    for (int d0 = 0; d0 < nd; d0 += kWave / kGroup) {
+        int gv[1] = {-1}, gb[1] = {0}, ge[1] = {0}, gcv[1] = {255}, gnc[1] = {0};
+        bool gact[1];
+        uint32_t gunc[1] = {};
+        if (d0 + gi < nd) {
+            gv[0] = ms[d0 + gi];
+            gb[0] = rp[gv[0]];
+            ge[0] = rp[gv[0] + 1];
+            if (PH != kAssign) gcv[0] = col8[gv[0]];
+        }
+        const RSOC_GLOBAL int32_t *gci[1] = {ci};
+        const RSOC_GLOBAL uint8_t *gc8[1] = {col8};
+        const RSOC_GLOBAL uint32_t *gc4[1] = {col4};
+        group_vertices<PH, TIE, kGroup, kGroupSlots, false, 1, NIB>(gv, gb, ge, gci, gc8, gcv, look, gnc, gact, gunc,
+                                                                   gc4);
+        const bool w = leader && gv[0] >= 0 && gact[0];
+        if (leader && gv[0] >= 0) degs += (uint64_t)(ge[0] - gb[0]);
+        if (w) {
+            wcol[gv[0]] = gnc[0];
+            wcol8[gv[0]] = (uint8_t)gnc[0];
+            // a recoloured vertex's nibble becomes 15: readers then use col8
+            if (NIB) atomicOr((uint32_t *)&wcol4[gv[0] >> 3], 0xfu << ((gv[0] & 7) << 2));
+        }
+        const uint64_t am = ballot(w);
+        if (w) mb[*mbn + lanes_below(am)] = gv[0];
+        wave_lds_sync();
+        if (lane_id() == 0) *mbn += __popcll(am);
+        wave_lds_sync();
+    }
 }
 
 // ---------------------------------------------------------------- round --
@@ -230,16 +298,27 @@ __device__ __forceinline__ void queue_flush(int *q, int *qn, int *qbase, int *co
 // ROUND0 (kAssign only): 0 = First-Fit over all neighbours, no appends;
 // 1 = First-Fit over the neighbours v loses to, sweeping in the order that
 // visits them first, and v is appended to the next worklist iff one of them
-// was still uncoloured when read (only such v can end round 0 defective).
+// was still uncoloured when read (only such v can end round 0 defective); a
+// thread-bin v also stores which neighbours those were (aux).
+// ROUND0 = 2 (kRecolor, optimistic, worklist): the round right after that:
+// thread-bin entries take one lane each and only test the stored positions
+// (lane_detect_masked); the defective ones are then recoloured by lane groups.
 template <int PHASE, int MODE, int TIE, bool SWEEP, int ROUND0 = 0>
 __global__ __launch_bounds__(kBlock) void k_round(const SingleArgs *__restrict__ A, SingleState *S, int parity,
                                                   int gB, int gW, int gT) {
     __shared__ uint32_t lds[kLdsWords];
+    constexpr bool kFlagAppend = PHASE == kAssign && ROUND0 == 1;
+    constexpr bool kMasked = PHASE == kRecolor && ROUND0 == 2 && !SWEEP && MODE == kOptimistic;
     __shared__ int q[kQueueCap];
+    __shared__ int4 qa[kFlagAppend ? kAuxCap : 1];
     __shared__ int sh_min, qn, qbase;
     __shared__ unsigned long long sh_acc[2];
     __shared__ int wbuf[kWavesPerBlock][kWaveBuf];
     __shared__ int wbn[kWavesPerBlock];
+    // masked round: per-wavefront defective staging and append buffer
+    __shared__ int mstage[kMasked ? kWavesPerBlock : 1][kMasked ? kWave : 1];
+    __shared__ int mbuf[kMasked ? kWavesPerBlock : 1][kMasked ? kMaskedBuf : 1];
+    __shared__ int mbn[kWavesPerBlock];
     const SingleArgs a = *A;
     if (!SWEEP && S->passes >= a.max_rounds) return;  // guard: the round may not run
     const int cT = SWEEP ? a.n : S->cnt_in[kBinThread];
@@ -263,7 +342,6 @@ __global__ __launch_bounds__(kBlock) void k_round(const SingleArgs *__restrict__
     constexpr bool kPublish = kNib && PHASE == kAssign && SWEEP;
     const RSOC_GLOBAL uint32_t *rcol4 = gro(a.col4);
     RSOC_GLOBAL uint32_t *wcol4 = grw(a.col4);
-    constexpr bool kFlagAppend = PHASE == kAssign && ROUND0 == 1;
     constexpr bool kWinOnly = kFlagAppend;
     constexpr bool kAppend = PHASE != kAssign || kFlagAppend;
     constexpr bool kWrite = PHASE != kDetect;
@@ -318,6 +396,57 @@ __global__ __launch_bounds__(kBlock) void k_round(const SingleArgs *__restrict__
                                        out + a.offW);
         }
         if (kAppend) wave_buf_flush(wbuf[wv], &wbn[wv], &S->cnt_out[kBinWave], out + a.offW);
+    } else if (kMasked) {
+        // one lane per list entry; wavefronts run independently (no workgroup
+        // barrier): defective vertices are staged in the wavefront's LDS slots
+        // and recoloured kGroup lanes each, appends gather in its LDS buffer
+        const int wv = threadIdx.x / kWave;
+        const int nwv = gT * kWavesPerBlock;
+        int *ms = mstage[wv];
+        int *mb = mbuf[wv];
+        if (lane_id() == 0) mbn[wv] = 0;
+        wave_lds_sync();
+        typedef int v4i __attribute__((ext_vector_type(4)));
+        const RSOC_GLOBAL v4i *ax = (const RSOC_GLOBAL v4i *)a.aux;
+        for (int64_t base = (int64_t)((bid - gB - gW) * kWavesPerBlock + wv) * kWave; base < cT;
+             base += (int64_t)nwv * kWave) {
+            const int64_t idx = base + lane_id();
+            int v = -1, cv = 255;
+            int4 x = {0, 0, 0, 0};
+            if (idx < cT) {
+                v = inT[idx];
+                const v4i y = ax[idx];
+                x = make_int4(y.x, y.y, y.z, y.w);
+                cv = rcol8[v];
+            }
+            // up to three kept neighbours: tested here; more: the lane groups
+            // run the full detection for that vertex
+            const bool over = v >= 0 && __popc((uint32_t)x.w) > 3;
+            const bool def = v >= 0 && !over && lane_detect_kept<kNib>(v, x, cv, rcol8, rcol4);
+            if (v >= 0) {
+                items += 1;
+                degs += (uint64_t)__popc((uint32_t)x.w);
+            }
+            wave_recolour_selected<kAssign, TIE, kNib>(ballot(def), v, ms, mb, &mbn[wv], rp, ci, rcol8, rcol4, wcol,
+                                                       wcol8, wcol4, a.look, degs);
+            const uint64_t om = ballot(over);
+            if (om)
+                wave_recolour_selected<kRecolor, TIE, kNib>(om, v, ms, mb, &mbn[wv], rp, ci, rcol8, rcol4, wcol,
+                                                            wcol8, wcol4, a.look, degs);
+            if (mbn[wv] >= kMaskedBuf - kWave) wave_buf_flush(mb, &mbn[wv], &S->cnt_out[kBinThread], out);
+        }
+        // what the wavefronts still hold leaves in one workgroup-wide flush
+        // (one global atomic per workgroup instead of one per wavefront)
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int tot = 0;
+            for (int w = 0; w < kWavesPerBlock; ++w) tot += mbn[w];
+            qbase = tot ? atomicAdd(&S->cnt_out[kBinThread], tot) : 0;
+        }
+        __syncthreads();
+        int off = qbase;
+        for (int w = 0; w < wv; ++w) off += mbn[w];
+        for (int i = lane_id(); i < mbn[wv]; i += kWave) out[off + i] = mb[i];
     } else {
         int tb = bid - gB - gW;
         // worklist-free sweeps that need no particular order keep each XCD on
@@ -337,7 +466,9 @@ __global__ __launch_bounds__(kBlock) void k_round(const SingleArgs *__restrict__
             for (int i = 0; i < kNV; ++i) acc[i] = ~0u;
             for (int r = 0; r < kChunk; ++r) {
                 int v[kNV], b[kNV], e[kNV], cv[kNV], nc[kNV];
-                bool act[kNV], unc[kNV] = {};
+                bool act[kNV];
+                uint32_t unc[kNV] = {};
+                int keep[kNV][4];
 #pragma unroll
                 for (int i = 0; i < kNV; ++i) {
                     const int64_t idx = base + step_offset(r, i, gi, a.chunk);
@@ -363,10 +494,14 @@ __global__ __launch_bounds__(kBlock) void k_round(const SingleArgs *__restrict__
 #pragma unroll
                 for (int i = 0; i < kNV; ++i) cis[i] = ci, c8s[i] = rcol8, c4s[i] = rcol4;
                 group_vertices<PHASE, TIE, kGroup, kGroupSlots, kWinOnly, kNV, kNib>(v, b, e, cis, c8s, cv, a.look, nc,
-                                                                                     act, unc, c4s);
+                                                                                     act, unc, c4s,
+                                                                                     kFlagAppend ? keep : nullptr);
 #pragma unroll
                 for (int i = 0; i < kNV; ++i) {
-                    if (v[i] < 0) act[i] = unc[i] = false;
+                    if (v[i] < 0) {
+                        act[i] = false;
+                        unc[i] = 0;
+                    }
                     if (leader && v[i] >= 0) {
                         items += 1;
                         degs += (uint64_t)(e[i] - b[i]);
@@ -404,13 +539,19 @@ __global__ __launch_bounds__(kBlock) void k_round(const SingleArgs *__restrict__
                 if (kAppend) {
 #pragma unroll
                     for (int i = 0; i < kNV; ++i)
-                        queue_push((kFlagAppend ? unc[i] : act[i]) && leader, v[i], q, &qn);
+                        queue_push<int4>((kFlagAppend ? unc[i] != 0 : act[i]) && leader, v[i], q, &qn,
+                                         kFlagAppend ? qa : nullptr,
+                                         kFlagAppend ? make_int4(keep[i][0], keep[i][1], keep[i][2], keep[i][3])
+                                                     : int4{});
                     __syncthreads();
-                    if (qn > kQueueCap - kSub) queue_flush(q, &qn, &qbase, &S->cnt_out[kBinThread], out);
+                    if (qn > (kFlagAppend ? kAuxCap : kQueueCap) - kSub)
+                        queue_flush<int4>(q, &qn, &qbase, &S->cnt_out[kBinThread], out, kFlagAppend ? qa : nullptr,
+                                          a.aux);
                 }
             }
         }
-        if (kAppend) queue_flush(q, &qn, &qbase, &S->cnt_out[kBinThread], out);
+        if (kAppend)
+            queue_flush<int4>(q, &qn, &qbase, &S->cnt_out[kBinThread], out, kFlagAppend ? qa : nullptr, a.aux);
     }
     if (kAcct) {
         if (threadIdx.x == 0) { sh_acc[0] = 0; sh_acc[1] = 0; }
@@ -485,6 +626,10 @@ __global__ void k_round_end(const SingleArgs *__restrict__ A, SingleState *S) {
     const int out_total = S->cnt_out[0] + S->cnt_out[1] + S->cnt_out[2];
     if (in_total > 0) {
         S->passes += 1;
+        if (S->passes == 1) {
+            S->inspected1 = S->inspected;
+            S->deg_sum1 = S->deg_sum;
+        }
         if (MODE == kTwoPhase) {
             if (S->rounds < kHistCap) S->hist[S->rounds] = out_total;
             S->rounds += 1;

@@ -32,8 +32,10 @@ namespace rsoc {
 // NV vertices per group are handled together so that their loads overlap.
 // In kAssign, WIN_ONLY restricts First-Fit to the neighbours v loses to plus
 // the neighbours it wins against whose id lies within `look` of v's (those
-// the sweep may already have coloured); unc[i] reports whether a neighbour v
-// loses to was still uncoloured when read.
+// the sweep may already have coloured); unc[i] gets one bit per row position
+// (bit p for row entry b+p) of the neighbours v loses to that were still
+// uncoloured when read (zero: none was).  When keep is given (kAssign only),
+// keep[i] = {ids of the first three such neighbours (-1 past the last), unc[i]}.
 // ci[i] / col8[i] / col4[i] are the (per-graph) bases vertex i's ids refer to.
 //
 // NIB: colours are first read from a 4-bit shadow (eight vertices per 32-bit
@@ -66,8 +68,10 @@ template <int PHASE, int TIE, int G, int S, bool WIN_ONLY, int NV, bool NIB = fa
 __device__ __forceinline__ void group_vertices(const int (&v)[NV], const int (&b)[NV], const int (&e)[NV],
                                                const RSOC_GLOBAL int32_t *const (&ci)[NV],
                                                const RSOC_GLOBAL uint8_t *const (&col8)[NV], const int (&cv)[NV],
-                                               int look, int (&newc)[NV], bool (&act)[NV], bool (&unc)[NV],
-                                               const RSOC_GLOBAL uint32_t *const *col4 = nullptr) {
+                                               int look, int (&newc)[NV], bool (&act)[NV], uint32_t (&unc)[NV],
+                                               const RSOC_GLOBAL uint32_t *const *col4 = nullptr,
+                                               int (*keep)[4] = nullptr) {
+    static_assert(G * S <= 32 && G < 64, "a row must fit one 32-bit position mask");
     const int k = lane_id() & (G - 1);
     int u[NV][S];
     int cu[NV][S];
@@ -118,11 +122,30 @@ __device__ __forceinline__ void group_vertices(const int (&v)[NV], const int (&b
                 take[s] = WIN_ONLY ? (win[s] || (u[i][s] != v[i] && dist < look)) : (u[i][s] != v[i]);
             }
             gather_colours<NIB, S>(u[i], take, col8[i], NIB ? col4[i] : nullptr, cu[i]);
-            bool un = false;
+            // lane k holds row positions k + s*G: slot s of the group's lanes
+            // is one G-bit field of the ballot
+            const int g0 = lane_id() & ~(G - 1);
+            uint32_t um = 0;
 #pragma unroll
-            for (int s = 0; s < S; ++s) un |= win[s] && cu[i][s] == 255;
-            unc[i] = group_any<G>(un);
+            for (int s = 0; s < S; ++s)
+                um |= (uint32_t)((ballot(win[s] && cu[i][s] == 255) >> g0) & ((1ull << G) - 1)) << (s * G);
+            unc[i] = um;
             act[i] = true;
+            if (keep) {
+                // row position p sits in slot p / G of lane g0 + p % G
+                uint32_t mm = um;
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    const int p = mm ? __builtin_ctz(mm) : 0;
+                    mm &= mm - 1;
+                    int cand = u[i][0];
+#pragma unroll
+                    for (int s = 1; s < S; ++s) cand = (p / G == s) ? u[i][s] : cand;
+                    const int got = __shfl(cand, g0 + (p & (G - 1)));
+                    keep[i][j] = (j < __popc(um)) ? got : -1;
+                }
+                keep[i][3] = (int)um;
+            }
         }
     }
 #pragma unroll
@@ -133,6 +156,31 @@ __device__ __forceinline__ void group_vertices(const int (&v)[NV], const int (&b
         mask = group_or64<G>(mask);
         newc[i] = (int)__builtin_ctzll(~mask);
     }
+}
+
+// Detection of the first worklist round after the pruned round 0, one lane per
+// vertex, for a v with at most three kept neighbours.  x is what round 0 kept
+// for v: the ids of the neighbours v loses to that were uncoloured when read
+// (x.x, x.y, x.z; -1 past the last) and in x.w their row positions (see
+// group_vertices).  Every other neighbour v loses to was already coloured
+// when v chose its colour, so v's First-Fit avoided that colour, and neither
+// has been recoloured since: only the kept neighbours can hold v's colour.
+template <bool NIB>
+__device__ __forceinline__ bool lane_detect_kept(int v, int4 x, int cv, const RSOC_GLOBAL uint8_t *col8,
+                                                 const RSOC_GLOBAL uint32_t *col4) {
+    const int cnt = __popc((uint32_t)x.w);
+    int u[3] = {x.x, x.y, x.z}, cu[3];
+    bool t[3];
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+        t[s] = s < cnt;
+        if (!t[s]) u[s] = v;
+    }
+    gather_colours<NIB, 3>(u, t, col8, col4, cu);
+    bool def = false;
+#pragma unroll
+    for (int s = 0; s < 3; ++s) def |= t[s] && cu[s] == cv;
+    return def;
 }
 
 // -------------------------------------------------------------- wavefront --

@@ -3,7 +3,8 @@
 The tunable options (rsoc_options) are the degree-bin thresholds (t_thread:
 largest row coloured by an 8-lane group; t_wave: largest row coloured by one
 wavefront), the workgroups given to the thread and wavefront bins, the run
-length of consecutive ids a lane group walks (chunk), the round-0 lookahead
+length of consecutive ids a lane group walks (chunk), the workgroups of the
+thread bin in worklist rounds (grid_list), the round-0 lookahead
 and the number of worklist rounds captured per host check.  The tuner runs
 coordinate descent over them: each option in turn is set to each candidate
 value while the others keep their best values so far, timed with the real
@@ -34,6 +35,7 @@ SPACE = {
     "t_wave": [256, 1024, 2048, 8192],
     "grid_thread": [512, 1024, 2048, 4096],
     "grid_wave": [128, 512, 1024],
+    "grid_list": [1024, 2048, 4096, 8192],
     "chunk": [1, 2, 4, 8],
     "lookahead": [-1, 1 << 18, 1 << 20, 1 << 22],
     "rounds_per_sync": [4, 8, 16],

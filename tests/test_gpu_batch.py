@@ -29,7 +29,7 @@ def _mixed_batch():
 
 GRAPHS = _mixed_batch()
 BATCH = gg.concat(GRAPHS)
-SPLITS = {"default": {}, "allbins": {"t_thread": 3, "t_wave": 8}, "runs1": {"chunk": 1, "grid_thread": 7},
+SPLITS = {"default": {}, "allbins": {"t_thread": 3, "t_wave": 8}, "runs1": {"chunk": 1, "grid_thread": 7, "grid_list": 2},
           "runs8": {"chunk": 8, "grid_thread": 3}}
 
 

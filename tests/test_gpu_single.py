@@ -40,6 +40,9 @@ def _small_cases():
         "isolated": (np.zeros(8, np.int32), np.zeros(0, np.int32)), "single": (np.zeros(2, np.int32), np.zeros(0, np.int32)),
         "rmat10": gg.rmat(10, 8, seed=2, shuffle_seed=3), "rgg": gg.rgg(3000, seed=4),
         "kbip": gg.complete_bipartite(40, 90),
+        # thread-bin rows whose neighbours are all coloured at the same instant:
+        # round 0 keeps more than three (K30) and full 32-position masks (K33)
+        "K30": gg.complete(30), "K33": gg.complete(33), "gnp_dense": gg.random_gnp(64, 0.45, 9),
     }
     rng = np.random.default_rng(1505)
     for i in range(6):
@@ -51,8 +54,8 @@ def _small_cases():
 CASES = _small_cases()
 # degree-bin thresholds small enough to route small graphs through every bin
 BIN_SPLITS = {"default": {}, "allbins": {"t_thread": 3, "t_wave": 8}, "wave_only": {"t_thread": 1, "t_wave": 100000},
-              "block_only": {"t_thread": 1, "t_wave": 1}, "runs1": {"chunk": 1, "grid_thread": 3},
-              "runs8": {"chunk": 8, "grid_thread": 5}, "runs2": {"chunk": 2, "t_thread": 16}}
+              "block_only": {"t_thread": 1, "t_wave": 1}, "runs1": {"chunk": 1, "grid_thread": 3, "grid_list": 3},
+              "runs8": {"chunk": 8, "grid_thread": 5, "grid_list": 1}, "runs2": {"chunk": 2, "t_thread": 16}}
 
 
 @pytest.mark.parametrize("split", sorted(BIN_SPLITS))
