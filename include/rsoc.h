@@ -102,7 +102,7 @@ typedef struct {
     int32_t full_sweep;
     /* Optimistic default flow: round 0 also reads neighbours it wins against
      * whose id is within this distance (the sweep may have coloured them
-     * already).  0 = library default (twice the ids all workgroups cover in one step),
+     * already).  0 = library default (the ids all workgroups cover in one step; for batches twice that),
      * -1 = none. */
     int32_t lookahead;
     /* Run of consecutive vertex ids one 8-lane group colours one after the

@@ -76,6 +76,14 @@ __device__ __forceinline__ bool group_any(bool p) {
     return ((m >> g0) & ((G == 64) ? ~0ull : ((1ull << G) - 1))) != 0;
 }
 
+// OR of a 32-bit value over the G-lane group (butterfly).
+template <int G>
+__device__ __forceinline__ uint32_t group_or32(uint32_t x) {
+#pragma unroll
+    for (int off = 1; off < G; off <<= 1) x |= __shfl_xor(x, off);
+    return x;
+}
+
 // OR of a 64-bit value over the G-lane group (butterfly).
 template <int G>
 __device__ __forceinline__ uint64_t group_or64(uint64_t x) {

@@ -324,7 +324,7 @@ inline int32_t run_single(rsoc_ctx *c, const int32_t *rp, const int32_t *ci, int
     const int gW = std::min(div_up(nW, kWavesPerBlock), o.grid_wave);
     int gTs = std::min(div_up(n, kStep), o.grid_thread);
     if (gTs >= kXcds) gTs -= gTs % kXcds;
-    const int64_t look = o.lookahead == -1 ? 0 : (o.lookahead > 0 ? o.lookahead : 2ll * gTs * kStep);
+    const int64_t look = o.lookahead == -1 ? 0 : (o.lookahead > 0 ? o.lookahead : (int64_t)gTs * kStep);
     a.look = (int)std::min<int64_t>(look, INT32_MAX);
     a.chunk = pick_chunk(o.chunk, h->head.near, h->head.sampled);
     RSOC_HIP(hipMemcpyAsync(c->args.p, &a, sizeof(a), hipMemcpyHostToDevice, s));

@@ -60,6 +60,15 @@ struct SingleState {
 
 __device__ __forceinline__ uint8_t shadow_of(int c) { return (uint8_t)((unsigned)c < 255u ? c : 255); }
 
+// Round 0 of the optimistic mode: v's nibble is 15 (nothing written since the
+// fill) and becomes min(c, 15) with one atomic AND, so that the colour is
+// visible to the 4-bit gathers as soon as it is chosen (hub bins; the lane
+// groups combine the nibbles of one word first).
+__device__ __forceinline__ void publish_nibble(RSOC_GLOBAL uint32_t *col4, int v, int c) {
+    const int sh = (v & 7) << 2;
+    atomicAnd((uint32_t *)&col4[v >> 3], ~(0xfu << sh) | ((uint32_t)min(c, 15) << sh));
+}
+
 // ------------------------------------------------------------------ fill --
 __global__ void k_fill(int32_t *p, uint8_t *p8, int64_t n, int32_t value) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
@@ -259,12 +268,18 @@ __device__ __forceinline__ void wave_recolour_selected(uint64_t sel, int v, int 
         int gv[1] = {-1}, gb[1] = {0}, ge[1] = {0}, gcv[1] = {255}, gnc[1] = {0};
         bool gact[1];
         uint32_t gunc[1] = {};
+        int x = 0;
+        const int k = lane_id() & (kGroup - 1);
         if (d0 + gi < nd) {
             gv[0] = ms[d0 + gi];
-            gb[0] = rp[gv[0]];
-            ge[0] = rp[gv[0] + 1];
-            if (PH != kAssign) gcv[0] = col8[gv[0]];
+            if (k < 2) x = rp[gv[0] + k];
+            else if (PH != kAssign && k == 2) x = col8[gv[0]];
         }
+        const int g0 = lane_id() & ~(kGroup - 1);
+        gb[0] = __shfl(x, g0);
+        ge[0] = __shfl(x, g0 + 1);
+        if (PH != kAssign) gcv[0] = __shfl(x, g0 + 2);
+        if (gv[0] < 0) gb[0] = ge[0] = 0, gcv[0] = 255;
         const RSOC_GLOBAL int32_t *gci[1] = {ci};
         const RSOC_GLOBAL uint8_t *gc8[1] = {col8};
         const RSOC_GLOBAL uint32_t *gc4[1] = {col4};
@@ -335,11 +350,11 @@ __global__ __launch_bounds__(kBlock) void k_round(const SingleArgs *__restrict__
     const RSOC_GLOBAL uint8_t *rcol8 = gro(a.col8);
     RSOC_GLOBAL int32_t *wcol = grw((MODE == kOptimistic) ? a.col : a.pend);
     RSOC_GLOBAL uint8_t *wcol8 = grw(a.col8);
-    // The 4-bit shadow is used by the optimistic, lower-keeps path (its sweeps
-    // run in ascending id order, so each 8-vertex word is finished by one
-    // wavefront inside one workgroup step and published with a plain store).
-    constexpr bool kNib = MODE == kOptimistic && TIE == kLowerKeeps;
-    constexpr bool kPublish = kNib && PHASE == kAssign && SWEEP;
+    // The 4-bit shadow is kept in optimistic mode (colours change in place):
+    // round 0 publishes each colour into it as soon as it is chosen
+    // (publish_nibble); a recoloured vertex's nibble becomes 15.
+    constexpr bool kNib = MODE == kOptimistic;
+    constexpr bool kPublish = kNib && PHASE == kAssign;
     const RSOC_GLOBAL uint32_t *rcol4 = gro(a.col4);
     RSOC_GLOBAL uint32_t *wcol4 = grw(a.col4);
     constexpr bool kWinOnly = kFlagAppend;
@@ -364,6 +379,8 @@ __global__ __launch_bounds__(kBlock) void k_round(const SingleArgs *__restrict__
                 if (act && kWrite) {
                     wcol[v] = nc;
                     if (MODE == kOptimistic) wcol8[v] = shadow_of(nc);
+                    if (kPublish) publish_nibble(wcol4, v, nc);
+                    else if (kNib) atomicOr((uint32_t *)&wcol4[v >> 3], 0xfu << ((v & 7) << 2));
                 }
                 if (take) q[qn++] = v;
             }
@@ -390,6 +407,8 @@ __global__ __launch_bounds__(kBlock) void k_round(const SingleArgs *__restrict__
                 if (act && kWrite) {
                     wcol[v] = nc;
                     if (MODE == kOptimistic) wcol8[v] = shadow_of(nc);
+                    if (kPublish) publish_nibble(wcol4, v, nc);
+                    else if (kNib) atomicOr((uint32_t *)&wcol4[v >> 3], 0xfu << ((v & 7) << 2));
                 }
             }
             if (kAppend) wave_buf_push((kFlagAppend ? unc : act), v, wbuf[wv], &wbn[wv], &S->cnt_out[kBinWave],
@@ -461,32 +480,42 @@ __global__ __launch_bounds__(kBlock) void k_round(const SingleArgs *__restrict__
         const int c = a.chunk;
         const int64_t stride = (int64_t)gT * kStep;
         for (int64_t base = (int64_t)tb * kStep; base < cT; base += stride) {
-            uint32_t acc[kNV];  // nibbles of the words being finished (kPublish)
-#pragma unroll
-            for (int i = 0; i < kNV; ++i) acc[i] = ~0u;
             for (int r = 0; r < kChunk; ++r) {
                 int v[kNV], b[kNV], e[kNV], cv[kNV], nc[kNV];
                 bool act[kNV];
                 uint32_t unc[kNV] = {};
                 int keep[kNV][4];
+                // per-vertex scalars are loaded by one lane of the group each
+                // and shuffled to the others: the texture addresser's work
+                // grows with the lanes a load has active, not with its lines
+                const int k = threadIdx.x & (kGroup - 1);
+                const int g0 = lane_id() & ~(kGroup - 1);
 #pragma unroll
                 for (int i = 0; i < kNV; ++i) {
                     const int64_t idx = base + step_offset(r, i, gi, a.chunk);
                     v[i] = -1;
-                    b[i] = e[i] = 0;
                     if (idx < cT) {
-                        v[i] = SWEEP ? ((kFlagAppend && TIE == kHigherKeeps) ? (int)(cT - 1 - idx) : (int)idx)
-                                     : inT[idx];
+                        if (SWEEP) {
+                            v[i] = (kFlagAppend && TIE == kHigherKeeps) ? (int)(cT - 1 - idx) : (int)idx;
+                        } else {
+                            int x = 0;
+                            if (k == 0) x = inT[idx];
+                            v[i] = __shfl(x, g0);
+                        }
                     }
                 }
 #pragma unroll
                 for (int i = 0; i < kNV; ++i) {
+                    int x = 0;
                     if (v[i] >= 0) {
-                        b[i] = rp[v[i]];
-                        e[i] = rp[v[i] + 1];
-                        if (SWEEP && e[i] - b[i] > a.t_thread) e[i] = b[i] = 0, v[i] = -1;  // another bin's vertex
+                        if (k < 2) x = rp[v[i] + k];
+                        else if (PHASE != kAssign && k == 2) x = rcol8[v[i]];
                     }
-                    cv[i] = (PHASE != kAssign && v[i] >= 0) ? (int)rcol8[v[i]] : 255;
+                    b[i] = __shfl(x, g0);
+                    e[i] = __shfl(x, g0 + 1);
+                    cv[i] = (PHASE != kAssign && v[i] >= 0) ? __shfl(x, g0 + 2) : 255;
+                    if (v[i] < 0) b[i] = e[i] = 0;
+                    if (SWEEP && e[i] - b[i] > a.t_thread) e[i] = b[i] = 0, v[i] = -1;  // another bin's vertex
                 }
                 const RSOC_GLOBAL int32_t *cis[kNV];
                 const RSOC_GLOBAL uint8_t *c8s[kNV];
@@ -509,31 +538,34 @@ __global__ __launch_bounds__(kBlock) void k_round(const SingleArgs *__restrict__
                             wcol[v[i]] = nc[i];
                             if (MODE == kOptimistic) wcol8[v[i]] = (uint8_t)nc[i];
                             // a recoloured vertex's nibble becomes 15: readers then use col8
+                            // (round 0 publishes nibbles below, one atomic per word)
                             if (kNib && !kPublish) atomicOr((uint32_t *)&wcol4[v[i] >> 3], 0xfu << ((v[i] & 7) << 2));
                         }
                     }
                 }
                 if (kPublish) {
-                    // nibble of each vertex coloured here; a word of 8 ids is
-                    // covered by 8/c groups of one wavefront over c sub-steps
+                    // Publish the nibbles coloured in this sub-step: the ids of
+                    // the wavefront's 8 groups are monotone in the group index,
+                    // so the groups sharing a 32-bit word are contiguous; a
+                    // segmented OR-scan over them gathers the bits to clear and
+                    // the last group of each word issues one atomic AND.
+                    const int g = lane_id() / kGroup;
 #pragma unroll
-                    for (int i = 0; i < kNV; ++i)
-                        if (v[i] >= 0) {
-                            const int sh = (v[i] & 7) << 2;
-                            acc[i] = (acc[i] & ~(0xfu << sh)) | ((uint32_t)min(nc[i], 15) << sh);
-                        }
-                    if ((r & (c - 1)) == c - 1) {
-                        const int span = 8 / c;  // lane groups sharing one word
+                    for (int i = 0; i < kNV; ++i) {
+                        const int64_t idx = base + step_offset(r, i, gi, c);
+                        const int id = idx < cT ? ((kFlagAppend && TIE == kHigherKeeps) ? (int)(cT - 1 - idx) : (int)idx)
+                                                : -1;
+                        const int key = id >= 0 ? (id >> 3) : -1 - g;
+                        uint32_t clr = v[i] >= 0 ? (0xfu ^ (uint32_t)min(nc[i], 15)) << ((v[i] & 7) << 2) : 0u;
 #pragma unroll
-                        for (int i = 0; i < kNV; ++i) {
-                            uint32_t x = acc[i];
-                            for (int off = kGroup; off < kGroup * span; off <<= 1) x &= __shfl_xor(x, off);
-                            if ((threadIdx.x & (kGroup * span - 1)) == 0) {
-                                const int64_t pos = base + step_offset(r - (c - 1), i, gi, c);
-                                if (pos < cT) wcol4[pos >> 3] = x;
-                            }
-                            acc[i] = ~0u;
+                        for (int d = 1; d < kWave / kGroup; d <<= 1) {
+                            const uint32_t oc = __shfl_up(clr, d * kGroup);
+                            const int ok = __shfl_up(key, d * kGroup);
+                            if (g >= d && ok == key) clr |= oc;
                         }
+                        const int nk = __shfl_down(key, kGroup);
+                        const bool last = g == kWave / kGroup - 1 || nk != key;
+                        if (leader && last && clr) atomicAnd((uint32_t *)&wcol4[key], ~clr);
                     }
                 }
                 if (kAppend) {

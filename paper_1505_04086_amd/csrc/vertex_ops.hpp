@@ -21,8 +21,7 @@ namespace rsoc {
 
 // ------------------------------------------------------------ lane group --
 // Rows of at most kThreadBinMax entries.  The G lanes of a group first load
-// the whole row (S entries per lane, all loads issued before any is used),
-// then gather neighbour colours from the byte-wide colour shadow col8
+// the whole row (load_row: one aligned 16-byte piece per lane), then gather neighbour colours from the byte-wide colour shadow col8
 // (min(colour, 255); 255 also marks "uncoloured").  A thread-bin vertex has a
 // colour <= its degree < 64, so only shadow values < 64 can equal it or block
 // its First-Fit, and the byte shadow loses nothing.  In detect phases only
@@ -40,28 +39,79 @@ namespace rsoc {
 //
 // NIB: colours are first read from a 4-bit shadow (eight vertices per 32-bit
 // word, value min(colour, 15)); a nibble of 15 ("15 or more, or uncoloured")
-// falls back to the byte shadow.  The 4-bit array is half the size of the
-// byte one, so far more of it stays in each XCD's L2 under random gathers.
+// falls back to the byte shadow where exact[s] is set, and reads as
+// uncoloured (255) elsewhere.  The 4-bit array is half the size of the byte
+// one, so far more of it stays in each XCD's L2 under random gathers.
+// Colour reads are agent-scope relaxed loads: a kernel that colours in place
+// must not be served a line its compute unit's L1 cached before another
+// compute unit wrote the colour (a stale "uncoloured" costs conflicts).
+__device__ __forceinline__ uint32_t colour_word(const RSOC_GLOBAL uint32_t *p) {
+    return __hip_atomic_load((const uint32_t *)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int colour_byte(const RSOC_GLOBAL uint8_t *p) {
+    return (int)__hip_atomic_load((const uint8_t *)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 template <bool NIB, int S>
-__device__ __forceinline__ void gather_colours(const int (&u)[S], const bool (&take)[S],
+__device__ __forceinline__ void gather_colours(const int (&u)[S], const bool (&take)[S], const bool (&exact)[S],
                                                const RSOC_GLOBAL uint8_t *col8, const RSOC_GLOBAL uint32_t *col4,
                                                int (&out)[S]) {
     if (!NIB) {
 #pragma unroll
-        for (int s = 0; s < S; ++s) out[s] = take[s] ? (int)col8[u[s]] : 255;
+        for (int s = 0; s < S; ++s) out[s] = take[s] ? colour_byte(col8 + u[s]) : 255;
         return;
     }
     uint32_t w[S];
 #pragma unroll
-    for (int s = 0; s < S; ++s) w[s] = take[s] ? col4[u[s] >> 3] : 0xffffffffu;
+    for (int s = 0; s < S; ++s) w[s] = take[s] ? colour_word(col4 + (u[s] >> 3)) : 0xffffffffu;
 #pragma unroll
     for (int s = 0; s < S; ++s) out[s] = (int)((w[s] >> ((u[s] & 7) << 2)) & 15u);
 #pragma unroll
     for (int s = 0; s < S; ++s)
-        if (take[s] && out[s] == 15) out[s] = col8[u[s]];
+        if (out[s] == 15) out[s] = (take[s] && exact[s]) ? colour_byte(col8 + u[s]) : 255;
 #pragma unroll
     for (int s = 0; s < S; ++s)
         if (!take[s]) out[s] = 255;
+}
+
+template <bool NIB, int S>
+__device__ __forceinline__ void gather_colours(const int (&u)[S], const bool (&take)[S],
+                                               const RSOC_GLOBAL uint8_t *col8, const RSOC_GLOBAL uint32_t *col4,
+                                               int (&out)[S]) {
+    gather_colours<NIB, S>(u, take, take, col8, col4, out);
+}
+
+// Row layout in a lane group (G = 8 lanes, rows of at most 32 entries): the
+// row [b, e) is read as the 16-byte-aligned pieces that overlap it.  With
+// off = (address of row entry 0 / 4) mod 4, lane k loads piece k of the
+// 128-byte window that starts off entries before the row (slots 0..3 = row
+// positions 4k - off .. 4k - off + 3), and lanes k < off load row position
+// 32 + k - off into slot 4 when the row reaches past the window.  A piece is
+// loaded only if it holds an entry of the row, so no load leaves the pages
+// the row occupies.  One instruction fetches the whole row (one or two cache
+// lines) instead of one per slot.
+constexpr int kRowSlots = 5;
+
+template <int G>
+__device__ __forceinline__ void load_row(int v, int b, int e, const RSOC_GLOBAL int32_t *ci, int (&u)[kRowSlots],
+                                         int (&pos)[kRowSlots], int &off) {
+    static_assert(G == 8, "row layout assumes 8 lanes of 4 entries");
+    typedef int v4i __attribute__((ext_vector_type(4)));
+    const int k = lane_id() & (G - 1);
+    const int deg = e - b;
+    const RSOC_GLOBAL int32_t *row = ci + b;
+    off = (int)(((uintptr_t)row >> 2) & 3);
+    const RSOC_GLOBAL int32_t *win = row - off;
+    const int p0 = 4 * k - off;
+    v4i q = {v, v, v, v};
+    if (p0 + 3 >= 0 && p0 < deg) q = __builtin_nontemporal_load((const RSOC_GLOBAL v4i *)win + k);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        pos[s] = p0 + s;
+        u[s] = (pos[s] >= 0 && pos[s] < deg) ? q[s] : v;
+    }
+    pos[4] = 32 + k - off;
+    u[4] = (pos[4] < deg) ? __builtin_nontemporal_load(win + 32 + k) : v;
 }
 
 template <int PHASE, int TIE, int G, int S, bool WIN_ONLY, int NV, bool NIB = false>
@@ -71,77 +121,80 @@ __device__ __forceinline__ void group_vertices(const int (&v)[NV], const int (&b
                                                int look, int (&newc)[NV], bool (&act)[NV], uint32_t (&unc)[NV],
                                                const RSOC_GLOBAL uint32_t *const *col4 = nullptr,
                                                int (*keep)[4] = nullptr) {
-    static_assert(G * S <= 32 && G < 64, "a row must fit one 32-bit position mask");
-    const int k = lane_id() & (G - 1);
-    int u[NV][S];
-    int cu[NV][S];
+    static_assert(G == 8 && S == 4, "rows of at most 32 entries over 8 lanes");
+    constexpr int T = kRowSlots;
+    int u[NV][T], pos[NV][T], off[NV];
+    int cu[NV][T];
 #pragma unroll
-    for (int i = 0; i < NV; ++i)
-#pragma unroll
-        for (int s = 0; s < S; ++s) {
-            const int j = b[i] + k + s * G;
-            u[i][s] = (j < e[i]) ? __builtin_nontemporal_load(ci[i] + j) : v[i];
-        }
+    for (int i = 0; i < NV; ++i) load_row<G>(v[i], b[i], e[i], ci[i], u[i], pos[i], off[i]);
     if (PHASE != kAssign) {
         bool def[NV];
 #pragma unroll
         for (int i = 0; i < NV; ++i) {
-            bool w[S];
+            bool w[T];
 #pragma unroll
-            for (int s = 0; s < S; ++s) w[s] = (u[i][s] != v[i]) && loses<TIE>(v[i], u[i][s]);
-            gather_colours<NIB, S>(u[i], w, col8[i], NIB ? col4[i] : nullptr, cu[i]);
+            for (int s = 0; s < T; ++s) w[s] = (u[i][s] != v[i]) && loses<TIE>(v[i], u[i][s]);
+            gather_colours<NIB, T>(u[i], w, col8[i], NIB ? col4[i] : nullptr, cu[i]);
         }
 #pragma unroll
         for (int i = 0; i < NV; ++i) {
             bool c = false;
 #pragma unroll
-            for (int s = 0; s < S; ++s) c |= (cu[i][s] == cv[i]);
+            for (int s = 0; s < T; ++s) c |= (cu[i][s] == cv[i]);
             def[i] = group_any<G>(c);
             act[i] = def[i];
         }
         if (PHASE == kDetect) return;
 #pragma unroll
         for (int i = 0; i < NV; ++i) {
-            bool rest[S];
-            int c2[S];
+            bool rest[T];
+            int c2[T];
 #pragma unroll
-            for (int s = 0; s < S; ++s) rest[s] = def[i] && u[i][s] != v[i] && !loses<TIE>(v[i], u[i][s]);
-            gather_colours<NIB, S>(u[i], rest, col8[i], NIB ? col4[i] : nullptr, c2);
+            for (int s = 0; s < T; ++s) rest[s] = def[i] && u[i][s] != v[i] && !loses<TIE>(v[i], u[i][s]);
+            gather_colours<NIB, T>(u[i], rest, col8[i], NIB ? col4[i] : nullptr, c2);
 #pragma unroll
-            for (int s = 0; s < S; ++s)
+            for (int s = 0; s < T; ++s)
                 if (rest[s]) cu[i][s] = c2[s];
         }
     } else {
 #pragma unroll
         for (int i = 0; i < NV; ++i) {
-            bool take[S], win[S];
+            bool take[T], win[T];
 #pragma unroll
-            for (int s = 0; s < S; ++s) {
+            for (int s = 0; s < T; ++s) {
                 win[s] = (u[i][s] != v[i]) && loses<TIE>(v[i], u[i][s]);
                 const int dist = u[i][s] > v[i] ? u[i][s] - v[i] : v[i] - u[i][s];
                 take[s] = WIN_ONLY ? (win[s] || (u[i][s] != v[i] && dist < look)) : (u[i][s] != v[i]);
             }
-            gather_colours<NIB, S>(u[i], take, col8[i], NIB ? col4[i] : nullptr, cu[i]);
-            // lane k holds row positions k + s*G: slot s of the group's lanes
-            // is one G-bit field of the ballot
-            const int g0 = lane_id() & ~(G - 1);
-            uint32_t um = 0;
+            // WIN_ONLY reads take a nibble of 15 as uncoloured, without the
+            // byte-shadow fallback: a colour of 15 or more then looks as if v
+            // had read u before u was coloured, an interleaving the round
+            // allows anyway (u gets v's unc bit if v loses to it)
+            bool exact[T];
 #pragma unroll
-            for (int s = 0; s < S; ++s)
-                um |= (uint32_t)((ballot(win[s] && cu[i][s] == 255) >> g0) & ((1ull << G) - 1)) << (s * G);
+            for (int s = 0; s < T; ++s) exact[s] = !WIN_ONLY && take[s];
+            gather_colours<NIB, T>(u[i], take, exact, col8[i], NIB ? col4[i] : nullptr, cu[i]);
+            uint32_t bits = 0;
+#pragma unroll
+            for (int s = 0; s < T; ++s)
+                if (win[s] && cu[i][s] == 255) bits |= 1u << pos[i][s];
+            const uint32_t um = group_or32<G>(bits);
             unc[i] = um;
             act[i] = true;
             if (keep) {
-                // row position p sits in slot p / G of lane g0 + p % G
+                // row position p sits in window entry q = p + off: slot q % 4
+                // of lane q / 4, or slot 4 of lane q - 32 past the window
+                const int g0 = lane_id() & ~(G - 1);
                 uint32_t mm = um;
 #pragma unroll
                 for (int j = 0; j < 3; ++j) {
-                    const int p = mm ? __builtin_ctz(mm) : 0;
+                    const int q = (mm ? __builtin_ctz(mm) : 0) + off[i];
                     mm &= mm - 1;
+                    const int slot = q < 32 ? (q & 3) : 4;
                     int cand = u[i][0];
 #pragma unroll
-                    for (int s = 1; s < S; ++s) cand = (p / G == s) ? u[i][s] : cand;
-                    const int got = __shfl(cand, g0 + (p & (G - 1)));
+                    for (int s = 1; s < T; ++s) cand = (slot == s) ? u[i][s] : cand;
+                    const int got = __shfl(cand, g0 + (q < 32 ? (q >> 2) : q - 32));
                     keep[i][j] = (j < __popc(um)) ? got : -1;
                 }
                 keep[i][3] = (int)um;
@@ -152,7 +205,7 @@ __device__ __forceinline__ void group_vertices(const int (&v)[NV], const int (&b
     for (int i = 0; i < NV; ++i) {
         uint64_t mask = 0;
 #pragma unroll
-        for (int s = 0; s < S; ++s) mask |= (cu[i][s] < 64) ? (1ull << cu[i][s]) : 0ull;
+        for (int s = 0; s < T; ++s) mask |= (cu[i][s] < 64) ? (1ull << cu[i][s]) : 0ull;
         mask = group_or64<G>(mask);
         newc[i] = (int)__builtin_ctzll(~mask);
     }
