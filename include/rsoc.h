@@ -90,7 +90,7 @@ typedef struct {
     int32_t t_wave;      /* max degree coloured by one wavefront; larger rows use a workgroup (default 2048) */
     int32_t grid_thread; /* workgroups given to the thread bin per round launch (default 1024) */
     int32_t grid_wave;   /* workgroups given to the wavefront bin (default 512) */
-    int32_t rounds_per_sync; /* rounds enqueued (as one HIP graph) per host check of the worklist (default 8, even) */
+    int32_t rounds_per_sync; /* rounds enqueued (as one HIP graph) per host check of the worklist (default 4, even) */
     int32_t small_cutoff;    /* batch: graphs with n <= this are coloured whole by one workgroup (default 4096; -1 disables) */
     int32_t timing;      /* 1: record per-kernel HIP events (fills the ms_* fields of rsoc_stats) */
     /* Optimistic mode only.  0 (default): round 0 gives each vertex the smallest
@@ -111,7 +111,7 @@ typedef struct {
      * neighbours coloured at the same instant would conflict), else 1. */
     int32_t chunk;
     /* Workgroups given to the thread bin of worklist rounds (rounds >= 1 over
-     * a list; default 2048).  Those rounds are latency-bound chains of
+     * a list; default 1024).  Those rounds are latency-bound chains of
      * dependent loads (list entry, row, neighbour colours), so they want more
      * workgroups in flight than the sweeps. */
     int32_t grid_list;

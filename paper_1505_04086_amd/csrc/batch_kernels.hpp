@@ -140,7 +140,7 @@ __global__ __launch_bounds__(kBlock) void k_blocality(const BatchArgs *__restric
     if (k < ns) {
         const int64_t task = a.tasks[(int)((int64_t)k * a.ntasks / ns)];
         const GraphView w = graph_view(a, item_graph(task));
-        locality_row(w.rp, w.ci, item_vertex(task), near, sampled);
+        locality_row(w.rp, w.ci, item_vertex(task), w.rp[w.n], near, sampled);
     }
     near = wave_sum_u64(near);
     sampled = wave_sum_u64(sampled);

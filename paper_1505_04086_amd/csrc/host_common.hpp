@@ -120,8 +120,8 @@ inline int32_t resolve_options(const rsoc_options *o, int64_t n, Options &r) {
     if (r.t_wave < r.t_thread) r.t_wave = r.t_thread;
     r.grid_thread = d.grid_thread ? d.grid_thread : 1024;
     r.grid_wave = d.grid_wave ? d.grid_wave : 512;
-    r.grid_list = d.grid_list ? d.grid_list : 2048;
-    r.rounds_per_sync = d.rounds_per_sync ? d.rounds_per_sync : 8;
+    r.grid_list = d.grid_list ? d.grid_list : 1024;
+    r.rounds_per_sync = d.rounds_per_sync ? d.rounds_per_sync : 4;
     if (r.rounds_per_sync & 1) r.rounds_per_sync += 1;  // worklist buffers alternate: keep it even
     r.small_cutoff = d.small_cutoff == 0 ? 4096 : (d.small_cutoff < 0 ? -1 : d.small_cutoff);
     r.timing = d.timing;

@@ -58,7 +58,7 @@ __global__ __launch_bounds__(kBlock) void k_pinit(PoolSlot *slots, int slot) {
             d = rp[v + 1] - rp[v];
             sp->col[v] = fillc;
             sp->col8[v] = shadow_of(fillc);
-            if ((v & 255) == 0) locality_row(rp, ci, v, near, sampled);  // id-locality sample
+            if ((v & 255) == 0) locality_row(rp, ci, v, rp[n], near, sampled);  // id-locality sample
         }
         md = max(md, d);
         queue_push(d > sp->t_wave, v, qB, &nqB);

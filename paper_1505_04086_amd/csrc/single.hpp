@@ -37,6 +37,7 @@ constexpr size_t kStateHeader = offsetof(SingleState, hist);
 struct HostStaging {
     SingleArgs args;
     SingleState head;  // only the header part is ever copied
+    int32_t L1;        // |L| of the first recolouring round
     int32_t rp_ends[2];
 };
 
@@ -139,11 +140,11 @@ inline void launch_sweep_rounds(rsoc_ctx *c, hipStream_t s, int32_t *col, int n,
         // round 0: against the all-uncoloured snapshot every vertex takes colour 0
         k_fill<<<fill_grid, kBlock, 0, s>>>(col, c->col8.as<uint8_t>(), n, 0);
     } else {
-        k_fill<<<fill_grid, kBlock, 0, s>>>(col, c->col8.as<uint8_t>(), n, -1);
+        // optimistic mode: every nibble 15 too (nothing published yet)
+        k_fill<<<fill_grid, kBlock, 0, s>>>(col, c->col8.as<uint8_t>(), n, -1,
+                                             MODE == kOptimistic ? c->col4.as<uint32_t>() : nullptr,
+                                             MODE == kOptimistic ? n / 8 + 1 : 0);
         if (MODE == kOptimistic) {
-            // every nibble 15: nothing published yet
-            k_fill<<<std::min(div_up(n / 8 + 1, kBlock), 4096), kBlock, 0, s>>>(
-                reinterpret_cast<int32_t *>(c->col4.p), nullptr, n / 8 + 1, -1);
             if (timing) (void)hipEventRecord(c->ev[2], s);
             // round 0: tentative First-Fit over all of V with live reads
             if (full_sweep) {
@@ -196,14 +197,17 @@ inline void launch_sweep_dyn(rsoc_ctx *c, hipStream_t s, int mode, int tie, int3
 #undef RSOC_SWEEP
 }
 
-inline int32_t ensure_single_scratch(rsoc_ctx *c, int64_t n, bool need_aux) {
+inline int32_t ensure_single_scratch(rsoc_ctx *c, int64_t n, bool need_aux, hipStream_t s) {
     const size_t b = sizeof(int32_t) * (size_t)(n + 2);
     RSOC_TRY(c->wl0.reserve(b));
     RSOC_TRY(c->wl1.reserve(b));
     RSOC_TRY(c->hubW.reserve(b));
     RSOC_TRY(c->hubB.reserve(b));
     RSOC_TRY(c->pend.reserve(b));
+    const size_t had = c->flags.bytes;
     RSOC_TRY(c->flags.reserve(b));
+    // colour flags stay zero between calls (k_count_flags clears what it counts)
+    if (c->flags.bytes != had) RSOC_HIP(hipMemsetAsync(c->flags.p, 0, c->flags.bytes, s));
     RSOC_TRY(c->col8.reserve((size_t)n + 64));
     RSOC_TRY(c->col4.reserve(sizeof(uint32_t) * (size_t)(n / 8 + 2)));
     if (need_aux) RSOC_TRY(c->aux.reserve(sizeof(int4) * (size_t)(n + 2)));
@@ -268,14 +272,7 @@ inline int32_t run_single(rsoc_ctx *c, const int32_t *rp, const int32_t *ci, int
         st->per_round_cap = cap;
     }
     if (n == 0) return 0;
-    // nnz and row_ptr[0]
-    RSOC_HIP(hipMemcpyAsync(&h->rp_ends[0], rp, 4, hipMemcpyDeviceToHost, s));
-    RSOC_HIP(hipMemcpyAsync(&h->rp_ends[1], rp + n, 4, hipMemcpyDeviceToHost, s));
-    RSOC_HIP(hipStreamSynchronize(s));
-    if (h->rp_ends[0] != 0 || h->rp_ends[1] < 0) return RSOC_ECSR;
-    const int64_t nnz = h->rp_ends[1];
-    if (nnz > 0 && !ci) return RSOC_EINVAL;
-    RSOC_TRY(ensure_single_scratch(c, n, o.mode == kOptimistic && !o.full_sweep));
+    RSOC_TRY(ensure_single_scratch(c, n, o.mode == kOptimistic && !o.full_sweep, s));
 
     SingleArgs &a = h->args;
     a.rp = rp;
@@ -296,24 +293,29 @@ inline int32_t run_single(rsoc_ctx *c, const int32_t *rp, const int32_t *ci, int
     a.offW = a.offB = 0;
     a.look = 0;
     a.chunk = 1;
-    RSOC_HIP(hipMemcpyAsync(c->args.p, &a, sizeof(a), hipMemcpyHostToDevice, s));
-    RSOC_HIP(hipMemsetAsync(S, 0, kStateHeader, s));
+    k_setup<<<1, kBlock, 0, s>>>(c->args.as<SingleArgs>(), a, S, (int)(kStateHeader / 4), 1);
     const int vgrid = std::min(div_up(n, kBlock), 4096);
-    if (o.validate & RSOC_CHECK_CSR) {
-        k_validate<<<vgrid, kBlock, 0, s>>>(rp, ci, n, nnz, &S->err);
+    // binning (reads row_ptr only: also checks its ends and publishes nnz),
+    // with the id-locality sample in extra workgroups unless the CSR is to be
+    // validated first (the sample reads rows)
+    const bool validate = (o.validate & RSOC_CHECK_CSR) != 0;
+    const int ns = (o.chunk == 0 && ci) ? std::min(n, 16384) : 0;
+    const int gloc = div_up(ns, kBlock);
+    k_bin<<<vgrid + (validate ? 0 : gloc), kBlock, 0, s>>>(c->args.as<SingleArgs>(), S, validate ? 0 : gloc, ns);
+    RSOC_LAUNCH_CHECK();
+    RSOC_HIP(hipMemcpyAsync(&h->head, S, kStateHeader, hipMemcpyDeviceToHost, s));
+    RSOC_HIP(hipStreamSynchronize(s));
+    if (h->head.err & 1) return RSOC_ECSR;
+    const int64_t nnz = h->head.nnz;
+    if (nnz > 0 && !ci) return RSOC_EINVAL;
+    if (validate) {
+        k_validate<<<vgrid, kBlock, 0, s>>>(rp, ci, n, &S->err);
+        if (gloc) k_bin<<<gloc, kBlock, 0, s>>>(c->args.as<SingleArgs>(), S, gloc, ns);
         RSOC_LAUNCH_CHECK();
         RSOC_HIP(hipMemcpyAsync(&h->head, S, kStateHeader, hipMemcpyDeviceToHost, s));
         RSOC_HIP(hipStreamSynchronize(s));
         RSOC_TRY(status_from_err(h->head.err));
     }
-    k_bin<<<vgrid, kBlock, 0, s>>>(c->args.as<SingleArgs>(), S);
-    if (o.chunk == 0 && nnz > 0) {
-        const int ns = std::min(n, 16384);
-        k_locality<<<div_up(ns, kBlock), kBlock, 0, s>>>(rp, ci, n, ns, S);
-    }
-    RSOC_LAUNCH_CHECK();
-    RSOC_HIP(hipMemcpyAsync(&h->head, S, kStateHeader, hipMemcpyDeviceToHost, s));
-    RSOC_HIP(hipStreamSynchronize(s));
     const int nW = h->head.nW, nB = h->head.nB, maxdeg = h->head.maxdeg;
     const int nT = n - nW - nB;
     a.offW = nT;
@@ -327,7 +329,7 @@ inline int32_t run_single(rsoc_ctx *c, const int32_t *rp, const int32_t *ci, int
     const int64_t look = o.lookahead == -1 ? 0 : (o.lookahead > 0 ? o.lookahead : (int64_t)gTs * kStep);
     a.look = (int)std::min<int64_t>(look, INT32_MAX);
     a.chunk = pick_chunk(o.chunk, h->head.near, h->head.sampled);
-    RSOC_HIP(hipMemcpyAsync(c->args.p, &a, sizeof(a), hipMemcpyHostToDevice, s));
+    k_setup<<<1, kBlock, 0, s>>>(c->args.as<SingleArgs>(), a, S, 0, 0);
     const int gBl = std::min(nB, 256);
     const int gWl = std::min(div_up(nW, kWavesPerBlock), o.grid_wave);
     const int gTl = std::max(1, std::min(div_up(nT, kStep), o.grid_list));
@@ -339,39 +341,43 @@ inline int32_t run_single(rsoc_ctx *c, const int32_t *rp, const int32_t *ci, int
     launch_sweep_dyn(c, s, o.mode, o.tie, col, n, gB, gW, gTs, gBl, gWl, gTl, o.timing != 0, o.full_sweep != 0);
     RSOC_LAUNCH_CHECK();
     int32_t status = RSOC_OK;
+    // colour count (K = max + 1) and distinct colours; every colour is at most
+    // min(max degree, n - 1) (a First-Fit value over at most that many
+    // neighbours).  The statistics are enqueued behind each replay, so the one
+    // host check per replay also brings them; they count once the worklist is
+    // empty.
+    const int clim = std::min(maxdeg, n - 1);
     for (;;) {
         RSOC_HIP(hipGraphLaunch(gexec, s));
         RSOC_HIP(hipEventRecord(c->ev[1], s));
+        k_colour_stats<<<std::min(div_up(n, 16 * kBlock), 2048), kBlock, 0, s>>>(c->col8.as<uint8_t>(), col, n, clim,
+                                                                                 c->flags.as<int32_t>(), S);
+        if (clim >= 255)
+            k_count_flags<<<std::min(div_up(clim + 1 - 255, kBlock), 1024), kBlock, 0, s>>>(
+                c->flags.as<int32_t>() + 255, clim + 1 - 255, &S->distinct);
+        RSOC_LAUNCH_CHECK();
         RSOC_HIP(hipMemcpyAsync(&h->head, S, kStateHeader, hipMemcpyDeviceToHost, s));
+        RSOC_HIP(hipMemcpyAsync(&h->L1, &S->hist[0], 4, hipMemcpyDeviceToHost, s));
         RSOC_HIP(hipStreamSynchronize(s));
         const int left = h->head.cnt_in[0] + h->head.cnt_in[1] + h->head.cnt_in[2];
         if (left == 0) break;
         if (h->head.passes >= o.max_rounds) { status = RSOC_ENOCONV; break; }
     }
-    // colour count (K = max + 1) and distinct colours; every colour is at most
-    // min(max degree, n - 1) (a First-Fit value over at most that many neighbours)
-    const int clim = std::min(maxdeg, n - 1);
-    RSOC_HIP(hipMemsetAsync(c->flags.p, 0, sizeof(int32_t) * (size_t)(clim + 1), s));
-    k_colour_stats<<<vgrid, kBlock, 0, s>>>(col, n, clim, c->flags.as<int32_t>(), &S->kmax, &S->err);
-    k_count_flags<<<std::min(div_up(clim + 1, kBlock), 1024), kBlock, 0, s>>>(c->flags.as<int32_t>(), clim + 1,
-                                                                               &S->distinct);
-    RSOC_LAUNCH_CHECK();
-    RSOC_HIP(hipMemcpyAsync(&h->head, S, kStateHeader, hipMemcpyDeviceToHost, s));
-    int32_t L1 = 0;
-    RSOC_HIP(hipMemcpyAsync(&L1, &S->hist[0], 4, hipMemcpyDeviceToHost, s));
     if (st && st->per_round_L && st->per_round_cap > 0) {
-        RSOC_HIP(hipStreamSynchronize(s));
         const int cnt = std::min(std::min(h->head.rounds, st->per_round_cap), kHistCap);
-        if (cnt > 0)
+        if (cnt > 0) {
             RSOC_HIP(hipMemcpyAsync(st->per_round_L, S->hist, sizeof(int32_t) * cnt, hipMemcpyDeviceToHost, s));
+            RSOC_HIP(hipStreamSynchronize(s));
+        }
     }
-    RSOC_HIP(hipStreamSynchronize(s));
     if (h->head.err & 4) return RSOC_EHIP;  // a colour outside [0, max degree]: never expected
     if (st) {
         st->rounds = h->head.rounds;
         st->passes = h->head.passes;
         st->colors = h->head.kmax;
-        st->colors_distinct = h->head.distinct;
+        int distinct = h->head.distinct;
+        for (uint32_t w : h->head.cbits) distinct += __builtin_popcount(w);
+        st->colors_distinct = distinct;
         st->conflicts = h->head.conflicts;
         const bool sweep1 = !(o.mode == kOptimistic && !o.full_sweep);
         st->inspected = (int64_t)h->head.inspected + (sweep1 ? n : 0);
@@ -390,7 +396,7 @@ inline int32_t run_single(rsoc_ctx *c, const int32_t *rp, const int32_t *ci, int
             st->ms_round1 = m1;
         }
         int64_t b0, b1, tot;
-        const int64_t l1 = h->head.rounds > 0 ? L1 : 0;
+        const int64_t l1 = h->head.rounds > 0 ? h->L1 : 0;
         alg_bytes(o.mode, o.full_sweep != 0, n, nnz, nW, nB, h->head.u0, l1, h->head.conflicts, h->head.inspected,
                   h->head.deg_sum, h->head.inspected1, h->head.deg_sum1, b0, b1, tot);
         st->bytes_round0 = b0;

@@ -45,9 +45,12 @@ struct SingleState {
     int32_t maxdeg;
     int32_t passes;       // inspection passes executed (rounds >= 1)
     int32_t rounds;       // passes that recoloured somebody
-    int32_t kmax;         // max colour + 1
-    int32_t distinct;
     int32_t err;          // bit 0 bad CSR, bit 1 self-loop, bit 2 colour out of range
+    int32_t nnz;          // row_ptr[n] (read by k_bin)
+    // colour statistics (k_colour_stats; cleared before each computation)
+    int32_t kmax;         // max colour + 1
+    int32_t distinct;     // distinct colours >= 255
+    uint32_t cbits[8];    // set of colours < 255 used
     int64_t conflicts;    // sum of |L|
     uint64_t inspected;   // vertices inspected by worklist rounds
     uint64_t deg_sum;     // their degree sum
@@ -70,22 +73,39 @@ __device__ __forceinline__ void publish_nibble(RSOC_GLOBAL uint32_t *col4, int v
 }
 
 // ------------------------------------------------------------------ fill --
-__global__ void k_fill(int32_t *p, uint8_t *p8, int64_t n, int32_t value) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+// p[0, n) = value, its byte shadow p8 (if given) and, if given, the 4-bit
+// shadow words p4[0, n4) = all ones (every nibble 15).
+__global__ void k_fill(int32_t *p, uint8_t *p8, int64_t n, int32_t value, uint32_t *p4 = nullptr, int64_t n4 = 0) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += stride) {
         p[i] = value;
         if (p8) p8[i] = shadow_of(value);
+    }
+    if (p4)
+        for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n4; i += stride) p4[i] = ~0u;
+}
+
+// ----------------------------------------------------------------- setup --
+// Writes the colouring's device-resident arguments (passed by value) and,
+// when clear is set, zeroes the round-state header (everything before hist):
+// one small launch instead of a copy and a fill.
+__global__ void k_setup(SingleArgs *A, SingleArgs a, SingleState *S, int header_words, int clear) {
+    if (threadIdx.x == 0) *A = a;
+    if (clear) {
+        int32_t *w = reinterpret_cast<int32_t *>(S);
+        for (int i = threadIdx.x; i < header_words; i += blockDim.x) w[i] = 0;
     }
 }
 
 // ------------------------------------------------------------- validate --
 // Flags malformed rows (decreasing offsets, offsets past nnz, column ids out
 // of range) and self-loops.
-__global__ void k_validate(const int32_t *__restrict__ rp, const int32_t *__restrict__ ci, int32_t n, int64_t nnz,
-                           int32_t *err) {
+__global__ void k_validate(const int32_t *__restrict__ rp, const int32_t *__restrict__ ci, int32_t n, int32_t *err) {
+    const int64_t nnz = rp[n];
     int flags = 0;
     for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
         const int b = rp[v], e = rp[v + 1];
-        if (b > e || b < 0 || (int64_t)e > nnz) { flags |= 1; continue; }
+        if (b > e || b < 0 || (int64_t)e > nnz || nnz < 0 || rp[0] != 0) { flags |= 1; continue; }
         for (int j = b; j < e; ++j) {
             const int u = ci[j];
             if ((unsigned)u >= (unsigned)n) flags |= 1;
@@ -112,24 +132,49 @@ __device__ __forceinline__ int block_max(int x, int *sh) {
 
 // ------------------------------------------------------------------ bin --
 // Splits V by degree: deg <= t_thread stays implicit (thread bin); larger rows
-// go to the static wavefront / workgroup lists.  Also finds the max degree.
+// go to the static wavefront / workgroup lists.  Also finds the max degree,
+// publishes nnz = row_ptr[n] and checks the ends of row_ptr (row_ptr[0] = 0,
+// row_ptr[n] >= 0; err bit 0 otherwise).  The first `gloc` workgroups take the
+// id-locality sample instead (ns rows), so that its dependent loads start
+// first and overlap the binning.
 template <class T = int>
 __device__ __forceinline__ void queue_push(bool take, int v, int *q, int *qn, T *qx = nullptr, T x = T());
 template <class T = int>
 __device__ __forceinline__ void queue_flush(int *q, int *qn, int *qbase, int *counter, int32_t *out,
                                             const T *qx = nullptr, T *outx = nullptr);
 
-__global__ __launch_bounds__(kBlock) void k_bin(const SingleArgs *__restrict__ A, SingleState *S) {
+__device__ __forceinline__ void locality_row(const RSOC_GLOBAL int32_t *rp, const RSOC_GLOBAL int32_t *ci, int v,
+                                             int64_t nnz, uint64_t &near, uint64_t &sampled);
+
+__global__ __launch_bounds__(kBlock) void k_bin(const SingleArgs *__restrict__ A, SingleState *S, int gloc, int ns) {
     __shared__ int sh[kWavesPerBlock];
     __shared__ int qW[kQueueCap], qB[kQueueCap];
     __shared__ int nqW, nqB, qbase;
     const SingleArgs a = *A;
     const RSOC_GLOBAL int32_t *rp = gro(a.rp);
+    if ((int)blockIdx.x < gloc) {
+        uint64_t near = 0, sampled = 0;
+        const int k = (int)blockIdx.x * kBlock + threadIdx.x;
+        if (k < ns) locality_row(rp, gro(a.ci), (int)((int64_t)k * a.n / ns), rp[a.n], near, sampled);
+        near = wave_sum_u64(near);
+        sampled = wave_sum_u64(sampled);
+        if (lane_id() == 0 && sampled) {
+            atomicAdd((unsigned long long *)&S->near, (unsigned long long)near);
+            atomicAdd((unsigned long long *)&S->sampled, (unsigned long long)sampled);
+        }
+        return;
+    }
+    const int bb = (int)blockIdx.x - gloc, nbb = (int)gridDim.x - gloc;
+    if (bb == 0 && threadIdx.x == 0) {
+        const int r0 = rp[0], rn = rp[a.n];
+        S->nnz = rn;
+        if (r0 != 0 || rn < 0) atomicOr(&S->err, 1);
+    }
     int md = 0;
     if (threadIdx.x == 0) nqW = nqB = 0;
     __syncthreads();
-    const int64_t stride = (int64_t)gridDim.x * kBlock;
-    for (int64_t base = (int64_t)blockIdx.x * kBlock; base < a.n; base += stride) {
+    const int64_t stride = (int64_t)nbb * kBlock;
+    for (int64_t base = (int64_t)bb * kBlock; base < a.n; base += stride) {
         const int v = (int)(base + threadIdx.x);
         int d = -1;
         if (v < a.n) d = rp[v + 1] - rp[v];
@@ -150,12 +195,13 @@ __global__ __launch_bounds__(kBlock) void k_bin(const SingleArgs *__restrict__ A
 }
 
 // Id-locality sample: rows of `ns` vertices spread evenly over [0, n) (rows
-// longer than the thread bin skipped); counts entries joining ids less than
-// kChunk apart.  One vertex per thread, its row read eight entries at a time.
+// longer than the thread bin, or not inside [0, nnz), skipped); counts
+// entries joining ids less than kChunk apart.  One vertex per thread, its row
+// read eight entries at a time.
 __device__ __forceinline__ void locality_row(const RSOC_GLOBAL int32_t *rp, const RSOC_GLOBAL int32_t *ci, int v,
-                                             uint64_t &near, uint64_t &sampled) {
+                                             int64_t nnz, uint64_t &near, uint64_t &sampled) {
     const int b = rp[v], e = rp[v + 1];
-    if (e - b > kThreadBinMax) return;
+    if (b < 0 || e < b || (int64_t)e > nnz || e - b > kThreadBinMax) return;
     for (int j0 = b; j0 < e; j0 += 8) {
         int u[8];
 #pragma unroll
@@ -164,21 +210,6 @@ __device__ __forceinline__ void locality_row(const RSOC_GLOBAL int32_t *rp, cons
         for (int k = 0; k < 8; ++k) near += (uint64_t)(abs(u[k] - v) < kChunk);
     }
     sampled += (uint64_t)(e - b);
-}
-
-__global__ __launch_bounds__(kBlock) void k_locality(const int32_t *__restrict__ rpp, const int32_t *__restrict__ cip,
-                                                     int32_t n, int32_t ns, SingleState *S) {
-    const RSOC_GLOBAL int32_t *rp = gro(rpp);
-    const RSOC_GLOBAL int32_t *ci = gro(cip);
-    uint64_t near = 0, sampled = 0;
-    const int k = blockIdx.x * kBlock + threadIdx.x;
-    if (k < ns) locality_row(rp, ci, (int)((int64_t)k * n / ns), near, sampled);
-    near = wave_sum_u64(near);
-    sampled = wave_sum_u64(sampled);
-    if (lane_id() == 0 && sampled) {
-        atomicAdd((unsigned long long *)&S->near, (unsigned long long)near);
-        atomicAdd((unsigned long long *)&S->sampled, (unsigned long long)sampled);
-    }
 }
 
 // Per-wavefront append buffer in LDS (wavefront-bin vertices are appended one
@@ -644,7 +675,11 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const SingleArgs *__restrict
 // PUBLISH_ONLY: after round 0 (no pass to count): only publish the appended list.
 template <int MODE, bool SWEEP, bool PUBLISH_ONLY = false>
 __global__ void k_round_end(const SingleArgs *__restrict__ A, SingleState *S) {
+    // the colour statistics that follow the rounds start from zero
+    if (threadIdx.x < 8) S->cbits[threadIdx.x] = 0;
     if (threadIdx.x != 0) return;
+    S->kmax = 0;
+    S->distinct = 0;
     if (PUBLISH_ONLY) {
         S->u0 = S->cnt_out[0] + S->cnt_out[1] + S->cnt_out[2];
         for (int b = 0; b < 3; ++b) {
@@ -679,29 +714,71 @@ __global__ void k_round_end(const SingleArgs *__restrict__ A, SingleState *S) {
 }
 
 // --------------------------------------------------------- colour stats --
-// K = max colour + 1; marks used colours (flags[0..maxdeg]) for the distinct
-// count; flags an error if any colour is outside [0, maxdeg].
-__global__ __launch_bounds__(kBlock) void k_colour_stats(const int32_t *__restrict__ colp, int64_t n, int32_t maxdeg,
-                                                         int32_t *flags, int32_t *kmax, int32_t *err) {
+// K = max colour + 1 and the set of colours used, read from the byte shadow
+// (16 vertices per thread and load); only a vertex whose shadow is 255
+// (colour 255 or more, or none) reads its full colour.  Colours below 64 are
+// gathered in a register mask, 64..254 in the workgroup's LDS set, both then
+// OR-ed into S->cbits; colours >= 255 mark flags[c] (counted, and cleared, by
+// k_count_flags).  A colour outside [0, maxdeg] sets err bit 2.
+__global__ __launch_bounds__(kBlock) void k_colour_stats(const uint8_t *__restrict__ col8p,
+                                                         const int32_t *__restrict__ colp, int64_t n, int32_t maxdeg,
+                                                         int32_t *flags, SingleState *S) {
+    __shared__ uint32_t bits[8];
     __shared__ int sh[kWavesPerBlock];
+    typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+    const RSOC_GLOBAL v4u *c16 = (const RSOC_GLOBAL v4u *)col8p;  // 16 bytes per entry (col8 holds n + 64 bytes)
     const RSOC_GLOBAL int32_t *col = gro(colp);
+    if (threadIdx.x < 8) bits[threadIdx.x] = 0;
+    __syncthreads();
     int m = -1;
     bool bad = false;
-    for (int64_t v = blockIdx.x * (int64_t)kBlock + threadIdx.x; v < n; v += (int64_t)gridDim.x * kBlock) {
-        const int c = col[v];
-        if (c < 0 || c > maxdeg) { bad = true; continue; }
-        m = max(m, c);
-        if (flags[c] == 0) flags[c] = 1;  // racy but idempotent; the read keeps most writes away
+    uint64_t low = 0;
+    const int64_t n16 = (n + 15) / 16;
+    for (int64_t t = blockIdx.x * (int64_t)kBlock + threadIdx.x; t < n16; t += (int64_t)gridDim.x * kBlock) {
+        const v4u w = c16[t];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const int64_t v = t * 16 + j;
+            if (v >= n) break;
+            int c = (int)((w[j >> 2] >> ((j & 3) * 8)) & 255u);
+            if (c == 255) {
+                c = col[v];
+                if (c < 0 || c > maxdeg) { bad = true; continue; }
+                if (c >= 255) {
+                    if (flags[c] == 0) flags[c] = 1;  // racy but idempotent
+                    m = max(m, c);
+                    continue;
+                }
+            }
+            if (c > maxdeg) { bad = true; continue; }
+            m = max(m, c);
+            if (c < 64) low |= 1ull << c;
+            else lds_or(&bits[c >> 5], 1u << (c & 31));
+        }
     }
-    if (ballot(bad) && lane_id() == 0) atomicOr(err, 4);
+    if (ballot(bad) && lane_id() == 0) atomicOr(&S->err, 4);
+    for (int off = 32; off > 0; off >>= 1) low |= __shfl_xor(low, off);
+    if (lane_id() == 0 && low) {
+        lds_or(&bits[0], (uint32_t)low);
+        lds_or(&bits[1], (uint32_t)(low >> 32));
+    }
     m = block_max(m, sh);
-    if (threadIdx.x == 0 && m + 1 > __hip_atomic_load(kmax, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-        atomicMax(kmax, m + 1);
+    __syncthreads();
+    if (threadIdx.x < 8 && bits[threadIdx.x] &&
+        (bits[threadIdx.x] & ~__hip_atomic_load(&S->cbits[threadIdx.x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)))
+        atomicOr(&S->cbits[threadIdx.x], bits[threadIdx.x]);
+    if (threadIdx.x == 0 && m + 1 > __hip_atomic_load(&S->kmax, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+        atomicMax(&S->kmax, m + 1);
 }
 
-__global__ __launch_bounds__(kBlock) void k_count_flags(const int32_t *__restrict__ flags, int64_t len, int32_t *out) {
+// Counts the marked flags[0, len) into *out and clears them.
+__global__ __launch_bounds__(kBlock) void k_count_flags(int32_t *flags, int64_t len, int32_t *out) {
     int s = 0;
-    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < len; i += (int64_t)gridDim.x * kBlock) s += flags[i];
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < len; i += (int64_t)gridDim.x * kBlock) {
+        const int f = flags[i];
+        s += f;
+        if (f) flags[i] = 0;
+    }
     for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
     if (lane_id() == 0 && s) atomicAdd(out, s);
 }
