@@ -115,7 +115,13 @@ typedef struct {
      * dependent loads (list entry, row, neighbour colours), so they want more
      * workgroups in flight than the sweeps. */
     int32_t grid_list;
-    int32_t reserved[1]; /* must be zero */
+    /* Optimistic mode: once the worklist holds at most this many vertices
+     * (0 = library default 1024, the most allowed; -1 = never), one round is
+     * run as an ordered pass over it -- each vertex detected and recoloured
+     * after the ones before it, seeing their new colours -- so that mutually
+     * adjacent hubs stop taking the same colour round after round. */
+    int32_t tail;
+    int32_t reserved[3]; /* must be zero */
 } rsoc_options;
 
 typedef struct {

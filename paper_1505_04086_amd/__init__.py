@@ -61,7 +61,8 @@ class rsoc_options(ctypes.Structure):
                 ("grid_thread", ctypes.c_int32), ("grid_wave", ctypes.c_int32),
                 ("rounds_per_sync", ctypes.c_int32), ("small_cutoff", ctypes.c_int32),
                 ("timing", ctypes.c_int32), ("full_sweep", ctypes.c_int32), ("lookahead", ctypes.c_int32),
-                ("chunk", ctypes.c_int32), ("grid_list", ctypes.c_int32), ("reserved", ctypes.c_int32 * 1)]
+                ("chunk", ctypes.c_int32), ("grid_list", ctypes.c_int32), ("tail", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 3)]
 
 
 class rsoc_stats(ctypes.Structure):

@@ -14,12 +14,14 @@
 
 #include "host_common.hpp"
 #include "single_kernels.hpp"
+#include "tail_kernels.hpp"
 
 struct rsoc_ctx {
     int device = 0;
     hipStream_t own = nullptr;    // stream for host-pointer calls
     hipStream_t cap = nullptr;    // capture stream
     rsoc::DevBuf wl0, wl1, hubW, hubB, pend, flags, col8, col4, aux;
+    rsoc::DevBuf mark, tail;      // ordered pass over a small worklist (tail_kernels.hpp)
     rsoc::DevBuf args, state;     // SingleArgs, SingleState (fixed addresses: graphs point at them)
     rsoc::HostPinned host;        // pinned staging for small copies
     rsoc::DevBuf drp, dci, dcol;  // device copies for host-pointer calls
@@ -61,7 +63,7 @@ inline void ctx_free(rsoc_ctx *c) {
     c->graphs.clear();
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);
-    for (rsoc::DevBuf *b : {&c->col8, &c->col4, &c->aux, &c->wl0, &c->wl1, &c->hubW, &c->hubB, &c->pend, &c->flags, &c->args, &c->state, &c->drp,
+    for (rsoc::DevBuf *b : {&c->col8, &c->col4, &c->aux, &c->mark, &c->tail, &c->wl0, &c->wl1, &c->hubW, &c->hubB, &c->pend, &c->flags, &c->args, &c->state, &c->drp,
                             &c->dci, &c->dcol, &c->b_desc, &c->b_wl0, &c->b_wl1, &c->b_pend, &c->b_flags,
                             &c->b_state, &c->b_hub, &c->b_kmax, &c->b_tasks, &c->b_args, &c->b_col8})
         b->release();
@@ -214,6 +216,31 @@ inline int32_t ensure_single_scratch(rsoc_ctx *c, int64_t n, bool need_aux, hipS
     return RSOC_OK;
 }
 
+// mark[] is zero between calls (k_tail_unmark restores what k_tail_mark set).
+inline int32_t ensure_tail_scratch(rsoc_ctx *c, int64_t n, hipStream_t s) {
+    const size_t had = c->mark.bytes;
+    RSOC_TRY(c->mark.reserve(sizeof(int32_t) * (size_t)(n + 2)));
+    if (c->mark.bytes != had) RSOC_HIP(hipMemsetAsync(c->mark.p, 0, c->mark.bytes, s));
+    RSOC_TRY(c->tail.reserve(tail_bytes()));
+    return RSOC_OK;
+}
+
+// One optimistic round over the current worklist (m entries, buffer 0) as an
+// ordered pass; its recoloured vertices become the next worklist.
+template <int TIE>
+inline void launch_tail(rsoc_ctx *c, hipStream_t s, int m) {
+    const SingleArgs *A = c->args.as<SingleArgs>();
+    SingleState *S = c->state.as<SingleState>();
+    const TailBuf t = tail_layout(c->tail.p);
+    int32_t *mark = c->mark.as<int32_t>();
+    const int g = div_up(m, kBlock);
+    k_tail_mark<<<g, kBlock, 0, s>>>(A, S, t, mark, m);
+    k_tail_prep<TIE><<<m, kBlock, 0, s>>>(A, t, mark);
+    k_tail_seq<TIE, true><<<1, kBlock, 0, s>>>(A, S, t, m);
+    k_tail_unmark<<<g, kBlock, 0, s>>>(t, mark, m);
+    k_round_end<kOptimistic, false><<<1, 64, 0, s>>>(A, S);
+}
+
 inline int32_t status_from_err(int32_t err) {
     if (err & 1) return RSOC_ECSR;
     if (err & 2) return RSOC_ESELFLOOP;
@@ -330,7 +357,7 @@ inline int32_t run_single(rsoc_ctx *c, const int32_t *rp, const int32_t *ci, int
     a.look = (int)std::min<int64_t>(look, INT32_MAX);
     a.chunk = pick_chunk(o.chunk, h->head.near, h->head.sampled);
     k_setup<<<1, kBlock, 0, s>>>(c->args.as<SingleArgs>(), a, S, 0, 0);
-    const int gBl = std::min(nB, 256);
+    const int gBl = std::min(nB, 256);  // more concurrent hubs only add hub conflicts
     const int gWl = std::min(div_up(nW, kWavesPerBlock), o.grid_wave);
     const int gTl = std::max(1, std::min(div_up(nT, kStep), o.grid_list));
 
@@ -347,6 +374,7 @@ inline int32_t run_single(rsoc_ctx *c, const int32_t *rp, const int32_t *ci, int
     // host check per replay also brings them; they count once the worklist is
     // empty.
     const int clim = std::min(maxdeg, n - 1);
+    const int tail_max = o.tail == -1 ? 0 : (o.tail == 0 ? kTailMax : std::min(o.tail, kTailMax));
     for (;;) {
         RSOC_HIP(hipGraphLaunch(gexec, s));
         RSOC_HIP(hipEventRecord(c->ev[1], s));
@@ -362,6 +390,11 @@ inline int32_t run_single(rsoc_ctx *c, const int32_t *rp, const int32_t *ci, int
         const int left = h->head.cnt_in[0] + h->head.cnt_in[1] + h->head.cnt_in[2];
         if (left == 0) break;
         if (h->head.passes >= o.max_rounds) { status = RSOC_ENOCONV; break; }
+        if (o.mode == kOptimistic && left <= tail_max) {
+            RSOC_TRY(ensure_tail_scratch(c, n, s));
+            o.tie ? launch_tail<kHigherKeeps>(c, s, left) : launch_tail<kLowerKeeps>(c, s, left);
+            RSOC_LAUNCH_CHECK();
+        }
     }
     if (st && st->per_round_L && st->per_round_cap > 0) {
         const int cnt = std::min(std::min(h->head.rounds, st->per_round_cap), kHistCap);

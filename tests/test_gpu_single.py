@@ -55,7 +55,10 @@ CASES = _small_cases()
 # degree-bin thresholds small enough to route small graphs through every bin
 BIN_SPLITS = {"default": {}, "allbins": {"t_thread": 3, "t_wave": 8}, "wave_only": {"t_thread": 1, "t_wave": 100000},
               "block_only": {"t_thread": 1, "t_wave": 1}, "runs1": {"chunk": 1, "grid_thread": 3, "grid_list": 3},
-              "runs8": {"chunk": 8, "grid_thread": 5, "grid_list": 1}, "runs2": {"chunk": 2, "t_thread": 16}}
+              "runs8": {"chunk": 8, "grid_thread": 5, "grid_list": 1}, "runs2": {"chunk": 2, "t_thread": 16},
+              # optimistic ordered pass over small worklists: off, and at a
+              # threshold of 4 with every degree bin in use
+              "notail": {"tail": -1}, "tail4": {"tail": 4, "t_thread": 3, "t_wave": 8}}
 
 
 @pytest.mark.parametrize("split", sorted(BIN_SPLITS))
@@ -106,6 +109,33 @@ def test_optimistic_valid(lib, ctx, name, tie, split, full_sweep):
     assert k <= (deg.max() + 1 if n else 0)
     # the method's termination bound: |L| strictly shrinks, so at most n recolouring rounds
     assert st["rounds"] <= max(n, 0)
+
+
+@pytest.mark.parametrize("tie", ["lower", "higher"])
+@pytest.mark.parametrize("name", ["K300", "rmat12", "hubcore"])
+def test_ordered_tail_pass(lib, ctx, name, tie):
+    """Mutually adjacent hubs: with the ordered pass over small worklists the
+    colouring stays valid and the rounds stop growing with the core's size."""
+    if name == "K300":
+        rp, ci = gg.complete(300)
+    elif name == "rmat12":
+        rp, ci = gg.rmat(12, 16, seed=7, shuffle_seed=8)
+    else:  # a 200-clique whose members also hold 40 leaves each
+        edges = [(i, j) for i in range(200) for j in range(i + 1, 200)]
+        edges += [(i, 200 + 40 * i + k) for i in range(200) for k in range(40)]
+        rp, ci = gg.from_edges(200 + 200 * 40, np.array(edges, dtype=np.int64))
+    d_rp, d_ci, d_col, n = _dev(lib, rp, ci)
+    for tail in (0, -1):
+        k, st = lib.rsoc_color_device(ctx, d_rp, d_ci, n, d_col, lib.make_options("optimistic", tie, tail=tail),
+                                      per_round_cap=4096)
+        got = d_col.cpu().numpy()[:n]
+        assert oracle.check(rp, ci, got) == 0, tail
+        assert k == oracle.colour_count(got) and k <= np.diff(rp).max() + 1
+        if name == "K300":
+            assert k == 300
+        if tail == 0:
+            # round 1, one replay of 4 rounds, the ordered pass, the round that checks it
+            assert st["rounds"] <= 7, st["L_sizes"]
 
 
 def test_host_pointer_entry_points(lib, ctx):
