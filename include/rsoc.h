@@ -116,10 +116,11 @@ typedef struct {
      * workgroups in flight than the sweeps. */
     int32_t grid_list;
     /* Optimistic mode: once the worklist holds at most this many vertices
-     * (0 = library default 1024, the most allowed; -1 = never), one round is
-     * run as an ordered pass over it -- each vertex detected and recoloured
-     * after the ones before it, seeing their new colours -- so that mutually
-     * adjacent hubs stop taking the same colour round after round. */
+     * (0 = library default 1024, the most allowed; -1 = never) and its last
+     * round shrank it by less than half, one round is run as an ordered pass
+     * over it -- each vertex detected and recoloured after the ones before
+     * it, seeing their new colours -- so that mutually adjacent hubs stop
+     * taking the same colour round after round. */
     int32_t tail;
     int32_t reserved[3]; /* must be zero */
 } rsoc_options;
@@ -206,8 +207,13 @@ int32_t rsoc_color_batch(rsoc_ctx *ctx, int32_t G, const int64_t *vtx_off, const
  */
 int32_t rsoc_pool_create(rsoc_ctx *ctx, int64_t hbm_budget_bytes, int32_t max_slots, rsoc_pool **out);
 void rsoc_pool_destroy(rsoc_pool *pool);
-/* Admits a graph; the device pointers must stay valid until rsoc_pool_result.
- * Returns a slot id >= 0, or RSOC_EBUDGET if its scratch does not fit now. */
+/* Admits a graph: reserves a slot and its scratch and enqueues the slot's
+ * set-up on the context's stream (no wait on the device; the next
+ * rsoc_pool_step orders itself after it).  The device pointers must stay valid
+ * until rsoc_pool_result.  Returns a slot id >= 0, or RSOC_EBUDGET if its
+ * scratch does not fit now.  Wrong row_ptr ends (row_ptr[0] != 0 or
+ * row_ptr[n] < 0, RSOC_ECSR) and edges without col_idx (RSOC_EINVAL) finish the
+ * slot at the next step with that status, returned by rsoc_pool_result. */
 int32_t rsoc_pool_admit(rsoc_pool *pool, const int32_t *d_row_ptr, const int32_t *d_col_idx, int32_t n,
                         int32_t *d_colors_out, const rsoc_options *opts);
 /* One fused round over all live slots on hip_stream (synchronised).  Writes up
@@ -219,7 +225,8 @@ int32_t rsoc_pool_live(const rsoc_pool *pool);
 /* Scratch bytes currently reserved by admitted slots. */
 int64_t rsoc_pool_reserved_bytes(const rsoc_pool *pool);
 /* Statistics of a finished slot (stats may be NULL); releases the slot and
- * its budget.  Returns K or RSOC_ENOTFOUND. */
+ * its budget.  Returns K, the slot's error status, or RSOC_ENOTFOUND when the
+ * slot is not a finished one.  Enqueues no device work that it waits for. */
 int32_t rsoc_pool_result(rsoc_pool *pool, int32_t slot, rsoc_stats *stats);
 
 /* Host-side CSR check (flags: RSOC_CHECK_*).  Returns RSOC_OK or the first error found. */

@@ -3,6 +3,13 @@
 // slots.  Slot scratch (worklists, hub lists, colour shadow, staging) comes
 // from an arena sized by the HBM budget; admission is refused with
 // RSOC_EBUDGET when it does not fit.
+//
+// The host waits on the device once or twice per step, never per request:
+// admission only enqueues the slot's set-up (k_pinit) on the context's own
+// stream and records p->ev; the next step waits for that event and finishes
+// the new slots' host fields with one look at their downloaded state; a step
+// in which slots finish enqueues their colour counts and downloads them once;
+// taking a result then needs no device work at all.
 #pragma once
 
 #include <map>
@@ -25,6 +32,9 @@ struct rsoc_pool {
     };
     std::vector<Alloc> allocs;
     std::vector<char> reported;  // finished slot already returned by a step
+    std::vector<char> pending;   // admitted, set-up enqueued, host fields not yet final
+    hipEvent_t ev = nullptr;     // recorded after admission / release work on the context's stream
+    rsoc::HostPinned stage;      // step download of all slots (copied into the mirror for active ones)
 };
 
 namespace rsoc {
@@ -108,9 +118,16 @@ int32_t rsoc_pool_create(rsoc_ctx *ctx, int64_t hbm_budget_bytes, int32_t max_sl
     p->max_slots = max_slots;
     p->allocs.resize((size_t)max_slots);
     p->reported.assign((size_t)max_slots, 0);
+    p->pending.assign((size_t)max_slots, 0);
     int32_t r = RSOC_OK;
+    if (hipEventCreateWithFlags(&p->ev, hipEventDisableTiming) != hipSuccess) {
+        p->ev = nullptr;
+        rsoc_pool_destroy(p);
+        return RSOC_EHIP;
+    }
     if ((r = p->slots_dev.reserve(sizeof(PoolSlot) * (size_t)max_slots)) < 0 ||
         (r = p->mirror.reserve(sizeof(PoolSlot) * (size_t)max_slots)) < 0 ||
+        (r = p->stage.reserve(sizeof(PoolSlot) * (size_t)max_slots)) < 0 ||
         (r = p->active_dev.reserve(sizeof(int32_t) * (size_t)max_slots)) < 0 ||
         (r = p->active_host.reserve(sizeof(int32_t) * (size_t)max_slots)) < 0 ||
         (hbm_budget_bytes > 0 && (r = p->arena.reserve((size_t)hbm_budget_bytes)) < 0)) {
@@ -133,8 +150,10 @@ void rsoc_pool_destroy(rsoc_pool *p) {
     (void)hipSetDevice(p->ctx->device);
     for (auto &a : p->allocs)
         if (a.own) (void)hipFree(a.own);
+    if (p->ev) (void)hipStreamSynchronize(p->ctx->own);
     for (rsoc::DevBuf *b : {&p->slots_dev, &p->tasks_dev, &p->active_dev, &p->arena}) b->release();
-    for (rsoc::HostPinned *b : {&p->mirror, &p->tasks_host, &p->active_host}) b->release();
+    for (rsoc::HostPinned *b : {&p->mirror, &p->tasks_host, &p->active_host, &p->stage}) b->release();
+    if (p->ev) (void)hipEventDestroy(p->ev);
     delete p;
 }
 
@@ -168,20 +187,7 @@ int32_t rsoc_pool_admit(rsoc_pool *p, const int32_t *d_row_ptr, const int32_t *d
     p->allocs[slot] = al;
     p->reserved += bytes;
     hipStream_t s = c->own;
-    HostStaging *h = c->host.as<HostStaging>();
     int32_t r = RSOC_OK;
-    int64_t nnz = 0;
-    if (n > 0) {
-        hipError_t e = hipMemcpyAsync(&h->rp_ends[1], d_row_ptr + n, 4, hipMemcpyDeviceToHost, s);
-        if (e == hipSuccess) e = hipStreamSynchronize(s);
-        if (e != hipSuccess) r = hip_fail(e, "read nnz", __FILE__, __LINE__);
-        nnz = h->rp_ends[1];
-        if (r == RSOC_OK && (nnz < 0 || (nnz > 0 && !d_col_idx))) r = RSOC_EINVAL;
-    }
-    if (r < 0) {
-        pool_release(p, slot);
-        return r;
-    }
     const int64_t l = align_up(4 * (int64_t)(n + 1), kPoolAlign);
     PoolSlot &m = pool_mirror(p)[slot];
     memset(&m, 0, sizeof(m));
@@ -194,7 +200,6 @@ int32_t rsoc_pool_admit(rsoc_pool *p, const int32_t *d_row_ptr, const int32_t *d
     m.hubB = reinterpret_cast<int32_t *>(base + 3 * l);
     m.col8 = reinterpret_cast<uint8_t *>(base + 4 * l);
     m.pend = o.mode == kOptimistic ? nullptr : reinterpret_cast<int32_t *>(base + 4 * l + align_up(n + 64, kPoolAlign));
-    m.nnz = nnz;
     m.n = n;
     m.mode = o.mode;
     m.tie = o.tie;
@@ -202,27 +207,18 @@ int32_t rsoc_pool_admit(rsoc_pool *p, const int32_t *d_row_ptr, const int32_t *d
     m.t_thread = o.t_thread;
     m.t_wave = o.t_wave;
     m.look = o.lookahead == -1 ? 0 : (o.lookahead > 0 ? o.lookahead : (1 << 20));
-    m.phase = kSlotNew;
-    m.chunk = 1;
+    m.phase = n > 0 ? kSlotNew : kSlotDone;  // nothing to colour: done at once
+    m.chunk = o.chunk;  // 0: chosen from the locality sample when the set-up is seen
     p->reported[slot] = 0;
     if ((r = pool_upload_slot(p, slot, s)) < 0) { pool_release(p, slot); return r; }
     if (n > 0) {
-        // fill the colours (round 0 of the round-synchronous mode) and bin by degree
         k_pinit<<<std::min(div_up(n, kBlock), 1024), kBlock, 0, s>>>(p->slots_dev.as<PoolSlot>(), slot);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) { pool_release(p, slot); return hip_fail(e, "k_pinit", __FILE__, __LINE__); }
         if ((r = pool_download_slot(p, slot, s)) < 0) { pool_release(p, slot); return r; }
-        e = hipStreamSynchronize(s);
-        if (e != hipSuccess) { pool_release(p, slot); return hip_fail(e, "admit sync", __FILE__, __LINE__); }
-        m.offW = n - m.nW - m.nB;
-        m.offB = n - m.nB;
-        m.chunk = pick_chunk(o.chunk, m.near, m.sampled);
-    } else {
-        m.phase = kSlotDone;  // nothing to colour
+        p->pending[slot] = 1;
     }
-    if ((r = pool_upload_slot(p, slot, s)) < 0) { pool_release(p, slot); return r; }
-    hipError_t e = hipStreamSynchronize(s);
-    if (e != hipSuccess) { pool_release(p, slot); return hip_fail(e, "admit sync", __FILE__, __LINE__); }
+    RSOC_HIP(hipEventRecord(p->ev, s));
     return slot;
 }
 
@@ -233,6 +229,27 @@ int32_t rsoc_pool_step(rsoc_pool *p, void *hip_stream, int32_t *finished_slots, 
     RSOC_HIP(hipSetDevice(c->device));
     hipStream_t s = (hipStream_t)hip_stream;
     PoolSlot *m = pool_mirror(p);
+    // admission and release work on the context's stream comes first
+    RSOC_HIP(hipStreamWaitEvent(s, p->ev, 0));
+    bool any_pending = false;
+    for (int i = 0; i < p->max_slots; ++i) any_pending |= p->pending[i] != 0;
+    if (any_pending) {
+        // the new slots' set-up is done and their state downloaded
+        RSOC_HIP(hipEventSynchronize(p->ev));
+        for (int i = 0; i < p->max_slots; ++i) {
+            if (!p->pending[i]) continue;
+            p->pending[i] = 0;
+            PoolSlot &ms = m[i];
+            if (ms.status < 0) {
+                ms.phase = kSlotDone;  // bad row_ptr ends or missing col_idx
+            } else {
+                ms.offW = ms.n - ms.nW - ms.nB;
+                ms.offB = ms.n - ms.nB;
+                ms.chunk = pick_chunk(ms.chunk, ms.near, ms.sampled);
+            }
+            RSOC_TRY(pool_upload_slot(p, i, s));
+        }
+    }
     // task table: workgroup-bin tasks, then wavefront-bin, then thread-bin
     std::vector<PoolTask> tb, tw, tt;
     int nact = 0;
@@ -281,8 +298,27 @@ int32_t rsoc_pool_step(rsoc_pool *p, void *hip_stream, int32_t *finished_slots, 
                                                                       p->active_dev.as<int32_t>(), nact);
         k_pround_end<<<1, 256, 0, s>>>(p->slots_dev.as<PoolSlot>(), p->active_dev.as<int32_t>(), nact);
         RSOC_LAUNCH_CHECK();
-        RSOC_HIP(hipMemcpyAsync(m, p->slots_dev.p, sizeof(PoolSlot) * (size_t)p->max_slots, hipMemcpyDeviceToHost, s));
+        PoolSlot *st = p->stage.as<PoolSlot>();
+        RSOC_HIP(hipMemcpyAsync(st, p->slots_dev.p, sizeof(PoolSlot) * (size_t)p->max_slots, hipMemcpyDeviceToHost, s));
         RSOC_HIP(hipStreamSynchronize(s));
+        // only the slots of this step changed on the device
+        for (int k = 0; k < nact; ++k) m[act[k]] = st[act[k]];
+        // colour counts of the slots that finished, one download for all
+        bool counted = false;
+        for (int k = 0; k < nact; ++k) {
+            const int i = act[k];
+            if (m[i].phase != kSlotDone) continue;
+            k_pcount<<<std::min(div_up(m[i].n, kBlock), 1024), kBlock, 0, s>>>(p->slots_dev.as<PoolSlot>(), i);
+            RSOC_HIP(hipMemcpyAsync(st + i, p->slots_dev.as<PoolSlot>() + i, sizeof(PoolSlot), hipMemcpyDeviceToHost,
+                                    s));
+            counted = true;
+        }
+        if (counted) {
+            RSOC_LAUNCH_CHECK();
+            RSOC_HIP(hipStreamSynchronize(s));
+            for (int k = 0; k < nact; ++k)
+                if (m[act[k]].phase == kSlotDone) m[act[k]] = st[act[k]];
+        }
     }
     // report finished slots (including ones a previous step could not fit in `cap`)
     for (int i = 0; i < p->max_slots && nfin < cap; ++i) {
@@ -308,16 +344,9 @@ int32_t rsoc_pool_result(rsoc_pool *p, int32_t slot, rsoc_stats *stats) {
     using namespace rsoc;
     if (!p || slot < 0 || slot >= p->max_slots) return RSOC_ENOTFOUND;
     PoolSlot &m = pool_mirror(p)[slot];
-    if (m.phase != kSlotDone) return RSOC_ENOTFOUND;
+    if (m.phase != kSlotDone || p->pending[slot]) return RSOC_ENOTFOUND;
     rsoc_ctx *c = p->ctx;
     RSOC_HIP(hipSetDevice(c->device));
-    hipStream_t s = c->own;
-    if (m.n > 0) {
-        k_pcount<<<std::min(div_up(m.n, kBlock), 1024), kBlock, 0, s>>>(p->slots_dev.as<PoolSlot>(), slot);
-        RSOC_LAUNCH_CHECK();
-        RSOC_TRY(pool_download_slot(p, slot, s));
-        RSOC_HIP(hipStreamSynchronize(s));
-    }
     if (stats) {
         int32_t *keep = stats->per_round_L;
         int32_t cap = stats->per_round_cap;
@@ -337,10 +366,11 @@ int32_t rsoc_pool_result(rsoc_pool *p, int32_t slot, rsoc_stats *stats) {
         stats->chunk = m.chunk;
     }
     const int32_t k = (m.err & 4) ? RSOC_EHIP : (m.status < 0 ? m.status : m.kmax);
+    // the freed slot's device copy is refreshed before the next step reads it
+    hipStream_t s = c->own;
     pool_release(p, slot);
-    int32_t r = pool_upload_slot(p, slot, s);
-    if (r < 0) return r;
-    RSOC_HIP(hipStreamSynchronize(s));
+    RSOC_TRY(pool_upload_slot(p, slot, s));
+    RSOC_HIP(hipEventRecord(p->ev, s));
     return k;
 }
 

@@ -38,6 +38,10 @@ struct PoolTask {
     int32_t slot, kind, begin, end;
 };
 
+// Admission: fills the colours (round 0 of the round-synchronous mode), bins
+// by degree, samples id locality, and checks the ends of row_ptr (status
+// RSOC_ECSR when row_ptr[0] != 0 or row_ptr[n] < 0, RSOC_EINVAL when edges
+// come without col_idx); nnz = row_ptr[n] is recorded for the host.
 __global__ __launch_bounds__(kBlock) void k_pinit(PoolSlot *slots, int slot) {
     __shared__ int sh[kWavesPerBlock];
     __shared__ int qW[kQueueCap], qB[kQueueCap];
@@ -49,6 +53,12 @@ __global__ __launch_bounds__(kBlock) void k_pinit(PoolSlot *slots, int slot) {
     const int n = sp->n;
     const int fillc = sp->mode == kOptimistic ? -1 : 0;
     const RSOC_GLOBAL int32_t *ci = gro(sp->ci);
+    const int64_t nnz = rp[n];
+    const bool rows_ok = rp[0] == 0 && nnz >= 0 && (nnz == 0 || sp->ci != nullptr);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sp->nnz = nnz;
+        if (!rows_ok) sp->status = (rp[0] != 0 || nnz < 0) ? -2 /* RSOC_ECSR */ : -1 /* RSOC_EINVAL */;
+    }
     int md = 0;
     uint64_t near = 0, sampled = 0;
     for (int64_t base = (int64_t)blockIdx.x * kBlock; base < n; base += (int64_t)gridDim.x * kBlock) {
@@ -58,7 +68,7 @@ __global__ __launch_bounds__(kBlock) void k_pinit(PoolSlot *slots, int slot) {
             d = rp[v + 1] - rp[v];
             sp->col[v] = fillc;
             sp->col8[v] = shadow_of(fillc);
-            if ((v & 255) == 0) locality_row(rp, ci, v, rp[n], near, sampled);  // id-locality sample
+            if ((v & 255) == 0 && rows_ok) locality_row(rp, ci, v, nnz, near, sampled);  // id-locality sample
         }
         md = max(md, d);
         queue_push(d > sp->t_wave, v, qB, &nqB);

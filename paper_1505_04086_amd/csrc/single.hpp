@@ -390,7 +390,10 @@ inline int32_t run_single(rsoc_ctx *c, const int32_t *rp, const int32_t *ci, int
         const int left = h->head.cnt_in[0] + h->head.cnt_in[1] + h->head.cnt_in[2];
         if (left == 0) break;
         if (h->head.passes >= o.max_rounds) { status = RSOC_ENOCONV; break; }
-        if (o.mode == kOptimistic && left <= tail_max) {
+        // the ordered pass pays off where the list has stopped shrinking
+        // quickly (mutually adjacent hubs), not where a round or two more
+        // would empty it
+        if (o.mode == kOptimistic && left <= tail_max && 2 * (int64_t)h->head.lastL >= h->head.prevL) {
             RSOC_TRY(ensure_tail_scratch(c, n, s));
             o.tie ? launch_tail<kHigherKeeps>(c, s, left) : launch_tail<kLowerKeeps>(c, s, left);
             RSOC_LAUNCH_CHECK();

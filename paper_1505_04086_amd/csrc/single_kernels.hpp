@@ -47,6 +47,7 @@ struct SingleState {
     int32_t rounds;       // passes that recoloured somebody
     int32_t err;          // bit 0 bad CSR, bit 1 self-loop, bit 2 colour out of range
     int32_t nnz;          // row_ptr[n] (read by k_bin)
+    int32_t lastL, prevL; // |L| of the last two rounds that inspected anything
     // colour statistics (k_colour_stats; cleared before each computation)
     int32_t kmax;         // max colour + 1
     int32_t distinct;     // distinct colours >= 255
@@ -692,6 +693,8 @@ __global__ void k_round_end(const SingleArgs *__restrict__ A, SingleState *S) {
     const int in_total = SWEEP ? A->n : (S->cnt_in[0] + S->cnt_in[1] + S->cnt_in[2]);
     const int out_total = S->cnt_out[0] + S->cnt_out[1] + S->cnt_out[2];
     if (in_total > 0) {
+        S->prevL = S->lastL;
+        S->lastL = out_total;
         S->passes += 1;
         if (S->passes == 1) {
             S->inspected1 = S->inspected;

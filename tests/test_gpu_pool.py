@@ -115,3 +115,32 @@ def test_pool_max_rounds_guard(lib, ctx):
     want = oracle.rsync(*gg.path(6), max_rounds=2, raise_on_noconv=False)
     assert np.array_equal(d[2].cpu().numpy()[:6], want["colors"])
     pool.close()
+
+
+def test_pool_admission_errors_arrive_with_the_result(lib, ctx):
+    """Admission waits on nothing: bad row_ptr ends and edges without col_idx
+    finish their slot at the next step and come back from rsoc_pool_result,
+    next to a good graph admitted beside them."""
+    import torch
+    pool = lib.Pool(ctx, 0, 8)
+    good = _dev(*gg.cycle(9))
+    rp, ci = gg.cycle(7)
+    bad_rp = rp.copy()
+    bad_rp[0] = 1
+    bad = _dev(bad_rp, ci)
+    d = torch.device("cuda:0")
+    nocol = (torch.from_numpy(rp).to(d), None, torch.empty(7, dtype=torch.int32, device=d))
+    slots = {"good": pool.admit(good[0], good[1], 9, good[2]), "bad": pool.admit(bad[0], bad[1], 7, bad[2]),
+             "nocol": pool.admit(nocol[0], nocol[1], 7, nocol[2])}
+    done = set()
+    while len(done) < 3:
+        done |= set(pool.step())
+    assert done == set(slots.values())
+    for name, code in (("bad", lib.RSOC_ECSR), ("nocol", lib.RSOC_EINVAL)):
+        with pytest.raises(lib.RsocError) as e:
+            pool.result(slots[name])
+        assert e.value.code == code
+    k, st = pool.result(slots["good"])
+    assert oracle.check(*gg.cycle(9), good[2].cpu().numpy()[:9]) == 0 and k == 3
+    assert pool.live() == 0 and pool.reserved_bytes() == 0
+    pool.close()
