@@ -43,9 +43,13 @@ constexpr int64_t kPoolAlign = 256;
 
 inline int64_t align_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
+// two worklists, two hub lists, the byte shadow, then the 4-bit shadow and
+// round 0's kept neighbours (optimistic) or the staged colours
+// (round-synchronous)
 inline int64_t pool_slot_bytes(int64_t n, int mode) {
     const int64_t l = align_up(4 * (n + 1), kPoolAlign);
-    return 4 * l + align_up(n + 64, kPoolAlign) + (mode == kOptimistic ? 0 : l);
+    return 4 * l + align_up(n + 64, kPoolAlign) +
+           (mode == kOptimistic ? align_up(4 * (n / 8 + 2), kPoolAlign) + align_up(16 * (n + 2), kPoolAlign) : l);
 }
 
 inline int64_t arena_alloc(rsoc_pool *p, int64_t bytes) {
@@ -199,7 +203,10 @@ int32_t rsoc_pool_admit(rsoc_pool *p, const int32_t *d_row_ptr, const int32_t *d
     m.hubW = reinterpret_cast<int32_t *>(base + 2 * l);
     m.hubB = reinterpret_cast<int32_t *>(base + 3 * l);
     m.col8 = reinterpret_cast<uint8_t *>(base + 4 * l);
-    m.pend = o.mode == kOptimistic ? nullptr : reinterpret_cast<int32_t *>(base + 4 * l + align_up(n + 64, kPoolAlign));
+    char *tail = base + 4 * l + align_up(n + 64, kPoolAlign);
+    m.pend = o.mode == kOptimistic ? nullptr : reinterpret_cast<int32_t *>(tail);
+    m.col4 = o.mode == kOptimistic ? reinterpret_cast<uint32_t *>(tail) : nullptr;
+    m.aux = o.mode == kOptimistic ? reinterpret_cast<int4 *>(tail + align_up(4 * (n / 8 + 2), kPoolAlign)) : nullptr;
     m.n = n;
     m.mode = o.mode;
     m.tie = o.tie;
@@ -250,8 +257,14 @@ int32_t rsoc_pool_step(rsoc_pool *p, void *hip_stream, int32_t *finished_slots, 
             RSOC_TRY(pool_upload_slot(p, i, s));
         }
     }
-    // task table: workgroup-bin tasks, then wavefront-bin, then thread-bin
-    std::vector<PoolTask> tb, tw, tt;
+    // task tables, one per (kind, tie rule): workgroup-bin tasks, then
+    // wavefront-bin, then thread-bin
+    constexpr int kKinds = 8;  // kind * 2 + tie
+    std::vector<PoolTask> tb[kKinds], tw[kKinds], tt[kKinds];
+    struct SlotSpan {
+        int slot, kind, kindT, cT, cW, cB;  // kind / kindT: table index (task kind * 2 + tie)
+    };
+    std::vector<SlotSpan> spans;
     int nact = 0;
     int32_t *act = p->active_host.as<int32_t>();
     for (int i = 0; i < p->max_slots; ++i) {
@@ -269,28 +282,99 @@ int32_t rsoc_pool_step(rsoc_pool *p, void *hip_stream, int32_t *finished_slots, 
             cW = sl.cnt_in[1];
             cB = sl.cnt_in[2];
         }
-        for (int b = 0; b < cB; b += kPoolTaskB) tb.push_back({i, kind, b, std::min(cB, b + kPoolTaskB)});
-        for (int b = 0; b < cW; b += kPoolTaskW) tw.push_back({i, kind, b, std::min(cW, b + kPoolTaskW)});
-        for (int b = 0; b < cT; b += kPoolTaskT) tt.push_back({i, kind, b, std::min(cT, b + kPoolTaskT)});
+        // the thread bin's part of the first worklist round after round 0
+        const int kindT = (sl.phase == kSlotRunning && sl.masked) ? kRecolorMasked : kind;
+        spans.push_back({i, kind * 2 + sl.tie, kindT * 2 + sl.tie, cT, cW, cB});
         act[nact++] = i;
     }
+    // Each bin's tasks are dealt in proportion over the launch: task r of a
+    // slot with T tasks lands in bucket r * kDealBuckets / T, buckets in
+    // order.  The workgroups take the table in order, so every graph advances
+    // through its ids at the same relative pace and has about the same small
+    // fraction of them in flight at any time, as a single-graph sweep does;
+    // dealt slot by slot, a graph would have all its vertices coloured in the
+    // same instant (each reading its neighbours uncoloured: most would end
+    // round 0 defective), and the last graphs of the table would get the
+    // whole grid to themselves.
+    constexpr int kDealBuckets = 4096;
+    std::vector<int> fill(kDealBuckets + 1);
+    auto deal = [&](int which, int per) {
+        for (int k = 0; k < kKinds; ++k) {
+            std::vector<PoolTask> &out = which == 0 ? tt[k] : (which == 1 ? tw[k] : tb[k]);
+            std::fill(fill.begin(), fill.end(), 0);
+            size_t total = 0;
+            for (const SlotSpan &sp : spans) {
+                if ((which == 0 ? sp.kindT : sp.kind) != k) continue;
+                const int cnt = which == 0 ? sp.cT : (which == 1 ? sp.cW : sp.cB);
+                const int T = (cnt + per - 1) / per;
+                for (int r = 0; r < T; ++r) fill[(int)((int64_t)r * kDealBuckets / T) + 1] += 1;
+                total += (size_t)T;
+            }
+            if (!total) continue;
+            for (int b = 0; b < kDealBuckets; ++b) fill[b + 1] += fill[b];
+            out.resize(total);
+            for (const SlotSpan &sp : spans) {
+                if ((which == 0 ? sp.kindT : sp.kind) != k) continue;
+                const int cnt = which == 0 ? sp.cT : (which == 1 ? sp.cW : sp.cB);
+                const int T = (cnt + per - 1) / per;
+                for (int r = 0; r < T; ++r) {
+                    const int64_t b = (int64_t)r * per;
+                    out[fill[(int)((int64_t)r * kDealBuckets / T)]++] = {sp.slot, k / 2, (int)b,
+                                                                         (int)std::min<int64_t>(cnt, b + per)};
+                }
+            }
+        }
+    };
+    deal(2, kPoolTaskB);
+    deal(1, kPoolTaskW);
+    deal(0, kPoolTaskT);
     int nfin = 0;
     if (nact > 0) {
-        const size_t ntask = tb.size() + tw.size() + tt.size();
+        size_t ntask = 0;
+        for (int k = 0; k < kKinds; ++k) ntask += tb[k].size() + tw[k].size() + tt[k].size();
         RSOC_TRY(p->tasks_dev.reserve(sizeof(PoolTask) * std::max<size_t>(ntask, 1)));
         RSOC_TRY(p->tasks_host.reserve(sizeof(PoolTask) * std::max<size_t>(ntask, 1)));
         PoolTask *th = p->tasks_host.as<PoolTask>();
-        std::copy(tb.begin(), tb.end(), th);
-        std::copy(tw.begin(), tw.end(), th + tb.size());
-        std::copy(tt.begin(), tt.end(), th + tb.size() + tw.size());
+        size_t at = 0, start[kKinds];
+        for (int k = 0; k < kKinds; ++k) {
+            start[k] = at;
+            for (const auto *v : {&tb[k], &tw[k], &tt[k]}) {
+                std::copy(v->begin(), v->end(), th + at);
+                at += v->size();
+            }
+        }
         RSOC_HIP(hipMemcpyAsync(p->tasks_dev.p, th, sizeof(PoolTask) * ntask, hipMemcpyHostToDevice, s));
         RSOC_HIP(hipMemcpyAsync(p->active_dev.p, act, sizeof(int32_t) * nact, hipMemcpyHostToDevice, s));
-        const int gB = (int)std::min<size_t>(tb.size(), 256);
-        const int gW = (int)std::min<size_t>(tw.size(), 512);
-        const int gT = (int)std::min<size_t>(tt.size(), 2048);
-        if (gB + gW + gT > 0)
-            k_pstep<<<gB + gW + gT, kBlock, 0, s>>>(p->slots_dev.as<PoolSlot>(), p->tasks_dev.as<PoolTask>(),
-                                                    (int)tb.size(), (int)tw.size(), (int)tt.size(), gB, gW, gT);
+        // one launch per (kind, tie rule) present; a slot's tasks are all of
+        // one kind but the masked round's wavefront/workgroup-bin ones, whose
+        // launch comes first (the launches run in stream order; each hub
+        // recoloured first reads the thread-bin colours as they stand, so
+        // the masked test of those vertices stays sound)
+        for (int k = 0; k < kKinds; ++k) {
+            const int gB = (int)std::min<size_t>(tb[k].size(), 256);
+            const int gW = (int)std::min<size_t>(tw[k].size(), 512);
+            // no more thread-bin workgroups than fit on the device at once: the
+            // grid-stride walk would otherwise leave the tasks of the ones
+            // that wait to the end, out of id order, and round 0 would read
+            // many more neighbours uncoloured
+            const int gT = (int)std::min<size_t>(tt[k].size(), 1024);
+            if (gB + gW + gT == 0) continue;
+            PoolTask *tk = p->tasks_dev.as<PoolTask>() + start[k];
+            PoolSlot *sl = p->slots_dev.as<PoolSlot>();
+            const int nb = (int)tb[k].size(), nw = (int)tw[k].size(), nt = (int)tt[k].size();
+#define RSOC_PSTEP(KD, T) k_pstep<KD, T><<<gB + gW + gT, kBlock, 0, s>>>(sl, tk, nb, nw, nt, gB, gW, gT)
+            switch (k) {
+                case 0: RSOC_PSTEP(kAssignSweep, kLowerKeeps); break;
+                case 1: RSOC_PSTEP(kAssignSweep, kHigherKeeps); break;
+                case 2: RSOC_PSTEP(kRecolorSweep, kLowerKeeps); break;
+                case 3: RSOC_PSTEP(kRecolorSweep, kHigherKeeps); break;
+                case 4: RSOC_PSTEP(kRecolorList, kLowerKeeps); break;
+                case 5: RSOC_PSTEP(kRecolorList, kHigherKeeps); break;
+                case 6: RSOC_PSTEP(kRecolorMasked, kLowerKeeps); break;
+                default: RSOC_PSTEP(kRecolorMasked, kHigherKeeps); break;
+            }
+#undef RSOC_PSTEP
+        }
         bool any_staged = false;
         for (int k = 0; k < nact; ++k) any_staged |= m[act[k]].mode != kOptimistic;
         if (any_staged)

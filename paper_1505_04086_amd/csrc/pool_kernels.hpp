@@ -12,7 +12,11 @@
 namespace rsoc {
 
 enum PoolPhase : int { kSlotFree = 0, kSlotNew = 1, kSlotRunning = 2, kSlotDone = 3 };
-enum PoolTaskKind : int { kAssignSweep = 0, kRecolorSweep = 1, kRecolorList = 2 };
+// kRecolorMasked: the thread-bin part of an optimistic slot's first worklist
+// round, whose entries carry what round 0 kept for them (see k_round's ROUND0)
+enum PoolTaskKind : int { kAssignSweep = 0, kRecolorSweep = 1, kRecolorList = 2, kRecolorMasked = 3 };
+constexpr int kPoolAuxCap = 256;     // round-0 queue length when entries carry their kept neighbours
+constexpr int kPoolMaskedBuf = 128;  // per-wavefront append buffer of the masked round
 constexpr int kPoolTaskT = kStep;  // thread-bin items per task (one workgroup step)
 constexpr int kPoolTaskW = 32;   // wavefront-bin items per task
 constexpr int kPoolTaskB = 2;    // workgroup-bin items per task
@@ -21,6 +25,8 @@ struct PoolSlot {
     const int32_t *rp, *ci;
     int32_t *col;
     uint8_t *col8;
+    uint32_t *col4;     // 4-bit shadow read and published by round 0 (optimistic slots)
+    int4 *aux;          // round 0's kept neighbours of U^0's thread-bin entries (optimistic slots)
     int32_t *pend;
     int32_t *wl[2];
     int32_t *hubW, *hubB;
@@ -30,7 +36,7 @@ struct PoolSlot {
     int32_t offW, offB;
     int32_t cnt_in[4], cnt_out[4];
     int32_t nW, nB, maxdeg, passes, rounds, kmax, err, phase, u0, status;
-    int32_t chunk, pad;
+    int32_t chunk, masked;  // masked: the next round is the first worklist round after round 0
     uint64_t near, sampled;  // id locality sample (admission)
 };
 
@@ -68,6 +74,7 @@ __global__ __launch_bounds__(kBlock) void k_pinit(PoolSlot *slots, int slot) {
             d = rp[v + 1] - rp[v];
             sp->col[v] = fillc;
             sp->col8[v] = shadow_of(fillc);
+            if (sp->col4 && (v & 7) == 0) sp->col4[v >> 3] = ~0u;  // every nibble 15: nothing published yet
             if ((v & 255) == 0 && rows_ok) locality_row(rp, ci, v, nnz, near, sampled);  // id-locality sample
         }
         md = max(md, d);
@@ -91,13 +98,17 @@ __global__ __launch_bounds__(kBlock) void k_pinit(PoolSlot *slots, int slot) {
 
 template <int TIE, int KIND>
 __device__ __forceinline__ void pool_thread_task(PoolSlot *sp, const PoolSlot &s, const PoolTask &tk, int *q, int *qn,
-                                                 int *qbase) {
+                                                 int *qbase, int4 *qa) {
     constexpr int PHASE = KIND == kAssignSweep ? kAssign : kRecolor;
     constexpr bool SWEEP = KIND != kRecolorList;
     constexpr bool kWinOnly = KIND == kAssignSweep;
+    // round 0 (optimistic slots only) reads and publishes the 4-bit shadow;
+    // later rounds read the byte shadow, so no nibble is ever read stale
+    constexpr bool kNib = KIND == kAssignSweep;
     const RSOC_GLOBAL int32_t *rp = gro(s.rp);
     const RSOC_GLOBAL int32_t *ci = gro(s.ci);
     const RSOC_GLOBAL uint8_t *c8 = gro(s.col8);
+    RSOC_GLOBAL uint32_t *c4 = grw(s.col4);
     const bool opt = s.mode == kOptimistic;
     RSOC_GLOBAL int32_t *wcol = grw(opt ? s.col : s.pend);
     RSOC_GLOBAL uint8_t *wcol8 = grw(s.col8);
@@ -110,6 +121,7 @@ __device__ __forceinline__ void pool_thread_task(PoolSlot *sp, const PoolSlot &s
             int v[kNV], b[kNV], e[kNV], cv[kNV], nc[kNV];
             bool act[kNV];
             uint32_t unc[kNV] = {};
+            int keep[kNV][4];
 #pragma unroll
             for (int i = 0; i < kNV; ++i) {
                 const int idx = base + step_offset(r, i, gi, s.chunk);
@@ -126,10 +138,11 @@ __device__ __forceinline__ void pool_thread_task(PoolSlot *sp, const PoolSlot &s
             }
             const RSOC_GLOBAL int32_t *cis[kNV];
             const RSOC_GLOBAL uint8_t *c8s[kNV];
+            const RSOC_GLOBAL uint32_t *c4s[kNV];
 #pragma unroll
-            for (int i = 0; i < kNV; ++i) cis[i] = ci, c8s[i] = c8;
-            group_vertices<PHASE, TIE, kGroup, kGroupSlots, kWinOnly, kNV>(v, b, e, cis, c8s, cv, s.look, nc, act,
-                                                                           unc);
+            for (int i = 0; i < kNV; ++i) cis[i] = ci, c8s[i] = c8, c4s[i] = c4;
+            group_vertices<PHASE, TIE, kGroup, kGroupSlots, kWinOnly, kNV, kNib>(v, b, e, cis, c8s, cv, s.look, nc,
+                                                                                 act, unc, c4s, kNib ? keep : nullptr);
 #pragma unroll
             for (int i = 0; i < kNV; ++i) {
                 if (v[i] < 0) {
@@ -141,14 +154,69 @@ __device__ __forceinline__ void pool_thread_task(PoolSlot *sp, const PoolSlot &s
                     if (opt) wcol8[v[i]] = (uint8_t)nc[i];
                 }
             }
+            if (kNib) {
+                int ids[kNV];
+#pragma unroll
+                for (int i = 0; i < kNV; ++i) {
+                    const int idx = base + step_offset(r, i, gi, s.chunk);
+                    ids[i] = idx < tk.end ? (TIE == kHigherKeeps ? s.n - 1 - idx : idx) : -1;
+                }
+                publish_nibbles<kNV>(ids, v, nc, c4, leader);
+            }
 #pragma unroll
             for (int i = 0; i < kNV; ++i)
-                queue_push((KIND == kAssignSweep ? unc[i] != 0 : act[i]) && leader, v[i], q, qn);
+                queue_push<int4>((KIND == kAssignSweep ? unc[i] != 0 : act[i]) && leader, v[i], q, qn,
+                                 kNib ? qa : nullptr,
+                                 kNib ? make_int4(keep[i][0], keep[i][1], keep[i][2], keep[i][3]) : int4{});
             __syncthreads();
-            if (*qn > kQueueCap - kSub) queue_flush(q, qn, qbase, &sp->cnt_out[kBinThread], out);
+            if (*qn > (kNib ? kPoolAuxCap : kQueueCap) - kSub)
+                queue_flush<int4>(q, qn, qbase, &sp->cnt_out[kBinThread], out, kNib ? qa : nullptr, s.aux);
         }
     }
-    queue_flush(q, qn, qbase, &sp->cnt_out[kBinThread], out);
+    queue_flush<int4>(q, qn, qbase, &sp->cnt_out[kBinThread], out, kNib ? qa : nullptr, s.aux);
+}
+
+// The first worklist round after round 0, thread-bin entries: one lane per
+// entry tests only the neighbours round 0 kept for it (lane_detect_kept);
+// defective entries, and entries that kept more than three, go to the lane
+// groups (wave_recolour_selected); appends gather in the wavefront's buffer.
+template <int TIE>
+__device__ __forceinline__ void pool_masked_task(PoolSlot *sp, const PoolSlot &s, const PoolTask &tk, int *ms,
+                                                 int *mb, int *mbn) {
+    typedef int v4i __attribute__((ext_vector_type(4)));
+    const int32_t *in = s.parity ? s.wl[1] : s.wl[0];
+    int32_t *out = s.parity ? s.wl[0] : s.wl[1];
+    const RSOC_GLOBAL int32_t *rp = gro(s.rp);
+    const RSOC_GLOBAL int32_t *ci = gro(s.ci);
+    const RSOC_GLOBAL uint8_t *c8 = gro(s.col8);
+    const RSOC_GLOBAL v4i *ax = (const RSOC_GLOBAL v4i *)s.aux;
+    RSOC_GLOBAL int32_t *wcol = grw(s.col);
+    RSOC_GLOBAL uint8_t *wcol8 = grw(s.col8);
+    const int wv = threadIdx.x / kWave;
+    uint64_t degs = 0;
+    if (lane_id() == 0) *mbn = 0;
+    wave_lds_sync();
+    for (int base = tk.begin + wv * kWave; base < tk.end; base += kWavesPerBlock * kWave) {
+        const int idx = base + lane_id();
+        int v = -1, cv = 255;
+        int4 x = {0, 0, 0, 0};
+        if (idx < tk.end) {
+            v = in[idx];
+            const v4i y = ax[idx];
+            x = make_int4(y.x, y.y, y.z, y.w);
+            cv = c8[v];
+        }
+        const bool over = v >= 0 && __popc((uint32_t)x.w) > 3;
+        const bool def = v >= 0 && !over && lane_detect_kept<false>(v, x, cv, c8, nullptr);
+        wave_recolour_selected<kAssign, TIE, false>(ballot(def), v, ms, mb, mbn, rp, ci, c8, nullptr, wcol, wcol8,
+                                                    nullptr, s.look, degs);
+        const uint64_t om = ballot(over);
+        if (om)
+            wave_recolour_selected<kRecolor, TIE, false>(om, v, ms, mb, mbn, rp, ci, c8, nullptr, wcol, wcol8,
+                                                         nullptr, s.look, degs);
+        if (*mbn >= kPoolMaskedBuf - kWave) wave_buf_flush(mb, mbn, &sp->cnt_out[kBinThread], out);
+    }
+    wave_buf_flush(mb, mbn, &sp->cnt_out[kBinThread], out);
 }
 
 template <int TIE, int KIND>
@@ -172,6 +240,7 @@ __device__ __forceinline__ void pool_wave_task(PoolSlot *sp, const PoolSlot &s, 
         if (lane_id() == 0 && act) {
             (opt ? s.col : s.pend)[v] = nc;
             if (opt) s.col8[v] = shadow_of(nc);
+            if (KIND == kAssignSweep) publish_nibble(grw(s.col4), v, nc);
         }
         wave_buf_push(KIND == kAssignSweep ? unc : act, v, wbuf, wbn, &sp->cnt_out[kBinWave], out);
     }
@@ -197,61 +266,51 @@ __device__ __forceinline__ void pool_block_task(PoolSlot *sp, const PoolSlot &s,
             if (act) {
                 (opt ? s.col : s.pend)[v] = nc;
                 if (opt) s.col8[v] = shadow_of(nc);
+                if (KIND == kAssignSweep) publish_nibble(grw(s.col4), v, nc);
             }
             if (KIND == kAssignSweep ? unc : act) out[atomicAdd(&sp->cnt_out[kBinBlock], 1)] = v;
         }
     }
 }
 
-// One fused pool round.  Blocks [0,gB) take workgroup-bin tasks, [gB,gB+gW)
-// wavefront-bin tasks, the rest thread-bin tasks (grid-stride over each).
+// One fused pool round for the tasks of one kind and tie rule (one launch per
+// pair present in the step, so that each gets the registers of its own code
+// and not those of the largest).  Blocks [0,gT) take thread-bin tasks,
+// [gT,gT+gW) wavefront-bin tasks, the rest workgroup-bin tasks (grid-stride
+// over each).  kRecolorMasked has thread-bin tasks only.
+template <int KIND, int TIE>
 __global__ __launch_bounds__(kBlock) void k_pstep(PoolSlot *slots, const PoolTask *__restrict__ tasks, int ntB,
                                                   int ntW, int ntT, int gB, int gW, int gT) {
-    __shared__ uint32_t lds[kLdsWords];
-    __shared__ int q[kQueueCap];
+    constexpr bool kMasked = KIND == kRecolorMasked;
+    constexpr bool kAux = KIND == kAssignSweep;
+    __shared__ uint32_t lds[kMasked ? 1 : kLdsWords];
+    __shared__ int q[kMasked ? 1 : kQueueCap];
     __shared__ int sh_min, qn, qbase;
-    __shared__ int wbuf[kWavesPerBlock][kWaveBuf];
+    __shared__ int wbuf[kWavesPerBlock][kMasked ? 1 : kWaveBuf];
     __shared__ int wbn[kWavesPerBlock];
+    __shared__ int4 qa[kAux ? kPoolAuxCap : 1];
+    __shared__ int mstage[kWavesPerBlock][kMasked ? kWave : 1];
+    __shared__ int mbuf[kWavesPerBlock][kMasked ? kPoolMaskedBuf : 1];
     const int bid = blockIdx.x;
     if (threadIdx.x == 0) qn = 0;
     __syncthreads();
+    // thread-bin workgroups come first in the grid, so they are dispatched
+    // first: the order in which round 0 walks the ids must not wait behind
+    // the hubs
+    const int sec = bid < gT ? 0 : (bid < gT + gW ? 1 : 2);
     int first, count, stride, self;
-    if (bid < gB) { first = 0; count = ntB; stride = gB; self = bid; }
-    else if (bid < gB + gW) { first = ntB; count = ntW; stride = gW; self = bid - gB; }
-    else { first = ntB + ntW; count = ntT; stride = gT; self = bid - gB - gW; }
+    if (sec == 0) { first = ntB + ntW; count = ntT; stride = gT; self = bid; }
+    else if (sec == 1) { first = ntB; count = ntW; stride = gW; self = bid - gT; }
+    else { first = 0; count = ntB; stride = gB; self = bid - gT - gW; }
+    const int wv = threadIdx.x / kWave;
     for (int t = self; t < count; t += stride) {
         const PoolTask tk = tasks[first + t];
         PoolSlot *sp = slots + tk.slot;
         const PoolSlot s = *sp;
-        const int sel = tk.kind * 2 + s.tie;
-        if (bid < gB) {
-            switch (sel) {
-                case 0: pool_block_task<kLowerKeeps, kAssignSweep>(sp, s, tk, lds, &sh_min); break;
-                case 1: pool_block_task<kHigherKeeps, kAssignSweep>(sp, s, tk, lds, &sh_min); break;
-                case 2: pool_block_task<kLowerKeeps, kRecolorSweep>(sp, s, tk, lds, &sh_min); break;
-                case 3: pool_block_task<kHigherKeeps, kRecolorSweep>(sp, s, tk, lds, &sh_min); break;
-                case 4: pool_block_task<kLowerKeeps, kRecolorList>(sp, s, tk, lds, &sh_min); break;
-                default: pool_block_task<kHigherKeeps, kRecolorList>(sp, s, tk, lds, &sh_min); break;
-            }
-        } else if (bid < gB + gW) {
-            switch (sel) {
-                case 0: pool_wave_task<kLowerKeeps, kAssignSweep>(sp, s, tk, lds, wbuf[threadIdx.x / kWave], &wbn[threadIdx.x / kWave]); break;
-                case 1: pool_wave_task<kHigherKeeps, kAssignSweep>(sp, s, tk, lds, wbuf[threadIdx.x / kWave], &wbn[threadIdx.x / kWave]); break;
-                case 2: pool_wave_task<kLowerKeeps, kRecolorSweep>(sp, s, tk, lds, wbuf[threadIdx.x / kWave], &wbn[threadIdx.x / kWave]); break;
-                case 3: pool_wave_task<kHigherKeeps, kRecolorSweep>(sp, s, tk, lds, wbuf[threadIdx.x / kWave], &wbn[threadIdx.x / kWave]); break;
-                case 4: pool_wave_task<kLowerKeeps, kRecolorList>(sp, s, tk, lds, wbuf[threadIdx.x / kWave], &wbn[threadIdx.x / kWave]); break;
-                default: pool_wave_task<kHigherKeeps, kRecolorList>(sp, s, tk, lds, wbuf[threadIdx.x / kWave], &wbn[threadIdx.x / kWave]); break;
-            }
-        } else {
-            switch (sel) {
-                case 0: pool_thread_task<kLowerKeeps, kAssignSweep>(sp, s, tk, q, &qn, &qbase); break;
-                case 1: pool_thread_task<kHigherKeeps, kAssignSweep>(sp, s, tk, q, &qn, &qbase); break;
-                case 2: pool_thread_task<kLowerKeeps, kRecolorSweep>(sp, s, tk, q, &qn, &qbase); break;
-                case 3: pool_thread_task<kHigherKeeps, kRecolorSweep>(sp, s, tk, q, &qn, &qbase); break;
-                case 4: pool_thread_task<kLowerKeeps, kRecolorList>(sp, s, tk, q, &qn, &qbase); break;
-                default: pool_thread_task<kHigherKeeps, kRecolorList>(sp, s, tk, q, &qn, &qbase); break;
-            }
-        }
+        if (kMasked) pool_masked_task<TIE>(sp, s, tk, mstage[wv], mbuf[wv], &wbn[wv]);
+        else if (sec == 2) pool_block_task<TIE, KIND>(sp, s, tk, lds, &sh_min);
+        else if (sec == 1) pool_wave_task<TIE, KIND>(sp, s, tk, lds, wbuf[wv], &wbn[wv]);
+        else pool_thread_task<TIE, KIND>(sp, s, tk, q, &qn, &qbase, qa);
     }
 }
 
@@ -282,6 +341,7 @@ __global__ void k_pround_end(PoolSlot *slots, const int32_t *__restrict__ active
         PoolSlot *sp = slots + active[k];
         const int out_total = sp->cnt_out[0] + sp->cnt_out[1] + sp->cnt_out[2];
         const bool round0 = sp->phase == kSlotNew && sp->mode == kOptimistic;
+        sp->masked = round0 ? 1 : 0;
         if (round0) {
             sp->u0 = out_total;
         } else {

@@ -333,6 +333,34 @@ __device__ __forceinline__ void wave_recolour_selected(uint64_t sel, int v, int 
     }
 }
 
+// Round 0 of the optimistic mode, lane groups: publishes into the 4-bit
+// shadow the colours this sub-step chose.  ids[i] is the vertex id slot i of
+// this lane's group covers (-1 past the end; v[i] is -1 when that vertex
+// belongs to another bin and was not coloured here).  The ids of a
+// wavefront's 8 groups are monotone in the group index, so the groups sharing
+// a 32-bit word are contiguous: a segmented OR-scan over them gathers the
+// bits to clear and the last group of each word issues one atomic AND (the
+// nibbles start at 15 and each is set once).
+template <int NV>
+__device__ __forceinline__ void publish_nibbles(const int (&ids)[NV], const int (&v)[NV], const int (&nc)[NV],
+                                                RSOC_GLOBAL uint32_t *col4, bool leader) {
+    const int g = lane_id() / kGroup;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        const int key = ids[i] >= 0 ? (ids[i] >> 3) : -1 - g;
+        uint32_t clr = v[i] >= 0 ? (0xfu ^ (uint32_t)min(nc[i], 15)) << ((v[i] & 7) << 2) : 0u;
+#pragma unroll
+        for (int d = 1; d < kWave / kGroup; d <<= 1) {
+            const uint32_t oc = __shfl_up(clr, d * kGroup);
+            const int ok = __shfl_up(key, d * kGroup);
+            if (g >= d && ok == key) clr |= oc;
+        }
+        const int nk = __shfl_down(key, kGroup);
+        const bool last = g == kWave / kGroup - 1 || nk != key;
+        if (leader && last && clr) atomicAnd((uint32_t *)&col4[key], ~clr);
+    }
+}
+
 // ---------------------------------------------------------------- round --
 // PHASE: kAssign (First-Fit), kRecolor (detect + First-Fit), kDetect.
 // MODE: kOptimistic writes colours in place (live reads); otherwise new
@@ -576,29 +604,13 @@ __global__ __launch_bounds__(kBlock) void k_round(const SingleArgs *__restrict__
                     }
                 }
                 if (kPublish) {
-                    // Publish the nibbles coloured in this sub-step: the ids of
-                    // the wavefront's 8 groups are monotone in the group index,
-                    // so the groups sharing a 32-bit word are contiguous; a
-                    // segmented OR-scan over them gathers the bits to clear and
-                    // the last group of each word issues one atomic AND.
-                    const int g = lane_id() / kGroup;
+                    int ids[kNV];
 #pragma unroll
                     for (int i = 0; i < kNV; ++i) {
                         const int64_t idx = base + step_offset(r, i, gi, c);
-                        const int id = idx < cT ? ((kFlagAppend && TIE == kHigherKeeps) ? (int)(cT - 1 - idx) : (int)idx)
-                                                : -1;
-                        const int key = id >= 0 ? (id >> 3) : -1 - g;
-                        uint32_t clr = v[i] >= 0 ? (0xfu ^ (uint32_t)min(nc[i], 15)) << ((v[i] & 7) << 2) : 0u;
-#pragma unroll
-                        for (int d = 1; d < kWave / kGroup; d <<= 1) {
-                            const uint32_t oc = __shfl_up(clr, d * kGroup);
-                            const int ok = __shfl_up(key, d * kGroup);
-                            if (g >= d && ok == key) clr |= oc;
-                        }
-                        const int nk = __shfl_down(key, kGroup);
-                        const bool last = g == kWave / kGroup - 1 || nk != key;
-                        if (leader && last && clr) atomicAnd((uint32_t *)&wcol4[key], ~clr);
+                        ids[i] = idx < cT ? ((kFlagAppend && TIE == kHigherKeeps) ? (int)(cT - 1 - idx) : (int)idx) : -1;
                     }
+                    publish_nibbles<kNV>(ids, v, nc, wcol4, leader);
                 }
                 if (kAppend) {
 #pragma unroll

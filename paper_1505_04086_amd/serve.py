@@ -85,7 +85,7 @@ def slot_scratch_bytes(n: int, deterministic: bool) -> int:
     as the library reserves it."""
     al = lambda x: (x + 255) // 256 * 256  # noqa: E731
     L = al(4 * (n + 1))
-    return 4 * L + al(n + 64) + (L if deterministic else 0)
+    return 4 * L + al(n + 64) + (L if deterministic else al(4 * (n // 8 + 2)) + al(16 * (n + 2)))
 
 
 def admit_fifo(queue: collections.deque, ledger: BudgetLedger, scratch_cap: int = 1 << 62):

@@ -72,7 +72,8 @@ def test_pool_staggered_admission(lib, ctx, split):
 def test_pool_budget_and_slots(lib, ctx):
     rp, ci = gg.tri_grid(64, 64)
     n = len(rp) - 1
-    per = 4 * (((4 * (n + 1) + 255) // 256) * 256) + ((n + 64 + 255) // 256) * 256  # optimistic slot scratch
+    from paper_1505_04086_amd import serve
+    per = serve.slot_scratch_bytes(n, False)  # optimistic slot scratch, as the serving layer accounts it
     pool = lib.Pool(ctx, per + per // 2, 8)
     a = _dev(rp, ci)
     b = _dev(rp, ci)

@@ -43,8 +43,10 @@ def test_ledger_and_fifo_admission():
 
 def test_slot_scratch_matches_library_formula():
     from paper_1505_04086_amd import serve
-    # 4 worklist-sized arrays (two worklists, two hub lists) + byte shadow, 256-byte aligned
-    assert serve.slot_scratch_bytes(1000, False) == 4 * 4096 + 1280
+    # 4 worklist-sized arrays (two worklists, two hub lists) + byte shadow, then
+    # the 4-bit shadow and round 0's kept neighbours (optimistic) or the
+    # staged colours, each 256-byte aligned
+    assert serve.slot_scratch_bytes(1000, False) == 4 * 4096 + 1280 + 512 + 16128
     assert serve.slot_scratch_bytes(1000, True) == 5 * 4096 + 1280
 
 
