@@ -42,7 +42,7 @@ inline void launch_blist_rounds_dyn(rsoc_ctx *c, hipStream_t s, int mode, int ti
 }
 
 inline int32_t get_batch_graph(rsoc_ctx *c, int mode, int tie, int K, int gB, int gW, int gT, hipGraphExec_t *out) {
-    auto key = std::make_tuple(100 + mode, tie, K, gB, gW, gT);
+    auto key = std::make_tuple(100 + mode, tie, K, gB, gW, gT, 0);
     auto it = c->graphs.find(key);
     if (it != c->graphs.end()) { *out = it->second; return RSOC_OK; }
     hipGraph_t g = nullptr;

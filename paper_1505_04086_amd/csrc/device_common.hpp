@@ -40,6 +40,16 @@ constexpr int kChunk = 8;                           // consecutive ids per run
 constexpr int kSub = kNV * kGpb;                    // vertices per sub-step
 constexpr int kStep = kSub * kChunk;                // vertices per workgroup step
 
+// Run length of consecutive ids per lane group: the option when given, else
+// kChunk when at least 2% of sampled row entries join ids less than kChunk
+// apart (a natural-order mesh: walking runs keeps those neighbours out of the
+// same instant), else 1 (scrambled ids: neighbouring groups stream
+// neighbouring rows).
+__host__ __device__ inline int pick_chunk(int option, uint64_t near, uint64_t sampled) {
+    if (option) return option;
+    return (sampled > 0 && near * 50 >= sampled) ? kChunk : 1;
+}
+
 // Position inside a workgroup step of sub-step r (0..kChunk-1), run i, lane
 // group gi, when each group walks runs of c consecutive ids (c a power of two
 // dividing kChunk; c = 1 puts consecutive ids in neighbouring groups, which

@@ -1,6 +1,7 @@
 // host_common.hpp -- error plumbing and small host utilities for the C ABI.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <stdio.h>
@@ -35,13 +36,14 @@ inline int32_t hip_fail(hipError_t e, const char *what, const char *file, int li
 
 #define RSOC_LAUNCH_CHECK() RSOC_HIP(hipGetLastError())
 
-// Run length of consecutive ids per lane group: the option when given, else 8
-// when at least 2% of sampled row entries join ids less than 8 apart (a
-// natural-order mesh: walking runs keeps those neighbours out of the same
-// instant), else 1 (scrambled ids: neighbouring groups stream neighbouring rows).
-inline int pick_chunk(int option, uint64_t near, uint64_t sampled) {
-    if (option) return option;
-    return (sampled > 0 && near * 50 >= sampled) ? 8 : 1;
+// Launches kernel f on `grid` workgroups of `block` lanes.  Events given
+// (either may be null) record the kernel's own start and end: they are part
+// of its dispatch, so no marker command waits between it and its neighbours
+// on the stream.
+template <typename... P, typename... Args>
+inline void launch_ev(void (*f)(P...), int grid, int block, hipStream_t s, hipEvent_t start, hipEvent_t stop,
+                      Args... args) {
+    hipExtLaunchKernelGGL(f, dim3(grid), dim3(block), 0, s, start, stop, 0, args...);
 }
 
 inline int div_up(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }

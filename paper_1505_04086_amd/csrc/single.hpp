@@ -1,5 +1,10 @@
 // single.hpp -- host driver of the single-graph path (rsoc_color_device and friends).
 //
+// Binning, the argument completion (k_args) and the sweeps are enqueued
+// without the host waiting in between: the sweeps read the bin sizes on the
+// device, and the host takes them (for the worklist launch shapes) from a
+// copy that lands while round 0 runs.  Validation, when asked for, is the one
+// step the host waits for before any round.
 // Round 0 and round 1 are launched directly (both cover all of V, except in
 // the default optimistic flow, where round 1 is the masked pass over U^0);
 // the later rounds only touch the worklist and are launched as a captured HIP graph of
@@ -25,7 +30,7 @@ struct rsoc_ctx {
     rsoc::DevBuf args, state;     // SingleArgs, SingleState (fixed addresses: graphs point at them)
     rsoc::HostPinned host;        // pinned staging for small copies
     rsoc::DevBuf drp, dci, dcol;  // device copies for host-pointer calls
-    std::map<std::tuple<int, int, int, int, int, int>, hipGraphExec_t> graphs;
+    std::map<std::tuple<int, int, int, int, int, int, int>, hipGraphExec_t> graphs;
     hipEvent_t ev[8] = {};
     // batched path scratch (batch.hpp)
     rsoc::DevBuf b_desc, b_wl0, b_wl1, b_pend, b_flags, b_state, b_hub, b_kmax, b_tasks, b_args, b_col8;
@@ -33,8 +38,6 @@ struct rsoc_ctx {
 };
 
 namespace rsoc {
-
-constexpr size_t kStateHeader = offsetof(SingleState, hist);
 
 struct HostStaging {
     SingleArgs args;
@@ -106,14 +109,22 @@ inline void launch_list_rounds_dyn(rsoc_ctx *c, hipStream_t s, int mode, int tie
             : launch_list_rounds<kTwoPhase, kLowerKeeps>(c, s, K, gB, gW, gT);
 }
 
-// Captured graph of K worklist rounds, cached per (mode, tie, K, grid split).
-inline int32_t get_round_graph(rsoc_ctx *c, int mode, int tie, int K, int gB, int gW, int gT, hipGraphExec_t *out) {
-    auto key = std::make_tuple(mode, tie, K, gB, gW, gT);
+// Captured graph of K worklist rounds followed by the colour statistics and
+// the copy of the state header to the host, cached per (mode, tie, K, grid
+// split, statistics grid).  Everything the kernels need beyond their launch
+// shapes is read on the device (arguments block, state), so one graph serves
+// every input with these shapes.
+inline int32_t get_round_graph(rsoc_ctx *c, int mode, int tie, int K, int gB, int gW, int gT, int gstat,
+                               hipGraphExec_t *out) {
+    auto key = std::make_tuple(mode, tie, K, gB, gW, gT, gstat);
     auto it = c->graphs.find(key);
     if (it != c->graphs.end()) { *out = it->second; return RSOC_OK; }
     hipGraph_t g = nullptr;
+    HostStaging *h = c->host.as<HostStaging>();
     RSOC_HIP(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
     launch_list_rounds_dyn(c, c->cap, mode, tie, K, gB, gW, gT);
+    k_colour_stats<<<gstat, kBlock, 0, c->cap>>>(c->args.as<SingleArgs>(), c->state.as<SingleState>());
+    k_head_out<<<1, kHeadBlock, 0, c->cap>>>(c->args.as<SingleArgs>(), c->state.as<SingleState>(), &h->head, &h->L1);
     hipError_t le = hipGetLastError();
     hipError_t ee = hipStreamEndCapture(c->cap, &g);
     if (le != hipSuccess) { if (g) (void)hipGraphDestroy(g); return hip_fail(le, "capture launch", __FILE__, __LINE__); }
@@ -127,49 +138,38 @@ inline int32_t get_round_graph(rsoc_ctx *c, int mode, int tie, int K, int gB, in
     return RSOC_OK;
 }
 
-// Rounds 0 and 1.  gB/gW/gT split the sweep grid, gBl/gWl/gTl the worklist
-// grid.  Returns after enqueueing; the next round reads worklist buffer 0.
+// Rounds 0 and 1 up to the first worklist round.  gB/gW/gT split the sweep
+// grid: the sweeps read the bin sizes on the device, so gB and gW may exceed
+// what the bins need (the surplus workgroups find nothing to do).  Returns
+// true when the first worklist round (the masked one, launch_masked_round1)
+// is still to be enqueued; the next round reads worklist buffer 0.
 template <int MODE, int TIE>
-inline void launch_sweep_rounds(rsoc_ctx *c, hipStream_t s, int32_t *col, int n, int gB, int gW, int gT, int gBl,
-                                int gWl, int gTl, bool timing, bool full_sweep) {
+inline bool launch_sweep_rounds(rsoc_ctx *c, hipStream_t s, int32_t *col, int n, int gB, int gW, int gT, bool timing,
+                                bool full_sweep) {
     const SingleArgs *A = c->args.as<SingleArgs>();
     SingleState *S = c->state.as<SingleState>();
     const int grid = gB + gW + gT;
-    const int fill_grid = std::min(div_up(n, kBlock), 4096);
-    // sweep rounds read no worklist and append into buffer 0 (parity 1)
-    if (timing) (void)hipEventRecord(c->ev[2], s);
-    if (MODE == kDeterministic) {
-        // round 0: against the all-uncoloured snapshot every vertex takes colour 0
-        k_fill<<<fill_grid, kBlock, 0, s>>>(col, c->col8.as<uint8_t>(), n, 0);
-    } else {
-        // optimistic mode: every nibble 15 too (nothing published yet)
-        k_fill<<<fill_grid, kBlock, 0, s>>>(col, c->col8.as<uint8_t>(), n, -1,
-                                             MODE == kOptimistic ? c->col4.as<uint32_t>() : nullptr,
-                                             MODE == kOptimistic ? n / 8 + 1 : 0);
-        if (MODE == kOptimistic) {
-            if (timing) (void)hipEventRecord(c->ev[2], s);
-            // round 0: tentative First-Fit over all of V with live reads
-            if (full_sweep) {
-                k_round<kAssign, kOptimistic, TIE, true, 0><<<grid, kBlock, 0, s>>>(A, S, 1, gB, gW, gT);
-            } else {
-                // ... over the neighbours each vertex loses to, collecting the
-                // only vertices that can end the round defective as U^0 (into
-                // buffer 1, with their position masks)
-                k_round<kAssign, kOptimistic, TIE, true, 1><<<grid, kBlock, 0, s>>>(A, S, 0, gB, gW, gT);
-                if (timing) (void)hipEventRecord(c->ev[3], s);
-                k_round_end<MODE, true, true><<<1, 64, 0, s>>>(A, S);
-                // round 1: detect-and-recolour over U^0, testing only the
-                // masked neighbours of thread-bin vertices; appends to buffer 0
-                if (timing) (void)hipEventRecord(c->ev[4], s);
-                k_round<kRecolor, kOptimistic, TIE, false, 2><<<gBl + gWl + gTl, kBlock, 0, s>>>(A, S, 1, gBl, gWl,
-                                                                                                  gTl);
-                if (timing) (void)hipEventRecord(c->ev[5], s);
-                k_round_end<MODE, false><<<1, 64, 0, s>>>(A, S);
-                return;
-            }
+    const int fill_grid = std::min(div_up(n, kBlock), 4096);  // two-phase scatter
+    hipEvent_t *ev = c->ev;
+    // Sweep rounds read no worklist and append into buffer 0 (parity 1); the
+    // colours were filled for round 0 by k_args (round-synchronous modes: that
+    // fill is round 0, every vertex colour 0).  With timing, ev[2..3] and
+    // ev[4..5] bracket round 0 and round 1.
+    if (MODE == kOptimistic) {
+        if (!full_sweep) {
+            // round 0: tentative First-Fit of all of V with live reads over
+            // the neighbours each vertex loses to, collecting the only
+            // vertices that can end the round defective as U^0 (into buffer
+            // 1, with what each read uncoloured)
+            launch_ev(k_round<kAssign, kOptimistic, TIE, true, 1>, grid, kBlock, s, timing ? ev[2] : nullptr,
+                      timing ? ev[3] : nullptr, A, S, 0, gB, gW, gT);
+            k_round_end<MODE, true, true><<<1, 64, 0, s>>>(A, S);
+            return true;
         }
+        // round 0 over all neighbours
+        launch_ev(k_round<kAssign, kOptimistic, TIE, true, 0>, grid, kBlock, s, timing ? ev[2] : nullptr,
+                  timing ? ev[3] : nullptr, A, S, 1, gB, gW, gT);
     }
-    if (timing) (void)hipEventRecord(c->ev[3], s);
     if (MODE == kTwoPhase) {
         // Algorithm 2, first round: tentative colouring of V, publish, detect
         k_round<kAssign, kTwoPhase, TIE, true><<<grid, kBlock, 0, s>>>(A, S, 1, gB, gW, gT);
@@ -185,17 +185,28 @@ inline void launch_sweep_rounds(rsoc_ctx *c, hipStream_t s, int32_t *col, int n,
         if (MODE == kDeterministic) k_scatter<false, false><<<std::max(1, gT), kBlock, 0, s>>>(A, S, 1);
     }
     k_round_end<MODE, true><<<1, 64, 0, s>>>(A, S);
+    return false;
 }
 
-inline void launch_sweep_dyn(rsoc_ctx *c, hipStream_t s, int mode, int tie, int32_t *col, int n, int gB, int gW,
-                             int gT, int gBl, int gWl, int gTl, bool timing, bool full) {
-#define RSOC_SWEEP(M, T) launch_sweep_rounds<M, T>(c, s, col, n, gB, gW, gT, gBl, gWl, gTl, timing, full)
+// Round 1 of the default optimistic flow: detect-and-recolour over U^0,
+// testing only the kept neighbours of thread-bin entries; appends to buffer 0.
+template <int TIE>
+inline void launch_masked_round1(rsoc_ctx *c, hipStream_t s, int gBl, int gWl, int gTl, bool timing) {
+    const SingleArgs *A = c->args.as<SingleArgs>();
+    SingleState *S = c->state.as<SingleState>();
+    launch_ev(k_round<kRecolor, kOptimistic, TIE, false, 2>, gBl + gWl + gTl, kBlock, s, timing ? c->ev[4] : nullptr,
+              timing ? c->ev[5] : nullptr, A, S, 1, gBl, gWl, gTl);
+    k_round_end<kOptimistic, false><<<1, 64, 0, s>>>(A, S);
+}
+
+inline bool launch_sweep_dyn(rsoc_ctx *c, hipStream_t s, int mode, int tie, int32_t *col, int n, int gB, int gW,
+                             int gT, bool timing, bool full) {
+#define RSOC_SWEEP(M, T) launch_sweep_rounds<M, T>(c, s, col, n, gB, gW, gT, timing, full)
     if (mode == kOptimistic)
-        tie ? RSOC_SWEEP(kOptimistic, kHigherKeeps) : RSOC_SWEEP(kOptimistic, kLowerKeeps);
-    else if (mode == kDeterministic)
-        tie ? RSOC_SWEEP(kDeterministic, kHigherKeeps) : RSOC_SWEEP(kDeterministic, kLowerKeeps);
-    else
-        tie ? RSOC_SWEEP(kTwoPhase, kHigherKeeps) : RSOC_SWEEP(kTwoPhase, kLowerKeeps);
+        return tie ? RSOC_SWEEP(kOptimistic, kHigherKeeps) : RSOC_SWEEP(kOptimistic, kLowerKeeps);
+    if (mode == kDeterministic)
+        return tie ? RSOC_SWEEP(kDeterministic, kHigherKeeps) : RSOC_SWEEP(kDeterministic, kLowerKeeps);
+    return tie ? RSOC_SWEEP(kTwoPhase, kHigherKeeps) : RSOC_SWEEP(kTwoPhase, kLowerKeeps);
 #undef RSOC_SWEEP
 }
 
@@ -208,7 +219,7 @@ inline int32_t ensure_single_scratch(rsoc_ctx *c, int64_t n, bool need_aux, hipS
     RSOC_TRY(c->pend.reserve(b));
     const size_t had = c->flags.bytes;
     RSOC_TRY(c->flags.reserve(b));
-    // colour flags stay zero between calls (k_count_flags clears what it counts)
+    // colour flags stay zero between calls (k_head_out clears what it counts)
     if (c->flags.bytes != had) RSOC_HIP(hipMemsetAsync(c->flags.p, 0, c->flags.bytes, s));
     RSOC_TRY(c->col8.reserve((size_t)n + 64));
     RSOC_TRY(c->col4.reserve(sizeof(uint32_t) * (size_t)(n / 8 + 2)));
@@ -317,9 +328,13 @@ inline int32_t run_single(rsoc_ctx *c, const int32_t *rp, const int32_t *ci, int
     a.t_thread = o.t_thread;
     a.t_wave = o.t_wave;
     a.max_rounds = o.max_rounds;
-    a.offW = a.offB = 0;
-    a.look = 0;
-    a.chunk = 1;
+    a.offW = a.offB = 0;  // k_args sets them once the bins are known
+    int gTs = std::min(div_up(n, kStep), o.grid_thread);
+    if (gTs >= kXcds) gTs -= gTs % kXcds;
+    const int64_t look = o.lookahead == -1 ? 0 : (o.lookahead > 0 ? o.lookahead : (int64_t)gTs * kStep);
+    a.look = (int)std::min<int64_t>(look, INT32_MAX);
+    a.chunk = o.chunk;  // 0: k_args picks it from the locality sample
+    a.flags = c->flags.as<int32_t>();
     k_setup<<<1, kBlock, 0, s>>>(c->args.as<SingleArgs>(), a, S, (int)(kStateHeader / 4), 1);
     const int vgrid = std::min(div_up(n, kBlock), 4096);
     // binning (reads row_ptr only: also checks its ends and publishes nnz),
@@ -330,12 +345,11 @@ inline int32_t run_single(rsoc_ctx *c, const int32_t *rp, const int32_t *ci, int
     const int gloc = div_up(ns, kBlock);
     k_bin<<<vgrid + (validate ? 0 : gloc), kBlock, 0, s>>>(c->args.as<SingleArgs>(), S, validate ? 0 : gloc, ns);
     RSOC_LAUNCH_CHECK();
-    RSOC_HIP(hipMemcpyAsync(&h->head, S, kStateHeader, hipMemcpyDeviceToHost, s));
-    RSOC_HIP(hipStreamSynchronize(s));
-    if (h->head.err & 1) return RSOC_ECSR;
-    const int64_t nnz = h->head.nnz;
-    if (nnz > 0 && !ci) return RSOC_EINVAL;
     if (validate) {
+        RSOC_HIP(hipMemcpyAsync(&h->head, S, kStateHeader, hipMemcpyDeviceToHost, s));
+        RSOC_HIP(hipStreamSynchronize(s));
+        if (h->head.err & 1) return RSOC_ECSR;
+        if (h->head.nnz > 0 && !ci) return RSOC_EINVAL;
         k_validate<<<vgrid, kBlock, 0, s>>>(rp, ci, n, &S->err);
         if (gloc) k_bin<<<gloc, kBlock, 0, s>>>(c->args.as<SingleArgs>(), S, gloc, ns);
         RSOC_LAUNCH_CHECK();
@@ -343,49 +357,56 @@ inline int32_t run_single(rsoc_ctx *c, const int32_t *rp, const int32_t *ci, int
         RSOC_HIP(hipStreamSynchronize(s));
         RSOC_TRY(status_from_err(h->head.err));
     }
+    // The bin sizes come back to the host (k_args writes the state header into
+    // the pinned staging) while round 0 runs: the sweeps read them on the
+    // device, and their hub sections are sized for the most the bins could
+    // need unless validation already brought the sizes.
+    // ... and it fills the colours for round 0; its start is the start of the
+    // colouring (ev[0]); with timing, ev[2..3] bracket it in the round-
+    // synchronous modes, where that fill is round 0
+    const bool opt = o.mode == kOptimistic;
+    const bool timing = o.timing != 0;
+    if (timing && !opt) RSOC_HIP(hipEventRecord(c->ev[2], s));
+    launch_ev(k_args, std::min(div_up(n, kBlock), 4096), kBlock, s, c->ev[0], nullptr, c->args.as<SingleArgs>(), S,
+              &h->head, col, c->col8.as<uint8_t>(), (int64_t)n, o.mode == kDeterministic ? 0 : -1,
+              opt ? c->col4.as<uint32_t>() : (uint32_t *)nullptr, (int64_t)(opt ? n / 8 + 1 : 0));
+    RSOC_LAUNCH_CHECK();
+    if (timing && !opt) RSOC_HIP(hipEventRecord(c->ev[3], s));
+    RSOC_HIP(hipEventRecord(c->ev[6], s));
+    const int gB = validate ? std::min(h->head.nB, 1024) : std::min(n, 1024);
+    const int gW = std::min(div_up(validate ? h->head.nW : n, kWavesPerBlock), o.grid_wave);
+    const bool masked = launch_sweep_dyn(c, s, o.mode, o.tie, col, n, gB, gW, gTs, o.timing != 0, o.full_sweep != 0);
+    RSOC_LAUNCH_CHECK();
+    RSOC_HIP(hipEventSynchronize(c->ev[6]));
+    if (h->head.err & kErrNoRun) {
+        // the sweeps return at once on such input; let them drain
+        RSOC_HIP(hipStreamSynchronize(s));
+        return (h->head.err & 1) ? RSOC_ECSR : RSOC_EINVAL;
+    }
+    const int64_t nnz = h->head.nnz;
     const int nW = h->head.nW, nB = h->head.nB, maxdeg = h->head.maxdeg;
     const int nT = n - nW - nB;
-    a.offW = nT;
-    a.offB = nT + nW;
-
-    // launch shapes
-    const int gB = std::min(nB, 1024);
-    const int gW = std::min(div_up(nW, kWavesPerBlock), o.grid_wave);
-    int gTs = std::min(div_up(n, kStep), o.grid_thread);
-    if (gTs >= kXcds) gTs -= gTs % kXcds;
-    const int64_t look = o.lookahead == -1 ? 0 : (o.lookahead > 0 ? o.lookahead : (int64_t)gTs * kStep);
-    a.look = (int)std::min<int64_t>(look, INT32_MAX);
-    a.chunk = pick_chunk(o.chunk, h->head.near, h->head.sampled);
-    k_setup<<<1, kBlock, 0, s>>>(c->args.as<SingleArgs>(), a, S, 0, 0);
+    const int chunk = h->head.chunk;
     const int gBl = std::min(nB, 256);  // more concurrent hubs only add hub conflicts
     const int gWl = std::min(div_up(nW, kWavesPerBlock), o.grid_wave);
     const int gTl = std::max(1, std::min(div_up(nT, kStep), o.grid_list));
-
+    if (masked) {
+        o.tie ? launch_masked_round1<kHigherKeeps>(c, s, gBl, gWl, gTl, o.timing != 0)
+              : launch_masked_round1<kLowerKeeps>(c, s, gBl, gWl, gTl, o.timing != 0);
+        RSOC_LAUNCH_CHECK();
+    }
     hipGraphExec_t gexec = nullptr;
-    RSOC_TRY(get_round_graph(c, o.mode, o.tie, o.rounds_per_sync, gBl, gWl, gTl, &gexec));
+    // colour count (K = max + 1) and distinct colours: the statistics close
+    // every replay, so the one host check per replay also brings them; they
+    // count once the worklist is empty
+    const int gstat = std::min(div_up(n, 16 * kBlock), 256);
+    RSOC_TRY(get_round_graph(c, o.mode, o.tie, o.rounds_per_sync, gBl, gWl, gTl, gstat, &gexec));
 
-    RSOC_HIP(hipEventRecord(c->ev[0], s));
-    launch_sweep_dyn(c, s, o.mode, o.tie, col, n, gB, gW, gTs, gBl, gWl, gTl, o.timing != 0, o.full_sweep != 0);
-    RSOC_LAUNCH_CHECK();
     int32_t status = RSOC_OK;
-    // colour count (K = max + 1) and distinct colours; every colour is at most
-    // min(max degree, n - 1) (a First-Fit value over at most that many
-    // neighbours).  The statistics are enqueued behind each replay, so the one
-    // host check per replay also brings them; they count once the worklist is
-    // empty.
-    const int clim = std::min(maxdeg, n - 1);
     const int tail_max = o.tail == -1 ? 0 : (o.tail == 0 ? kTailMax : std::min(o.tail, kTailMax));
     for (;;) {
         RSOC_HIP(hipGraphLaunch(gexec, s));
         RSOC_HIP(hipEventRecord(c->ev[1], s));
-        k_colour_stats<<<std::min(div_up(n, 16 * kBlock), 2048), kBlock, 0, s>>>(c->col8.as<uint8_t>(), col, n, clim,
-                                                                                 c->flags.as<int32_t>(), S);
-        if (clim >= 255)
-            k_count_flags<<<std::min(div_up(clim + 1 - 255, kBlock), 1024), kBlock, 0, s>>>(
-                c->flags.as<int32_t>() + 255, clim + 1 - 255, &S->distinct);
-        RSOC_LAUNCH_CHECK();
-        RSOC_HIP(hipMemcpyAsync(&h->head, S, kStateHeader, hipMemcpyDeviceToHost, s));
-        RSOC_HIP(hipMemcpyAsync(&h->L1, &S->hist[0], 4, hipMemcpyDeviceToHost, s));
         RSOC_HIP(hipStreamSynchronize(s));
         const int left = h->head.cnt_in[0] + h->head.cnt_in[1] + h->head.cnt_in[2];
         if (left == 0) break;
@@ -437,7 +458,7 @@ inline int32_t run_single(rsoc_ctx *c, const int32_t *rp, const int32_t *ci, int
                   h->head.deg_sum, h->head.inspected1, h->head.deg_sum1, b0, b1, tot);
         st->bytes_round0 = b0;
         st->worklist0 = sweep1 ? n : h->head.u0;
-        st->chunk = a.chunk;
+        st->chunk = chunk;
         st->bytes_round1 = b1;
         st->alg_bytes = tot;
     }

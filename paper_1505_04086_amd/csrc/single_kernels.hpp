@@ -35,6 +35,7 @@ struct SingleArgs {
     int32_t offW, offB;  // segment offsets inside wl buffers
     int32_t look;        // round-0 lookahead (ids within `look` of v are read even when v wins against them)
     int32_t chunk;       // run of consecutive ids one lane group walks (1, 2, 4 or 8)
+    int32_t *flags;      // flags[c] for colours c >= 255 in use (zero between calls)
 };
 
 // Device-side round state.
@@ -45,7 +46,7 @@ struct SingleState {
     int32_t maxdeg;
     int32_t passes;       // inspection passes executed (rounds >= 1)
     int32_t rounds;       // passes that recoloured somebody
-    int32_t err;          // bit 0 bad CSR, bit 1 self-loop, bit 2 colour out of range
+    int32_t err;          // bit 0 bad CSR, bit 1 self-loop, bit 2 colour out of range, bit 3 edges without col_idx
     int32_t nnz;          // row_ptr[n] (read by k_bin)
     int32_t lastL, prevL; // |L| of the last two rounds that inspected anything
     // colour statistics (k_colour_stats; cleared before each computation)
@@ -56,11 +57,49 @@ struct SingleState {
     uint64_t inspected;   // vertices inspected by worklist rounds
     uint64_t deg_sum;     // their degree sum
     int32_t u0;           // |U^0| when round 0 collects it (optimistic, default flow)
-    int32_t pad;
+    int32_t chunk;        // run length of the sweeps (k_args)
     uint64_t inspected1, deg_sum1;  // inspected / deg_sum as they stood after the first worklist round
     uint64_t near, sampled;  // id locality sample: row entries with |u - v| < kChunk, entries sampled
     int32_t hist[kHistCap];  // |L| of recolouring round i+1
 };
+
+// the part of SingleState the host reads after a round (everything but hist)
+constexpr size_t kStateHeader = offsetof(SingleState, hist);
+static_assert(kStateHeader % 4 == 0, "header copied as 32-bit words");
+
+// Closes a round graph (one workgroup): counts the flags k_colour_stats set
+// for colours 255 .. min(max degree, n - 1) into S->distinct and clears them,
+// then copies the state header (and |L| of the first recolouring round) into
+// the host's pinned staging, from the device, so that no copy command follows
+// the rounds: the host reads it once the stream is synchronised.
+constexpr int kHeadBlock = 1024;
+__global__ __launch_bounds__(kHeadBlock) void k_head_out(const SingleArgs *__restrict__ A, SingleState *S,
+                                                         SingleState *dst, int32_t *l1) {
+    __shared__ int sh[kHeadBlock / kWave];
+    const int64_t len = (int64_t)min(S->maxdeg, A->n - 1) + 1 - 255;
+    if (len > 0) {
+        int32_t *const flags = A->flags + 255;
+        int cnt = 0;
+        for (int64_t i = threadIdx.x; i < len; i += kHeadBlock) {
+            const int f = flags[i];
+            cnt += f;
+            if (f) flags[i] = 0;
+        }
+        for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
+        if (lane_id() == 0) sh[threadIdx.x / kWave] = cnt;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int t = 0;
+            for (int w = 0; w < kHeadBlock / kWave; ++w) t += sh[w];
+            S->distinct += t;
+        }
+        __syncthreads();
+    }
+    const int32_t *src = reinterpret_cast<const int32_t *>(S);
+    int32_t *d = reinterpret_cast<int32_t *>(dst);
+    for (int i = threadIdx.x; i < (int)(kStateHeader / 4); i += kHeadBlock) d[i] = src[i];
+    if (threadIdx.x == 0) *l1 = S->hist[0];
+}
 
 __device__ __forceinline__ uint8_t shadow_of(int c) { return (uint8_t)((unsigned)c < 255u ? c : 255); }
 
@@ -76,7 +115,8 @@ __device__ __forceinline__ void publish_nibble(RSOC_GLOBAL uint32_t *col4, int v
 // ------------------------------------------------------------------ fill --
 // p[0, n) = value, its byte shadow p8 (if given) and, if given, the 4-bit
 // shadow words p4[0, n4) = all ones (every nibble 15).
-__global__ void k_fill(int32_t *p, uint8_t *p8, int64_t n, int32_t value, uint32_t *p4 = nullptr, int64_t n4 = 0) {
+__device__ __forceinline__ void fill_colours(int32_t *p, uint8_t *p8, int64_t n, int32_t value, uint32_t *p4,
+                                             int64_t n4) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += stride) {
         p[i] = value;
@@ -84,6 +124,9 @@ __global__ void k_fill(int32_t *p, uint8_t *p8, int64_t n, int32_t value, uint32
     }
     if (p4)
         for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n4; i += stride) p4[i] = ~0u;
+}
+__global__ void k_fill(int32_t *p, uint8_t *p8, int64_t n, int32_t value, uint32_t *p4 = nullptr, int64_t n4 = 0) {
+    fill_colours(p, p8, n, value, p4, n4);
 }
 
 // ----------------------------------------------------------------- setup --
@@ -193,6 +236,35 @@ __global__ __launch_bounds__(kBlock) void k_bin(const SingleArgs *__restrict__ A
     // most workgroups find nothing larger than what is already published
     if (threadIdx.x == 0 && md > __hip_atomic_load(&S->maxdeg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
         atomicMax(&S->maxdeg, md);
+}
+
+// Completes the arguments once binning is done, on the device, so that the
+// rounds can be enqueued behind binning without the host waiting for it: the
+// worklists' bin segments, the run length (option 0: from the locality
+// sample), and bit 3 of err when there are edges but no col_idx.  The sweeps
+// do not run while err has bit 0 (row_ptr ends, from k_bin) or bit 3 set.
+constexpr int kErrNoRun = 1 | 8;
+// Workgroup 0 does that and then sends the header to the host's staging (dst)
+// as k_head_out does; the whole grid meanwhile fills the colours for round 0
+// (value, its byte shadow, and all-ones 4-bit shadow words p4[0, n4) if
+// given), as k_fill would.
+__global__ void k_args(SingleArgs *A, SingleState *S, SingleState *dst, int32_t *col, uint8_t *col8, int64_t n,
+                       int32_t value, uint32_t *col4, int64_t n4) {
+    if (blockIdx.x == 0) {
+        if (threadIdx.x == 0) {
+            const int nv = A->n;
+            A->offW = nv - S->nW - S->nB;
+            A->offB = nv - S->nB;
+            A->chunk = pick_chunk(A->chunk, S->near, S->sampled);
+            S->chunk = A->chunk;
+            if (A->ci == nullptr && S->nnz > 0) S->err |= 8;
+        }
+        __syncthreads();
+        const int32_t *src = reinterpret_cast<const int32_t *>(S);
+        int32_t *d = reinterpret_cast<int32_t *>(dst);
+        for (int i = threadIdx.x; i < (int)(kStateHeader / 4); i += blockDim.x) d[i] = src[i];
+    }
+    fill_colours(col, col8, n, value, col4, n4);
 }
 
 // Id-locality sample: rows of `ns` vertices spread evenly over [0, n) (rows
@@ -368,7 +440,7 @@ __device__ __forceinline__ void publish_nibbles(const int (&ids)[NV], const int 
 // SWEEP: the round covers all of V (rounds 0 and 1): the thread bin walks
 //        vertex ids directly, the other bins read the static lists; otherwise
 //        the round reads worklist buffer `parity` and appends to parity^1.
-// Sections: blocks [0,gB) workgroup bin, [gB,gB+gW) wavefront bin, rest
+// Sections: blocks [0,gB) workgroup bin, [gB,gB+gW) wavefront bin, then gT
 // thread bin (kGroup lanes per vertex).
 // ROUND0 (kAssign only): 0 = First-Fit over all neighbours, no appends;
 // 1 = First-Fit over the neighbours v loses to, sweeping in the order that
@@ -377,10 +449,10 @@ __device__ __forceinline__ void publish_nibbles(const int (&ids)[NV], const int 
 // thread-bin v also stores which neighbours those were (aux).
 // ROUND0 = 2 (kRecolor, optimistic, worklist): the round right after that:
 // thread-bin entries take one lane each and only test the stored positions
-// (lane_detect_masked); the defective ones are then recoloured by lane groups.
+// (lane_detect_kept); the defective ones are then recoloured by lane groups.
 template <int PHASE, int MODE, int TIE, bool SWEEP, int ROUND0 = 0>
 __global__ __launch_bounds__(kBlock) void k_round(const SingleArgs *__restrict__ A, SingleState *S, int parity,
-                                                  int gB, int gW, int gT) {
+                                                  int gB_, int gW_, int gT) {
     __shared__ uint32_t lds[kLdsWords];
     constexpr bool kFlagAppend = PHASE == kAssign && ROUND0 == 1;
     constexpr bool kMasked = PHASE == kRecolor && ROUND0 == 2 && !SWEEP && MODE == kOptimistic;
@@ -396,6 +468,7 @@ __global__ __launch_bounds__(kBlock) void k_round(const SingleArgs *__restrict__
     __shared__ int mbn[kWavesPerBlock];
     const SingleArgs a = *A;
     if (!SWEEP && S->passes >= a.max_rounds) return;  // guard: the round may not run
+    if (SWEEP && (S->err & kErrNoRun)) return;        // the input failed its checks
     const int cT = SWEEP ? a.n : S->cnt_in[kBinThread];
     const int cW = SWEEP ? S->nW : S->cnt_in[kBinWave];
     const int cB = SWEEP ? S->nB : S->cnt_in[kBinBlock];
@@ -415,6 +488,10 @@ __global__ __launch_bounds__(kBlock) void k_round(const SingleArgs *__restrict__
     // (publish_nibble); a recoloured vertex's nibble becomes 15.
     constexpr bool kNib = MODE == kOptimistic;
     constexpr bool kPublish = kNib && PHASE == kAssign;
+    // a round 0 over all neighbours (ROUND0 = 0) gathers from the byte
+    // shadow: half its neighbours are still uncoloured, and each of those
+    // would cost a nibble read and then a byte read
+    constexpr bool kNibRead = kNib && (PHASE != kAssign || kFlagAppend);
     const RSOC_GLOBAL uint32_t *rcol4 = gro(a.col4);
     RSOC_GLOBAL uint32_t *wcol4 = grw(a.col4);
     constexpr bool kWinOnly = kFlagAppend;
@@ -422,7 +499,13 @@ __global__ __launch_bounds__(kBlock) void k_round(const SingleArgs *__restrict__
     constexpr bool kWrite = PHASE != kDetect;
     constexpr bool kAcct = PHASE != kAssign && !SWEEP;  // worklist rounds count their inspections
     uint64_t items = 0, degs = 0;
+    // A sweep's hub sections may be launched larger than its bins need (the
+    // host enqueues it before it knows the bin sizes): the workgroups the bins
+    // need keep the front of the grid and the surplus, at its end, leaves.
+    const int gB = SWEEP ? min(gB_, cB) : gB_;
+    const int gW = SWEEP ? min(gW_, (cW + kWavesPerBlock - 1) / kWavesPerBlock) : gW_;
     const int bid = blockIdx.x;
+    if (bid >= gB + gW + gT) return;
     if (bid < gB) {
         if (threadIdx.x == 0) qn = 0;
         __syncthreads();
@@ -537,10 +620,17 @@ __global__ __launch_bounds__(kBlock) void k_round(const SingleArgs *__restrict__
             if (threadIdx.x == 0) qn = 0;
             __syncthreads();
         }
-        const int c = a.chunk;
-        const int64_t stride = (int64_t)gT * kStep;
-        for (int64_t base = (int64_t)tb * kStep; base < cT; base += stride) {
-            for (int r = 0; r < kChunk; ++r) {
+        // A sweep gives each workgroup step kStep ids, walked as runs in
+        // order.  A worklist has no order to keep and is often short after
+        // round 1, so there a step is kSub entries: the list spreads over the
+        // whole grid instead of a few workgroups walking kChunk dependent
+        // sub-steps each.
+        constexpr int kUnit = SWEEP ? kStep : kSub;
+        constexpr int kRuns = SWEEP ? kChunk : 1;
+        const int c = SWEEP ? a.chunk : 1;
+        const int64_t stride = (int64_t)gT * kUnit;
+        for (int64_t base = (int64_t)tb * kUnit; base < cT; base += stride) {
+            for (int r = 0; r < kRuns; ++r) {
                 int v[kNV], b[kNV], e[kNV], cv[kNV], nc[kNV];
                 bool act[kNV];
                 uint32_t unc[kNV] = {};
@@ -552,7 +642,7 @@ __global__ __launch_bounds__(kBlock) void k_round(const SingleArgs *__restrict__
                 const int g0 = lane_id() & ~(kGroup - 1);
 #pragma unroll
                 for (int i = 0; i < kNV; ++i) {
-                    const int64_t idx = base + step_offset(r, i, gi, a.chunk);
+                    const int64_t idx = base + step_offset(r, i, gi, c);
                     v[i] = -1;
                     if (idx < cT) {
                         if (SWEEP) {
@@ -582,7 +672,7 @@ __global__ __launch_bounds__(kBlock) void k_round(const SingleArgs *__restrict__
                 const RSOC_GLOBAL uint32_t *c4s[kNV];
 #pragma unroll
                 for (int i = 0; i < kNV; ++i) cis[i] = ci, c8s[i] = rcol8, c4s[i] = rcol4;
-                group_vertices<PHASE, TIE, kGroup, kGroupSlots, kWinOnly, kNV, kNib>(v, b, e, cis, c8s, cv, a.look, nc,
+                group_vertices<PHASE, TIE, kGroup, kGroupSlots, kWinOnly, kNV, kNibRead>(v, b, e, cis, c8s, cv, a.look, nc,
                                                                                      act, unc, c4s,
                                                                                      kFlagAppend ? keep : nullptr);
 #pragma unroll
@@ -730,45 +820,62 @@ __global__ void k_round_end(const SingleArgs *__restrict__ A, SingleState *S) {
 
 // --------------------------------------------------------- colour stats --
 // K = max colour + 1 and the set of colours used, read from the byte shadow
-// (16 vertices per thread and load); only a vertex whose shadow is 255
+// (16 vertices per lane and load, four loads at a time); only a vertex whose shadow is 255
 // (colour 255 or more, or none) reads its full colour.  Colours below 64 are
 // gathered in a register mask, 64..254 in the workgroup's LDS set, both then
 // OR-ed into S->cbits; colours >= 255 mark flags[c] (counted, and cleared, by
-// k_count_flags).  A colour outside [0, maxdeg] sets err bit 2.
-__global__ __launch_bounds__(kBlock) void k_colour_stats(const uint8_t *__restrict__ col8p,
-                                                         const int32_t *__restrict__ colp, int64_t n, int32_t maxdeg,
-                                                         int32_t *flags, SingleState *S) {
+// k_head_out).  A colour outside [0, maxdeg] sets err bit 2.
+// Everything is read on the device (arguments block, max degree), so the
+// kernel can close a captured round graph; every colour is at most
+// min(max degree, n - 1), a First-Fit value over at most that many neighbours.
+__global__ __launch_bounds__(kBlock) void k_colour_stats(const SingleArgs *__restrict__ A, SingleState *S) {
     __shared__ uint32_t bits[8];
     __shared__ int sh[kWavesPerBlock];
     typedef unsigned int v4u __attribute__((ext_vector_type(4)));
-    const RSOC_GLOBAL v4u *c16 = (const RSOC_GLOBAL v4u *)col8p;  // 16 bytes per entry (col8 holds n + 64 bytes)
-    const RSOC_GLOBAL int32_t *col = gro(colp);
+    const int64_t n = A->n;
+    const int32_t maxdeg = min(S->maxdeg, A->n - 1);
+    int32_t *const flags = A->flags;
+    const RSOC_GLOBAL v4u *c16 = (const RSOC_GLOBAL v4u *)A->col8;  // 16 bytes per entry (col8 holds n + 64 bytes)
+    const RSOC_GLOBAL int32_t *col = gro(A->col);
     if (threadIdx.x < 8) bits[threadIdx.x] = 0;
     __syncthreads();
     int m = -1;
     bool bad = false;
     uint64_t low = 0;
     const int64_t n16 = (n + 15) / 16;
-    for (int64_t t = blockIdx.x * (int64_t)kBlock + threadIdx.x; t < n16; t += (int64_t)gridDim.x * kBlock) {
-        const v4u w = c16[t];
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    // four 16-byte loads in flight per lane before any is examined
+    constexpr int kIn = 4;
+    for (int64_t t0 = blockIdx.x * (int64_t)kBlock + threadIdx.x; t0 < n16; t0 += kIn * stride) {
+        v4u w[kIn];
 #pragma unroll
-        for (int j = 0; j < 16; ++j) {
-            const int64_t v = t * 16 + j;
-            if (v >= n) break;
-            int c = (int)((w[j >> 2] >> ((j & 3) * 8)) & 255u);
-            if (c == 255) {
-                c = col[v];
-                if (c < 0 || c > maxdeg) { bad = true; continue; }
-                if (c >= 255) {
-                    if (flags[c] == 0) flags[c] = 1;  // racy but idempotent
-                    m = max(m, c);
-                    continue;
+        for (int k = 0; k < kIn; ++k) {
+            const int64_t t = t0 + k * stride;
+            if (t < n16) w[k] = c16[t];
+        }
+#pragma unroll
+        for (int k = 0; k < kIn; ++k) {
+            const int64_t t = t0 + k * stride;
+            if (t >= n16) break;
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const int64_t v = t * 16 + j;
+                if (v >= n) break;
+                int c = (int)((w[k][j >> 2] >> ((j & 3) * 8)) & 255u);
+                if (c == 255) {
+                    c = col[v];
+                    if (c < 0 || c > maxdeg) { bad = true; continue; }
+                    if (c >= 255) {
+                        if (flags[c] == 0) flags[c] = 1;  // racy but idempotent
+                        m = max(m, c);
+                        continue;
+                    }
                 }
+                if (c > maxdeg) { bad = true; continue; }
+                m = max(m, c);
+                if (c < 64) low |= 1ull << c;
+                else lds_or(&bits[c >> 5], 1u << (c & 31));
             }
-            if (c > maxdeg) { bad = true; continue; }
-            m = max(m, c);
-            if (c < 64) low |= 1ull << c;
-            else lds_or(&bits[c >> 5], 1u << (c & 31));
         }
     }
     if (ballot(bad) && lane_id() == 0) atomicOr(&S->err, 4);
@@ -784,18 +891,6 @@ __global__ __launch_bounds__(kBlock) void k_colour_stats(const uint8_t *__restri
         atomicOr(&S->cbits[threadIdx.x], bits[threadIdx.x]);
     if (threadIdx.x == 0 && m + 1 > __hip_atomic_load(&S->kmax, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
         atomicMax(&S->kmax, m + 1);
-}
-
-// Counts the marked flags[0, len) into *out and clears them.
-__global__ __launch_bounds__(kBlock) void k_count_flags(int32_t *flags, int64_t len, int32_t *out) {
-    int s = 0;
-    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < len; i += (int64_t)gridDim.x * kBlock) {
-        const int f = flags[i];
-        s += f;
-        if (f) flags[i] = 0;
-    }
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-    if (lane_id() == 0 && s) atomicAdd(out, s);
 }
 
 }  // namespace rsoc

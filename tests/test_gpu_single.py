@@ -186,6 +186,32 @@ def test_device_validation_errors(lib, ctx):
     torch.cuda.synchronize()
 
 
+@pytest.mark.parametrize("mode", ["optimistic", "deterministic", "two_phase"])
+def test_unvalidated_input_checks(lib, ctx, mode):
+    """Without validation the rounds are enqueued behind binning before the
+    host sees its checks: bad row_ptr ends and edges without col_idx must
+    still come back as RSOC_ECSR / RSOC_EINVAL (the sweeps return at once on
+    them), and the context must colour the next graph normally."""
+    rp, ci = gg.cycle(9)
+    bad = rp.copy()
+    bad[0] = 1
+    d_rp, d_ci, d_col, n = _dev(lib, bad, ci)
+    with pytest.raises(lib.RsocError) as e:
+        lib.rsoc_color_device(ctx, d_rp, d_ci, n, d_col, lib.make_options(mode))
+    assert e.value.code == lib.RSOC_ECSR
+    d_rp, d_ci, d_col, n = _dev(lib, rp, ci)
+    with pytest.raises(lib.RsocError) as e:
+        lib.rsoc_color_device(ctx, d_rp, None, n, d_col, lib.make_options(mode))
+    assert e.value.code == lib.RSOC_EINVAL
+    k, st = lib.rsoc_color_device(ctx, d_rp, d_ci, n, d_col, lib.make_options(mode))
+    got = d_col.cpu().numpy()[:n]
+    if mode == "optimistic":
+        assert oracle.check(rp, ci, got) == 0 and k == oracle.colour_count(got)
+    else:
+        want = oracle.rsync(rp, ci) if mode == "deterministic" else oracle.cat(rp, ci)
+        assert np.array_equal(got, want["colors"]) and k == want["K"]
+
+
 def test_empty_graph(lib, ctx):
     import torch
     d = torch.device("cuda:0")
