@@ -68,6 +68,8 @@ class OracleLib:
             f.restype = i32
         lib.orc_check.argtypes = [i32, p, p, p]
         lib.orc_check.restype = i64
+        lib.orc_classes.argtypes = [i32, p, i32, p, p]
+        lib.orc_classes.restype = i32
         self.lib = lib
         self.path = path
 
@@ -116,6 +118,21 @@ class OracleLib:
         return int(self.lib.orc_check(n, rp.ctypes.data, ci.ctypes.data, c.ctypes.data))
 
 
+    def classes(self, colors, K=None):
+        """Colour classes: (ptr int32[K+1], vtx int32[n]); class k is
+        vtx[ptr[k]:ptr[k+1]], ascending ids.  K defaults to max + 1."""
+        c = np.ascontiguousarray(colors, dtype=np.int32)
+        n = len(c)
+        if K is None:
+            K = int(c.max()) + 1 if n else 0
+        ptr = np.zeros(K + 1, dtype=np.int32)
+        vtx = np.empty(max(n, 1), dtype=np.int32)
+        r = self.lib.orc_classes(n, c.ctypes.data if n else None, int(K), ptr.ctypes.data, vtx.ctypes.data)
+        if r < 0:
+            raise ValueError("orc_classes: colour outside [0, K)")
+        return ptr, vtx[:n]
+
+
 def _csr(row_ptr, col_idx):
     rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
     ci = np.ascontiguousarray(col_idx, dtype=np.int32)
@@ -128,8 +145,8 @@ def default() -> OracleLib:
     global _lib
     with _lock:
         if _lib is None:
-            if not os.path.exists(_LIB):
-                build(force=False)
+            if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+                build(force=True)
             _lib = OracleLib(_LIB)
     return _lib
 
@@ -148,6 +165,10 @@ def cat(row_ptr, col_idx, tie="lower", max_rounds=None, raise_on_noconv=True):
 
 def check(row_ptr, col_idx, colors) -> int:
     return default().check(row_ptr, col_idx, colors)
+
+
+def classes(colors, K=None):
+    return default().classes(colors, K)
 
 
 def colour_count(colors) -> int:

@@ -1,6 +1,6 @@
 /*
  * oracle.c -- plain, slow, obviously-correct CPU reference for speculative
- * First-Fit colouring.  TEST INFRASTRUCTURE ONLY: only the test suite, the
+ * First-Fit colouring and the colour classes a colouring defines.  TEST INFRASTRUCTURE ONLY: only the test suite, the
  * smoke check and the benchmark's CPU-baseline leg may call it.  It shares no
  * code, header or helper with the GPU library.
  *
@@ -231,4 +231,28 @@ int64_t orc_check(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, con
         }
     }
     return bad;
+}
+
+/*
+ * Colour classes.  A colouring splits V into independent sets, one per
+ * colour, whose vertices can be processed concurrently (the use of colouring
+ * the introduction describes, Section 1).  Class k holds the vertices of
+ * colour k in ascending id: class_vtx[ptr[k] .. ptr[k+1]).  Written as the
+ * counting sort it is: count each colour, prefix sums give each class's
+ * start, then one pass over the vertices in id order places each one.
+ * Returns 0, or ORC_EINVAL when a colour lies outside [0, K).
+ */
+int32_t orc_classes(int32_t n, const int32_t *colors, int32_t K, int32_t *ptr, int32_t *vtx) {
+    if (n < 0 || K < 0 || !ptr || (n > 0 && (!colors || !vtx))) return ORC_EINVAL;
+    for (int32_t v = 0; v < n; ++v)
+        if (colors[v] < 0 || colors[v] >= K) return ORC_EINVAL;
+    for (int32_t k = 0; k <= K; ++k) ptr[k] = 0;
+    for (int32_t v = 0; v < n; ++v) ptr[colors[v] + 1] += 1;  /* size of each class */
+    for (int32_t k = 0; k < K; ++k) ptr[k + 1] += ptr[k];     /* start of each class */
+    int32_t *next = (int32_t *)malloc(sizeof(int32_t) * (size_t)(K > 0 ? K : 1));
+    if (!next) return ORC_ENOMEM;
+    for (int32_t k = 0; k < K; ++k) next[k] = ptr[k];
+    for (int32_t v = 0; v < n; ++v) vtx[next[colors[v]]++] = v;  /* ascending id within a class */
+    free(next);
+    return 0;
 }

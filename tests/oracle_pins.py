@@ -290,6 +290,56 @@ def pin_check(O):
     assert O.check(rp, ci, np.array([0, 1, 0, 1, -1], np.int32)) > 0
 
 
+# ------------------------------------------------------------ colour classes
+
+def pin_classes_golden(O):
+    g = _load("colour_classes_example.json")
+    c = np.array(g["colors"], np.int32)
+    for key, K in (("K3", 3), ("K5", 5)):
+        ptr, vtx = O.classes(c, K)
+        assert ptr.tolist() == g[key]["ptr"] and vtx.tolist() == g[key]["vtx"], key
+
+
+def pin_classes_library(O):
+    """Class k = the vertices of colour k in ascending id is exactly a stable
+    sort of the ids by colour; the starts are the running sums of a bincount."""
+    rng = np.random.default_rng(1505)
+    for n, K in ((1, 1), (2, 1), (17, 3), (1000, 7), (4096, 300), (5000, 5000)):
+        c = rng.integers(0, K, size=n).astype(np.int32)
+        ptr, vtx = O.classes(c, K)
+        assert np.array_equal(vtx, np.argsort(c, kind="stable").astype(np.int32))
+        want = np.concatenate([[0], np.cumsum(np.bincount(c, minlength=K))])
+        assert np.array_equal(ptr, want.astype(np.int32))
+    ptr, vtx = O.classes(np.zeros(0, np.int32), 4)
+    assert ptr.tolist() == [0, 0, 0, 0, 0] and len(vtx) == 0
+
+
+def pin_classes_independent_sets(O):
+    """On valid colourings every class is an independent set and the classes
+    partition V."""
+    for rp, ci in _small_graphs(40, seed=77, nmax=40):
+        n = len(rp) - 1
+        c, K = O.seq_ff(rp, ci)
+        ptr, vtx = O.classes(c, K)
+        assert ptr[0] == 0 and ptr[-1] == n and sorted(vtx.tolist()) == list(range(n))
+        for k in range(K):
+            members = vtx[ptr[k]:ptr[k + 1]]
+            assert np.all(np.diff(members) > 0) and np.all(c[members] == k)
+            s = set(members.tolist())
+            for v in members:
+                assert not any(int(u) in s for u in ci[rp[v]:rp[v + 1]] if u != v)
+
+
+def pin_classes_range(O):
+    for bad in ([0, 3, 1], [0, -1, 1]):
+        try:
+            O.classes(np.array(bad, np.int32), 3)
+        except ValueError:
+            continue
+        raise AssertionError("colour outside [0, K) accepted: %s" % bad)
+
+
 ALL_PINS = [pin_seq_closed_forms, pin_seq_golden_tri_grid, pin_seq_networkx, pin_seq_bounds_and_bruteforce,
             pin_seq_some_order_is_optimal, pin_rsync_fig7, pin_rsync_worked_examples, pin_rsync_closed_forms,
-            pin_rsync_first_round, pin_rsync_invariants, pin_rsync_reversal, pin_cat_examples, pin_check]
+            pin_rsync_first_round, pin_rsync_invariants, pin_rsync_reversal, pin_cat_examples, pin_check,
+            pin_classes_golden, pin_classes_library, pin_classes_independent_sets, pin_classes_range]

@@ -24,6 +24,11 @@ MUTANTS = {
     "worklist_not_swapped": ("int32_t *t = U; U = L; L = t; /* U^i <- L */", "/* U^i <- L forgotten */"),
     "check_ignores_degree_bound": ("if (colors[v] < 0 || colors[v] > d) ++bad;", "if (colors[v] < 0) ++bad;"),
     "mex_ignores_top_colour": ("if (cu >= 0 && cu <= d) seen[cu] = 1;", "if (cu >= 0 && cu < d - 1) seen[cu] = 1;"),
+    "classes_counts_shifted": ("ptr[colors[v] + 1] += 1;", "ptr[colors[v]] += 1;"),
+    "classes_descending_ids": ("for (int32_t v = 0; v < n; ++v) vtx[next[colors[v]]++] = v;",
+                               "for (int32_t v = n - 1; v >= 0; --v) vtx[next[colors[v]]++] = v;"),
+    "classes_range_unchecked": ("if (colors[v] < 0 || colors[v] >= K) return ORC_EINVAL;",
+                                "if (colors[v] < 0) return ORC_EINVAL;"),
 }
 
 
