@@ -229,6 +229,23 @@ int64_t rsoc_pool_reserved_bytes(const rsoc_pool *pool);
  * slot is not a finished one.  Enqueues no device work that it waits for. */
 int32_t rsoc_pool_result(rsoc_pool *pool, int32_t slot, rsoc_stats *stats);
 
+/*
+ * Colour classes (Section 1: a colouring splits the vertices into independent
+ * sets, one per colour, whose members can be processed concurrently).
+ * d_colors[n]: device int32 colours in [0, K) (K = the count rsoc_color_*
+ * returns, or any larger palette size).  Outputs, device and caller-owned:
+ * d_class_ptr[K+1] and d_class_vtx[n]; class k is
+ * d_class_vtx[d_class_ptr[k] .. d_class_ptr[k+1]), in ascending vertex id
+ * (unused colours give empty classes).  Runs on hip_stream and synchronises
+ * it; its scratch (4 bytes per colour and 1024 vertices, at most 2 bytes per
+ * vertex) is the context's.
+ * Returns RSOC_OK, or RSOC_EINVAL for null pointers, n < 0, K < 0, K = 0 with
+ * n > 0, or a colour outside [0, K) (found on the device; the outputs are then
+ * unspecified).
+ */
+int32_t rsoc_color_classes(rsoc_ctx *ctx, const int32_t *d_colors, int32_t n, int32_t K, int32_t *d_class_ptr,
+                           int32_t *d_class_vtx, void *hip_stream);
+
 /* Host-side CSR check (flags: RSOC_CHECK_*).  Returns RSOC_OK or the first error found. */
 int32_t rsoc_check_csr(const int32_t *row_ptr, const int32_t *col_idx, int32_t n, int32_t flags);
 

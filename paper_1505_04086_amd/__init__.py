@@ -94,6 +94,7 @@ _sig = {
     "rsoc_pool_live": (_i32, [_p]),
     "rsoc_pool_reserved_bytes": (_i64, [_p]),
     "rsoc_pool_result": (_i32, [_p, _i32, ctypes.POINTER(rsoc_stats)]),
+    "rsoc_color_classes": (_i32, [_p, _p, _i32, _i32, _p, _p, _p]),
     "rsoc_check_csr": (_i32, [_p, _p, _i32, _i32]),
     "rsoc_strerror": (ctypes.c_char_p, [_i32]),
     "rsoc_last_error": (ctypes.c_char_p, []),
@@ -253,6 +254,13 @@ def rsoc_color_device(ctx: Context, d_row_ptr, d_col_idx, n, d_colors_out, optio
                                     ctypes.byref(o), ctypes.byref(st), _stream_ptr(stream)),
              "rsoc_color_device", ok_noconv=allow_noconv)
     return k, stats_dict(st, L)
+
+
+def rsoc_color_classes(ctx: Context, d_colors, n, K, d_class_ptr, d_class_vtx, stream=None):
+    """Colour classes of a device colouring: fills d_class_ptr (K+1) and
+    d_class_vtx (n); class k is d_class_vtx[d_class_ptr[k]:d_class_ptr[k+1]]."""
+    _chk(_lib.rsoc_color_classes(ctx.h, _dev_ptr(d_colors), int(n), int(K), _dev_ptr(d_class_ptr),
+                                 _dev_ptr(d_class_vtx), _stream_ptr(stream)), "rsoc_color_classes")
 
 
 def rsoc_color_batch(ctx: Context, vtx_off, nnz_off, d_row_ptr_cat, d_col_idx_cat, d_colors_cat, options=None,

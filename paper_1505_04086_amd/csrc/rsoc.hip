@@ -8,6 +8,7 @@
 #include "single.hpp"
 #include "batch.hpp"
 #include "pool.hpp"
+#include "classes.hpp"
 
 using namespace rsoc;
 
@@ -137,6 +138,14 @@ int32_t rsoc_color_ex(rsoc_ctx *ctx, const int32_t *row_ptr, const int32_t *col_
     RSOC_HIP(hipMemcpyAsync(colors_out, ctx->dcol.p, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost, s));
     RSOC_HIP(hipStreamSynchronize(s));
     return k;
+}
+
+int32_t rsoc_color_classes(rsoc_ctx *ctx, const int32_t *d_colors, int32_t n, int32_t K, int32_t *d_class_ptr,
+                           int32_t *d_class_vtx, void *hip_stream) {
+    if (!ctx || n < 0 || K < 0 || (n > 0 && K < 1) || !d_class_ptr || (n > 0 && (!d_colors || !d_class_vtx)))
+        return RSOC_EINVAL;
+    RSOC_HIP(hipSetDevice(ctx->device));
+    return run_classes(ctx, d_colors, n, K, d_class_ptr, d_class_vtx, (hipStream_t)hip_stream);
 }
 
 static std::mutex g_default_mu;

@@ -27,6 +27,7 @@ struct rsoc_ctx {
     hipStream_t cap = nullptr;    // capture stream
     rsoc::DevBuf wl0, wl1, hubW, hubB, pend, flags, col8, col4, aux;
     rsoc::DevBuf mark, tail;      // ordered pass over a small worklist (tail_kernels.hpp)
+    rsoc::DevBuf cls_h, cls_p, cls_st;  // colour classes (classes.hpp)
     rsoc::DevBuf args, state;     // SingleArgs, SingleState (fixed addresses: graphs point at them)
     rsoc::HostPinned host;        // pinned staging for small copies
     rsoc::DevBuf drp, dci, dcol;  // device copies for host-pointer calls
@@ -44,6 +45,7 @@ struct HostStaging {
     SingleState head;  // only the header part is ever copied
     int32_t L1;        // |L| of the first recolouring round
     int32_t rp_ends[2];
+    int32_t cls_err;   // colour classes: a colour was outside [0, K)
 };
 
 inline int32_t ctx_init(rsoc_ctx *c, int device) {
@@ -66,7 +68,7 @@ inline void ctx_free(rsoc_ctx *c) {
     c->graphs.clear();
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);
-    for (rsoc::DevBuf *b : {&c->col8, &c->col4, &c->aux, &c->mark, &c->tail, &c->wl0, &c->wl1, &c->hubW, &c->hubB, &c->pend, &c->flags, &c->args, &c->state, &c->drp,
+    for (rsoc::DevBuf *b : {&c->col8, &c->col4, &c->aux, &c->mark, &c->tail, &c->cls_h, &c->cls_p, &c->cls_st, &c->wl0, &c->wl1, &c->hubW, &c->hubB, &c->pend, &c->flags, &c->args, &c->state, &c->drp,
                             &c->dci, &c->dcol, &c->b_desc, &c->b_wl0, &c->b_wl1, &c->b_pend, &c->b_flags,
                             &c->b_state, &c->b_hub, &c->b_kmax, &c->b_tasks, &c->b_args, &c->b_col8})
         b->release();
