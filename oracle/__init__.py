@@ -70,6 +70,8 @@ class OracleLib:
         lib.orc_check.restype = i64
         lib.orc_classes.argtypes = [i32, p, i32, p, p]
         lib.orc_classes.restype = i32
+        lib.orc_recolor.argtypes = [i32, p, p, i32, i32, p, p, i32, ctypes.POINTER(i32), ctypes.POINTER(i64), p, i32]
+        lib.orc_recolor.restype = i32
         self.lib = lib
         self.path = path
 
@@ -117,6 +119,34 @@ class OracleLib:
             return 0
         return int(self.lib.orc_check(n, rp.ctypes.data, ci.ctypes.data, c.ctypes.data))
 
+
+    def recolor(self, row_ptr, col_idx, prev_colors, touched, tie="lower", max_rounds=None, raise_on_noconv=True):
+        """Recolouring after topology edits: Algorithm 3 (snapshot reading)
+        from the previous colouring with U^0 = touched vertices plus those
+        whose colour is negative or above their degree.  Returns the dict of
+        rsync (colors, K, rounds, conflicts, L_sizes, status)."""
+        rp, ci, n = _csr(row_ptr, col_idx)
+        col = np.empty(max(n, 1), dtype=np.int32)
+        col[:n] = np.asarray(prev_colors, dtype=np.int32)[:n]
+        t = np.ascontiguousarray(touched, dtype=np.int32)
+        if len(t) == 0:
+            t = np.zeros(1, dtype=np.int32)
+            nt = 0
+        else:
+            nt = len(t)
+        cap = n + 2
+        Ls = np.zeros(cap, dtype=np.int32)
+        rounds = ctypes.c_int32(0)
+        conflicts = ctypes.c_int64(0)
+        k = self.lib.orc_recolor(n, rp.ctypes.data, ci.ctypes.data, _TIES[tie], int(max_rounds or 0), col.ctypes.data,
+                                 t.ctypes.data, nt, ctypes.byref(rounds), ctypes.byref(conflicts), Ls.ctypes.data, cap)
+        if k == -1:
+            raise ValueError("orc_recolor: bad argument (touched id outside [0, n)?)")
+        if k < 0 and (k != ENOCONV or raise_on_noconv):
+            raise RuntimeError("oracle failed: %d" % k)
+        R = int(rounds.value)
+        return {"colors": col[:n], "K": int(k), "rounds": R, "conflicts": int(conflicts.value),
+                "L_sizes": Ls[:min(R, cap)].copy(), "status": 0 if k >= 0 else int(k)}
 
     def classes(self, colors, K=None):
         """Colour classes: (ptr int32[K+1], vtx int32[n]); class k is
@@ -169,6 +199,10 @@ def check(row_ptr, col_idx, colors) -> int:
 
 def classes(colors, K=None):
     return default().classes(colors, K)
+
+
+def recolor(row_ptr, col_idx, prev_colors, touched, tie="lower", max_rounds=None, raise_on_noconv=True):
+    return default().recolor(row_ptr, col_idx, prev_colors, touched, tie, max_rounds, raise_on_noconv)
 
 
 def colour_count(colors) -> int:

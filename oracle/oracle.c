@@ -256,3 +256,80 @@ int32_t orc_classes(int32_t n, const int32_t *colors, int32_t K, int32_t *ptr, i
     free(next);
     return 0;
 }
+
+/*
+ * Recolouring after topology edits.  The introduction (Section 1) names
+ * applications that change the graph between colourings (morph kernels, mesh
+ * adaptivity) and so recolour in every iteration.  Reading: Algorithm 3 under
+ * the snapshot reading of orc_rsync, started from the colouring the graph had
+ * before the edits instead of from round 0, with
+ *   U^0 = the touched vertices (the endpoints of inserted edges; an edge
+ *         deletion cannot create a conflict) together with every vertex whose
+ *         colour is negative (no colour yet, e.g. a new vertex) or above its
+ *         degree (outside the First-Fit bound c(v) <= deg(v) of Section 2.1,
+ *         possible after deletions),
+ * and a vertex of U^{i-1} counted defective when its colour is such a one or
+ * when it shares its colour with a neighbour it loses to.  Defective vertices
+ * take the smallest colour absent among their neighbours' snapshot colours
+ * (negative ones ignored) and form L; U^i <- L.  colors[] is read as the
+ * previous colouring and written with the result; touched[0, nt) may repeat
+ * ids.  Outputs and return value as for orc_rsync (ORC_EINVAL also for a
+ * touched id outside [0, n)).
+ */
+int32_t orc_recolor(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, int32_t tie, int32_t max_rounds,
+                    int32_t *colors, const int32_t *touched, int32_t nt, int32_t *rounds_out,
+                    int64_t *conflicts_out, int32_t *L_sizes, int32_t L_cap) {
+    if (n < 0 || nt < 0 || (n > 0 && (!row_ptr || !colors)) || (nt > 0 && !touched) || tie < 0 || tie > 1)
+        return ORC_EINVAL;
+    for (int32_t k = 0; k < nt; ++k)
+        if (touched[k] < 0 || touched[k] >= n) return ORC_EINVAL;
+    if (max_rounds <= 0) max_rounds = n + 1;
+    int32_t *snap = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    int32_t *U = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    int32_t *L = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    unsigned char *in_u0 = (unsigned char *)calloc((size_t)(n > 0 ? n : 1), 1);
+    unsigned char *seen = (unsigned char *)calloc((size_t)max_degree(n, row_ptr) + 2, 1);
+    if (!snap || !U || !L || !in_u0 || !seen) {
+        free(snap); free(U); free(L); free(in_u0); free(seen);
+        return ORC_ENOMEM;
+    }
+    /* U^0: touched vertices and those without a valid First-Fit colour */
+    for (int32_t k = 0; k < nt; ++k) in_u0[touched[k]] = 1;
+    int32_t nU = 0;
+    for (int32_t v = 0; v < n; ++v) {
+        const int32_t d = row_ptr[v + 1] - row_ptr[v];
+        if (in_u0[v] || colors[v] < 0 || colors[v] > d) U[nU++] = v;
+    }
+    int32_t rounds = 0, passes = 0;
+    int64_t conflicts = 0;
+    int32_t rc = 0;
+    while (nU > 0) {
+        if (passes == max_rounds) { rc = ORC_ENOCONV; break; }
+        passes++;
+        memcpy(snap, colors, sizeof(int32_t) * (size_t)n);
+        int32_t nL = 0;
+        for (int32_t k = 0; k < nU; ++k) {
+            int32_t v = U[k];
+            const int32_t d = row_ptr[v + 1] - row_ptr[v];
+            int defective = snap[v] < 0 || snap[v] > d;
+            for (int32_t j = row_ptr[v]; j < row_ptr[v + 1] && !defective; ++j) {
+                int32_t u = col_idx[j];
+                if (u != v && loses(v, u, tie) && snap[u] == snap[v]) defective = 1;
+            }
+            if (defective) {
+                colors[v] = smallest_free_colour(v, row_ptr, col_idx, snap, seen);
+                L[nL++] = v;
+            }
+        }
+        if (nL == 0) break;
+        if (L_sizes && rounds < L_cap) L_sizes[rounds] = nL;
+        rounds++;
+        conflicts += nL;
+        int32_t *t = U; U = L; L = t;
+        nU = nL;
+    }
+    if (rounds_out) *rounds_out = rounds;
+    if (conflicts_out) *conflicts_out = conflicts;
+    free(snap); free(U); free(L); free(in_u0); free(seen);
+    return rc < 0 ? rc : colour_count(n, colors);
+}

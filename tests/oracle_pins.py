@@ -339,7 +339,88 @@ def pin_classes_range(O):
         raise AssertionError("colour outside [0, K) accepted: %s" % bad)
 
 
+# ------------------------------------------------------------ recolouring after edits
+
+def _csr_from_edges(n, edges):
+    adj = [[] for _ in range(n)]
+    for a, b in edges:
+        adj[a].append(b)
+        adj[b].append(a)
+    rp = np.zeros(n + 1, np.int32)
+    rp[1:] = np.cumsum([len(x) for x in adj])
+    ci = np.array([u for x in adj for u in sorted(x)], np.int32)
+    return rp, ci
+
+
+def pin_recolor_worked_examples(O):
+    g = _load("recolor_worked_examples.json")
+    for case in g["cases"]:
+        rp, ci = _csr_from_edges(case["n"], case["edges"])
+        for tie, key in (("lower", "lower_keeps"), ("higher", "higher_keeps")):
+            r = O.recolor(rp, ci, np.array(case["prev"], np.int32), case["touched"], tie=tie)
+            w = case[key]
+            assert r["colors"].tolist() == w["colors"] and r["rounds"] == w["rounds"], (case["name"], tie)
+            assert r["L_sizes"].tolist() == w["L_sizes"], (case["name"], tie)
+
+
+def pin_recolor_reduces_to_rsync(O):
+    """From all colours 0 with every vertex touched, the recolouring is the
+    round-synchronous schedule itself (its round 0 is that state)."""
+    graphs = list(_small_graphs(30, seed=91, nmax=12)) + [gg.cycle(6), gg.complete(5), gg.path(7)]
+    for rp, ci in graphs:
+        n = len(rp) - 1
+        for tie in ("lower", "higher"):
+            want = O.rsync(rp, ci, tie=tie)
+            r = O.recolor(rp, ci, np.zeros(n, np.int32), np.arange(n), tie=tie)
+            assert np.array_equal(r["colors"], want["colors"]) and r["rounds"] == want["rounds"]
+            assert np.array_equal(r["L_sizes"], want["L_sizes"])
+
+
+def pin_recolor_from_uncoloured(O):
+    """From no colours at all, the first pass gives everyone colour 0 (every
+    vertex is defective and sees no coloured neighbour); the rest is the
+    round-synchronous schedule."""
+    for rp, ci in _small_graphs(30, seed=92, nmax=12):
+        n = len(rp) - 1
+        want = O.rsync(rp, ci)
+        r = O.recolor(rp, ci, np.full(n, -1, np.int32), [])
+        assert np.array_equal(r["colors"], want["colors"]) and r["rounds"] == want["rounds"] + 1
+        assert r["L_sizes"].tolist() == [n] + want["L_sizes"].tolist()
+
+
+def pin_recolor_edits(O):
+    """Random edge insertions into validly coloured graphs: the result is a
+    valid colouring within the First-Fit bound, only recoloured vertices
+    change, and a valid colouring with nothing touched is left alone."""
+    rng = np.random.default_rng(93)
+    for rp, ci in _small_graphs(40, seed=94, nmax=30):
+        n = len(rp) - 1
+        prev, _ = O.seq_ff(rp, ci)
+        same = O.recolor(rp, ci, prev, [])
+        assert np.array_equal(same["colors"], prev) and same["rounds"] == 0
+        edges = {(int(a), int(b)) for a in range(n) for b in ci[rp[a]:rp[a + 1]] if a < b}
+        add = [(int(a), int(b)) for a, b in rng.integers(0, n, size=(3, 2)) if a != b]
+        edges |= {(min(a, b), max(a, b)) for a, b in add}
+        rp2, ci2 = _csr_from_edges(n, sorted(edges))
+        touched = [x for e in add for x in e]
+        for tie in ("lower", "higher"):
+            r = O.recolor(rp2, ci2, prev, touched, tie=tie)
+            assert _valid(rp2, ci2, r["colors"]) and np.all(r["colors"] <= np.diff(rp2))
+            assert int(np.sum(r["colors"] != prev)) <= r["conflicts"]
+
+
+def pin_recolor_range(O):
+    rp, ci = gg.path(4)
+    try:
+        O.recolor(rp, ci, np.zeros(4, np.int32), [4])
+    except ValueError:
+        return
+    raise AssertionError("touched id outside [0, n) accepted")
+
+
 ALL_PINS = [pin_seq_closed_forms, pin_seq_golden_tri_grid, pin_seq_networkx, pin_seq_bounds_and_bruteforce,
             pin_seq_some_order_is_optimal, pin_rsync_fig7, pin_rsync_worked_examples, pin_rsync_closed_forms,
             pin_rsync_first_round, pin_rsync_invariants, pin_rsync_reversal, pin_cat_examples, pin_check,
-            pin_classes_golden, pin_classes_library, pin_classes_independent_sets, pin_classes_range]
+            pin_classes_golden, pin_classes_library, pin_classes_independent_sets, pin_classes_range,
+            pin_recolor_worked_examples, pin_recolor_reduces_to_rsync, pin_recolor_from_uncoloured,
+            pin_recolor_edits, pin_recolor_range]

@@ -14,8 +14,10 @@ SRC = os.path.join(os.path.dirname(oracle.__file__), "oracle.c")
 MUTANTS = {
     "tie_direction_flipped": ("if (tie == TIE_LOWER_KEEPS) return u < v;", "if (tie == TIE_LOWER_KEEPS) return u > v;"),
     "mex_starts_at_one": ("int32_t m = 0;\n    while (seen[m])", "int32_t m = 1;\n    while (seen[m])"),
-    "recolour_reads_live_state": ("colors[v] = smallest_free_colour(v, row_ptr, col_idx, snap, seen);",
-                                  "colors[v] = smallest_free_colour(v, row_ptr, col_idx, colors, seen);"),
+    "recolour_reads_live_state": ("{ defective = 1; break; }\n            }\n            if (defective) {\n"
+                                  "                colors[v] = smallest_free_colour(v, row_ptr, col_idx, snap, seen);",
+                                  "{ defective = 1; break; }\n            }\n            if (defective) {\n"
+                                  "                colors[v] = smallest_free_colour(v, row_ptr, col_idx, colors, seen);"),
     "detect_reads_live_state": ("loses(v, u, tie) && snap[u] == snap[v]) { defective = 1; break; }",
                                 "loses(v, u, tie) && colors[u] == colors[v]) { defective = 1; break; }"),
     "round0_uncoloured": ("for (int32_t v = 0; v < n; ++v) colors[v] = 0;", "for (int32_t v = 0; v < n; ++v) colors[v] = -1;"),
@@ -29,6 +31,11 @@ MUTANTS = {
                                "for (int32_t v = n - 1; v >= 0; --v) vtx[next[colors[v]]++] = v;"),
     "classes_range_unchecked": ("if (colors[v] < 0 || colors[v] >= K) return ORC_EINVAL;",
                                 "if (colors[v] < 0) return ORC_EINVAL;"),
+    "recolor_uncoloured_not_defective": ("int defective = snap[v] < 0 || snap[v] > d;", "int defective = 0;"),
+    "recolor_touched_ignored": ("if (in_u0[v] || colors[v] < 0 || colors[v] > d) U[nU++] = v;",
+                                "if (colors[v] < 0 || colors[v] > d) U[nU++] = v;"),
+    "recolor_live_reads": ("if (u != v && loses(v, u, tie) && snap[u] == snap[v]) defective = 1;",
+                           "if (u != v && loses(v, u, tie) && colors[u] == colors[v]) defective = 1;"),
 }
 
 
