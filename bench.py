@@ -116,6 +116,65 @@ def colouring_valid(rp, ci, col) -> bool:
     return True
 
 
+def insert_edges(rp, ci, add):
+    """CSR with the edges `add` (pairs, no duplicates of existing edges, no
+    self-loops) inserted at the ends of their rows."""
+    import numpy as np
+    n = len(rp) - 1
+    a = np.concatenate([add[:, 0], add[:, 1]])
+    b = np.concatenate([add[:, 1], add[:, 0]])
+    extra = np.bincount(a, minlength=n)
+    rp2 = np.zeros(n + 1, np.int64)
+    rp2[1:] = np.cumsum(np.diff(rp) + extra)
+    ci2 = np.empty(int(rp2[-1]), np.int32)
+    shift = np.concatenate([[0], np.cumsum(extra)[:-1]])  # inserted entries in rows before each row
+    row = np.repeat(np.arange(n, dtype=np.int32), np.diff(rp))
+    ci2[np.arange(len(ci), dtype=np.int64) + shift[row]] = ci
+    order = np.argsort(a, kind="stable")
+    a, b = a[order], b[order]
+    first = np.searchsorted(a, a)  # rank of each inserted entry inside its row
+    ci2[rp2[a + 1] - extra[a] + (np.arange(len(a)) - first)] = b
+    return rp2.astype(np.int32), ci2
+
+
+def bench_recolor(args, rsoc, ctx, rp, ci, col, stream, full_s, edits=10000):
+    import numpy as np
+    import torch
+    dev = torch.device("cuda:0")
+    n = len(rp) - 1
+    rng = np.random.default_rng(args.seed + 7)
+    pairs = rng.integers(0, n, size=(edits * 2, 2))
+    pairs = np.unique(np.sort(pairs[pairs[:, 0] != pairs[:, 1]], axis=1), axis=0)
+    # drop pairs that are edges already (a row is at most a few dozen entries here)
+    present = np.array([p[1] in ci[rp[p[0]]:rp[p[0] + 1]] for p in pairs], bool)
+    add = pairs[~present][:edits]
+    rp2, ci2 = insert_edges(rp, ci, add)
+    touched = np.unique(add.ravel()).astype(np.int32)
+    d_rp, d_ci = torch.from_numpy(rp2).to(dev), torch.from_numpy(ci2).to(dev)
+    d_t = torch.from_numpy(touched).to(dev)
+    d_prev = torch.from_numpy(np.ascontiguousarray(col, dtype=np.int32)).to(dev)
+    d_col = torch.empty_like(d_prev)
+    opts = rsoc.make_options(args.mode, "lower")
+    d_col.copy_(d_prev)
+    rsoc.rsoc_recolor_device(ctx, d_rp, d_ci, n, d_col, d_t, opts, stream=stream)
+    reps = max(3, args.steps // 2)
+    times = []
+    for _ in range(reps):
+        d_col.copy_(d_prev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        k, st = rsoc.rsoc_recolor_device(ctx, d_rp, d_ci, n, d_col, d_t, opts, stream=stream)
+        times.append(time.perf_counter() - t0)
+    got = d_col.cpu().numpy()
+    if not colouring_valid(rp2, ci2, got):
+        raise SystemExit("bench: invalid colouring after recolouring")
+    t = float(np.median(times))
+    return {"inserted_edges": int(len(add)), "touched": int(len(touched)), "worklist0": st["worklist0"],
+            "recoloured": st["conflicts"], "rounds": st["rounds"], "colors": k, "ms": t * 1e3,
+            "full_colouring_ms": full_s * 1e3, "speedup_vs_full": full_s / t,
+            "changed": int(np.sum(got != col))}
+
+
 def bench_single(args):
     import numpy as np
     import torch
@@ -217,6 +276,9 @@ def bench_single(args):
     cls_bytes = 8 * n + 4 * (K + 1)
     out["color_classes"] = {"ms": tc * 1e3, "classes": K, "alg_bytes": cls_bytes,
                             "GBps": cls_bytes / tc / 1e9, "frac_hbm": cls_bytes / tc / 1e9 / HBM_PEAK_GBS}
+    # recolouring after topology edits: random edges inserted (both endpoints
+    # touched), starting from the colouring just made
+    out["recolor_after_edits"] = bench_recolor(args, rsoc, ctx, rp, ci, col, stream, elapsed / args.steps)
     if args.mode == "optimistic":
         # the literal reading (round 0 over all neighbours, round 1 over all of V)
         o3 = rsoc.make_options("optimistic", "lower", timing=1, full_sweep=1)

@@ -230,6 +230,28 @@ int64_t rsoc_pool_reserved_bytes(const rsoc_pool *pool);
 int32_t rsoc_pool_result(rsoc_pool *pool, int32_t slot, rsoc_stats *stats);
 
 /*
+ * Recolouring after topology edits (Section 1: graphs whose topology changes
+ * between colourings, as in morph kernels and mesh adaptivity, are recoloured
+ * in every iteration).  Device pointers as for rsoc_color_device, on the
+ * edited graph.  d_colors_inout[n] holds the colouring from before the edits
+ * (negative: no colour yet, e.g. a new vertex) and receives the result.
+ * d_touched[n_touched] (device, may repeat ids) lists the vertices the edits
+ * touched: both endpoints of every inserted edge (deletions create no
+ * conflict).  Algorithm 3's rounds then run from that state, with
+ * U^0 = the touched vertices plus every vertex whose colour is negative or
+ * above its degree, such a vertex counting as defective; no round 0.  Modes
+ * RSOC_MODE_OPTIMISTIC (any valid colouring) and RSOC_MODE_DETERMINISTIC
+ * (round-synchronous: identical to the reference schedule); two-phase is
+ * RSOC_EINVAL.  Options and statistics as for rsoc_color_device (worklist0 =
+ * |U^0|; ms_round0/ms_round1 are not measured).  Synchronises hip_stream.
+ * Returns K, or RSOC_EINVAL (also for a touched id outside [0, n), found on
+ * the device), RSOC_ECSR, RSOC_ENOCONV, RSOC_EHIP.
+ */
+int32_t rsoc_recolor_device(rsoc_ctx *ctx, const int32_t *d_row_ptr, const int32_t *d_col_idx, int32_t n,
+                            int32_t *d_colors_inout, const int32_t *d_touched, int32_t n_touched,
+                            const rsoc_options *opts, rsoc_stats *stats, void *hip_stream);
+
+/*
  * Colour classes (Section 1: a colouring splits the vertices into independent
  * sets, one per colour, whose members can be processed concurrently).
  * d_colors[n]: device int32 colours in [0, K) (K = the count rsoc_color_*

@@ -94,6 +94,8 @@ _sig = {
     "rsoc_pool_live": (_i32, [_p]),
     "rsoc_pool_reserved_bytes": (_i64, [_p]),
     "rsoc_pool_result": (_i32, [_p, _i32, ctypes.POINTER(rsoc_stats)]),
+    "rsoc_recolor_device": (_i32, [_p, _p, _p, _i32, _p, _p, _i32, ctypes.POINTER(rsoc_options),
+                                   ctypes.POINTER(rsoc_stats), _p]),
     "rsoc_color_classes": (_i32, [_p, _p, _i32, _i32, _p, _p, _p]),
     "rsoc_check_csr": (_i32, [_p, _p, _i32, _i32]),
     "rsoc_strerror": (ctypes.c_char_p, [_i32]),
@@ -253,6 +255,27 @@ def rsoc_color_device(ctx: Context, d_row_ptr, d_col_idx, n, d_colors_out, optio
     k = _chk(_lib.rsoc_color_device(ctx.h, _dev_ptr(d_row_ptr), _dev_ptr(d_col_idx), int(n), _dev_ptr(d_colors_out),
                                     ctypes.byref(o), ctypes.byref(st), _stream_ptr(stream)),
              "rsoc_color_device", ok_noconv=allow_noconv)
+    return k, stats_dict(st, L)
+
+
+def rsoc_recolor_device(ctx: Context, d_row_ptr, d_col_idx, n, d_colors_inout, d_touched, options=None,
+                        stream=None, per_round_cap=0, allow_noconv=False):
+    """Recolouring after topology edits: d_colors_inout holds the colouring
+    before the edits (negative = none) and receives the result; d_touched
+    (device int32, may be None or empty) lists the touched vertices.
+    Returns (K, stats dict)."""
+    o = options if options is not None else make_options()
+    st = rsoc_stats()
+    L = None
+    if per_round_cap:
+        L = np.zeros(per_round_cap, dtype=np.int32)
+        st.per_round_L = L.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        st.per_round_cap = per_round_cap
+    nt = 0 if d_touched is None else int(d_touched.numel())
+    k = _chk(_lib.rsoc_recolor_device(ctx.h, _dev_ptr(d_row_ptr), _dev_ptr(d_col_idx), int(n),
+                                      _dev_ptr(d_colors_inout), _dev_ptr(d_touched) if nt else None, nt,
+                                      ctypes.byref(o), ctypes.byref(st), _stream_ptr(stream)),
+             "rsoc_recolor_device", ok_noconv=allow_noconv)
     return k, stats_dict(st, L)
 
 

@@ -140,6 +140,19 @@ int32_t rsoc_color_ex(rsoc_ctx *ctx, const int32_t *row_ptr, const int32_t *col_
     return k;
 }
 
+int32_t rsoc_recolor_device(rsoc_ctx *ctx, const int32_t *d_row_ptr, const int32_t *d_col_idx, int32_t n,
+                            int32_t *d_colors_inout, const int32_t *d_touched, int32_t n_touched,
+                            const rsoc_options *opts, rsoc_stats *stats, void *hip_stream) {
+    if (!ctx || n < 0 || n_touched < 0 || (n > 0 && (!d_row_ptr || !d_colors_inout)) || (n_touched > 0 && !d_touched))
+        return RSOC_EINVAL;
+    Options o;
+    RSOC_TRY(resolve_options(opts, n, o));
+    if (o.mode == kTwoPhase) return RSOC_EINVAL;  // Algorithm 2 recolours all of U: no incremental reading
+    RSOC_HIP(hipSetDevice(ctx->device));
+    return run_single(ctx, d_row_ptr, d_col_idx, n, d_colors_inout, o, stats, (hipStream_t)hip_stream, d_touched,
+                      n_touched);
+}
+
 int32_t rsoc_color_classes(rsoc_ctx *ctx, const int32_t *d_colors, int32_t n, int32_t K, int32_t *d_class_ptr,
                            int32_t *d_class_vtx, void *hip_stream) {
     if (!ctx || n < 0 || K < 0 || (n > 0 && K < 1) || !d_class_ptr || (n > 0 && (!d_colors || !d_class_vtx)))

@@ -299,9 +299,16 @@ inline void alg_bytes(int mode, bool full_sweep, int64_t n, int64_t nnz, int64_t
     total = b0 + b1 + 16 * (int64_t)inspected + 8 * (int64_t)deg_sum + per_rec * (conflicts - L1);
 }
 
-// The single-graph driver.  All pointers are device pointers.
+// The single-graph driver.  All pointers are device pointers.  nt >= 0: a
+// recolouring after topology edits instead of a colouring: col holds the
+// colouring before the edits, touched[0, nt) the vertices the edits touched;
+// the rounds start from that state with U^0 = the touched vertices plus those
+// without a valid First-Fit colour (no round 0; Algorithm 3's rounds as in a
+// colouring).
 inline int32_t run_single(rsoc_ctx *c, const int32_t *rp, const int32_t *ci, int32_t n, int32_t *col,
-                          const Options &o, rsoc_stats *st, hipStream_t s) {
+                          const Options &o, rsoc_stats *st, hipStream_t s, const int32_t *touched = nullptr,
+                          int32_t nt = -1) {
+    const bool inc = nt >= 0;
     HostStaging *h = c->host.as<HostStaging>();
     SingleState *S = c->state.as<SingleState>();
     if (st) {
@@ -312,7 +319,7 @@ inline int32_t run_single(rsoc_ctx *c, const int32_t *rp, const int32_t *ci, int
         st->per_round_cap = cap;
     }
     if (n == 0) return 0;
-    RSOC_TRY(ensure_single_scratch(c, n, o.mode == kOptimistic && !o.full_sweep, s));
+    RSOC_TRY(ensure_single_scratch(c, n, o.mode == kOptimistic && !o.full_sweep && !inc, s));
 
     SingleArgs &a = h->args;
     a.rp = rp;
@@ -335,7 +342,7 @@ inline int32_t run_single(rsoc_ctx *c, const int32_t *rp, const int32_t *ci, int
     if (gTs >= kXcds) gTs -= gTs % kXcds;
     const int64_t look = o.lookahead == -1 ? 0 : (o.lookahead > 0 ? o.lookahead : (int64_t)gTs * kStep);
     a.look = (int)std::min<int64_t>(look, INT32_MAX);
-    a.chunk = o.chunk;  // 0: k_args picks it from the locality sample
+    a.chunk = inc ? 1 : o.chunk;  // 0: k_args picks it from the locality sample
     a.flags = c->flags.as<int32_t>();
     k_setup<<<1, kBlock, 0, s>>>(c->args.as<SingleArgs>(), a, S, (int)(kStateHeader / 4), 1);
     const int vgrid = std::min(div_up(n, kBlock), 4096);
@@ -343,7 +350,7 @@ inline int32_t run_single(rsoc_ctx *c, const int32_t *rp, const int32_t *ci, int
     // with the id-locality sample in extra workgroups unless the CSR is to be
     // validated first (the sample reads rows)
     const bool validate = (o.validate & RSOC_CHECK_CSR) != 0;
-    const int ns = (o.chunk == 0 && ci) ? std::min(n, 16384) : 0;
+    const int ns = (o.chunk == 0 && ci && !inc) ? std::min(n, 16384) : 0;
     const int gloc = div_up(ns, kBlock);
     k_bin<<<vgrid + (validate ? 0 : gloc), kBlock, 0, s>>>(c->args.as<SingleArgs>(), S, validate ? 0 : gloc, ns);
     RSOC_LAUNCH_CHECK();
@@ -367,18 +374,38 @@ inline int32_t run_single(rsoc_ctx *c, const int32_t *rp, const int32_t *ci, int
     // colouring (ev[0]); with timing, ev[2..3] bracket it in the round-
     // synchronous modes, where that fill is round 0
     const bool opt = o.mode == kOptimistic;
-    const bool timing = o.timing != 0;
-    if (timing && !opt) RSOC_HIP(hipEventRecord(c->ev[2], s));
-    launch_ev(k_args, std::min(div_up(n, kBlock), 4096), kBlock, s, c->ev[0], nullptr, c->args.as<SingleArgs>(), S,
-              &h->head, col, c->col8.as<uint8_t>(), (int64_t)n, o.mode == kDeterministic ? 0 : -1,
-              opt ? c->col4.as<uint32_t>() : (uint32_t *)nullptr, (int64_t)(opt ? n / 8 + 1 : 0));
-    RSOC_LAUNCH_CHECK();
-    if (timing && !opt) RSOC_HIP(hipEventRecord(c->ev[3], s));
-    RSOC_HIP(hipEventRecord(c->ev[6], s));
-    const int gB = validate ? std::min(h->head.nB, 1024) : std::min(n, 1024);
-    const int gW = std::min(div_up(validate ? h->head.nW : n, kWavesPerBlock), o.grid_wave);
-    const bool masked = launch_sweep_dyn(c, s, o.mode, o.tie, col, n, gB, gW, gTs, o.timing != 0, o.full_sweep != 0);
-    RSOC_LAUNCH_CHECK();
+    const bool timing = o.timing != 0 && !inc;
+    bool masked = false;
+    if (!inc) {
+        if (timing && !opt) RSOC_HIP(hipEventRecord(c->ev[2], s));
+        launch_ev(k_args, std::min(div_up(n, kBlock), 4096), kBlock, s, c->ev[0], nullptr, c->args.as<SingleArgs>(),
+                  S, &h->head, col, c->col8.as<uint8_t>(), (int64_t)n, o.mode == kDeterministic ? 0 : -1,
+                  opt ? c->col4.as<uint32_t>() : (uint32_t *)nullptr, (int64_t)(opt ? n / 8 + 1 : 0));
+        RSOC_LAUNCH_CHECK();
+        if (timing && !opt) RSOC_HIP(hipEventRecord(c->ev[3], s));
+        RSOC_HIP(hipEventRecord(c->ev[6], s));
+        const int gB = validate ? std::min(h->head.nB, 1024) : std::min(n, 1024);
+        const int gW = std::min(div_up(validate ? h->head.nW : n, kWavesPerBlock), o.grid_wave);
+        masked = launch_sweep_dyn(c, s, o.mode, o.tie, col, n, gB, gW, gTs, timing, o.full_sweep != 0);
+        RSOC_LAUNCH_CHECK();
+    } else {
+        // the colours stay (no fill); shadows and U^0 come from them and the
+        // touched list (pend serves as the mark array: the staged colours of
+        // the round-synchronous mode are written before they are read)
+        launch_ev(k_args, 1, kBlock, s, c->ev[0], nullptr, c->args.as<SingleArgs>(), S, &h->head, (int32_t *)nullptr,
+                  (uint8_t *)nullptr, (int64_t)0, 0, (uint32_t *)nullptr, (int64_t)0);
+        RSOC_HIP(hipEventRecord(c->ev[6], s));
+        const int g = std::min(div_up(n, kBlock), 4096);
+        int32_t *mark = c->pend.as<int32_t>();
+        const SingleArgs *A = c->args.as<SingleArgs>();
+        if (opt) k_inc_shadow<true><<<g, kBlock, 0, s>>>(A, mark);
+        else k_inc_shadow<false><<<g, kBlock, 0, s>>>(A, mark);
+        if (nt > 0) k_inc_touch<<<std::min(div_up(nt, kBlock), 1024), kBlock, 0, s>>>(A, S, touched, nt, mark);
+        k_inc_list<<<g, kBlock, 0, s>>>(A, S, mark);
+        if (opt) k_round_end<kOptimistic, true, true><<<1, 64, 0, s>>>(A, S);
+        else k_round_end<kDeterministic, true, true><<<1, 64, 0, s>>>(A, S);
+        RSOC_LAUNCH_CHECK();
+    }
     RSOC_HIP(hipEventSynchronize(c->ev[6]));
     if (h->head.err & kErrNoRun) {
         // the sweeps return at once on such input; let them drain
@@ -393,8 +420,8 @@ inline int32_t run_single(rsoc_ctx *c, const int32_t *rp, const int32_t *ci, int
     const int gWl = std::min(div_up(nW, kWavesPerBlock), o.grid_wave);
     const int gTl = std::max(1, std::min(div_up(nT, kStep), o.grid_list));
     if (masked) {
-        o.tie ? launch_masked_round1<kHigherKeeps>(c, s, gBl, gWl, gTl, o.timing != 0)
-              : launch_masked_round1<kLowerKeeps>(c, s, gBl, gWl, gTl, o.timing != 0);
+        o.tie ? launch_masked_round1<kHigherKeeps>(c, s, gBl, gWl, gTl, timing)
+              : launch_masked_round1<kLowerKeeps>(c, s, gBl, gWl, gTl, timing);
         RSOC_LAUNCH_CHECK();
     }
     hipGraphExec_t gexec = nullptr;
@@ -430,6 +457,7 @@ inline int32_t run_single(rsoc_ctx *c, const int32_t *rp, const int32_t *ci, int
         }
     }
     if (h->head.err & 4) return RSOC_EHIP;  // a colour outside [0, max degree]: never expected
+    if (h->head.err & 16) return RSOC_EINVAL;  // a touched id outside [0, n)
     if (st) {
         st->rounds = h->head.rounds;
         st->passes = h->head.passes;
@@ -438,7 +466,7 @@ inline int32_t run_single(rsoc_ctx *c, const int32_t *rp, const int32_t *ci, int
         for (uint32_t w : h->head.cbits) distinct += __builtin_popcount(w);
         st->colors_distinct = distinct;
         st->conflicts = h->head.conflicts;
-        const bool sweep1 = !(o.mode == kOptimistic && !o.full_sweep);
+        const bool sweep1 = !inc && !(o.mode == kOptimistic && !o.full_sweep);
         st->inspected = (int64_t)h->head.inspected + (sweep1 ? n : 0);
         st->max_degree = maxdeg;
         st->bin_counts[0] = nT;
@@ -447,7 +475,7 @@ inline int32_t run_single(rsoc_ctx *c, const int32_t *rp, const int32_t *ci, int
         float ms = 0;
         RSOC_HIP(hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
         st->ms = ms;
-        if (o.timing) {
+        if (timing) {
             float m0 = 0, m1 = 0;
             RSOC_HIP(hipEventElapsedTime(&m0, c->ev[2], c->ev[3]));
             RSOC_HIP(hipEventElapsedTime(&m1, c->ev[4], c->ev[5]));
@@ -456,8 +484,18 @@ inline int32_t run_single(rsoc_ctx *c, const int32_t *rp, const int32_t *ci, int
         }
         int64_t b0, b1, tot;
         const int64_t l1 = h->head.rounds > 0 ? h->L1 : 0;
-        alg_bytes(o.mode, o.full_sweep != 0, n, nnz, nW, nB, h->head.u0, l1, h->head.conflicts, h->head.inspected,
-                  h->head.deg_sum, h->head.inspected1, h->head.deg_sum1, b0, b1, tot);
+        if (inc) {
+            // set-up: colours read, shadows written, row_ptr for degrees, marks
+            // written and read, touched ids, U^0 appended; then the rounds
+            b0 = 4 * n + n + (opt ? 4 * (n / 8 + 1) : 0) + 4 * (n + 1) + 8 * (int64_t)n + 4 * (int64_t)nt +
+                 4 * (int64_t)h->head.u0;
+            b1 = 0;
+            tot = b0 + 16 * (int64_t)h->head.inspected + 8 * (int64_t)h->head.deg_sum +
+                  (opt ? 8 : 20) * h->head.conflicts;
+        } else {
+            alg_bytes(o.mode, o.full_sweep != 0, n, nnz, nW, nB, h->head.u0, l1, h->head.conflicts,
+                      h->head.inspected, h->head.deg_sum, h->head.inspected1, h->head.deg_sum1, b0, b1, tot);
+        }
         st->bytes_round0 = b0;
         st->worklist0 = sweep1 ? n : h->head.u0;
         st->chunk = chunk;

@@ -46,7 +46,8 @@ struct SingleState {
     int32_t maxdeg;
     int32_t passes;       // inspection passes executed (rounds >= 1)
     int32_t rounds;       // passes that recoloured somebody
-    int32_t err;          // bit 0 bad CSR, bit 1 self-loop, bit 2 colour out of range, bit 3 edges without col_idx
+    int32_t err;          // bit 0 bad CSR, bit 1 self-loop, bit 2 colour out of range, bit 3 edges without
+                          // col_idx, bit 4 a touched id out of range (recolouring)
     int32_t nnz;          // row_ptr[n] (read by k_bin)
     int32_t lastL, prevL; // |L| of the last two rounds that inspected anything
     // colour statistics (k_colour_stats; cleared before each computation)
@@ -770,6 +771,79 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const SingleArgs *__restrict
             col8[v] = shadow_of(cc);
         }
     }
+}
+
+// ------------------------------------------------ recolouring after edits --
+// Set-up of a recolouring that starts from a given colouring (col[], the
+// colouring before the edits; negative = no colour): the byte shadow and, in
+// the optimistic mode (NIB), the 4-bit shadow follow col, and mark[v] = 1 for
+// every vertex without a valid First-Fit colour (negative, or above its
+// degree), else 0.
+template <bool NIB>
+__global__ __launch_bounds__(kBlock) void k_inc_shadow(const SingleArgs *__restrict__ A, int32_t *mark) {
+    const SingleArgs a = *A;
+    const RSOC_GLOBAL int32_t *col = gro(a.col);
+    const RSOC_GLOBAL int32_t *rp = gro(a.rp);
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    const int64_t t0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    for (int64_t v = t0; v < a.n; v += stride) {
+        const int c = col[v];
+        a.col8[v] = shadow_of(c);
+        mark[v] = (c < 0 || c > rp[v + 1] - rp[v]) ? 1 : 0;
+    }
+    if (NIB)
+        for (int64_t w = t0; w < (int64_t)a.n / 8 + 1; w += stride) {
+            uint32_t word = 0;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int64_t v = w * 8 + k;
+                const int c = v < a.n ? col[v] : -1;
+                word |= ((c < 0 || c > 15) ? 15u : (uint32_t)c) << (4 * k);
+            }
+            a.col4[w] = word;
+        }
+}
+
+// Marks the touched vertices; an id outside [0, n) sets err bit 4 and is
+// skipped.
+__global__ __launch_bounds__(kBlock) void k_inc_touch(const SingleArgs *__restrict__ A, SingleState *S,
+                                                      const int32_t *__restrict__ touched, int64_t nt, int32_t *mark) {
+    const int n = A->n;
+    bool bad = false;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < nt; i += (int64_t)gridDim.x * kBlock) {
+        const int t = touched[i];
+        if (t < 0 || t >= n) bad = true;
+        else mark[t] = 1;
+    }
+    if (ballot(bad) && lane_id() == 0) atomicOr(&S->err, 16);
+}
+
+// U^0 of the recolouring: the marked vertices, appended by degree bin into
+// worklist buffer 0 (k_round_end then publishes them as the current list).
+__global__ __launch_bounds__(kBlock) void k_inc_list(const SingleArgs *__restrict__ A, SingleState *S,
+                                                     const int32_t *__restrict__ mark) {
+    __shared__ int qT[kQueueCap], qW[kQueueCap], qB[kQueueCap];
+    __shared__ int nqT, nqW, nqB, qbase;
+    const SingleArgs a = *A;
+    const RSOC_GLOBAL int32_t *rp = gro(a.rp);
+    int32_t *const out = a.wl[0];
+    if (threadIdx.x == 0) nqT = nqW = nqB = 0;
+    __syncthreads();
+    for (int64_t base = (int64_t)blockIdx.x * kBlock; base < a.n; base += (int64_t)gridDim.x * kBlock) {
+        const int v = (int)(base + threadIdx.x);
+        const bool m = v < a.n && mark[v] != 0;
+        const int d = m ? rp[v + 1] - rp[v] : 0;
+        queue_push(m && d > a.t_wave, v, qB, &nqB);
+        queue_push(m && d > a.t_thread && d <= a.t_wave, v, qW, &nqW);
+        queue_push(m && d <= a.t_thread, v, qT, &nqT);
+        __syncthreads();
+        if (nqB > kQueueCap - kBlock) queue_flush(qB, &nqB, &qbase, &S->cnt_out[kBinBlock], out + a.offB);
+        if (nqW > kQueueCap - kBlock) queue_flush(qW, &nqW, &qbase, &S->cnt_out[kBinWave], out + a.offW);
+        if (nqT > kQueueCap - kBlock) queue_flush(qT, &nqT, &qbase, &S->cnt_out[kBinThread], out);
+    }
+    queue_flush(qB, &nqB, &qbase, &S->cnt_out[kBinBlock], out + a.offB);
+    queue_flush(qW, &nqW, &qbase, &S->cnt_out[kBinWave], out + a.offW);
+    queue_flush(qT, &nqT, &qbase, &S->cnt_out[kBinThread], out);
 }
 
 // ------------------------------------------------------------ round end --

@@ -10,7 +10,9 @@
 //     has at most e-b neighbours, the answer is at most e-b, so a window of
 //     colours [base, base+W) with W > e-b always contains it.
 // Phase kAssign computes First-Fit only; kRecolor detects and, if defective,
-// computes First-Fit; kDetect only detects.
+// computes First-Fit; kDetect only detects.  A vertex whose own colour is
+// negative or above its degree counts as defective (only a recolouring that
+// starts from a given colouring meets one).
 #pragma once
 
 #include <limits.h>
@@ -141,7 +143,10 @@ __device__ __forceinline__ void group_vertices(const int (&v)[NV], const int (&b
             bool c = false;
 #pragma unroll
             for (int s = 0; s < T; ++s) c |= (cu[i][s] == cv[i]);
-            def[i] = group_any<G>(c);
+            // a vertex without a valid First-Fit colour (none, shadow 255, or
+            // one above its degree; only a recolouring from a given colouring
+            // meets such a vertex) is defective too
+            def[i] = group_any<G>(c) || (v[i] >= 0 && cv[i] > e[i] - b[i]);
             act[i] = def[i];
         }
         if (PHASE == kDetect) return;
@@ -251,7 +256,7 @@ __device__ __forceinline__ bool wave_vertex(int v, int b, int e, const RSOC_GLOB
     bool unc = false;
     if (PHASE != kAssign) {
         const int cv = col[v];
-        bool any = false;
+        bool any = cv < 0 || cv > e - b;  // no valid First-Fit colour: defective
         for (int j0 = b; j0 < e && !any; j0 += U * kWave) {
             int u[U];
 #pragma unroll
@@ -326,8 +331,8 @@ __device__ __forceinline__ bool block_vertex(int v, int b, int e, const RSOC_GLO
     bool unc = false;
     if (PHASE != kAssign) {
         const int cv = col[v];
-        int any = 0;
-        for (int j0 = b; j0 < e; j0 += kBlock * U * 4) {
+        int any = cv < 0 || cv > e - b;  // no valid First-Fit colour: defective
+        for (int j0 = b; j0 < e && !any; j0 += kBlock * U * 4) {
             bool c = false;
             const int j1 = min(e, j0 + kBlock * U * 4);
             for (int jj = j0; jj < j1; jj += kBlock * U) {
