@@ -216,6 +216,19 @@ void rsoc_pool_destroy(rsoc_pool *pool);
  * slot at the next step with that status, returned by rsoc_pool_result. */
 int32_t rsoc_pool_admit(rsoc_pool *pool, const int32_t *d_row_ptr, const int32_t *d_col_idx, int32_t n,
                         int32_t *d_colors_out, const rsoc_options *opts);
+/* Admits a recolouring after topology edits (as rsoc_recolor_device: the
+ * colouring before the edits in d_colors_inout, negative = none, the touched
+ * vertices in d_touched[n_touched], which may repeat ids): the slot starts
+ * with Algorithm 3's worklist rounds over U^0 = the touched vertices plus
+ * those without a valid First-Fit colour, in the same fused rounds as the
+ * other slots.  d_touched must stay valid until the next rsoc_pool_step
+ * returns, the other pointers until rsoc_pool_result.  Modes as for
+ * rsoc_recolor_device.  Returns a slot id, RSOC_EBUDGET or RSOC_EINVAL; a
+ * touched id outside [0, n) finishes the slot with RSOC_EINVAL (returned by
+ * rsoc_pool_result). */
+int32_t rsoc_pool_admit_recolor(rsoc_pool *pool, const int32_t *d_row_ptr, const int32_t *d_col_idx, int32_t n,
+                                int32_t *d_colors_inout, const int32_t *d_touched, int32_t n_touched,
+                                const rsoc_options *opts);
 /* One fused round over all live slots on hip_stream (synchronised).  Writes up
  * to `cap` finished slot ids to finished_slots.  Returns the number finished
  * (they stay reserved until rsoc_pool_result). */

@@ -14,6 +14,7 @@ is no CPU fallback.
 from __future__ import annotations
 
 import ctypes
+import weakref
 import os
 
 import numpy as np
@@ -90,6 +91,7 @@ _sig = {
     "rsoc_pool_create": (_i32, [_p, _i64, _i32, ctypes.POINTER(_p)]),
     "rsoc_pool_destroy": (None, [_p]),
     "rsoc_pool_admit": (_i32, [_p, _p, _p, _i32, _p, ctypes.POINTER(rsoc_options)]),
+    "rsoc_pool_admit_recolor": (_i32, [_p, _p, _p, _i32, _p, _p, _i32, ctypes.POINTER(rsoc_options)]),
     "rsoc_pool_step": (_i32, [_p, _p, _p, _i32]),
     "rsoc_pool_live": (_i32, [_p]),
     "rsoc_pool_reserved_bytes": (_i64, [_p]),
@@ -196,9 +198,13 @@ class Context:
         _chk(_lib.rsoc_ctx_create(ctypes.byref(h), int(device)), "rsoc_ctx_create")
         self.h = h
         self.device = device
+        self._pools = weakref.WeakSet()
 
     def close(self):
         if self.h:
+            # pools hold the context's scratch and streams: they go first
+            for pool in list(self._pools):
+                pool.close()
             _lib.rsoc_ctx_destroy(self.h)
             self.h = _p()
 
@@ -317,6 +323,7 @@ class Pool:
         _chk(_lib.rsoc_pool_create(ctx.h, int(hbm_budget_bytes), int(max_slots), ctypes.byref(h)), "rsoc_pool_create")
         self.h = h
         self.ctx = ctx
+        ctx._pools.add(self)
 
     def admit(self, d_row_ptr, d_col_idx, n, d_colors_out, options=None) -> int:
         """Returns a slot id, or raises RsocError (code RSOC_EBUDGET when it does not fit now)."""
@@ -330,6 +337,26 @@ class Pool:
                                  ctypes.byref(o))
         if r < 0 and r != RSOC_EBUDGET:
             raise RsocError(r, "rsoc_pool_admit")
+        return r
+
+    def admit_recolor(self, d_row_ptr, d_col_idx, n, d_colors_inout, d_touched, options=None) -> int:
+        """Recolouring after edits (d_colors_inout: the colouring before them,
+        negative = none; d_touched: device int32 or None).  Returns a slot id,
+        or raises RsocError (RSOC_EBUDGET when it does not fit now)."""
+        o = options if options is not None else make_options()
+        nt = 0 if d_touched is None else int(d_touched.numel())
+        return _chk(_lib.rsoc_pool_admit_recolor(self.h, _dev_ptr(d_row_ptr), _dev_ptr(d_col_idx), int(n),
+                                                 _dev_ptr(d_colors_inout), _dev_ptr(d_touched) if nt else None, nt,
+                                                 ctypes.byref(o)), "rsoc_pool_admit_recolor")
+
+    def try_admit_recolor(self, d_row_ptr, d_col_idx, n, d_colors_inout, d_touched, options=None) -> int:
+        o = options if options is not None else make_options()
+        nt = 0 if d_touched is None else int(d_touched.numel())
+        r = _lib.rsoc_pool_admit_recolor(self.h, _dev_ptr(d_row_ptr), _dev_ptr(d_col_idx), int(n),
+                                         _dev_ptr(d_colors_inout), _dev_ptr(d_touched) if nt else None, nt,
+                                         ctypes.byref(o))
+        if r < 0 and r != RSOC_EBUDGET:
+            raise RsocError(r, "rsoc_pool_admit_recolor")
         return r
 
     def step(self, stream=None, cap=1024):

@@ -161,10 +161,17 @@ void rsoc_pool_destroy(rsoc_pool *p) {
     delete p;
 }
 
-int32_t rsoc_pool_admit(rsoc_pool *p, const int32_t *d_row_ptr, const int32_t *d_col_idx, int32_t n,
-                        int32_t *d_colors_out, const rsoc_options *opts) {
-    using namespace rsoc;
-    if (!p || n < 0 || (n > 0 && (!d_row_ptr || !d_colors_out))) return RSOC_EINVAL;
+namespace rsoc {
+
+// Admission of a colouring (recolor = false) or of a recolouring after edits
+// (col holds the colouring before the edits, touched[0, nt) the touched
+// vertices): the slot starts with its round 0, or straight with worklist
+// rounds over U^0.
+inline int32_t pool_admit(rsoc_pool *p, const int32_t *d_row_ptr, const int32_t *d_col_idx, int32_t n,
+                          int32_t *d_colors_out, const rsoc_options *opts, bool recolor, const int32_t *d_touched,
+                          int32_t nt) {
+    if (!p || n < 0 || (n > 0 && (!d_row_ptr || !d_colors_out)) || nt < 0 || (nt > 0 && !d_touched))
+        return RSOC_EINVAL;
     Options o;
     RSOC_TRY(resolve_options(opts, n, o));
     if (o.mode == RSOC_MODE_TWO_PHASE) return RSOC_EINVAL;  // the pool runs Algorithm 3 only
@@ -214,12 +221,19 @@ int32_t rsoc_pool_admit(rsoc_pool *p, const int32_t *d_row_ptr, const int32_t *d
     m.t_thread = o.t_thread;
     m.t_wave = o.t_wave;
     m.look = o.lookahead == -1 ? 0 : (o.lookahead > 0 ? o.lookahead : (1 << 20));
-    m.phase = n > 0 ? kSlotNew : kSlotDone;  // nothing to colour: done at once
-    m.chunk = o.chunk;  // 0: chosen from the locality sample when the set-up is seen
+    m.phase = n > 0 ? (recolor ? kSlotRunning : kSlotNew) : kSlotDone;  // nothing to colour: done at once
+    m.chunk = recolor ? 1 : o.chunk;  // 0: chosen from the locality sample when the set-up is seen
+    m.recolor = recolor ? 1 : 0;
+    m.touched = d_touched;
+    m.nt = recolor ? nt : 0;
     p->reported[slot] = 0;
     if ((r = pool_upload_slot(p, slot, s)) < 0) { pool_release(p, slot); return r; }
     if (n > 0) {
         k_pinit<<<std::min(div_up(n, kBlock), 1024), kBlock, 0, s>>>(p->slots_dev.as<PoolSlot>(), slot);
+        if (recolor) {
+            if (nt > 0) k_ptouch<<<std::min(div_up(nt, kBlock), 256), kBlock, 0, s>>>(p->slots_dev.as<PoolSlot>(), slot);
+            k_plist<<<std::min(div_up(n, kBlock), 1024), kBlock, 0, s>>>(p->slots_dev.as<PoolSlot>(), slot);
+        }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) { pool_release(p, slot); return hip_fail(e, "k_pinit", __FILE__, __LINE__); }
         if ((r = pool_download_slot(p, slot, s)) < 0) { pool_release(p, slot); return r; }
@@ -227,6 +241,19 @@ int32_t rsoc_pool_admit(rsoc_pool *p, const int32_t *d_row_ptr, const int32_t *d
     }
     RSOC_HIP(hipEventRecord(p->ev, s));
     return slot;
+}
+
+}  // namespace rsoc
+
+int32_t rsoc_pool_admit(rsoc_pool *p, const int32_t *d_row_ptr, const int32_t *d_col_idx, int32_t n,
+                        int32_t *d_colors_out, const rsoc_options *opts) {
+    return rsoc::pool_admit(p, d_row_ptr, d_col_idx, n, d_colors_out, opts, false, nullptr, 0);
+}
+
+int32_t rsoc_pool_admit_recolor(rsoc_pool *p, const int32_t *d_row_ptr, const int32_t *d_col_idx, int32_t n,
+                                int32_t *d_colors_inout, const int32_t *d_touched, int32_t n_touched,
+                                const rsoc_options *opts) {
+    return rsoc::pool_admit(p, d_row_ptr, d_col_idx, n, d_colors_inout, opts, true, d_touched, n_touched);
 }
 
 int32_t rsoc_pool_step(rsoc_pool *p, void *hip_stream, int32_t *finished_slots, int32_t cap) {
@@ -248,11 +275,14 @@ int32_t rsoc_pool_step(rsoc_pool *p, void *hip_stream, int32_t *finished_slots, 
             p->pending[i] = 0;
             PoolSlot &ms = m[i];
             if (ms.status < 0) {
-                ms.phase = kSlotDone;  // bad row_ptr ends or missing col_idx
+                ms.phase = kSlotDone;  // bad row_ptr ends, missing col_idx, touched id out of range
             } else {
                 ms.offW = ms.n - ms.nW - ms.nB;
                 ms.offB = ms.n - ms.nB;
                 ms.chunk = pick_chunk(ms.chunk, ms.near, ms.sampled);
+                // an empty U^0 still takes one (empty) step, which ends the
+                // slot and counts its colours
+                if (ms.recolor) ms.u0 = ms.cnt_in[0] + ms.cnt_in[1] + ms.cnt_in[2];
             }
             RSOC_TRY(pool_upload_slot(p, i, s));
         }

@@ -37,6 +37,8 @@ struct PoolSlot {
     int32_t cnt_in[4], cnt_out[4];
     int32_t nW, nB, maxdeg, passes, rounds, kmax, err, phase, u0, status;
     int32_t chunk, masked;  // masked: the next round is the first worklist round after round 0
+    const int32_t *touched;  // recolouring after edits: the touched vertices (nt of them)
+    int32_t nt, recolor;     // recolor: the slot starts from the colouring in col
     uint64_t near, sampled;  // id locality sample (admission)
 };
 
@@ -72,10 +74,19 @@ __global__ __launch_bounds__(kBlock) void k_pinit(PoolSlot *slots, int slot) {
         int d = -1;
         if (v < n) {
             d = rp[v + 1] - rp[v];
-            sp->col[v] = fillc;
-            sp->col8[v] = shadow_of(fillc);
-            if (sp->col4 && (v & 7) == 0) sp->col4[v >> 3] = ~0u;  // every nibble 15: nothing published yet
-            if ((v & 255) == 0 && rows_ok) locality_row(rp, ci, v, nnz, near, sampled);  // id-locality sample
+            if (sp->recolor) {
+                // recolouring: colours stay; byte shadow from them; mark in
+                // wl[1] (free until the first round appends there) every
+                // vertex without a valid First-Fit colour
+                const int c = sp->col[v];
+                sp->col8[v] = shadow_of(c);
+                sp->wl[1][v] = (c < 0 || c > d) ? 1 : 0;
+            } else {
+                sp->col[v] = fillc;
+                sp->col8[v] = shadow_of(fillc);
+                if (sp->col4 && (v & 7) == 0) sp->col4[v >> 3] = ~0u;  // every nibble 15: nothing published yet
+                if ((v & 255) == 0 && rows_ok) locality_row(rp, ci, v, nnz, near, sampled);  // id-locality sample
+            }
         }
         md = max(md, d);
         queue_push(d > sp->t_wave, v, qB, &nqB);
@@ -94,6 +105,49 @@ __global__ __launch_bounds__(kBlock) void k_pinit(PoolSlot *slots, int slot) {
     }
     md = block_max(md, sh);
     if (threadIdx.x == 0) atomicMax(&sp->maxdeg, md);
+}
+
+// Recolouring slots, after k_pinit: the touched vertices are marked too (an
+// id outside [0, n) gives status RSOC_EINVAL) ...
+__global__ __launch_bounds__(kBlock) void k_ptouch(PoolSlot *slots, int slot) {
+    PoolSlot *sp = slots + slot;
+    bool bad = false;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < sp->nt; i += (int64_t)gridDim.x * kBlock) {
+        const int t = sp->touched[i];
+        if (t < 0 || t >= sp->n) bad = true;
+        else sp->wl[1][t] = 1;
+    }
+    if (ballot(bad) && lane_id() == 0) atomicMin(&sp->status, -1);  // RSOC_EINVAL
+}
+
+// ... and the marked vertices become the first worklist, by degree bin, in
+// wl[0] (parity 0), counted straight into cnt_in.
+__global__ __launch_bounds__(kBlock) void k_plist(PoolSlot *slots, int slot) {
+    __shared__ int qT[kQueueCap], qW[kQueueCap], qB[kQueueCap];
+    __shared__ int nqT, nqW, nqB, qbase;
+    PoolSlot *sp = slots + slot;
+    const RSOC_GLOBAL int32_t *rp = gro(sp->rp);
+    const int n = sp->n;
+    const int offW = n - sp->nW - sp->nB, offB = n - sp->nB;
+    const int32_t *mark = sp->wl[1];
+    int32_t *const out = sp->wl[0];
+    if (threadIdx.x == 0) nqT = nqW = nqB = 0;
+    __syncthreads();
+    for (int64_t base = (int64_t)blockIdx.x * kBlock; base < n; base += (int64_t)gridDim.x * kBlock) {
+        const int v = (int)(base + threadIdx.x);
+        const bool m = v < n && mark[v] != 0;
+        const int d = m ? rp[v + 1] - rp[v] : 0;
+        queue_push(m && d > sp->t_wave, v, qB, &nqB);
+        queue_push(m && d > sp->t_thread && d <= sp->t_wave, v, qW, &nqW);
+        queue_push(m && d <= sp->t_thread, v, qT, &nqT);
+        __syncthreads();
+        if (nqB > kQueueCap - kBlock) queue_flush(qB, &nqB, &qbase, &sp->cnt_in[kBinBlock], out + offB);
+        if (nqW > kQueueCap - kBlock) queue_flush(qW, &nqW, &qbase, &sp->cnt_in[kBinWave], out + offW);
+        if (nqT > kQueueCap - kBlock) queue_flush(qT, &nqT, &qbase, &sp->cnt_in[kBinThread], out);
+    }
+    queue_flush(qB, &nqB, &qbase, &sp->cnt_in[kBinBlock], out + offB);
+    queue_flush(qW, &nqW, &qbase, &sp->cnt_in[kBinWave], out + offW);
+    queue_flush(qT, &nqT, &qbase, &sp->cnt_in[kBinThread], out);
 }
 
 template <int TIE, int KIND>

@@ -1,6 +1,8 @@
 """Request loop with continuous batching over the librsoc pool.
 
-Colouring requests (host CSR graphs) arrive over time.  The server keeps an
+Colouring requests (host CSR graphs) arrive over time; a request may instead
+be a recolouring after topology edits (the colouring from before the edits and
+the touched vertices), which joins the pool the same way.  The server keeps an
 HBM budget: a request is admitted when its CSR, colour array and pool
 scratch fit; its CSR is copied to the device on a copy stream while the
 compute stream keeps running pool steps, then it joins the pool, whose every
@@ -27,12 +29,17 @@ import paper_1505_04086_amd as rsoc
 torch = rsoc.torch
 
 
-def csr_bytes(n: int, nnz: int, resident: bool = False) -> int:
+def csr_bytes(n: int, nnz: int, resident: bool = False, touched: int = 0) -> int:
     """Device bytes the server holds for one request: row_ptr, col_idx and
-    colours, or only the colours when the CSR is already on the device."""
+    colours, or only the colours when the CSR is already on the device (plus
+    the touched list of a recolouring)."""
     if resident:
-        return 4 * max(n, 1)
-    return 4 * (n + 1) + 4 * max(nnz, 1) + 4 * max(n, 1)
+        return 4 * max(n, 1) + 4 * touched
+    return 4 * (n + 1) + 4 * max(nnz, 1) + 4 * max(n, 1) + 4 * touched
+
+
+def _n_touched(req) -> int:
+    return 0 if req.touched is None else len(req.touched)
 
 
 def _on_device(t) -> bool:
@@ -48,6 +55,11 @@ class Request:
     n: int = 0
     nnz: int = 0
     options: object = None
+    # a recolouring after topology edits: the colouring before the edits
+    # (int32[n], negative = none) and the touched vertices (int32), host or
+    # device; None for a colouring request
+    prev_colors: object = None
+    touched: object = None
     # filled by the server
     admitted: float = 0.0
     done: float = 0.0
@@ -97,7 +109,7 @@ def admit_fifo(queue: collections.deque, ledger: BudgetLedger, scratch_cap: int 
     pool scratch exceeds scratch_cap) is yielded with nbytes = -1: reject it."""
     while queue:
         req = queue[0]
-        nbytes = csr_bytes(req.n, req.nnz, _on_device(req.row_ptr))
+        nbytes = csr_bytes(req.n, req.nnz, _on_device(req.row_ptr), _n_touched(req))
         det = req.options is not None and req.options.mode != rsoc.RSOC_MODE_OPTIMISTIC
         if nbytes > ledger.budget or slot_scratch_bytes(req.n, det) > scratch_cap:
             queue.popleft()
@@ -107,6 +119,19 @@ def admit_fifo(queue: collections.deque, ledger: BudgetLedger, scratch_cap: int 
             break
         queue.popleft()
         yield req, nbytes
+
+
+def _colour_tensors(req, dev):
+    """The request's colour tensor on the device (the previous colouring for a
+    recolouring, else uninitialised) and its touched list (or None); enqueued
+    on the current stream."""
+    if req.prev_colors is None:
+        return torch.empty(max(req.n, 1), dtype=torch.int32, device=dev), None
+    col = torch.as_tensor(req.prev_colors).to(dev, non_blocking=True).to(torch.int32).clone()
+    tch = None
+    if _n_touched(req):
+        tch = torch.as_tensor(req.touched).to(dev, non_blocking=True).to(torch.int32)
+    return col, tch
 
 
 class Server:
@@ -153,10 +178,10 @@ class Server:
                     rp = torch.as_tensor(req.row_ptr).to(self.dev, non_blocking=True)
                     ci = torch.as_tensor(req.col_idx if req.nnz else np.zeros(1, np.int32)).to(self.dev,
                                                                                              non_blocking=True)
-                col = torch.empty(max(req.n, 1), dtype=torch.int32, device=self.dev)
+                col, tch = _colour_tensors(req, self.dev)
                 ev = torch.cuda.Event()
                 ev.record(self.copy)
-            self.staging.append((req, (rp, ci, col), ev, nbytes))
+            self.staging.append((req, (rp, ci, col, tch), ev, nbytes))
 
     def _admit_copied(self):
         keep = []
@@ -164,8 +189,11 @@ class Server:
             if not ev.query():
                 keep.append((req, tens, ev, nbytes))
                 continue
-            rp, ci, col = tens
-            slot = self.pool.try_admit(rp, ci, req.n, col, req.options or self.options)
+            rp, ci, col, tch = tens
+            if req.prev_colors is not None:
+                slot = self.pool.try_admit_recolor(rp, ci, req.n, col, tch, req.options or self.options)
+            else:
+                slot = self.pool.try_admit(rp, ci, req.n, col, req.options or self.options)
             if slot == rsoc.RSOC_EBUDGET:
                 keep.append((req, tens, ev, nbytes))
                 continue
@@ -176,7 +204,7 @@ class Server:
     # -- completion -----------------------------------------------------
     def _retire(self, slots):
         for slot in slots:
-            req, (rp, ci, col), nbytes = self.live.pop(slot)
+            req, (rp, ci, col, tch), nbytes = self.live.pop(slot)
             try:
                 req.k, req.stats = self.pool.result(slot)
             except rsoc.RsocError as e:
@@ -196,7 +224,7 @@ class Server:
                 ev = torch.cuda.Event()
                 ev.record(self.copy)
             # the device tensors stay referenced until the copy has completed
-            self.draining.append((req, host, ev, nbytes, (rp, ci, col)))
+            self.draining.append((req, host, ev, nbytes, (rp, ci, col, tch)))
 
     def _drain(self, block=False):
         keep = []
@@ -278,10 +306,14 @@ class PlainServer:
                     rp = torch.as_tensor(req.row_ptr).to(self.dev, non_blocking=True)
                     ci = torch.as_tensor(req.col_idx if req.nnz else np.zeros(1, np.int32)).to(self.dev,
                                                                                              non_blocking=True)
-                col = torch.empty(max(req.n, 1), dtype=torch.int32, device=self.dev)
+                col, tch = _colour_tensors(req, self.dev)
                 req.admitted = time.monotonic()
-                req.k, req.stats = rsoc.rsoc_color_device(self.ctx, rp, ci, req.n, col, req.options or self.options,
-                                                          stream=self.stream)
+                if req.prev_colors is not None:
+                    req.k, req.stats = rsoc.rsoc_recolor_device(self.ctx, rp, ci, req.n, col, tch,
+                                                                req.options or self.options, stream=self.stream)
+                else:
+                    req.k, req.stats = rsoc.rsoc_color_device(self.ctx, rp, ci, req.n, col,
+                                                              req.options or self.options, stream=self.stream)
                 req.colors = col[:req.n] if resident else col.cpu().numpy()[:req.n]
             req.done = time.monotonic()
             out.append(req)

@@ -145,3 +145,78 @@ def test_pool_admission_errors_arrive_with_the_result(lib, ctx):
     assert oracle.check(*gg.cycle(9), good[2].cpu().numpy()[:9]) == 0 and k == 3
     assert pool.live() == 0 and pool.reserved_bytes() == 0
     pool.close()
+
+
+def test_pool_recolour_requests(lib, ctx):
+    """Recolouring requests (previous colouring + touched vertices) admitted
+    beside ordinary colourings into the same fused rounds: deterministic ones
+    equal the oracle's recolouring, optimistic ones are valid; an empty U^0
+    leaves the colouring as it was; a touched id out of range comes back as
+    RSOC_EINVAL."""
+    import torch
+    from tests.graph_edits import edit
+    d = torch.device("cuda:0")
+    jobs = []
+    graphs = [G for G in GRAPHS if len(G[0]) > 1]
+    for g, (mode, tie) in enumerate(MODES * 2):
+        rp, ci = graphs[(g * 3) % len(graphs)]
+        n = len(rp) - 1
+        prev, _ = oracle.seq_ff(rp, ci)
+        rp2, ci2, touched = edit(rp, ci, seed=g, add=20, delete=20, new=3)
+        prev2 = np.concatenate([prev, np.full(len(rp2) - 1 - n, -1, np.int32)])
+        jobs.append(("recolor", mode, tie, rp2, ci2, prev2, touched))
+        jobs.append(("colour", mode, tie, rp, ci, None, None))
+    rp, ci = gg.cycle(9)
+    prev, _ = oracle.seq_ff(rp, ci)
+    jobs.append(("recolor", "deterministic", "lower", rp, ci, prev, np.zeros(0, np.int32)))  # nothing to do
+    pool = lib.Pool(ctx, 0, 64)
+    live, done, tensors = {}, {}, {}  # slot -> job index (slot ids are reused once released); job index -> result
+
+    def collect(slots):
+        for f in slots:
+            done[live.pop(f)] = pool.result(f)
+
+    for j, (kind, mode, tie, rp, ci, prev, touched) in enumerate(jobs):
+        n = len(rp) - 1
+        d_rp, d_ci = torch.from_numpy(rp).to(d), torch.from_numpy(ci).to(d)
+        opts = lib.make_options(mode, tie)
+        if kind == "recolor":
+            d_col = torch.from_numpy(prev).to(d)
+            d_t = torch.from_numpy(touched).to(d) if len(touched) else None
+            slot = pool.admit_recolor(d_rp, d_ci, n, d_col, d_t, opts)
+        else:
+            d_col = torch.empty(n, dtype=torch.int32, device=d)
+            d_t = None
+            slot = pool.admit(d_rp, d_ci, n, d_col, opts)
+        live[slot] = j
+        tensors[j] = (d_rp, d_ci, d_col, d_t)
+        collect(pool.step())  # staggered: older slots are mid-way when newer ones arrive
+    steps = 0
+    while len(done) < len(jobs):
+        collect(pool.step())
+        steps += 1
+        assert steps < 5000
+    for j, (kind, mode, tie, rp, ci, prev, touched) in enumerate(jobs):
+        k, st = done[j]
+        got = tensors[j][2].cpu().numpy()
+        slot = j
+        if kind == "recolor" and mode == "deterministic":
+            want = oracle.recolor(rp, ci, prev, touched, tie=tie)
+            assert np.array_equal(got, want["colors"]) and k == want["K"], (slot, tie)
+        elif kind == "colour" and mode == "deterministic":
+            want = oracle.rsync(rp, ci, tie=tie)
+            assert np.array_equal(got, want["colors"]) and k == want["K"], (slot, tie)
+        else:
+            assert oracle.check(rp, ci, got) == 0 and k == oracle.colour_count(got), (slot, kind, mode)
+    assert pool.live() == 0
+    # a touched id outside [0, n)
+    rp, ci = gg.path(5)
+    d_col = torch.zeros(5, dtype=torch.int32, device=d)
+    slot = pool.admit_recolor(torch.from_numpy(rp).to(d), torch.from_numpy(ci).to(d), 5, d_col,
+                              torch.tensor([7], dtype=torch.int32, device=d))
+    while slot not in pool.step():
+        pass
+    with pytest.raises(lib.RsocError) as e:
+        pool.result(slot)
+    assert e.value.code == lib.RSOC_EINVAL
+    pool.close()

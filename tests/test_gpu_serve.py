@@ -77,3 +77,43 @@ def test_alone_equals_mix(lib):
         else:
             assert oracle.check(rp, ci, got) == 0, m.rid
     ctx.close()
+
+
+def test_recolour_requests_served(lib):
+    """Recolouring requests (colouring from before the edits + touched
+    vertices) served beside colouring requests, in the mix and alone:
+    deterministic ones equal the oracle's recolouring, optimistic ones are
+    valid."""
+    from paper_1505_04086_amd import serve
+    from tests.graph_edits import edit
+    ctx = lib.Context(0)
+    specs = []
+    for i, (rp, ci) in enumerate(GRAPHS[:7]):
+        n = len(rp) - 1
+        prev, _ = oracle.seq_ff(rp, ci)
+        rp2, ci2, touched = edit(rp, ci, seed=100 + i, add=200, delete=100, new=10)
+        prev2 = np.concatenate([prev, np.full(len(rp2) - 1 - n, -1, np.int32)])
+        mode = "deterministic" if i % 2 == 0 else "optimistic"
+        specs.append((rp2, ci2, prev2, touched, mode))
+        specs.append((rp, ci, None, None, mode))
+
+    def make():
+        return [serve.Request(k, rp, ci, 0.0002 * k, options=lib.make_options(mode), prev_colors=prev,
+                              touched=touched) for k, (rp, ci, prev, touched, mode) in enumerate(specs)]
+
+    largest = max(serve.csr_bytes(len(s[0]) - 1, len(s[1])) for s in specs)
+    sv = serve.Server(ctx, hbm_budget=int(3 * largest / 0.65), scratch_share=0.35, max_slots=8)
+    mix = sv.run(make())
+    sv.close()
+    alone = serve.PlainServer(ctx).run(make())
+    for out in (mix, alone):
+        assert len(out) == len(specs)
+        for r in out:
+            rp, ci, prev, touched, mode = specs[r.rid]
+            if mode == "deterministic":
+                want = oracle.recolor(rp, ci, prev, touched) if prev is not None else oracle.rsync(rp, ci)
+                assert np.array_equal(r.colors, want["colors"]) and r.k == want["K"], r.rid
+            else:
+                assert oracle.check(rp, ci, r.colors) == 0 and r.k == oracle.colour_count(r.colors), r.rid
+    assert sv.ledger.used == 0
+    ctx.close()
