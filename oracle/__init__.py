@@ -72,6 +72,8 @@ class OracleLib:
         lib.orc_classes.restype = i32
         lib.orc_recolor.argtypes = [i32, p, p, i32, i32, p, p, i32, ctypes.POINTER(i32), ctypes.POINTER(i64), p, i32]
         lib.orc_recolor.restype = i32
+        lib.orc_square.argtypes = [i32, p, p, p, p, i64]
+        lib.orc_square.restype = i64
         self.lib = lib
         self.path = path
 
@@ -148,6 +150,20 @@ class OracleLib:
         return {"colors": col[:n], "K": int(k), "rounds": R, "conflicts": int(conflicts.value),
                 "L_sizes": Ls[:min(R, cap)].copy(), "status": 0 if k >= 0 else int(k)}
 
+    def square(self, row_ptr, col_idx):
+        """G^2 as CSR (row_ptr int64[n+1], col_idx int32, rows ascending,
+        no self-loops, no repeats)."""
+        rp, ci, n = _csr(row_ptr, col_idx)
+        out_rp = np.zeros(n + 1, dtype=np.int64)
+        nnz = self.lib.orc_square(n, rp.ctypes.data, ci.ctypes.data, out_rp.ctypes.data, None, 0)
+        if nnz < 0:
+            raise RuntimeError("orc_square failed: %d" % nnz)
+        out_ci = np.empty(max(nnz, 1), dtype=np.int32)
+        r = self.lib.orc_square(n, rp.ctypes.data, ci.ctypes.data, out_rp.ctypes.data, out_ci.ctypes.data, nnz)
+        if r != nnz:
+            raise RuntimeError("orc_square failed: %d" % r)
+        return out_rp, out_ci[:nnz]
+
     def classes(self, colors, K=None):
         """Colour classes: (ptr int32[K+1], vtx int32[n]); class k is
         vtx[ptr[k]:ptr[k+1]], ascending ids.  K defaults to max + 1."""
@@ -199,6 +215,22 @@ def check(row_ptr, col_idx, colors) -> int:
 
 def classes(colors, K=None):
     return default().classes(colors, K)
+
+
+def square(row_ptr, col_idx):
+    return default().square(row_ptr, col_idx)
+
+
+def seq_ff_d2(row_ptr, col_idx):
+    """Distance-2 colouring by Algorithm 1: First-Fit on G^2."""
+    rp2, ci2 = square(row_ptr, col_idx)
+    return seq_ff(rp2.astype(np.int32), ci2)
+
+
+def rsync_d2(row_ptr, col_idx, tie="lower", max_rounds=None, raise_on_noconv=True):
+    """Distance-2 colouring by Algorithm 3 (snapshot reading) on G^2."""
+    rp2, ci2 = square(row_ptr, col_idx)
+    return rsync(rp2.astype(np.int32), ci2, tie, max_rounds, raise_on_noconv)
 
 
 def recolor(row_ptr, col_idx, prev_colors, touched, tie="lower", max_rounds=None, raise_on_noconv=True):

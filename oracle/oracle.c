@@ -333,3 +333,50 @@ int32_t orc_recolor(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, i
     free(snap); free(U); free(L); free(in_u0); free(seen);
     return rc < 0 ? rc : colour_count(n, colors);
 }
+
+/*
+ * The square G^2 of a graph (Section 7 names d-distance colouring, i.e. the
+ * colouring of the d-th power graph G^d, as the extension the method suits:
+ * u and w are adjacent in G^2 iff they are within distance 2 in G).  Row v of
+ * G^2 lists, in ascending order and once each, every vertex other than v that
+ * is a neighbour of v or a neighbour of one of v's neighbours.  Two passes
+ * over the same loop: the first counts into out_rp (out_rp[n] = nnz of G^2),
+ * the second (out_ci non-NULL, out_cap entries) writes.  `mark` is the
+ * last-visited stamp of each vertex.  Returns nnz(G^2), ORC_EINVAL, or
+ * ORC_ENOMEM (also when out_cap is too small).
+ */
+int64_t orc_square(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, int64_t *out_rp, int32_t *out_ci,
+                   int64_t out_cap) {
+    if (n < 0 || (n > 0 && (!row_ptr || !out_rp))) return ORC_EINVAL;
+    int32_t *mark = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    int32_t *row = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    if (!mark || !row) { free(mark); free(row); return ORC_ENOMEM; }
+    for (int32_t v = 0; v < n; ++v) mark[v] = -1;
+    out_rp[0] = 0;
+    for (int32_t v = 0; v < n; ++v) {
+        int32_t len = 0;
+        mark[v] = v; /* v itself is never listed */
+        for (int32_t j = row_ptr[v]; j < row_ptr[v + 1]; ++j) {
+            const int32_t u = col_idx[j];
+            if (mark[u] != v) { mark[u] = v; row[len++] = u; }
+            for (int32_t k = row_ptr[u]; k < row_ptr[u + 1]; ++k) {
+                const int32_t w = col_idx[k];
+                if (mark[w] != v) { mark[w] = v; row[len++] = w; }
+            }
+        }
+        out_rp[v + 1] = out_rp[v] + len;
+        if (out_ci) {
+            if (out_rp[v + 1] > out_cap) { free(mark); free(row); return ORC_ENOMEM; }
+            /* ascending order: insertion sort of the (short) row */
+            for (int32_t a = 1; a < len; ++a) {
+                const int32_t x = row[a];
+                int32_t b = a - 1;
+                while (b >= 0 && row[b] > x) { row[b + 1] = row[b]; --b; }
+                row[b + 1] = x;
+            }
+            memcpy(out_ci + out_rp[v], row, sizeof(int32_t) * (size_t)len);
+        }
+    }
+    free(mark); free(row);
+    return out_rp[n];
+}

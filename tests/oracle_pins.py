@@ -418,9 +418,65 @@ def pin_recolor_range(O):
     raise AssertionError("touched id outside [0, n) accepted")
 
 
+# ------------------------------------------------------------ distance-2 (the square G^2)
+
+def _within2(rp, ci, v):
+    """Vertices at distance 1 or 2 from v, by breadth-first search."""
+    seen = {v: 0}
+    frontier = [v]
+    for depth in (1, 2):
+        nxt = []
+        for x in frontier:
+            for u in ci[rp[x]:rp[x + 1]]:
+                u = int(u)
+                if u not in seen:
+                    seen[u] = depth
+                    nxt.append(u)
+        frontier = nxt
+    return sorted(u for u in seen if u != v)
+
+
+def pin_square_bruteforce(O):
+    for rp, ci in list(_small_graphs(40, seed=95, nmax=25)) + [gg.star(7), gg.grid4(5, 4), gg.tri_grid(6, 5)]:
+        rp2, ci2 = O.square(rp, ci)
+        for v in range(len(rp) - 1):
+            assert ci2[rp2[v]:rp2[v + 1]].tolist() == _within2(rp, ci, v), v
+
+
+def pin_square_closed_forms(O):
+    n = 9
+    rp, ci = gg.path(n)
+    rp2, ci2 = O.square(rp, ci)
+    for v in range(n):
+        assert ci2[rp2[v]:rp2[v + 1]].tolist() == [u for u in range(v - 2, v + 3) if 0 <= u < n and u != v]
+    rp, ci = gg.cycle(n)
+    rp2, ci2 = O.square(rp, ci)
+    for v in range(n):
+        assert ci2[rp2[v]:rp2[v + 1]].tolist() == sorted((v + d) % n for d in (-2, -1, 1, 2))
+    rp, ci = gg.star(5)  # centre 0 and 5 leaves: G^2 is K6
+    rp2, ci2 = O.square(rp, ci)
+    assert np.diff(rp2).tolist() == [5] * 6
+    # distance-2 First-Fit in id order: a path gets v mod 3, a star's leaves all differ
+    c, K = O.seq_ff(*[np.asarray(x, np.int32) for x in O.square(*gg.path(10))])
+    assert c.tolist() == [v % 3 for v in range(10)] and K == 3
+    c, K = O.seq_ff(*[np.asarray(x, np.int32) for x in O.square(*gg.star(5))])
+    assert c.tolist() == list(range(6)) and K == 6
+
+
+def pin_square_colouring_valid(O):
+    """A colouring of G^2 separates every pair within distance 2 in G."""
+    for rp, ci in _small_graphs(20, seed=96, nmax=30):
+        rp2, ci2 = O.square(rp, ci)
+        for tie in ("lower", "higher"):
+            c = O.rsync(rp2.astype(np.int32), ci2, tie=tie)["colors"]
+            for v in range(len(rp) - 1):
+                assert all(c[u] != c[v] for u in _within2(rp, ci, v))
+
+
 ALL_PINS = [pin_seq_closed_forms, pin_seq_golden_tri_grid, pin_seq_networkx, pin_seq_bounds_and_bruteforce,
             pin_seq_some_order_is_optimal, pin_rsync_fig7, pin_rsync_worked_examples, pin_rsync_closed_forms,
             pin_rsync_first_round, pin_rsync_invariants, pin_rsync_reversal, pin_cat_examples, pin_check,
             pin_classes_golden, pin_classes_library, pin_classes_independent_sets, pin_classes_range,
             pin_recolor_worked_examples, pin_recolor_reduces_to_rsync, pin_recolor_from_uncoloured,
-            pin_recolor_edits, pin_recolor_range]
+            pin_recolor_edits, pin_recolor_range, pin_square_bruteforce, pin_square_closed_forms,
+            pin_square_colouring_valid]

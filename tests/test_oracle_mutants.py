@@ -34,6 +34,8 @@ MUTANTS = {
     "recolor_uncoloured_not_defective": ("int defective = snap[v] < 0 || snap[v] > d;", "int defective = 0;"),
     "recolor_touched_ignored": ("if (in_u0[v] || colors[v] < 0 || colors[v] > d) U[nU++] = v;",
                                 "if (colors[v] < 0 || colors[v] > d) U[nU++] = v;"),
+    "square_misses_two_hop": ("if (mark[w] != v) { mark[w] = v; row[len++] = w; }", "(void)w;"),
+    "square_lists_self": ("mark[v] = v; /* v itself is never listed */", "/* v listed */"),
     "recolor_live_reads": ("if (u != v && loses(v, u, tie) && snap[u] == snap[v]) defective = 1;",
                            "if (u != v && loses(v, u, tie) && colors[u] == colors[v]) defective = 1;"),
 }
