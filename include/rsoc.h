@@ -122,7 +122,16 @@ typedef struct {
      * it, seeing their new colours -- so that mutually adjacent hubs stop
      * taking the same colour round after round. */
     int32_t tail;
-    int32_t reserved[3]; /* must be zero */
+    /* 1 (or 0): colour G; 2: distance-2 colouring, i.e. colour G^2, in which
+     * vertices within distance 2 in G are adjacent (Section 7).  G^2 is built
+     * on the device (about 4 bytes per entry of G^2, kept by the context) and
+     * coloured by the same rounds; statistics (max_degree, bins, bytes)
+     * refer to G^2.  Single-graph entry points only (rsoc_color_device,
+     * rsoc_color_ex, rsoc_color); needs every 2-hop walk deg(v) + the degrees
+     * of v's neighbours <= 8192, n <= 2^26 and G^2 below 2^31 entries, else
+     * RSOC_EINVAL. */
+    int32_t distance;
+    int32_t reserved[2]; /* must be zero */
 } rsoc_options;
 
 typedef struct {

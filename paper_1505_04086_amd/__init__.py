@@ -63,7 +63,7 @@ class rsoc_options(ctypes.Structure):
                 ("rounds_per_sync", ctypes.c_int32), ("small_cutoff", ctypes.c_int32),
                 ("timing", ctypes.c_int32), ("full_sweep", ctypes.c_int32), ("lookahead", ctypes.c_int32),
                 ("chunk", ctypes.c_int32), ("grid_list", ctypes.c_int32), ("tail", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 3)]
+                ("distance", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
 
 
 class rsoc_stats(ctypes.Structure):

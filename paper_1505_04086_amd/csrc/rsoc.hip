@@ -9,6 +9,7 @@
 #include "batch.hpp"
 #include "pool.hpp"
 #include "classes.hpp"
+#include "square.hpp"
 
 using namespace rsoc;
 
@@ -102,7 +103,7 @@ int32_t rsoc_color_device(rsoc_ctx *ctx, const int32_t *d_row_ptr, const int32_t
     Options o;
     RSOC_TRY(resolve_options(opts, n, o));
     RSOC_HIP(hipSetDevice(ctx->device));
-    return run_single(ctx, d_row_ptr, d_col_idx, n, d_colors_out, o, stats, (hipStream_t)hip_stream);
+    return run_colouring(ctx, d_row_ptr, d_col_idx, n, d_colors_out, o, stats, (hipStream_t)hip_stream);
 }
 
 int32_t rsoc_color_ex(rsoc_ctx *ctx, const int32_t *row_ptr, const int32_t *col_idx, int32_t n, int32_t *colors_out,
@@ -133,7 +134,8 @@ int32_t rsoc_color_ex(rsoc_ctx *ctx, const int32_t *row_ptr, const int32_t *col_
     if (nnz > 0)
         RSOC_HIP(hipMemcpyAsync(ctx->dci.p, col_idx, sizeof(int32_t) * (size_t)nnz, hipMemcpyHostToDevice, s));
     o.validate = 0;  // already checked on the host
-    int32_t k = run_single(ctx, ctx->drp.as<int32_t>(), ctx->dci.as<int32_t>(), n, ctx->dcol.as<int32_t>(), o, stats, s);
+    int32_t k = run_colouring(ctx, ctx->drp.as<int32_t>(), ctx->dci.as<int32_t>(), n, ctx->dcol.as<int32_t>(), o, stats,
+                              s);
     if (k < 0 && k != RSOC_ENOCONV) return k;
     RSOC_HIP(hipMemcpyAsync(colors_out, ctx->dcol.p, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost, s));
     RSOC_HIP(hipStreamSynchronize(s));
@@ -148,6 +150,7 @@ int32_t rsoc_recolor_device(rsoc_ctx *ctx, const int32_t *d_row_ptr, const int32
     Options o;
     RSOC_TRY(resolve_options(opts, n, o));
     if (o.mode == kTwoPhase) return RSOC_EINVAL;  // Algorithm 2 recolours all of U: no incremental reading
+    if (o.distance == 2) return RSOC_EINVAL;
     RSOC_HIP(hipSetDevice(ctx->device));
     return run_single(ctx, d_row_ptr, d_col_idx, n, d_colors_inout, o, stats, (hipStream_t)hip_stream, d_touched,
                       n_touched);
