@@ -28,7 +28,7 @@ struct rsoc_ctx {
     rsoc::DevBuf wl0, wl1, hubW, hubB, pend, flags, col8, col4, aux;
     rsoc::DevBuf mark, tail;      // ordered pass over a small worklist (tail_kernels.hpp)
     rsoc::DevBuf cls_h, cls_p, cls_st;  // colour classes (classes.hpp)
-    rsoc::DevBuf sq_t, sq_rp, sq_ci, sq_misc;  // G^2 for distance-2 colouring (square.hpp)
+    rsoc::DevBuf sq_t, sq_rp, sq_ci, sq_misc, sq_big;  // G^2 for distance-2 colouring (square.hpp)
     rsoc::DevBuf args, state;     // SingleArgs, SingleState (fixed addresses: graphs point at them)
     rsoc::HostPinned host;        // pinned staging for small copies
     rsoc::DevBuf drp, dci, dcol;  // device copies for host-pointer calls
@@ -73,7 +73,7 @@ inline void ctx_free(rsoc_ctx *c) {
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);
     for (rsoc::DevBuf *b : {&c->col8, &c->col4, &c->aux, &c->mark, &c->tail, &c->cls_h, &c->cls_p, &c->cls_st,
-                            &c->sq_t, &c->sq_rp, &c->sq_ci, &c->sq_misc, &c->wl0, &c->wl1, &c->hubW, &c->hubB, &c->pend, &c->flags, &c->args, &c->state, &c->drp,
+                            &c->sq_t, &c->sq_rp, &c->sq_ci, &c->sq_misc, &c->sq_big, &c->wl0, &c->wl1, &c->hubW, &c->hubB, &c->pend, &c->flags, &c->args, &c->state, &c->drp,
                             &c->dci, &c->dcol, &c->b_desc, &c->b_wl0, &c->b_wl1, &c->b_pend, &c->b_flags,
                             &c->b_state, &c->b_hub, &c->b_kmax, &c->b_tasks, &c->b_args, &c->b_col8})
         b->release();

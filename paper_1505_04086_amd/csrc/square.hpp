@@ -23,15 +23,18 @@ inline int32_t build_square(rsoc_ctx *c, const int32_t *rp, const int32_t *ci, i
     int32_t *R = c->sq_rp.as<int32_t>();
     unsigned long long *total = c->sq_misc.as<unsigned long long>();
     int32_t *err = reinterpret_cast<int32_t *>(total + 1);
+    int32_t *nbig = err + 1;
+    RSOC_TRY(c->sq_big.reserve(sizeof(int32_t) * (size_t)(n + 1)));
+    int32_t *big = c->sq_big.as<int32_t>();
     RSOC_HIP(hipMemsetAsync(c->sq_misc.p, 0, 16, s));
     const int g = std::min(div_up(n, kBlock), 4096);
-    k_sq_size<<<g, kBlock, 0, s>>>(rp, ci, n, T, err);
+    k_sq_size<<<std::min(div_up(n, kBlock / 8), 8192), kBlock, 0, s>>>(rp, ci, n, T, err, big, nbig);
     // count pass: rows with T <= kSqSmallT four wavefronts a workgroup, the
-    // rest one wavefront with a larger table
-    k_sq_rows<4, kSqSmallTab, false><<<std::min(div_up(n, 4), 65536), 4 * kWave, 0, s>>>(rp, ci, n, T, -1, kSqSmallT,
-                                                                                       R, nullptr, nullptr);
-    k_sq_rows<1, kSqBigTab, false><<<std::min(n, 8192), kWave, 0, s>>>(rp, ci, n, T, kSqSmallT, kSqBigT, R, nullptr,
-                                                                         nullptr);
+    // listed rest one wavefront each with a larger table
+    k_sq_rows<4, kSqSmallTab, false><<<std::min(div_up(n, 4), 65536), 4 * kWave, 0, s>>>(
+        rp, ci, n, T, -1, kSqSmallT, nullptr, nullptr, R, nullptr, nullptr);
+    k_sq_rows<1, kSqBigTab, false><<<std::min(n, 2048), kWave, 0, s>>>(rp, ci, n, T, kSqSmallT, kSqBigT, big, nbig, R,
+                                                                         nullptr, nullptr);
     k_sq_total<<<g, kBlock, 0, s>>>(R, n, total);
     RSOC_LAUNCH_CHECK();
     RSOC_HIP(hipMemcpyAsync(&h->sq_total, c->sq_misc.p, 16, hipMemcpyDeviceToHost, s));
@@ -48,10 +51,10 @@ inline int32_t build_square(rsoc_ctx *c, const int32_t *rp, const int32_t *ci, i
     k_sq_tail<<<1, 64, 0, s>>>(R, n, total);
     RSOC_TRY(c->sq_ci.reserve(sizeof(int32_t) * (size_t)std::max<unsigned long long>(h->sq_total, 1)));
     int32_t *C = c->sq_ci.as<int32_t>();
-    k_sq_rows<4, kSqSmallTab, true><<<std::min(div_up(n, 4), 65536), 4 * kWave, 0, s>>>(rp, ci, n, T, -1, kSqSmallT,
-                                                                                      nullptr, R, C);
-    k_sq_rows<1, kSqBigTab, true><<<std::min(n, 8192), kWave, 0, s>>>(rp, ci, n, T, kSqSmallT, kSqBigT, nullptr, R,
-                                                                        C);
+    k_sq_rows<4, kSqSmallTab, true><<<std::min(div_up(n, 4), 65536), 4 * kWave, 0, s>>>(
+        rp, ci, n, T, -1, kSqSmallT, nullptr, nullptr, nullptr, R, C);
+    k_sq_rows<1, kSqBigTab, true><<<std::min(n, 2048), kWave, 0, s>>>(rp, ci, n, T, kSqSmallT, kSqBigT, big, nbig,
+                                                                        nullptr, R, C);
     RSOC_LAUNCH_CHECK();
     *rp2 = R;
     *ci2 = C;

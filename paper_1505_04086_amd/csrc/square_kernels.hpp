@@ -7,9 +7,10 @@
 // without repeats.  One wavefront per vertex walks that multiset (T(v) =
 // deg(v) + sum of deg(u) entries) flattened: 64 neighbours u at a time, their
 // row lengths scanned across the lanes, then 64 entries of the concatenated
-// rows per step, each lane finding its row by a binary search over the 64
-// offsets held by the lanes (shuffles).  Repeats are dropped by an open-addressing hash set in the
-// wavefront's LDS (at least twice T slots).  Two passes use the same walk: the
+// rows per step (four steps' loads in flight together), each lane finding its
+// row by a binary search over the 64 offsets held by the lanes (shuffles).
+// Repeats are dropped by an open-addressing hash set in the wavefront's LDS
+// (at least twice T slots).  Two passes use the same walk: the
 // first counts the distinct entries of each row, the second (after an
 // exclusive scan of the counts) writes them, in hash-table order.
 #pragma once
@@ -24,20 +25,31 @@ constexpr int kSqSmallTab = 2 * kSqSmallT;
 constexpr int kSqBigTab = 2 * kSqBigT;
 
 // T(v) = deg(v) + sum over u in N(v) of deg(u), capped just above kSqBigT
-// (counting stops there); err bit 0 when some T(v) exceeds kSqBigT.  One lane
-// per vertex.
+// (counting stops there); err bit 0 when some T(v) exceeds kSqBigT.  Eight
+// lanes per vertex gather the neighbours' degrees side by side.  Vertices with
+// T(v) > kSqSmallT (few: near hubs) are listed in big[], *nbig of them.
 __global__ __launch_bounds__(kBlock) void k_sq_size(const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
-                                                    int32_t n, int32_t *T, int32_t *err) {
+                                                    int32_t n, int32_t *T, int32_t *err, int32_t *big,
+                                                    int32_t *nbig) {
+    constexpr int G = 8;
+    const int k = threadIdx.x & (G - 1);
     bool over = false;
-    for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < n; v += (int64_t)gridDim.x * kBlock) {
+    const int64_t ng = (int64_t)gridDim.x * (kBlock / G);
+    for (int64_t v = (int64_t)blockIdx.x * (kBlock / G) + threadIdx.x / G; v < n; v += ng) {
         const int b = rp[v], e = rp[v + 1];
-        int64_t t = e - b;
-        for (int j = b; j < e && t <= kSqBigT; ++j) {
+        int64_t t = 0;
+        for (int j = b + k; j < e && t <= kSqBigT; j += G) {
             const int u = ci[j];
             t += rp[u + 1] - rp[u];
         }
-        over |= t > kSqBigT;
-        T[v] = (int32_t)min<int64_t>(t, kSqBigT + 1);
+#pragma unroll
+        for (int o = 1; o < G; o <<= 1) t += __shfl_xor(t, o);
+        t += e - b;
+        if (k == 0) {
+            over |= t > kSqBigT;
+            T[v] = (int32_t)min<int64_t>(t, kSqBigT + 1);
+            if (t > kSqSmallT && t <= kSqBigT) big[atomicAdd(nbig, 1)] = (int32_t)v;
+        }
     }
     if (ballot(over) && lane_id() == 0) atomicOr(err, 1);
 }
@@ -45,13 +57,19 @@ __global__ __launch_bounds__(kBlock) void k_sq_size(const int32_t *__restrict__ 
 __device__ __forceinline__ uint32_t sq_hash(int x) { return (uint32_t)x * 2654435761u; }
 
 // Inserts x into the wavefront's table (size a power of two); true when x
-// was not there yet.  Lanes insert concurrently (LDS compare-and-swap).
+// was not there yet.  Lanes insert concurrently: a plain read settles the
+// common case (x already there, most 2-hop entries being repeats); an empty
+// slot is claimed with an LDS compare-and-swap.
 __device__ __forceinline__ bool sq_insert(int32_t *tab, int mask, int shift, int x) {
     uint32_t h = sq_hash(x) >> shift;
     for (;;) {
-        const int prev = atomicCAS(&tab[h], -1, x);
-        if (prev == -1) return true;
-        if (prev == x) return false;
+        const int cur = tab[h];
+        if (cur == x) return false;
+        if (cur == -1) {
+            const int prev = atomicCAS(&tab[h], -1, x);
+            if (prev == -1) return true;
+            if (prev == x) return false;
+        }
         h = (h + 1) & mask;
     }
 }
@@ -62,15 +80,18 @@ __device__ __forceinline__ bool sq_insert(int32_t *tab, int mask, int shift, int
 template <int WPB, int TAB, bool FILL>
 __global__ __launch_bounds__(WPB *kWave) void k_sq_rows(const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
                                                        int32_t n, const int32_t *__restrict__ T, int lo, int hi,
-                                                       int32_t *cnt, const int32_t *__restrict__ start, int32_t *out) {
+                                                       const int32_t *list, const int32_t *nlist, int32_t *cnt,
+                                                       const int32_t *__restrict__ start, int32_t *out) {
     __shared__ int32_t tabs[WPB][TAB];
     const int wv = threadIdx.x / kWave, lane = lane_id();
     int32_t *tab = tabs[wv];
     const RSOC_GLOBAL int32_t *rpg = gro(rp);
     const RSOC_GLOBAL int32_t *cig = gro(ci);
     const int64_t nw = (int64_t)gridDim.x * WPB;
-    for (int64_t v0 = (int64_t)blockIdx.x * WPB + wv; v0 < n; v0 += nw) {
-        const int v = (int)v0;
+    // all vertices, or the listed ones
+    const int64_t items = list ? *nlist : n;
+    for (int64_t v0 = (int64_t)blockIdx.x * WPB + wv; v0 < items; v0 += nw) {
+        const int v = list ? list[v0] : (int)v0;
         const int t = T[v];
         if (t <= lo || t > hi) continue;  // the same for every lane of the wavefront
         // table of at least 2T slots (a power of two, at most TAB): at most
@@ -98,22 +119,27 @@ __global__ __launch_bounds__(WPB *kWave) void k_sq_rows(const int32_t *__restric
             }
             const int excl = incl - len;
             const int total = __shfl(incl, kWave - 1);
-            for (int t0 = 0; t0 < total; t0 += kWave) {
-                const int q = t0 + lane;
-                // the neighbour whose row holds entry q of the concatenation:
-                // the last lane k with excl(k) <= q (every lane takes part in
-                // the shuffles)
-                int k = 0;
+            constexpr int kIn = 4;  // steps of 64 entries whose loads are in flight together
+            for (int t0 = 0; t0 < total; t0 += kIn * kWave) {
+                int w[kIn];
 #pragma unroll
-                for (int step = kWave / 2; step > 0; step >>= 1) {
-                    const int cand = __shfl(excl, k + step);
-                    if (cand <= q) k += step;
+                for (int r = 0; r < kIn; ++r) {
+                    const int q = t0 + r * kWave + lane;
+                    // the neighbour whose row holds entry q of the
+                    // concatenation: the last lane k with excl(k) <= q (every
+                    // lane takes part in the shuffles)
+                    int k = 0;
+#pragma unroll
+                    for (int step = kWave / 2; step > 0; step >>= 1) {
+                        const int cand = __shfl(excl, k + step);
+                        if (cand <= q) k += step;
+                    }
+                    const int rbk = __shfl(rb, k), ek = __shfl(excl, k);
+                    w[r] = q < total ? cig[rbk + (q - ek)] : v;
                 }
-                const int rbk = __shfl(rb, k), ek = __shfl(excl, k);
-                if (q < total) {
-                    const int w = cig[rbk + (q - ek)];
-                    if (w != v) fresh += sq_insert(tab, mask, shift, w);
-                }
+#pragma unroll
+                for (int r = 0; r < kIn; ++r)
+                    if (w[r] != v) fresh += sq_insert(tab, mask, shift, w[r]);
             }
         }
         wave_lds_sync();
