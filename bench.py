@@ -287,47 +287,48 @@ def bench_single(args):
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "kernel_ms": kms, "alg_bytes_per_launch": kbytes},
     }
-    # colour classes of the colouring just made (its independent sets, one per
-    # colour, ids ascending): read colours, write ids and class starts
-    K = st["colors"]
-    d_ptr = torch.empty(K + 1, dtype=torch.int32, device=dev)
-    d_vtx = torch.empty(n, dtype=torch.int32, device=dev)
-    rsoc.rsoc_color_classes(ctx, d_col, n, K, d_ptr, d_vtx, stream=stream)
-    torch.cuda.synchronize()
-    reps = max(3, args.steps // 2)
-    tc = time.perf_counter()
-    for _ in range(reps):
+    if not args.no_extras:
+        # colour classes of the colouring just made (its independent sets, one per
+        # colour, ids ascending): read colours, write ids and class starts
+        K = st["colors"]
+        d_ptr = torch.empty(K + 1, dtype=torch.int32, device=dev)
+        d_vtx = torch.empty(n, dtype=torch.int32, device=dev)
         rsoc.rsoc_color_classes(ctx, d_col, n, K, d_ptr, d_vtx, stream=stream)
-    torch.cuda.synchronize()
-    tc = (time.perf_counter() - tc) / reps
-    ptr, vtx = d_ptr.cpu().numpy(), d_vtx.cpu().numpy()
-    if not (ptr[0] == 0 and ptr[-1] == n and np.all(np.diff(ptr) >= 0)
-            and np.all(col[vtx] == np.repeat(np.arange(K), np.diff(ptr)))):
-        raise SystemExit("bench: colour classes inconsistent with the colouring")
-    cls_bytes = 8 * n + 4 * (K + 1)
-    out["color_classes"] = {"ms": tc * 1e3, "classes": K, "alg_bytes": cls_bytes,
-                            "GBps": cls_bytes / tc / 1e9, "frac_hbm": cls_bytes / tc / 1e9 / HBM_PEAK_GBS}
-    # distance-2 colouring of the same graph (G^2 built on the device, then
-    # the same rounds); timed end to end, the build of G^2 included
-    out["distance2"] = bench_distance2(args, rsoc, ctx, d_rp, d_ci, n, E, stream)
-    # recolouring after topology edits: random edges inserted (both endpoints
-    # touched), starting from the colouring just made
-    out["recolor_after_edits"] = bench_recolor(args, rsoc, ctx, rp, ci, col, stream, elapsed / args.steps)
-    if args.mode == "optimistic":
-        # the literal reading (round 0 over all neighbours, round 1 over all of V)
-        o3 = rsoc.make_options("optimistic", "lower", timing=1, full_sweep=1)
-        rsoc.rsoc_color_device(ctx, d_rp, d_ci, n, d_col, o3, stream=stream)
         torch.cuda.synchronize()
-        tf = time.perf_counter()
-        reps = max(1, args.steps // 4)
+        reps = max(3, args.steps // 2)
+        tc = time.perf_counter()
         for _ in range(reps):
-            kf, sf = rsoc.rsoc_color_device(ctx, d_rp, d_ci, n, d_col, o3, stream=stream)
+            rsoc.rsoc_color_classes(ctx, d_col, n, K, d_ptr, d_vtx, stream=stream)
         torch.cuda.synchronize()
-        tf = (time.perf_counter() - tf) / reps
-        out["full_sweep"] = {"GEps": E / tf / 1e9, "colors": kf, "rounds": sf["rounds"], "conflicts": sf["conflicts"],
-                             "ms_round0": sf["ms_round0"], "ms_round1": sf["ms_round1"]}
-        if not colouring_valid(rp, ci, d_col.cpu().numpy()):
-            raise SystemExit("bench: invalid colouring produced (full sweep)")
+        tc = (time.perf_counter() - tc) / reps
+        ptr, vtx = d_ptr.cpu().numpy(), d_vtx.cpu().numpy()
+        if not (ptr[0] == 0 and ptr[-1] == n and np.all(np.diff(ptr) >= 0)
+                and np.all(col[vtx] == np.repeat(np.arange(K), np.diff(ptr)))):
+            raise SystemExit("bench: colour classes inconsistent with the colouring")
+        cls_bytes = 8 * n + 4 * (K + 1)
+        out["color_classes"] = {"ms": tc * 1e3, "classes": K, "alg_bytes": cls_bytes,
+                                "GBps": cls_bytes / tc / 1e9, "frac_hbm": cls_bytes / tc / 1e9 / HBM_PEAK_GBS}
+        # distance-2 colouring of the same graph (G^2 built on the device, then
+        # the same rounds); timed end to end, the build of G^2 included
+        out["distance2"] = bench_distance2(args, rsoc, ctx, d_rp, d_ci, n, E, stream)
+        # recolouring after topology edits: random edges inserted (both endpoints
+        # touched), starting from the colouring just made
+        out["recolor_after_edits"] = bench_recolor(args, rsoc, ctx, rp, ci, col, stream, elapsed / args.steps)
+        if args.mode == "optimistic":
+            # the literal reading (round 0 over all neighbours, round 1 over all of V)
+            o3 = rsoc.make_options("optimistic", "lower", timing=1, full_sweep=1)
+            rsoc.rsoc_color_device(ctx, d_rp, d_ci, n, d_col, o3, stream=stream)
+            torch.cuda.synchronize()
+            tf = time.perf_counter()
+            reps = max(1, args.steps // 4)
+            for _ in range(reps):
+                kf, sf = rsoc.rsoc_color_device(ctx, d_rp, d_ci, n, d_col, o3, stream=stream)
+            torch.cuda.synchronize()
+            tf = (time.perf_counter() - tf) / reps
+            out["full_sweep"] = {"GEps": E / tf / 1e9, "colors": kf, "rounds": sf["rounds"], "conflicts": sf["conflicts"],
+                                 "ms_round0": sf["ms_round0"], "ms_round1": sf["ms_round1"]}
+            if not colouring_valid(rp, ci, d_col.cpu().numpy()):
+                raise SystemExit("bench: invalid colouring produced (full sweep)")
     if args.det_too and args.mode == "optimistic":
         o2 = rsoc.make_options("deterministic", "lower", timing=0)
         rsoc.rsoc_color_device(ctx, d_rp, d_ci, n, d_col, o2, stream=stream)
@@ -612,6 +613,8 @@ def main():
     ap.add_argument("--mode", default="optimistic", choices=["optimistic", "deterministic", "two_phase"])
     ap.add_argument("--seed", type=int, default=1505)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="only the colouring (no colour classes, recolouring, distance-2 or literal-flow runs)")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--det-too", action="store_true", help="also time deterministic mode once")
     ap.add_argument("--batch-graphs", type=int, default=4096)

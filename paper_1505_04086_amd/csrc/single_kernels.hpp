@@ -81,10 +81,19 @@ __global__ __launch_bounds__(kHeadBlock) void k_head_out(const SingleArgs *__res
     if (len > 0) {
         int32_t *const flags = A->flags + 255;
         int cnt = 0;
-        for (int64_t i = threadIdx.x; i < len; i += kHeadBlock) {
-            const int f = flags[i];
-            cnt += f;
-            if (f) flags[i] = 0;
+        constexpr int kIn = 8;  // loads in flight per lane
+        for (int64_t i0 = threadIdx.x; i0 < len; i0 += (int64_t)kIn * kHeadBlock) {
+            int f[kIn];
+#pragma unroll
+            for (int k = 0; k < kIn; ++k) {
+                const int64_t i = i0 + (int64_t)k * kHeadBlock;
+                f[k] = i < len ? flags[i] : 0;
+            }
+#pragma unroll
+            for (int k = 0; k < kIn; ++k) {
+                cnt += f[k];
+                if (f[k]) flags[i0 + (int64_t)k * kHeadBlock] = 0;
+            }
         }
         for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
         if (lane_id() == 0) sh[threadIdx.x / kWave] = cnt;

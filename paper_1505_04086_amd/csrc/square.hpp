@@ -29,6 +29,11 @@ inline int32_t build_square(rsoc_ctx *c, const int32_t *rp, const int32_t *ci, i
     RSOC_HIP(hipMemsetAsync(c->sq_misc.p, 0, 16, s));
     const int g = std::min(div_up(n, kBlock), 4096);
     k_sq_size<<<std::min(div_up(n, kBlock / 8), 8192), kBlock, 0, s>>>(rp, ci, n, T, err, big, nbig);
+    // a walk over the limit ends it here, before the expensive passes
+    RSOC_LAUNCH_CHECK();
+    RSOC_HIP(hipMemcpyAsync(&h->sq_total, c->sq_misc.p, 16, hipMemcpyDeviceToHost, s));
+    RSOC_HIP(hipStreamSynchronize(s));
+    if (h->sq_err) return RSOC_EINVAL;
     // count pass: rows with T <= kSqSmallT four wavefronts a workgroup, the
     // listed rest one wavefront each with a larger table
     k_sq_rows<4, kSqSmallTab, false><<<std::min(div_up(n, 4), 65536), 4 * kWave, 0, s>>>(
