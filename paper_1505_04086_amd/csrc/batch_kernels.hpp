@@ -238,7 +238,7 @@ __global__ __launch_bounds__(kBlock) void k_bround(const BatchArgs *__restrict__
             const int b = w.rp[v], e = w.rp[v + 1];
             int nc = 0;
             bool unc = false;
-            const bool act = block_vertex<PHASE, TIE, kWinOnly>(v, b, e, w.ci, w.col, lds, &sh_min, a.look, nc, unc);
+            const bool act = block_vertex<PHASE, TIE, kWinOnly>(v, b, e, w.ci, w.col, w.col8, lds, &sh_min, a.look, nc, unc);
             const bool take = (kFlagAppend ? unc : act) && kAppend;
             if (threadIdx.x == 0) {
                 items += 1;
@@ -267,7 +267,7 @@ __global__ __launch_bounds__(kBlock) void k_bround(const BatchArgs *__restrict__
             const int b = w.rp[v], e = w.rp[v + 1];
             int nc = 0;
             bool unc = false;
-            const bool act = wave_vertex<PHASE, TIE, kWinOnly>(v, b, e, w.ci, w.col, bm, a.look, nc, unc);
+            const bool act = wave_vertex<PHASE, TIE, kWinOnly>(v, b, e, w.ci, w.col, w.col8, bm, a.look, nc, unc);
             if (lane_id() == 0) {
                 items += 1;
                 degs += (uint64_t)(e - b);

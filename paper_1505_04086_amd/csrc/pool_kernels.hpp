@@ -290,7 +290,7 @@ __device__ __forceinline__ void pool_wave_task(PoolSlot *sp, const PoolSlot &s, 
         const int b = s.rp[v], e = s.rp[v + 1];
         int nc = 0;
         bool unc = false;
-        const bool act = wave_vertex<PHASE, TIE, kWinOnly>(v, b, e, gro(s.ci), gro(s.col), bm, s.look, nc, unc);
+        const bool act = wave_vertex<PHASE, TIE, kWinOnly>(v, b, e, gro(s.ci), gro(s.col), gro(s.col8), bm, s.look, nc, unc);
         if (lane_id() == 0 && act) {
             (opt ? s.col : s.pend)[v] = nc;
             if (opt) s.col8[v] = shadow_of(nc);
@@ -314,7 +314,7 @@ __device__ __forceinline__ void pool_block_task(PoolSlot *sp, const PoolSlot &s,
         const int b = s.rp[v], e = s.rp[v + 1];
         int nc = 0;
         bool unc = false;
-        const bool act = block_vertex<PHASE, TIE, kWinOnly>(v, b, e, gro(s.ci), gro(s.col), lds, sh_min, s.look, nc,
+        const bool act = block_vertex<PHASE, TIE, kWinOnly>(v, b, e, gro(s.ci), gro(s.col), gro(s.col8), lds, sh_min, s.look, nc,
                                                               unc);
         if (threadIdx.x == 0) {
             if (act) {

@@ -524,7 +524,7 @@ __global__ __launch_bounds__(kBlock) void k_round(const SingleArgs *__restrict__
             const int b = rp[v], e = rp[v + 1];
             int nc = 0;
             bool unc = false;
-            const bool act = block_vertex<PHASE, TIE, kWinOnly>(v, b, e, ci, rcol, lds, &sh_min, a.look, nc, unc);
+            const bool act = block_vertex<PHASE, TIE, kWinOnly>(v, b, e, ci, rcol, rcol8, lds, &sh_min, a.look, nc, unc);
             const bool take = (kFlagAppend ? unc : act) && kAppend;
             if (threadIdx.x == 0) {
                 items += 1;
@@ -553,7 +553,7 @@ __global__ __launch_bounds__(kBlock) void k_round(const SingleArgs *__restrict__
             const int b = rp[v], e = rp[v + 1];
             int nc = 0;
             bool unc = false;
-            const bool act = wave_vertex<PHASE, TIE, kWinOnly>(v, b, e, ci, rcol, bm, a.look, nc, unc);
+            const bool act = wave_vertex<PHASE, TIE, kWinOnly>(v, b, e, ci, rcol, rcol8, bm, a.look, nc, unc);
             if (lane_id() == 0) {
                 items += 1;
                 degs += (uint64_t)(e - b);

@@ -241,63 +241,148 @@ __device__ __forceinline__ bool lane_detect_kept(int v, int4 x, int cv, const RS
     return def;
 }
 
-// -------------------------------------------------------------- wavefront --
-// One wavefront per vertex: lanes stride the row (coalesced, four chunks of 64
-// entries in flight per ballot), the conflict flag is a ballot, and the
-// forbidden colours go into a per-wavefront LDS bitmap window of
-// kWaveWindowBits bits, scanned for its first clear bit with ballots.
-// Returns the same value in every lane; newc valid in every lane.
+// Colours of long rows (wavefront and workgroup shapes) are gathered from the
+// byte shadow col8 (min(colour, 255); 4 bytes per vertex less to pull through
+// L2 than col), and from col only where the shadow saturates (255: uncoloured,
+// or 255 and above).  Entries with take[s] false read as uncoloured (-1).
+// LOOSE (round 0 over the neighbours v loses to, optimistic): a saturated
+// shadow reads as uncoloured without the second load.  Round 0 may read any
+// neighbour before it is coloured, so this is one of its interleavings: First-Fit
+// ignores that neighbour and, if v loses to it, v enters U^0 with it.
+template <bool LOOSE, int U>
+__device__ __forceinline__ void hub_gather(const int (&u)[U], const bool (&take)[U], const RSOC_GLOBAL int32_t *col,
+                                           const RSOC_GLOBAL uint8_t *col8, int (&x)[U]) {
+    int y[U];
+#pragma unroll
+    for (int s = 0; s < U; ++s) y[s] = take[s] ? (int)col8[u[s]] : -1;
+#pragma unroll
+    for (int s = 0; s < U; ++s) x[s] = (y[s] == 255) ? (LOOSE ? -1 : col[u[s]]) : y[s];
+}
+
+// Row entries each lane of a wavefront or workgroup holds per step: all the
+// loads of a step are in flight together, and so are its gathers.
+constexpr int kWaveSlots = 8;
+constexpr int kBlockSlots = 8;
+
+// ------------------------------------------------------------- wavefront --
+// One wavefront per vertex: lanes stride the row kWaveSlots entries at a time;
+// forbidden colours go into an LDS bitmap window of kWaveWindowBits bits.
+// Rows of at most kWaveSlots * kWave entries (every row of the default bins)
+// are read once: the detection keeps the row and the colours it gathered, and
+// the recolouring gathers only the remaining neighbours' colours.  Its colour
+// is at most its degree, below the window, so one window pass settles it.
 template <int PHASE, int TIE, bool WIN_ONLY>
 __device__ __forceinline__ bool wave_vertex(int v, int b, int e, const RSOC_GLOBAL int32_t *ci,
-                                            const RSOC_GLOBAL int32_t *col, uint32_t *bm, int look, int &newc,
-                                            bool &unc_win) {
+                                            const RSOC_GLOBAL int32_t *col, const RSOC_GLOBAL uint8_t *col8,
+                                            uint32_t *bm, int look, int &newc, bool &unc_win) {
     const int lane = lane_id();
-    constexpr int U = 4;
+    constexpr int U = kWaveSlots;
+    constexpr bool kLoose = PHASE == kAssign && WIN_ONLY;
+    static_assert(kWaveSlots * kWave <= kWaveWindowBits, "a one-step row must fit the window");
+    if (e - b <= U * kWave) {
+        int u[U], x[U];
+        bool w[U];
+#pragma unroll
+        for (int s = 0; s < U; ++s) {
+            const int j = b + s * kWave + lane;
+            u[s] = (j < e) ? __builtin_nontemporal_load(ci + j) : v;
+        }
+#pragma unroll
+        for (int s = 0; s < U; ++s) w[s] = (u[s] != v) && loses<TIE>(v, u[s]);
+        if (PHASE != kAssign) {
+            const int cv = col[v];
+            hub_gather<false, U>(u, w, col, col8, x);
+            bool c = false;
+#pragma unroll
+            for (int s = 0; s < U; ++s) c |= w[s] && x[s] == cv;
+            const bool any = cv < 0 || cv > e - b || ballot(c) != 0;
+            if (!any) return false;
+            if (PHASE == kDetect) return true;
+            bool r[U];
+            int x2[U];
+#pragma unroll
+            for (int s = 0; s < U; ++s) r[s] = (u[s] != v) && !w[s];
+            hub_gather<false, U>(u, r, col, col8, x2);
+#pragma unroll
+            for (int s = 0; s < U; ++s)
+                if (r[s]) x[s] = x2[s];
+        } else {
+            bool take[U];
+#pragma unroll
+            for (int s = 0; s < U; ++s) {
+                const int dist = u[s] > v ? u[s] - v : v - u[s];
+                take[s] = WIN_ONLY ? (w[s] || (u[s] != v && dist < look)) : (u[s] != v);
+            }
+            hub_gather<kLoose, U>(u, take, col, col8, x);
+            bool unc = false;
+#pragma unroll
+            for (int s = 0; s < U; ++s) unc |= w[s] && x[s] < 0;
+            unc_win = ballot(unc) != 0;
+        }
+        for (int q = lane; q < kWaveWindowWords; q += kWave) bm[q] = 0u;
+        wave_lds_sync();
+#pragma unroll
+        for (int s = 0; s < U; ++s)
+            if (x[s] >= 0 && x[s] < kWaveWindowBits) lds_or(&bm[x[s] >> 5], 1u << (x[s] & 31));
+        wave_lds_sync();
+        // at most e - b <= kWaveSlots * kWave bits are set, so a clear one
+        // lies within the first kWave words
+        const uint32_t word = bm[lane];
+        const uint64_t m = ballot(word != 0xffffffffu);
+        const int l = __ffsll((unsigned long long)m) - 1;
+        const uint32_t wl = __shfl(word, l);
+        newc = l * 32 + __builtin_ctz(~wl);
+        wave_lds_sync();
+        return true;
+    }
+    // longer rows (a wavefront bin raised past kWaveSlots * kWave): one pass
+    // for the detection, then a pass per colour window
     bool unc = false;
     if (PHASE != kAssign) {
         const int cv = col[v];
         bool any = cv < 0 || cv > e - b;  // no valid First-Fit colour: defective
         for (int j0 = b; j0 < e && !any; j0 += U * kWave) {
-            int u[U];
+            int u[U], x[U];
+            bool w[U];
 #pragma unroll
             for (int s = 0; s < U; ++s) {
                 const int j = j0 + s * kWave + lane;
-                u[s] = (j < e) ? ci[j] : v;
+                u[s] = (j < e) ? __builtin_nontemporal_load(ci + j) : v;
             }
+#pragma unroll
+            for (int s = 0; s < U; ++s) w[s] = (u[s] != v) && loses<TIE>(v, u[s]);
+            hub_gather<false, U>(u, w, col, col8, x);
             bool c = false;
 #pragma unroll
-            for (int s = 0; s < U; ++s) {
-                const bool w = (u[s] != v) && loses<TIE>(v, u[s]);
-                c |= w && (col[u[s]] == cv);
-            }
+            for (int s = 0; s < U; ++s) c |= w[s] && x[s] == cv;
             any = ballot(c) != 0;
         }
         if (!any) return false;
         if (PHASE == kDetect) return true;
     }
     for (int base = 0;; base += kWaveWindowBits) {
-        for (int w = lane; w < kWaveWindowWords; w += kWave) bm[w] = 0u;
+        for (int q = lane; q < kWaveWindowWords; q += kWave) bm[q] = 0u;
         wave_lds_sync();
         for (int j0 = b; j0 < e; j0 += U * kWave) {
-            int u[U];
+            int u[U], x[U];
+            bool take[U], w[U];
 #pragma unroll
             for (int s = 0; s < U; ++s) {
                 const int j = j0 + s * kWave + lane;
-                u[s] = (j < e) ? ci[j] : v;
+                u[s] = (j < e) ? __builtin_nontemporal_load(ci + j) : v;
             }
-            int c[U];
 #pragma unroll
             for (int s = 0; s < U; ++s) {
-                const bool win = (u[s] != v) && loses<TIE>(v, u[s]);
+                w[s] = (u[s] != v) && loses<TIE>(v, u[s]);
                 const int dist = u[s] > v ? u[s] - v : v - u[s];
-                const bool take = (PHASE == kAssign && WIN_ONLY) ? (win || (u[s] != v && dist < look)) : (u[s] != v);
-                c[s] = take ? col[u[s]] : -1;
-                if (PHASE == kAssign) unc |= win && c[s] < 0;
+                take[s] = (PHASE == kAssign && WIN_ONLY) ? (w[s] || (u[s] != v && dist < look)) : (u[s] != v);
             }
+            hub_gather<kLoose, U>(u, take, col, col8, x);
 #pragma unroll
             for (int s = 0; s < U; ++s) {
-                const int rel = c[s] - base;
-                if (c[s] >= 0 && (unsigned)rel < (unsigned)kWaveWindowBits) lds_or(&bm[rel >> 5], 1u << (rel & 31));
+                if (PHASE == kAssign) unc |= w[s] && x[s] < 0;
+                const int rel = x[s] - base;
+                if (x[s] >= 0 && (unsigned)rel < (unsigned)kWaveWindowBits) lds_or(&bm[rel >> 5], 1u << (rel & 31));
             }
         }
         if (PHASE == kAssign) unc_win = ballot(unc) != 0;
@@ -318,73 +403,75 @@ __device__ __forceinline__ bool wave_vertex(int v, int b, int e, const RSOC_GLOB
 }
 
 // -------------------------------------------------------------- workgroup --
-// One workgroup per vertex (hubs): threads stride the row, the conflict flag
-// is a workgroup OR, forbidden colours go into an LDS bitmap window of
-// kBlockWindowBits bits; the first clear word is found with an LDS atomicMin.
-// Must be called by the whole workgroup; newc valid in every thread.
+// One workgroup per vertex (hubs): threads stride the row kBlockSlots entries
+// at a time, the conflict flag is a workgroup OR per step, forbidden colours
+// go into an LDS bitmap window of kBlockWindowBits bits; the first clear word
+// is found with an LDS atomicMin.  Must be called by the whole workgroup;
+// newc valid in every thread.
 template <int PHASE, int TIE, bool WIN_ONLY>
 __device__ __forceinline__ bool block_vertex(int v, int b, int e, const RSOC_GLOBAL int32_t *ci,
-                                             const RSOC_GLOBAL int32_t *col, uint32_t *bm, int *sh_min, int look,
-                                             int &newc, bool &unc_win) {
+                                             const RSOC_GLOBAL int32_t *col, const RSOC_GLOBAL uint8_t *col8,
+                                             uint32_t *bm, int *sh_min, int look, int &newc, bool &unc_win) {
     const int t = threadIdx.x;
-    constexpr int U = 4;
+    constexpr int U = kBlockSlots;
+    constexpr bool kLoose = PHASE == kAssign && WIN_ONLY;
     bool unc = false;
     if (PHASE != kAssign) {
         const int cv = col[v];
         int any = cv < 0 || cv > e - b;  // no valid First-Fit colour: defective
-        for (int j0 = b; j0 < e && !any; j0 += kBlock * U * 4) {
-            bool c = false;
-            const int j1 = min(e, j0 + kBlock * U * 4);
-            for (int jj = j0; jj < j1; jj += kBlock * U) {
-                int u[U];
+        for (int j0 = b; j0 < e && !any; j0 += kBlock * U) {
+            int u[U], x[U];
+            bool w[U];
 #pragma unroll
-                for (int s = 0; s < U; ++s) {
-                    const int j = jj + s * kBlock + t;
-                    u[s] = (j < j1) ? ci[j] : v;
-                }
-#pragma unroll
-                for (int s = 0; s < U; ++s) c |= (u[s] != v) && loses<TIE>(v, u[s]) && (col[u[s]] == cv);
+            for (int s = 0; s < U; ++s) {
+                const int j = j0 + s * kBlock + t;
+                u[s] = (j < e) ? __builtin_nontemporal_load(ci + j) : v;
             }
+#pragma unroll
+            for (int s = 0; s < U; ++s) w[s] = (u[s] != v) && loses<TIE>(v, u[s]);
+            hub_gather<false, U>(u, w, col, col8, x);
+            bool c = false;
+#pragma unroll
+            for (int s = 0; s < U; ++s) c |= w[s] && x[s] == cv;
             any = __syncthreads_or(c);
-            if (any) break;
         }
         if (!any) return false;
         if (PHASE == kDetect) return true;
     }
     for (int base = 0;; base += kBlockWindowBits) {
-        for (int w = t; w < kBlockWindowWords; w += kBlock) bm[w] = 0u;
+        for (int q = t; q < kBlockWindowWords; q += kBlock) bm[q] = 0u;
         if (t == 0) *sh_min = INT_MAX;
         __syncthreads();
         for (int j0 = b; j0 < e; j0 += kBlock * U) {
-            int u[U];
+            int u[U], x[U];
+            bool take[U], w[U];
 #pragma unroll
             for (int s = 0; s < U; ++s) {
                 const int j = j0 + s * kBlock + t;
-                u[s] = (j < e) ? ci[j] : v;
+                u[s] = (j < e) ? __builtin_nontemporal_load(ci + j) : v;
             }
-            int c[U];
 #pragma unroll
             for (int s = 0; s < U; ++s) {
-                const bool win = (u[s] != v) && loses<TIE>(v, u[s]);
+                w[s] = (u[s] != v) && loses<TIE>(v, u[s]);
                 const int dist = u[s] > v ? u[s] - v : v - u[s];
-                const bool take = (PHASE == kAssign && WIN_ONLY) ? (win || (u[s] != v && dist < look)) : (u[s] != v);
-                c[s] = take ? col[u[s]] : -1;
-                if (PHASE == kAssign) unc |= win && c[s] < 0;
+                take[s] = (PHASE == kAssign && WIN_ONLY) ? (w[s] || (u[s] != v && dist < look)) : (u[s] != v);
             }
+            hub_gather<kLoose, U>(u, take, col, col8, x);
 #pragma unroll
             for (int s = 0; s < U; ++s) {
-                const int rel = c[s] - base;
-                if (c[s] >= 0 && (unsigned)rel < (unsigned)kBlockWindowBits) lds_or(&bm[rel >> 5], 1u << (rel & 31));
+                if (PHASE == kAssign) unc |= w[s] && x[s] < 0;
+                const int rel = x[s] - base;
+                if (x[s] >= 0 && (unsigned)rel < (unsigned)kBlockWindowBits) lds_or(&bm[rel >> 5], 1u << (rel & 31));
             }
         }
         if (PHASE == kAssign) unc_win = __syncthreads_or(unc) != 0;
         __syncthreads();
-        for (int w = t; w < kBlockWindowWords; w += kBlock)
-            if (bm[w] != 0xffffffffu) { atomicMin(sh_min, w); break; }
+        for (int q = t; q < kBlockWindowWords; q += kBlock)
+            if (bm[q] != 0xffffffffu) { atomicMin(sh_min, q); break; }
         __syncthreads();
-        const int w = *sh_min;
-        if (w != INT_MAX) {
-            newc = base + w * 32 + __builtin_ctz(~bm[w]);
+        const int q = *sh_min;
+        if (q != INT_MAX) {
+            newc = base + q * 32 + __builtin_ctz(~bm[q]);
             __syncthreads();
             return true;
         }
