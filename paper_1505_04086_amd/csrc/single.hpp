@@ -433,7 +433,9 @@ inline int32_t run_single(rsoc_ctx *c, const int32_t *rp, const int32_t *ci, int
     // colour count (K = max + 1) and distinct colours: the statistics close
     // every replay, so the one host check per replay also brings them; they
     // count once the worklist is empty
-    const int gstat = std::min(div_up(n, 16 * kBlock), 2048);
+    // four 16-byte loads in flight per lane; few workgroups, so that their
+    // merges into the shared statistics words stay few
+    const int gstat = std::min(div_up(n, 16 * 4 * kBlock), 512);
     RSOC_TRY(get_round_graph(c, o.mode, o.tie, o.rounds_per_sync, gBl, gWl, gTl, gstat, &gexec));
 
     int32_t status = RSOC_OK;

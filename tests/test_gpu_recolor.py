@@ -116,6 +116,34 @@ def test_recolor_large_lattice(lib, ctx):
         assert st["worklist0"] <= len(touched) + 100 + 4000
 
 
+def _spider(leaves, tie):
+    """A hub joined to `leaves` leaves; the hub loses every tie (highest id
+    under lower-keeps, id 0 under higher-keeps)."""
+    n = leaves + 1
+    hub = n - 1 if tie == "lower" else 0
+    others = np.array([v for v in range(n) if v != hub], np.int64)
+    e = np.stack([np.full(leaves, hub, np.int64), others], axis=1)
+    rp, ci = gg.from_edges(n, e)
+    return rp, ci, hub, others
+
+
+@pytest.mark.parametrize("top", [1000, 5000])
+@pytest.mark.parametrize("tie", ["lower", "higher"])
+@pytest.mark.parametrize("mode", ["deterministic", "optimistic"])
+def test_recolor_hub_high_colour(lib, ctx, mode, tie, top):
+    """A 5000-leaf hub (workgroup bin) whose leaves hold colours 0..top-1
+    (cycling) and whose own colour clashes with a leaf it loses to: its
+    First-Fit answer is top, beyond the wavefront window (4096 colours) and,
+    for top = 5000, beyond every colour the byte shadow can hold."""
+    rp, ci, hub, others = _spider(5000, tie)
+    prev = np.zeros(len(rp) - 1, np.int32)
+    prev[others] = np.arange(len(others)) % top
+    prev[hub] = 0
+    print("case", mode, tie, top, flush=True)
+    st = _check(lib, ctx, rp, ci, prev, [hub], mode, tie)
+    assert st["rounds"] >= 1
+
+
 def test_recolor_errors(lib, ctx):
     import torch
     rp, ci = gg.cycle(8)
