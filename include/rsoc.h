@@ -102,8 +102,9 @@ typedef struct {
     int32_t full_sweep;
     /* Optimistic default flow: round 0 also reads neighbours it wins against
      * whose id is within this distance (the sweep may have coloured them
-     * already).  0 = library default (the ids all workgroups cover in one step; for batches twice that),
-     * -1 = none. */
+     * already).  0 = library default: none where the ids carry no locality
+     * (run length 1), else the ids all workgroups cover in one step; for
+     * batches twice that.  -1 = none. */
     int32_t lookahead;
     /* Run of consecutive vertex ids one 8-lane group colours one after the
      * other in sweeps (1, 2, 4 or 8).  0 = chosen per graph from a sample of

@@ -347,6 +347,7 @@ inline int32_t run_single(rsoc_ctx *c, const int32_t *rp, const int32_t *ci, int
     if (gTs >= kXcds) gTs -= gTs % kXcds;
     const int64_t look = o.lookahead == -1 ? 0 : (o.lookahead > 0 ? o.lookahead : (int64_t)gTs * kStep);
     a.look = (int)std::min<int64_t>(look, INT32_MAX);
+    a.look_auto = o.lookahead == 0 ? 1 : 0;
     a.chunk = inc ? 1 : o.chunk;  // 0: k_args picks it from the locality sample
     a.flags = c->flags.as<int32_t>();
     k_setup<<<1, kBlock, 0, s>>>(c->args.as<SingleArgs>(), a, S, (int)(kStateHeader / 4), 1);

@@ -35,6 +35,7 @@ struct SingleArgs {
     int32_t offW, offB;  // segment offsets inside wl buffers
     int32_t look;        // round-0 lookahead (ids within `look` of v are read even when v wins against them)
     int32_t chunk;       // run of consecutive ids one lane group walks (1, 2, 4 or 8)
+    int32_t look_auto;   // look is the default: k_args sets it to 0 once chunk turns out 1
     int32_t *flags;      // flags[c] for colours c >= 255 in use (zero between calls)
 };
 
@@ -267,6 +268,10 @@ __global__ void k_args(SingleArgs *A, SingleState *S, SingleState *dst, int32_t 
             A->offB = nv - S->nB;
             A->chunk = pick_chunk(A->chunk, S->near, S->sampled);
             S->chunk = A->chunk;
+            // ids without locality: a neighbour v wins against is seldom
+            // coloured before v (the sweep's band is gT * kSub ids wide), so by
+            // default round 0 reads none of them
+            if (A->look_auto && A->chunk == 1) A->look = 0;
             if (A->ci == nullptr && S->nnz > 0) S->err |= 8;
         }
         __syncthreads();
@@ -630,14 +635,18 @@ __global__ __launch_bounds__(kBlock) void k_round(const SingleArgs *__restrict__
             if (threadIdx.x == 0) qn = 0;
             __syncthreads();
         }
-        // A sweep gives each workgroup step kStep ids, walked as runs in
-        // order.  A worklist has no order to keep and is often short after
-        // round 1, so there a step is kSub entries: the list spreads over the
-        // whole grid instead of a few workgroups walking kChunk dependent
-        // sub-steps each.
-        constexpr int kUnit = SWEEP ? kStep : kSub;
-        constexpr int kRuns = SWEEP ? kChunk : 1;
+        // A sweep over ids with locality (chunk c > 1) gives each workgroup
+        // step kStep ids, walked as runs of c in order.  Over ids without
+        // locality (c = 1) a step is one sub-step of kSub ids: the grid then
+        // sweeps a band of gT * kSub ids at a time, not gT * kStep, so a
+        // vertex finds far fewer of the lower ids it reads still uncoloured
+        // (round 0 collects fewer vertices into U^0).  A worklist has no
+        // order to keep and is often short after round 1, so there a step is
+        // kSub entries too: the list spreads over the whole grid instead of a
+        // few workgroups walking kChunk dependent sub-steps each.
         const int c = SWEEP ? a.chunk : 1;
+        const int kRuns = c > 1 ? kChunk : 1;
+        const int kUnit = c > 1 ? kStep : kSub;
         const int64_t stride = (int64_t)gT * kUnit;
         for (int64_t base = (int64_t)tb * kUnit; base < cT; base += stride) {
             for (int r = 0; r < kRuns; ++r) {

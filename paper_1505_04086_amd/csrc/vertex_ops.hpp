@@ -171,13 +171,12 @@ __device__ __forceinline__ void group_vertices(const int (&v)[NV], const int (&b
                 const int dist = u[i][s] > v[i] ? u[i][s] - v[i] : v[i] - u[i][s];
                 take[s] = WIN_ONLY ? (win[s] || (u[i][s] != v[i] && dist < look)) : (u[i][s] != v[i]);
             }
-            // WIN_ONLY reads take a nibble of 15 as uncoloured, without the
-            // byte-shadow fallback: a colour of 15 or more then looks as if v
-            // had read u before u was coloured, an interleaving the round
-            // allows anyway (u gets v's unc bit if v loses to it)
+            // a nibble of 15 (colour 15 or more, or none yet) is settled from
+            // the byte shadow: otherwise every neighbour v loses to with a
+            // colour of 15 or more would look uncoloured and send v to U^0
             bool exact[T];
 #pragma unroll
-            for (int s = 0; s < T; ++s) exact[s] = !WIN_ONLY && take[s];
+            for (int s = 0; s < T; ++s) exact[s] = take[s];
             gather_colours<NIB, T>(u[i], take, exact, col8[i], NIB ? col4[i] : nullptr, cu[i]);
             uint32_t bits = 0;
 #pragma unroll
