@@ -351,7 +351,10 @@ inline int32_t run_single(rsoc_ctx *c, const int32_t *rp, const int32_t *ci, int
     a.chunk = inc ? 1 : o.chunk;  // 0: k_args picks it from the locality sample
     a.flags = c->flags.as<int32_t>();
     k_setup<<<1, kBlock, 0, s>>>(c->args.as<SingleArgs>(), a, S, (int)(kStateHeader / 4), 1);
-    const int vgrid = std::min(div_up(n, kBlock), 4096);
+    // binning: each workgroup ends with one global atomic per non-empty hub
+    // queue, so fewer, longer-running workgroups (power-law graphs fill the
+    // queues of nearly every workgroup)
+    const int vgrid = std::min(div_up(n, kBlock), 1024);
     // binning (reads row_ptr only: also checks its ends and publishes nnz),
     // with the id-locality sample in extra workgroups unless the CSR is to be
     // validated first (the sample reads rows)
