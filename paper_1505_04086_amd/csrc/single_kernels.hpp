@@ -70,7 +70,7 @@ constexpr size_t kStateHeader = offsetof(SingleState, hist);
 static_assert(kStateHeader % 4 == 0, "header copied as 32-bit words");
 
 // Closes a round graph (one workgroup): counts the flags k_colour_stats set
-// for colours 255 .. min(max degree, n - 1) into S->distinct and clears them,
+// for colours 255 .. min(max degree, n - 1, kmax - 1) into S->distinct and clears them,
 // then copies the state header (and |L| of the first recolouring round) into
 // the host's pinned staging, from the device, so that no copy command follows
 // the rounds: the host reads it once the stream is synchronised.
@@ -78,7 +78,9 @@ constexpr int kHeadBlock = 1024;
 __global__ __launch_bounds__(kHeadBlock) void k_head_out(const SingleArgs *__restrict__ A, SingleState *S,
                                                          SingleState *dst, int32_t *l1) {
     __shared__ int sh[kHeadBlock / kWave];
-    const int64_t len = (int64_t)min(S->maxdeg, A->n - 1) + 1 - 255;
+    // flags are set only for colours 255 .. kmax - 1 (k_colour_stats raised
+    // kmax past every colour it flagged)
+    const int64_t len = (int64_t)min(min(S->maxdeg, A->n - 1) + 1, S->kmax) - 255;
     if (len > 0) {
         int32_t *const flags = A->flags + 255;
         int cnt = 0;

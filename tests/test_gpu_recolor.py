@@ -45,6 +45,7 @@ def _check(lib, ctx, rp, ci, prev, touched, mode, tie, **kw):
         assert st["rounds"] == want["rounds"] and list(st["L_sizes"]) == list(want["L_sizes"])
     else:
         assert oracle.check(rp, ci, got) == 0 and k == oracle.colour_count(got)
+    assert st["colors_distinct"] == len(np.unique(got))
     return st
 
 

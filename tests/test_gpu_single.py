@@ -74,6 +74,7 @@ def test_deterministic_matches_oracle(lib, ctx, name, tie, split):
     got = d_col.cpu().numpy()[:n]
     assert np.array_equal(got, want["colors"])
     assert k == want["K"]
+    assert st["colors_distinct"] == len(np.unique(want["colors"]))
     assert st["rounds"] == want["rounds"] and st["conflicts"] == want["conflicts"]
     assert list(st["L_sizes"]) == list(want["L_sizes"])
 
@@ -105,6 +106,7 @@ def test_optimistic_valid(lib, ctx, name, tie, split, full_sweep):
     got = d_col.cpu().numpy()[:n]
     assert oracle.check(rp, ci, got) == 0
     assert k == oracle.colour_count(got)
+    assert st["colors_distinct"] == len(np.unique(got))
     deg = np.diff(rp)
     assert k <= (deg.max() + 1 if n else 0)
     # the method's termination bound: |L| strictly shrinks, so at most n recolouring rounds
@@ -131,6 +133,8 @@ def test_ordered_tail_pass(lib, ctx, name, tie):
         got = d_col.cpu().numpy()[:n]
         assert oracle.check(rp, ci, got) == 0, tail
         assert k == oracle.colour_count(got) and k <= np.diff(rp).max() + 1
+        # colours of 255 and more are counted through per-colour flags
+        assert st["colors_distinct"] == len(np.unique(got))
         if name == "K300":
             assert k == 300
         if tail == 0:
