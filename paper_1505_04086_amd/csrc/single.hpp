@@ -387,12 +387,11 @@ inline int32_t run_single(rsoc_ctx *c, const int32_t *rp, const int32_t *ci, int
     bool masked = false;
     if (!inc) {
         if (timing && !opt) RSOC_HIP(hipEventRecord(c->ev[2], s));
-        launch_ev(k_args, std::min(div_up(n, kBlock), 4096), kBlock, s, c->ev[0], nullptr, c->args.as<SingleArgs>(),
+        launch_ev(k_args, std::min(div_up(n, kBlock), 4096), kBlock, s, c->ev[0], c->ev[6], c->args.as<SingleArgs>(),
                   S, &h->head, col, c->col8.as<uint8_t>(), (int64_t)n, o.mode == kDeterministic ? 0 : -1,
                   opt ? c->col4.as<uint32_t>() : (uint32_t *)nullptr, (int64_t)(opt ? n / 8 + 1 : 0));
         RSOC_LAUNCH_CHECK();
         if (timing && !opt) RSOC_HIP(hipEventRecord(c->ev[3], s));
-        RSOC_HIP(hipEventRecord(c->ev[6], s));
         const int gB = validate ? std::min(h->head.nB, 1024) : std::min(n, 1024);
         const int gW = std::min(div_up(validate ? h->head.nW : n, kWavesPerBlock), o.grid_wave);
         masked = launch_sweep_dyn(c, s, o.mode, o.tie, col, n, gB, gW, gTs, timing, o.full_sweep != 0);
@@ -401,9 +400,8 @@ inline int32_t run_single(rsoc_ctx *c, const int32_t *rp, const int32_t *ci, int
         // the colours stay (no fill); shadows and U^0 come from them and the
         // touched list (pend serves as the mark array: the staged colours of
         // the round-synchronous mode are written before they are read)
-        launch_ev(k_args, 1, kBlock, s, c->ev[0], nullptr, c->args.as<SingleArgs>(), S, &h->head, (int32_t *)nullptr,
+        launch_ev(k_args, 1, kBlock, s, c->ev[0], c->ev[6], c->args.as<SingleArgs>(), S, &h->head, (int32_t *)nullptr,
                   (uint8_t *)nullptr, (int64_t)0, 0, (uint32_t *)nullptr, (int64_t)0);
-        RSOC_HIP(hipEventRecord(c->ev[6], s));
         const int g = std::min(div_up(n, kBlock), 4096);
         int32_t *mark = c->pend.as<int32_t>();
         const SingleArgs *A = c->args.as<SingleArgs>();
