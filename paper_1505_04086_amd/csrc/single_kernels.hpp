@@ -39,6 +39,9 @@ struct SingleArgs {
     int32_t *flags;      // flags[c] for colours c >= 255 in use (zero between calls)
 };
 
+constexpr int kAccSlots = 16;   // cache lines the inspection counts are spread over
+constexpr int kAccStride = 16;  // 64-bit words per line (128 bytes)
+
 // Device-side round state.
 struct SingleState {
     int32_t cnt_in[4];    // size of each bin of the current worklist
@@ -63,6 +66,10 @@ struct SingleState {
     uint64_t inspected1, deg_sum1;  // inspected / deg_sum as they stood after the first worklist round
     uint64_t near, sampled;  // id locality sample: row entries with |u - v| < kChunk, entries sampled
     int32_t hist[kHistCap];  // |L| of recolouring round i+1
+    // worklist rounds' inspection counts (inspected, degree sum), spread over
+    // kAccSlots cache lines so that a round's workgroups do not all add to one
+    // line; k_round_end folds them into inspected / deg_sum
+    alignas(128) unsigned long long acc[kAccSlots * kAccStride];
 };
 
 // the part of SingleState the host reads after a round (everything but hist)
@@ -151,6 +158,7 @@ __global__ void k_setup(SingleArgs *A, SingleArgs a, SingleState *S, int header_
     if (clear) {
         int32_t *w = reinterpret_cast<int32_t *>(S);
         for (int i = threadIdx.x; i < header_words; i += blockDim.x) w[i] = 0;
+        for (int i = threadIdx.x; i < kAccSlots * kAccStride; i += blockDim.x) S->acc[i] = 0;
     }
 }
 
@@ -751,8 +759,9 @@ __global__ __launch_bounds__(kBlock) void k_round(const SingleArgs *__restrict__
         }
         __syncthreads();
         if (threadIdx.x == 0 && sh_acc[0]) {
-            atomicAdd((unsigned long long *)&S->inspected, sh_acc[0]);
-            atomicAdd((unsigned long long *)&S->deg_sum, sh_acc[1]);
+            unsigned long long *slot = S->acc + (blockIdx.x % kAccSlots) * kAccStride;
+            atomicAdd(&slot[0], sh_acc[0]);
+            atomicAdd(&slot[1], sh_acc[1]);
         }
     }
 }
@@ -886,6 +895,12 @@ __global__ void k_round_end(const SingleArgs *__restrict__ A, SingleState *S) {
         return;
     }
     if (!SWEEP && S->passes >= A->max_rounds) return;  // the guarded round did nothing
+    for (int k = 0; k < kAccSlots; ++k) {
+        unsigned long long *slot = S->acc + k * kAccStride;
+        S->inspected += slot[0];
+        S->deg_sum += slot[1];
+        slot[0] = slot[1] = 0;
+    }
     const int in_total = SWEEP ? A->n : (S->cnt_in[0] + S->cnt_in[1] + S->cnt_in[2]);
     const int out_total = S->cnt_out[0] + S->cnt_out[1] + S->cnt_out[2];
     if (in_total > 0) {

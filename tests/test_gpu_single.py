@@ -76,6 +76,8 @@ def test_deterministic_matches_oracle(lib, ctx, name, tie, split):
     assert k == want["K"]
     assert st["colors_distinct"] == len(np.unique(want["colors"]))
     assert st["rounds"] == want["rounds"] and st["conflicts"] == want["conflicts"]
+    # round 1 sweeps V; every later pass inspects the list the pass before recoloured
+    assert st["inspected"] == n + want["conflicts"]
     assert list(st["L_sizes"]) == list(want["L_sizes"])
 
 
