@@ -238,27 +238,18 @@ __global__ __launch_bounds__(kBlock) void k_bin(const SingleArgs *__restrict__ A
     int md = 0;
     if (threadIdx.x == 0) nqW = nqB = 0;
     __syncthreads();
-    // each thread takes kBinRun consecutive vertices per step: their kBinRun + 1
-    // row_ptr entries are loaded together
-    constexpr int kBinRun = 4;
-    const int64_t stride = (int64_t)nbb * kBlock * kBinRun;
-    for (int64_t base = (int64_t)bb * kBlock * kBinRun; base < a.n; base += stride) {
-        const int64_t v0 = base + (int64_t)threadIdx.x * kBinRun;
-        int r[kBinRun + 1];
-#pragma unroll
-        for (int k = 0; k <= kBinRun; ++k) r[k] = (v0 + k <= a.n) ? rp[v0 + k] : 0;
-#pragma unroll
-        for (int k = 0; k < kBinRun; ++k) {
-            const int v = (int)(v0 + k);
-            const int d = (v0 + k < a.n) ? r[k + 1] - r[k] : -1;
-            md = max(md, d);
-            // workgroup queues: one global atomic per flush, not per wavefront
-            queue_push(d > a.t_wave, v, qB, &nqB);
-            queue_push(d > a.t_thread && d <= a.t_wave, v, qW, &nqW);
-            __syncthreads();
-            if (nqB > kQueueCap - kBlock) queue_flush(qB, &nqB, &qbase, &S->nB, a.hubB);
-            if (nqW > kQueueCap - kBlock) queue_flush(qW, &nqW, &qbase, &S->nW, a.hubW);
-        }
+    const int64_t stride = (int64_t)nbb * kBlock;
+    for (int64_t base = (int64_t)bb * kBlock; base < a.n; base += stride) {
+        const int v = (int)(base + threadIdx.x);
+        int d = -1;
+        if (v < a.n) d = rp[v + 1] - rp[v];
+        md = max(md, d);
+        // workgroup queues: one global atomic per flush, not per wavefront
+        queue_push(d > a.t_wave, v, qB, &nqB);
+        queue_push(d > a.t_thread && d <= a.t_wave, v, qW, &nqW);
+        __syncthreads();
+        if (nqB > kQueueCap - kBlock) queue_flush(qB, &nqB, &qbase, &S->nB, a.hubB);
+        if (nqW > kQueueCap - kBlock) queue_flush(qW, &nqW, &qbase, &S->nW, a.hubW);
     }
     queue_flush(qB, &nqB, &qbase, &S->nB, a.hubB);
     queue_flush(qW, &nqW, &qbase, &S->nW, a.hubW);
