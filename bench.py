@@ -310,10 +310,20 @@ def bench_single(args):
                                 "GBps": cls_bytes / tc / 1e9, "frac_hbm": cls_bytes / tc / 1e9 / HBM_PEAK_GBS}
         # distance-2 colouring of the same graph (G^2 built on the device, then
         # the same rounds); timed end to end, the build of G^2 included
-        out["distance2"] = bench_distance2(args, rsoc, ctx, d_rp, d_ci, n, E, stream)
+        # (an extra that fails is recorded with its error beside the headline
+        # figures, which are already measured)
+        try:
+            out["distance2"] = bench_distance2(args, rsoc, ctx, d_rp, d_ci, n, E, stream)
+        except rsoc.RsocError as e:
+            out["distance2"] = {"error": str(e)}
+            print("[bench] distance-2 colouring failed: %s" % e, file=sys.stderr, flush=True)
         # recolouring after topology edits: random edges inserted (both endpoints
         # touched), starting from the colouring just made
-        out["recolor_after_edits"] = bench_recolor(args, rsoc, ctx, rp, ci, col, stream, elapsed / args.steps)
+        try:
+            out["recolor_after_edits"] = bench_recolor(args, rsoc, ctx, rp, ci, col, stream, elapsed / args.steps)
+        except rsoc.RsocError as e:
+            out["recolor_after_edits"] = {"error": str(e)}
+            print("[bench] recolouring after edits failed: %s" % e, file=sys.stderr, flush=True)
         if args.mode == "optimistic":
             # the literal reading (round 0 over all neighbours, round 1 over all of V)
             o3 = rsoc.make_options("optimistic", "lower", timing=1, full_sweep=1)
