@@ -54,7 +54,11 @@ typedef enum {
     RSOC_EHIP = -6,       /* a HIP runtime error (see rsoc_last_error) */
     RSOC_ENOCONV = -7,    /* the worklist was still non-empty after max_rounds passes */
     RSOC_EBUDGET = -8,    /* pool admission refused: HBM budget or slot table full */
-    RSOC_ENOTFOUND = -9   /* unknown or unfinished pool slot */
+    RSOC_ENOTFOUND = -9,  /* unknown or unfinished pool slot */
+    RSOC_EINTERNAL = -10  /* an internal consistency check failed on the device: a colour outside
+                             [0, degree], or a worklist / hub list whose size differs from an independent
+                             count of the entries it must hold.  Never expected: it signals a defect of the
+                             library, not of the input; the colours are then unspecified. */
 } rsoc_status;
 
 typedef enum {
@@ -124,7 +128,7 @@ typedef struct {
      * taking the same colour round after round. */
     int32_t tail;
     /* 1 (or 0): colour G; 2: distance-2 colouring, i.e. colour G^2, in which
-     * vertices within distance 2 in G are adjacent (Section 7).  G^2 is built
+     * vertices within distance 2 in G are adjacent (Section 6).  G^2 is built
      * on the device (about 4 bytes per entry of G^2, kept by the context) and
      * coloured by the same rounds; statistics (max_degree, bins, bytes)
      * refer to G^2.  Single-graph entry points only (rsoc_color_device,
@@ -132,7 +136,15 @@ typedef struct {
      * of v's neighbours <= 8192, n <= 2^26 and G^2 below 2^31 entries, else
      * RSOC_EINVAL. */
     int32_t distance;
-    int32_t reserved[2]; /* must be zero */
+    /* Workgroups of the launches that bin the vertices by degree and build
+     * list-shaped inputs (a recolouring's first worklist): 0 = library
+     * default (1024 for a single graph and a pool slot, up to 8192 for a
+     * batch).  Each such workgroup walks its share of the ids and appends to
+     * workgroup queues in LDS; a small value makes every workgroup's queue
+     * fill and flush many times, which tests use to reach those flushes on
+     * small graphs. */
+    int32_t grid_bin;
+    int32_t reserved[1]; /* must be zero */
 } rsoc_options;
 
 typedef struct {

@@ -335,7 +335,7 @@ int32_t orc_recolor(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, i
 }
 
 /*
- * The square G^2 of a graph (Section 7 names d-distance colouring, i.e. the
+ * The square G^2 of a graph (Section 6 names d-distance colouring, i.e. the
  * colouring of the d-th power graph G^d, as the extension the method suits:
  * u and w are adjacent in G^2 iff they are within distance 2 in G).  Row v of
  * G^2 lists, in ascending order and once each, every vertex other than v that

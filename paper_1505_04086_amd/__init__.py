@@ -43,6 +43,7 @@ RSOC_EHIP = -6
 RSOC_ENOCONV = -7
 RSOC_EBUDGET = -8
 RSOC_ENOTFOUND = -9
+RSOC_EINTERNAL = -10
 
 RSOC_MODE_OPTIMISTIC = 0
 RSOC_MODE_DETERMINISTIC = 1
@@ -63,7 +64,7 @@ class rsoc_options(ctypes.Structure):
                 ("rounds_per_sync", ctypes.c_int32), ("small_cutoff", ctypes.c_int32),
                 ("timing", ctypes.c_int32), ("full_sweep", ctypes.c_int32), ("lookahead", ctypes.c_int32),
                 ("chunk", ctypes.c_int32), ("grid_list", ctypes.c_int32), ("tail", ctypes.c_int32),
-                ("distance", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
+                ("distance", ctypes.c_int32), ("grid_bin", ctypes.c_int32), ("reserved", ctypes.c_int32 * 1)]
 
 
 class rsoc_stats(ctypes.Structure):

@@ -190,7 +190,7 @@ inline int32_t run_batch(rsoc_ctx *c, int32_t G, const int64_t *vtx_off, const i
     RSOC_HIP(hipMemcpyAsync(c->b_args.p, &a, sizeof(a), hipMemcpyHostToDevice, s));
     RSOC_HIP(hipMemsetAsync(S, 0, kStateHeader, s));
     RSOC_HIP(hipMemsetAsync(c->b_kmax.p, 0, sizeof(int32_t) * (size_t)G, s));
-    const int tgrid = std::min(ntasks, 8192);
+    const int tgrid = std::min(ntasks, o.grid_bin ? o.grid_bin : 8192);
     if (o.validate & RSOC_CHECK_CSR) {
         k_bvalidate<<<tgrid, kBlock, 0, s>>>(c->b_args.as<BatchArgs>(), &S->err);
         RSOC_LAUNCH_CHECK();
@@ -247,7 +247,7 @@ inline int32_t run_batch(rsoc_ctx *c, int32_t G, const int64_t *vtx_off, const i
             RSOC_HIP(hipMemcpyAsync(st->per_round_L, S->hist, sizeof(int32_t) * cnt, hipMemcpyDeviceToHost, s));
     }
     RSOC_HIP(hipStreamSynchronize(s));
-    if (h->head.err & 4) return RSOC_EHIP;
+    if (h->head.err & (4 | kErrListCount)) return RSOC_EINTERNAL;  // never expected
     int32_t kmax = 0;
     for (int g = 0; g < G; ++g) {
         if (counts_out) counts_out[g] = kg[g];

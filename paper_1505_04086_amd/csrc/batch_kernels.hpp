@@ -82,12 +82,14 @@ __device__ __forceinline__ void queue_push64(bool take, int64_t x, int64_t *q, i
 
 // Flushes a workgroup queue into the static hub list (workgroup bin: written
 // from the back of the list).
-__device__ __forceinline__ void hub_flush(int64_t *q, int *qn, int *qbase, int *counter, int64_t *hub, bool from_back,
-                                          int64_t cap) {
-    __syncthreads();
-    const int cnt = *qn;
+// cnt: the queue size every wavefront agreed on (see queue_flush_n).
+__device__ __forceinline__ void hub_flush_n(int cnt, int64_t *q, int *qn, int *qbase, int *counter, int64_t *hub,
+                                            bool from_back, int64_t cap) {
     if (cnt == 0) return;
-    if (threadIdx.x == 0) *qbase = atomicAdd(counter, cnt);
+    if (threadIdx.x == 0) {
+        *qbase = atomicAdd(counter, cnt);
+        *qn = 0;
+    }
     __syncthreads();
     const int base = *qbase;
     for (int i = threadIdx.x; i < cnt; i += kBlock) {
@@ -95,8 +97,10 @@ __device__ __forceinline__ void hub_flush(int64_t *q, int *qn, int *qbase, int *
         hub[from_back ? cap - 1 - pos : pos] = q[i];
     }
     __syncthreads();
-    if (threadIdx.x == 0) *qn = 0;
-    __syncthreads();
+}
+__device__ __forceinline__ void hub_flush(int64_t *q, int *qn, int *qbase, int *counter, int64_t *hub, bool from_back,
+                                          int64_t cap) {
+    hub_flush_n(queue_size(qn), q, qn, qbase, counter, hub, from_back, cap);
 }
 
 __global__ __launch_bounds__(kBlock) void k_bbin(const BatchArgs *__restrict__ A, SingleState *S) {
@@ -119,9 +123,10 @@ __global__ __launch_bounds__(kBlock) void k_bbin(const BatchArgs *__restrict__ A
             md = max(md, d);
             queue_push64(d > a.t_wave, pack_item(g, v), qB, &nqB);
             queue_push64(d > a.t_thread && d <= a.t_wave, pack_item(g, v), qW, &nqW);
-            __syncthreads();
-            if (nqB > kQueueCap / 2 - kBlock) hub_flush(qB, &nqB, &qbase, &S->nB, a.hub, true, a.hub_cap);
-            if (nqW > kQueueCap / 2 - kBlock) hub_flush(qW, &nqW, &qbase, &S->nW, a.hub, false, a.hub_cap);
+            int cB, cW;
+            queue_sizes(&nqB, &nqW, cB, cW);
+            if (cB > kQueueCap / 2 - kBlock) hub_flush_n(cB, qB, &nqB, &qbase, &S->nB, a.hub, true, a.hub_cap);
+            if (cW > kQueueCap / 2 - kBlock) hub_flush_n(cW, qW, &nqW, &qbase, &S->nW, a.hub, false, a.hub_cap);
         }
     }
     hub_flush(qB, &nqB, &qbase, &S->nB, a.hub, true, a.hub_cap);
@@ -188,17 +193,20 @@ __device__ __forceinline__ void queue_push64(bool take, int64_t x, int64_t *q, i
     if (take) q[base + lanes_below(m)] = x;
 }
 
-__device__ __forceinline__ void queue_flush64(int64_t *q, int *qn, int *qbase, int *counter, int64_t *out) {
-    __syncthreads();
-    const int cnt = *qn;
+// cnt: the queue size every wavefront agreed on (see queue_flush_n).
+__device__ __forceinline__ void queue_flush64_n(int cnt, int64_t *q, int *qn, int *qbase, int *counter, int64_t *out) {
     if (cnt == 0) return;
-    if (threadIdx.x == 0) *qbase = atomicAdd(counter, cnt);
+    if (threadIdx.x == 0) {
+        *qbase = atomicAdd(counter, cnt);
+        *qn = 0;
+    }
     __syncthreads();
     const int base = *qbase;
     for (int i = threadIdx.x; i < cnt; i += kBlock) out[base + i] = q[i];
     __syncthreads();
-    if (threadIdx.x == 0) *qn = 0;
-    __syncthreads();
+}
+__device__ __forceinline__ void queue_flush64(int64_t *q, int *qn, int *qbase, int *counter, int64_t *out) {
+    queue_flush64_n(queue_size(qn), q, qn, qbase, counter, out);
 }
 
 // ----------------------------------------------------------------- round --
@@ -249,8 +257,8 @@ __global__ __launch_bounds__(kBlock) void k_bround(const BatchArgs *__restrict__
                 }
                 if (take) q[qn++] = it;
             }
-            __syncthreads();
-            if (qn == kQueueCap) queue_flush64(q, &qn, &qbase, &S->cnt_out[kBinBlock], out + a.offB);
+            const int cq = queue_size(&qn);
+            if (cq == kQueueCap) queue_flush64_n(cq, q, &qn, &qbase, &S->cnt_out[kBinBlock], out + a.offB);
         }
         if (kAppend) queue_flush64(q, &qn, &qbase, &S->cnt_out[kBinBlock], out + a.offB);
     } else if (bid < gB + gW) {
@@ -366,8 +374,8 @@ __global__ __launch_bounds__(kBlock) void k_bround(const BatchArgs *__restrict__
 #pragma unroll
                     for (int i = 0; i < kNV; ++i)
                         queue_push64((kFlagAppend ? unc[i] != 0 : act[i]) && leader, pack_item(gg[i], v[i]), q, &qn);
-                    __syncthreads();
-                    if (qn > kQueueCap - kSub) queue_flush64(q, &qn, &qbase, &S->cnt_out[kBinThread], out);
+                    const int cq = queue_size(&qn);
+                    if (cq > kQueueCap - kSub) queue_flush64_n(cq, q, &qn, &qbase, &S->cnt_out[kBinThread], out);
                 }
             }
         }

@@ -129,6 +129,35 @@ __device__ __forceinline__ void wave_append(bool take, int v, int *counter, int 
     if (take) list[base + lanes_below(m)] = v;
 }
 
+// Sizes of a workgroup's LDS append queues as every wavefront sees them; the
+// whole workgroup calls this between its appends and any flush decision.  A
+// wavefront goes on to its next append (an LDS atomic on the same counter) as
+// soon as it has read the counter, so a count read after a single barrier can
+// differ between wavefronts: a slower one may already see the next step's
+// appends, decide to flush alone, and its flush barriers then pair with the
+// other wavefronts' loop barriers (entries lost, duplicated, or written past
+// the queue).  The first barrier ends the appends in flight; the second holds
+// every wavefront until all have read the same values.
+__device__ __forceinline__ int queue_size(const int *qn) {
+    __syncthreads();
+    const int c = *(const volatile int *)qn;
+    __syncthreads();
+    return c;
+}
+__device__ __forceinline__ void queue_sizes(const int *qa, const int *qb, int &ca, int &cb) {
+    __syncthreads();
+    ca = *(const volatile int *)qa;
+    cb = *(const volatile int *)qb;
+    __syncthreads();
+}
+__device__ __forceinline__ void queue_sizes(const int *qa, const int *qb, const int *qc, int &ca, int &cb, int &cc) {
+    __syncthreads();
+    ca = *(const volatile int *)qa;
+    cb = *(const volatile int *)qb;
+    cc = *(const volatile int *)qc;
+    __syncthreads();
+}
+
 // Wavefront sum of a 64-bit value (result valid in every lane).
 __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t x) {
     for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);

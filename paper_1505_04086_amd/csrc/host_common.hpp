@@ -93,7 +93,7 @@ struct HostPinned {
 
 struct Options {
     int mode, tie, max_rounds, validate, t_thread, t_wave, grid_thread, grid_wave, rounds_per_sync, small_cutoff,
-        timing, full_sweep, lookahead, chunk, grid_list, tail, distance;
+        timing, full_sweep, lookahead, chunk, grid_list, tail, distance, grid_bin;
 };
 
 inline int32_t resolve_options(const rsoc_options *o, int64_t n, Options &r) {
@@ -107,8 +107,8 @@ inline int32_t resolve_options(const rsoc_options *o, int64_t n, Options &r) {
     if (d.max_rounds < 0 || d.t_thread < 0 || d.t_thread > 32 || d.t_wave < 0 || d.grid_thread < 0 ||
         d.grid_wave < 0 || d.rounds_per_sync < 0 || d.validate < 0 || d.validate > 3 || d.grid_list < 0)
         return RSOC_EINVAL;
-    for (int i = 0; i < 2; ++i)
-        if (d.reserved[i]) return RSOC_EINVAL;
+    if (d.reserved[0] || d.grid_bin < 0) return RSOC_EINVAL;
+    r.grid_bin = d.grid_bin;  // 0: each launch site's own default
     if (d.distance < 0 || d.distance > 2) return RSOC_EINVAL;
     r.distance = d.distance == 2 ? 2 : 1;
     if (d.tail < -1) return RSOC_EINVAL;

@@ -230,10 +230,11 @@ inline int32_t pool_admit(rsoc_pool *p, const int32_t *d_row_ptr, const int32_t 
     p->reported[slot] = 0;
     if ((r = pool_upload_slot(p, slot, s)) < 0) { pool_release(p, slot); return r; }
     if (n > 0) {
-        k_pinit<<<std::min(div_up(n, kBlock), 1024), kBlock, 0, s>>>(p->slots_dev.as<PoolSlot>(), slot);
+        const int gbin = std::min(div_up(n, kBlock), o.grid_bin ? o.grid_bin : 1024);
+        k_pinit<<<gbin, kBlock, 0, s>>>(p->slots_dev.as<PoolSlot>(), slot);
         if (recolor) {
             if (nt > 0) k_ptouch<<<std::min(div_up(nt, kBlock), 256), kBlock, 0, s>>>(p->slots_dev.as<PoolSlot>(), slot);
-            k_plist<<<std::min(div_up(n, kBlock), 1024), kBlock, 0, s>>>(p->slots_dev.as<PoolSlot>(), slot);
+            k_plist<<<gbin, kBlock, 0, s>>>(p->slots_dev.as<PoolSlot>(), slot);
         }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) { pool_release(p, slot); return hip_fail(e, "k_pinit", __FILE__, __LINE__); }
@@ -480,7 +481,7 @@ int32_t rsoc_pool_result(rsoc_pool *p, int32_t slot, rsoc_stats *stats) {
         stats->worklist0 = m.mode == kOptimistic ? m.u0 : m.n;
         stats->chunk = m.chunk;
     }
-    const int32_t k = (m.err & 4) ? RSOC_EHIP : (m.status < 0 ? m.status : m.kmax);
+    const int32_t k = (m.err & 4) ? RSOC_EINTERNAL : (m.status < 0 ? m.status : m.kmax);
     // the freed slot's device copy is refreshed before the next step reads it
     hipStream_t s = c->own;
     pool_release(p, slot);

@@ -91,9 +91,10 @@ __global__ __launch_bounds__(kBlock) void k_pinit(PoolSlot *slots, int slot) {
         md = max(md, d);
         queue_push(d > sp->t_wave, v, qB, &nqB);
         queue_push(d > sp->t_thread && d <= sp->t_wave, v, qW, &nqW);
-        __syncthreads();
-        if (nqB > kQueueCap - kBlock) queue_flush(qB, &nqB, &qbase, &sp->nB, sp->hubB);
-        if (nqW > kQueueCap - kBlock) queue_flush(qW, &nqW, &qbase, &sp->nW, sp->hubW);
+        int cB, cW;
+        queue_sizes(&nqB, &nqW, cB, cW);
+        if (cB > kQueueCap - kBlock) queue_flush_n(cB, qB, &nqB, &qbase, &sp->nB, sp->hubB);
+        if (cW > kQueueCap - kBlock) queue_flush_n(cW, qW, &nqW, &qbase, &sp->nW, sp->hubW);
     }
     queue_flush(qB, &nqB, &qbase, &sp->nB, sp->hubB);
     queue_flush(qW, &nqW, &qbase, &sp->nW, sp->hubW);
@@ -140,10 +141,11 @@ __global__ __launch_bounds__(kBlock) void k_plist(PoolSlot *slots, int slot) {
         queue_push(m && d > sp->t_wave, v, qB, &nqB);
         queue_push(m && d > sp->t_thread && d <= sp->t_wave, v, qW, &nqW);
         queue_push(m && d <= sp->t_thread, v, qT, &nqT);
-        __syncthreads();
-        if (nqB > kQueueCap - kBlock) queue_flush(qB, &nqB, &qbase, &sp->cnt_in[kBinBlock], out + offB);
-        if (nqW > kQueueCap - kBlock) queue_flush(qW, &nqW, &qbase, &sp->cnt_in[kBinWave], out + offW);
-        if (nqT > kQueueCap - kBlock) queue_flush(qT, &nqT, &qbase, &sp->cnt_in[kBinThread], out);
+        int cB, cW, cT;
+        queue_sizes(&nqB, &nqW, &nqT, cB, cW, cT);
+        if (cB > kQueueCap - kBlock) queue_flush_n(cB, qB, &nqB, &qbase, &sp->cnt_in[kBinBlock], out + offB);
+        if (cW > kQueueCap - kBlock) queue_flush_n(cW, qW, &nqW, &qbase, &sp->cnt_in[kBinWave], out + offW);
+        if (cT > kQueueCap - kBlock) queue_flush_n(cT, qT, &nqT, &qbase, &sp->cnt_in[kBinThread], out);
     }
     queue_flush(qB, &nqB, &qbase, &sp->cnt_in[kBinBlock], out + offB);
     queue_flush(qW, &nqW, &qbase, &sp->cnt_in[kBinWave], out + offW);
@@ -222,9 +224,9 @@ __device__ __forceinline__ void pool_thread_task(PoolSlot *sp, const PoolSlot &s
                 queue_push<int4>((KIND == kAssignSweep ? unc[i] != 0 : act[i]) && leader, v[i], q, qn,
                                  kNib ? qa : nullptr,
                                  kNib ? make_int4(keep[i][0], keep[i][1], keep[i][2], keep[i][3]) : int4{});
-            __syncthreads();
-            if (*qn > (kNib ? kPoolAuxCap : kQueueCap) - kSub)
-                queue_flush<int4>(q, qn, qbase, &sp->cnt_out[kBinThread], out, kNib ? qa : nullptr, s.aux);
+            const int cq = queue_size(qn);
+            if (cq > (kNib ? kPoolAuxCap : kQueueCap) - kSub)
+                queue_flush_n<int4>(cq, q, qn, qbase, &sp->cnt_out[kBinThread], out, kNib ? qa : nullptr, s.aux);
         }
     }
     queue_flush<int4>(q, qn, qbase, &sp->cnt_out[kBinThread], out, kNib ? qa : nullptr, s.aux);
@@ -247,7 +249,7 @@ __device__ __forceinline__ void pool_masked_task(PoolSlot *sp, const PoolSlot &s
     RSOC_GLOBAL int32_t *wcol = grw(s.col);
     RSOC_GLOBAL uint8_t *wcol8 = grw(s.col8);
     const int wv = threadIdx.x / kWave;
-    uint64_t degs = 0;
+    uint64_t degs = 0, apps = 0;
     if (lane_id() == 0) *mbn = 0;
     wave_lds_sync();
     for (int base = tk.begin + wv * kWave; base < tk.end; base += kWavesPerBlock * kWave) {
@@ -263,11 +265,11 @@ __device__ __forceinline__ void pool_masked_task(PoolSlot *sp, const PoolSlot &s
         const bool over = v >= 0 && __popc((uint32_t)x.w) > 3;
         const bool def = v >= 0 && !over && lane_detect_kept<false>(v, x, cv, c8, nullptr);
         wave_recolour_selected<kAssign, TIE, false>(ballot(def), v, ms, mb, mbn, rp, ci, c8, nullptr, wcol, wcol8,
-                                                    nullptr, s.look, degs);
+                                                    nullptr, s.look, degs, apps);
         const uint64_t om = ballot(over);
         if (om)
             wave_recolour_selected<kRecolor, TIE, false>(om, v, ms, mb, mbn, rp, ci, c8, nullptr, wcol, wcol8,
-                                                         nullptr, s.look, degs);
+                                                         nullptr, s.look, degs, apps);
         if (*mbn >= kPoolMaskedBuf - kWave) wave_buf_flush(mb, mbn, &sp->cnt_out[kBinThread], out);
     }
     wave_buf_flush(mb, mbn, &sp->cnt_out[kBinThread], out);

@@ -34,6 +34,8 @@ const char *rsoc_strerror(int32_t status) {
         case RSOC_ENOCONV: return "worklist not empty after max_rounds passes";
         case RSOC_EBUDGET: return "pool admission refused (HBM budget or slot table full)";
         case RSOC_ENOTFOUND: return "unknown or unfinished pool slot";
+        case RSOC_EINTERNAL: return "internal consistency check failed (a colour outside [0, degree] or a list size "
+                                    "that differs from its independent count): a library defect";
         default: return status >= 0 ? "ok" : "unknown error";
     }
 }

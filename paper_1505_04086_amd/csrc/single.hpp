@@ -354,7 +354,7 @@ inline int32_t run_single(rsoc_ctx *c, const int32_t *rp, const int32_t *ci, int
     // binning: each workgroup ends with one global atomic per non-empty hub
     // queue, so fewer, longer-running workgroups (power-law graphs fill the
     // queues of nearly every workgroup)
-    const int vgrid = std::min(div_up(n, kBlock), 1024);
+    const int vgrid = std::min(div_up(n, kBlock), o.grid_bin ? o.grid_bin : 1024);
     // binning (reads row_ptr only: also checks its ends and publishes nnz),
     // with the id-locality sample in extra workgroups unless the CSR is to be
     // validated first (the sample reads rows)
@@ -408,7 +408,7 @@ inline int32_t run_single(rsoc_ctx *c, const int32_t *rp, const int32_t *ci, int
         if (opt) k_inc_shadow<true><<<g, kBlock, 0, s>>>(A, mark);
         else k_inc_shadow<false><<<g, kBlock, 0, s>>>(A, mark);
         if (nt > 0) k_inc_touch<<<std::min(div_up(nt, kBlock), 1024), kBlock, 0, s>>>(A, S, touched, nt, mark);
-        k_inc_list<<<g, kBlock, 0, s>>>(A, S, mark);
+        k_inc_list<<<o.grid_bin ? std::min(g, o.grid_bin) : g, kBlock, 0, s>>>(A, S, mark);
         if (opt) k_round_end<kOptimistic, true, true><<<1, 64, 0, s>>>(A, S);
         else k_round_end<kDeterministic, true, true><<<1, 64, 0, s>>>(A, S);
         RSOC_LAUNCH_CHECK();
@@ -465,7 +465,7 @@ inline int32_t run_single(rsoc_ctx *c, const int32_t *rp, const int32_t *ci, int
             RSOC_HIP(hipStreamSynchronize(s));
         }
     }
-    if (h->head.err & 4) return RSOC_EHIP;  // a colour outside [0, max degree]: never expected
+    if (h->head.err & (4 | kErrListCount)) return RSOC_EINTERNAL;  // never expected
     if (h->head.err & 16) return RSOC_EINVAL;  // a touched id outside [0, n)
     if (st) {
         st->rounds = h->head.rounds;

@@ -41,6 +41,12 @@ struct SingleArgs {
 
 constexpr int kAccSlots = 16;   // cache lines the inspection counts are spread over
 constexpr int kAccStride = 16;  // 64-bit words per line (128 bytes)
+// Words of each acc line: what the worklist rounds inspected, and the
+// independent counts that check the list sizes (bit 5 of err): entries a
+// round decided to append (counted where the decision is taken, not by the
+// queues), and the rows binning found in the wavefront / workgroup ranges.
+enum AccWord : int { kAccItems = 0, kAccDegs = 1, kAccAppended = 2, kAccBinW = 3, kAccBinB = 4 };
+constexpr int kErrListCount = 32;
 
 // Device-side round state.
 struct SingleState {
@@ -51,7 +57,8 @@ struct SingleState {
     int32_t passes;       // inspection passes executed (rounds >= 1)
     int32_t rounds;       // passes that recoloured somebody
     int32_t err;          // bit 0 bad CSR, bit 1 self-loop, bit 2 colour out of range, bit 3 edges without
-                          // col_idx, bit 4 a touched id out of range (recolouring)
+                          // col_idx, bit 4 a touched id out of range (recolouring), bit 5 a list size
+                          // that differs from the independent count of its entries
     int32_t nnz;          // row_ptr[n] (read by k_bin)
     int32_t lastL, prevL; // |L| of the last two rounds that inspected anything
     // colour statistics (k_colour_stats; cleared before each computation)
@@ -207,6 +214,9 @@ __device__ __forceinline__ void queue_push(bool take, int v, int *q, int *qn, T 
 template <class T = int>
 __device__ __forceinline__ void queue_flush(int *q, int *qn, int *qbase, int *counter, int32_t *out,
                                             const T *qx = nullptr, T *outx = nullptr);
+template <class T = int>
+__device__ __forceinline__ void queue_flush_n(int cnt, int *q, int *qn, int *qbase, int *counter, int32_t *out,
+                                              const T *qx = nullptr, T *outx = nullptr);
 
 __device__ __forceinline__ void locality_row(const RSOC_GLOBAL int32_t *rp, const RSOC_GLOBAL int32_t *ci, int v,
                                              int64_t nnz, uint64_t &near, uint64_t &sampled);
@@ -236,6 +246,7 @@ __global__ __launch_bounds__(kBlock) void k_bin(const SingleArgs *__restrict__ A
         if (r0 != 0 || rn < 0) atomicOr(&S->err, 1);
     }
     int md = 0;
+    uint64_t rowsW = 0, rowsB = 0;  // independent count of the rows each hub list must receive
     if (threadIdx.x == 0) nqW = nqB = 0;
     __syncthreads();
     const int64_t stride = (int64_t)nbb * kBlock;
@@ -244,19 +255,40 @@ __global__ __launch_bounds__(kBlock) void k_bin(const SingleArgs *__restrict__ A
         int d = -1;
         if (v < a.n) d = rp[v + 1] - rp[v];
         md = max(md, d);
+        rowsB += d > a.t_wave;
+        rowsW += d > a.t_thread && d <= a.t_wave;
         // workgroup queues: one global atomic per flush, not per wavefront
         queue_push(d > a.t_wave, v, qB, &nqB);
         queue_push(d > a.t_thread && d <= a.t_wave, v, qW, &nqW);
-        __syncthreads();
-        if (nqB > kQueueCap - kBlock) queue_flush(qB, &nqB, &qbase, &S->nB, a.hubB);
-        if (nqW > kQueueCap - kBlock) queue_flush(qW, &nqW, &qbase, &S->nW, a.hubW);
+        int cB, cW;
+        queue_sizes(&nqB, &nqW, cB, cW);
+        if (cB > kQueueCap - kBlock) queue_flush_n(cB, qB, &nqB, &qbase, &S->nB, a.hubB);
+        if (cW > kQueueCap - kBlock) queue_flush_n(cW, qW, &nqW, &qbase, &S->nW, a.hubW);
     }
     queue_flush(qB, &nqB, &qbase, &S->nB, a.hubB);
     queue_flush(qW, &nqW, &qbase, &S->nW, a.hubW);
+    rowsW = wave_sum_u64(rowsW);
+    rowsB = wave_sum_u64(rowsB);
+    if (lane_id() == 0 && (rowsW | rowsB)) {
+        unsigned long long *slot = S->acc + (blockIdx.x % kAccSlots) * kAccStride;
+        if (rowsW) atomicAdd(&slot[kAccBinW], (unsigned long long)rowsW);
+        if (rowsB) atomicAdd(&slot[kAccBinB], (unsigned long long)rowsB);
+    }
     md = block_max(md, sh);
     // most workgroups find nothing larger than what is already published
     if (threadIdx.x == 0 && md > __hip_atomic_load(&S->maxdeg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
         atomicMax(&S->maxdeg, md);
+}
+
+// Folds the acc words w of all lines into one total and clears them.
+__device__ __forceinline__ unsigned long long acc_take(SingleState *S, int w) {
+    unsigned long long t = 0;
+    for (int k = 0; k < kAccSlots; ++k) {
+        unsigned long long *slot = S->acc + k * kAccStride;
+        t += slot[w];
+        slot[w] = 0;
+    }
+    return t;
 }
 
 // Completes the arguments once binning is done, on the device, so that the
@@ -283,6 +315,9 @@ __global__ void k_args(SingleArgs *A, SingleState *S, SingleState *dst, int32_t 
             // default round 0 reads none of them
             if (A->look_auto && A->chunk == 1) A->look = 0;
             if (A->ci == nullptr && S->nnz > 0) S->err |= 8;
+            // the hub lists hold exactly the rows binning counted in their ranges
+            const unsigned long long rw = acc_take(S, kAccBinW), rb = acc_take(S, kAccBinB);
+            if (rw != (unsigned long long)S->nW || rb != (unsigned long long)S->nB) S->err |= kErrListCount;
         }
         __syncthreads();
         const int32_t *src = reinterpret_cast<const int32_t *>(S);
@@ -355,15 +390,20 @@ __device__ __forceinline__ void queue_push(bool take, int v, int *q, int *qn, T 
     }
 }
 
-// Moves the queue to the global list (one global atomic per flush); the side
-// entries qx, when given, go to the same positions of outx.
+// Moves the queue's cnt entries to the global list (one global atomic per
+// flush); the side entries qx, when given, go to the same positions of outx.
+// cnt is the queue size every wavefront agreed on (queue_size), so the whole
+// workgroup takes the same path; the counter is reset before the first
+// barrier (every wavefront has read it already and none appends until the
+// flush returns), and the last barrier frees the queue and qbase again.
 template <class T>
-__device__ __forceinline__ void queue_flush(int *q, int *qn, int *qbase, int *counter, int32_t *out, const T *qx,
-                                            T *outx) {
-    __syncthreads();
-    const int cnt = *qn;
+__device__ __forceinline__ void queue_flush_n(int cnt, int *q, int *qn, int *qbase, int *counter, int32_t *out,
+                                              const T *qx, T *outx) {
     if (cnt == 0) return;
-    if (threadIdx.x == 0) *qbase = atomicAdd(counter, cnt);
+    if (threadIdx.x == 0) {
+        *qbase = atomicAdd(counter, cnt);
+        *qn = 0;
+    }
     __syncthreads();
     const int base = *qbase;
     for (int i = threadIdx.x; i < cnt; i += kBlock) {
@@ -371,8 +411,12 @@ __device__ __forceinline__ void queue_flush(int *q, int *qn, int *qbase, int *co
         if (qx) outx[base + i] = qx[i];
     }
     __syncthreads();
-    if (threadIdx.x == 0) *qn = 0;
-    __syncthreads();
+}
+
+template <class T>
+__device__ __forceinline__ void queue_flush(int *q, int *qn, int *qbase, int *counter, int32_t *out, const T *qx,
+                                            T *outx) {
+    queue_flush_n<T>(queue_size(qn), q, qn, qbase, counter, out, qx, outx);
 }
 
 // Masked round: the entries of this wavefront selected by sel (bit = lane,
@@ -387,7 +431,7 @@ __device__ __forceinline__ void wave_recolour_selected(uint64_t sel, int v, int 
                                                        const RSOC_GLOBAL uint8_t *col8,
                                                        const RSOC_GLOBAL uint32_t *col4, RSOC_GLOBAL int32_t *wcol,
                                                        RSOC_GLOBAL uint8_t *wcol8, RSOC_GLOBAL uint32_t *wcol4,
-                                                       int look, uint64_t &degs) {
+                                                       int look, uint64_t &degs, uint64_t &napp) {
     if (sel & (1ull << lane_id())) ms[lanes_below(sel)] = v;
     wave_lds_sync();
     const int nd = __popcll(sel);
@@ -423,6 +467,7 @@ __device__ __forceinline__ void wave_recolour_selected(uint64_t sel, int v, int 
             if (NIB) atomicOr((uint32_t *)&wcol4[gv[0] >> 3], 0xfu << ((gv[0] & 7) << 2));
         }
         const uint64_t am = ballot(w);
+        if (lane_id() == 0) napp += (uint64_t)__popcll(am);
         if (w) mb[*mbn + lanes_below(am)] = gv[0];
         wave_lds_sync();
         if (lane_id() == 0) *mbn += __popcll(am);
@@ -484,7 +529,7 @@ __global__ __launch_bounds__(kBlock) void k_round(const SingleArgs *__restrict__
     __shared__ int q[kQueueCap];
     __shared__ int4 qa[kFlagAppend ? kAuxCap : 1];
     __shared__ int sh_min, qn, qbase;
-    __shared__ unsigned long long sh_acc[2];
+    __shared__ unsigned long long sh_acc[3];
     __shared__ int wbuf[kWavesPerBlock][kWaveBuf];
     __shared__ int wbn[kWavesPerBlock];
     // masked round: per-wavefront defective staging and append buffer
@@ -524,6 +569,7 @@ __global__ __launch_bounds__(kBlock) void k_round(const SingleArgs *__restrict__
     constexpr bool kWrite = PHASE != kDetect;
     constexpr bool kAcct = PHASE != kAssign && !SWEEP;  // worklist rounds count their inspections
     uint64_t items = 0, degs = 0;
+    uint64_t apps = 0;  // entries this thread decided to append (the list-size check)
     // A sweep's hub sections may be launched larger than its bins need (the
     // host enqueues it before it knows the bin sizes): the workgroups the bins
     // need keep the front of the grid and the surplus, at its end, leaves.
@@ -550,10 +596,13 @@ __global__ __launch_bounds__(kBlock) void k_round(const SingleArgs *__restrict__
                     if (kPublish) publish_nibble(wcol4, v, nc);
                     else if (kNib) atomicOr((uint32_t *)&wcol4[v >> 3], 0xfu << ((v & 7) << 2));
                 }
-                if (take) q[qn++] = v;
+                if (take) {
+                    q[qn++] = v;
+                    apps += 1;
+                }
             }
-            __syncthreads();
-            if (qn == kQueueCap) queue_flush(q, &qn, &qbase, &S->cnt_out[kBinBlock], out + a.offB);
+            const int cq = queue_size(&qn);
+            if (cq == kQueueCap) queue_flush_n(cq, q, &qn, &qbase, &S->cnt_out[kBinBlock], out + a.offB);
         }
         if (kAppend) queue_flush(q, &qn, &qbase, &S->cnt_out[kBinBlock], out + a.offB);
     } else if (bid < gB + gW) {
@@ -579,6 +628,7 @@ __global__ __launch_bounds__(kBlock) void k_round(const SingleArgs *__restrict__
                     else if (kNib) atomicOr((uint32_t *)&wcol4[v >> 3], 0xfu << ((v & 7) << 2));
                 }
             }
+            if (kAppend && lane_id() == 0 && (kFlagAppend ? unc : act)) apps += 1;
             if (kAppend) wave_buf_push((kFlagAppend ? unc : act), v, wbuf[wv], &wbn[wv], &S->cnt_out[kBinWave],
                                        out + a.offW);
         }
@@ -615,11 +665,11 @@ __global__ __launch_bounds__(kBlock) void k_round(const SingleArgs *__restrict__
                 degs += (uint64_t)__popc((uint32_t)x.w);
             }
             wave_recolour_selected<kAssign, TIE, kNib>(ballot(def), v, ms, mb, &mbn[wv], rp, ci, rcol8, rcol4, wcol,
-                                                       wcol8, wcol4, a.look, degs);
+                                                       wcol8, wcol4, a.look, degs, apps);
             const uint64_t om = ballot(over);
             if (om)
                 wave_recolour_selected<kRecolor, TIE, kNib>(om, v, ms, mb, &mbn[wv], rp, ci, rcol8, rcol4, wcol,
-                                                            wcol8, wcol4, a.look, degs);
+                                                            wcol8, wcol4, a.look, degs, apps);
             if (mbn[wv] >= kMaskedBuf - kWave) wave_buf_flush(mb, &mbn[wv], &S->cnt_out[kBinThread], out);
         }
         // what the wavefronts still hold leaves in one workgroup-wide flush
@@ -733,36 +783,41 @@ __global__ __launch_bounds__(kBlock) void k_round(const SingleArgs *__restrict__
                 }
                 if (kAppend) {
 #pragma unroll
+                    for (int i = 0; i < kNV; ++i) apps += ((kFlagAppend ? unc[i] != 0 : act[i]) && leader) ? 1 : 0;
+#pragma unroll
                     for (int i = 0; i < kNV; ++i)
                         queue_push<int4>((kFlagAppend ? unc[i] != 0 : act[i]) && leader, v[i], q, &qn,
                                          kFlagAppend ? qa : nullptr,
                                          kFlagAppend ? make_int4(keep[i][0], keep[i][1], keep[i][2], keep[i][3])
                                                      : int4{});
-                    __syncthreads();
-                    if (qn > (kFlagAppend ? kAuxCap : kQueueCap) - kSub)
-                        queue_flush<int4>(q, &qn, &qbase, &S->cnt_out[kBinThread], out, kFlagAppend ? qa : nullptr,
-                                          a.aux);
+                    const int cq = queue_size(&qn);
+                    if (cq > (kFlagAppend ? kAuxCap : kQueueCap) - kSub)
+                        queue_flush_n<int4>(cq, q, &qn, &qbase, &S->cnt_out[kBinThread], out,
+                                            kFlagAppend ? qa : nullptr, a.aux);
                 }
             }
         }
         if (kAppend)
             queue_flush<int4>(q, &qn, &qbase, &S->cnt_out[kBinThread], out, kFlagAppend ? qa : nullptr, a.aux);
     }
-    if (kAcct) {
-        if (threadIdx.x == 0) { sh_acc[0] = 0; sh_acc[1] = 0; }
+    if (kAcct || kAppend) {
+        if (threadIdx.x < 3) sh_acc[threadIdx.x] = 0;
         __syncthreads();
         items = wave_sum_u64(items);
         degs = wave_sum_u64(degs);
-        if (lane_id() == 0 && items) {
+        apps = wave_sum_u64(apps);
+        if (lane_id() == 0 && kAcct && items) {
             atomicAdd(&sh_acc[0], (unsigned long long)items);
             atomicAdd(&sh_acc[1], (unsigned long long)degs);
         }
+        if (lane_id() == 0 && apps) atomicAdd(&sh_acc[2], (unsigned long long)apps);
         __syncthreads();
+        unsigned long long *slot = S->acc + (blockIdx.x % kAccSlots) * kAccStride;
         if (threadIdx.x == 0 && sh_acc[0]) {
-            unsigned long long *slot = S->acc + (blockIdx.x % kAccSlots) * kAccStride;
-            atomicAdd(&slot[0], sh_acc[0]);
-            atomicAdd(&slot[1], sh_acc[1]);
+            atomicAdd(&slot[kAccItems], sh_acc[0]);
+            atomicAdd(&slot[kAccDegs], sh_acc[1]);
         }
+        if (threadIdx.x == 0 && sh_acc[2]) atomicAdd(&slot[kAccAppended], sh_acc[2]);
     }
 }
 
@@ -856,23 +911,29 @@ __global__ __launch_bounds__(kBlock) void k_inc_list(const SingleArgs *__restric
     const SingleArgs a = *A;
     const RSOC_GLOBAL int32_t *rp = gro(a.rp);
     int32_t *const out = a.wl[0];
+    uint64_t apps = 0;
     if (threadIdx.x == 0) nqT = nqW = nqB = 0;
     __syncthreads();
     for (int64_t base = (int64_t)blockIdx.x * kBlock; base < a.n; base += (int64_t)gridDim.x * kBlock) {
         const int v = (int)(base + threadIdx.x);
         const bool m = v < a.n && mark[v] != 0;
         const int d = m ? rp[v + 1] - rp[v] : 0;
+        apps += m ? 1 : 0;
         queue_push(m && d > a.t_wave, v, qB, &nqB);
         queue_push(m && d > a.t_thread && d <= a.t_wave, v, qW, &nqW);
         queue_push(m && d <= a.t_thread, v, qT, &nqT);
-        __syncthreads();
-        if (nqB > kQueueCap - kBlock) queue_flush(qB, &nqB, &qbase, &S->cnt_out[kBinBlock], out + a.offB);
-        if (nqW > kQueueCap - kBlock) queue_flush(qW, &nqW, &qbase, &S->cnt_out[kBinWave], out + a.offW);
-        if (nqT > kQueueCap - kBlock) queue_flush(qT, &nqT, &qbase, &S->cnt_out[kBinThread], out);
+        int cB, cW, cT;
+        queue_sizes(&nqB, &nqW, &nqT, cB, cW, cT);
+        if (cB > kQueueCap - kBlock) queue_flush_n(cB, qB, &nqB, &qbase, &S->cnt_out[kBinBlock], out + a.offB);
+        if (cW > kQueueCap - kBlock) queue_flush_n(cW, qW, &nqW, &qbase, &S->cnt_out[kBinWave], out + a.offW);
+        if (cT > kQueueCap - kBlock) queue_flush_n(cT, qT, &nqT, &qbase, &S->cnt_out[kBinThread], out);
     }
     queue_flush(qB, &nqB, &qbase, &S->cnt_out[kBinBlock], out + a.offB);
     queue_flush(qW, &nqW, &qbase, &S->cnt_out[kBinWave], out + a.offW);
     queue_flush(qT, &nqT, &qbase, &S->cnt_out[kBinThread], out);
+    apps = wave_sum_u64(apps);
+    if (lane_id() == 0 && apps)
+        atomicAdd(&S->acc[(blockIdx.x % kAccSlots) * kAccStride + kAccAppended], (unsigned long long)apps);
 }
 
 // ------------------------------------------------------------ round end --
@@ -886,6 +947,9 @@ __global__ void k_round_end(const SingleArgs *__restrict__ A, SingleState *S) {
     if (threadIdx.x != 0) return;
     S->kmax = 0;
     S->distinct = 0;
+    // the appended list holds exactly the entries the round decided to append
+    if (acc_take(S, kAccAppended) != (unsigned long long)(S->cnt_out[0] + S->cnt_out[1] + S->cnt_out[2]))
+        S->err |= kErrListCount;
     if (PUBLISH_ONLY) {
         S->u0 = S->cnt_out[0] + S->cnt_out[1] + S->cnt_out[2];
         for (int b = 0; b < 3; ++b) {
@@ -895,12 +959,8 @@ __global__ void k_round_end(const SingleArgs *__restrict__ A, SingleState *S) {
         return;
     }
     if (!SWEEP && S->passes >= A->max_rounds) return;  // the guarded round did nothing
-    for (int k = 0; k < kAccSlots; ++k) {
-        unsigned long long *slot = S->acc + k * kAccStride;
-        S->inspected += slot[0];
-        S->deg_sum += slot[1];
-        slot[0] = slot[1] = 0;
-    }
+    S->inspected += acc_take(S, kAccItems);
+    S->deg_sum += acc_take(S, kAccDegs);
     const int in_total = SWEEP ? A->n : (S->cnt_in[0] + S->cnt_in[1] + S->cnt_in[2]);
     const int out_total = S->cnt_out[0] + S->cnt_out[1] + S->cnt_out[2];
     if (in_total > 0) {

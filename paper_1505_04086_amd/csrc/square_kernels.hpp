@@ -1,5 +1,5 @@
 // square_kernels.hpp -- the square G^2 of a graph, for distance-2 colouring
-// (Section 7: d-distance colouring is the colouring of the power graph G^d;
+// (Section 6: d-distance colouring is the colouring of the power graph G^d;
 // u and w are adjacent in G^2 iff they are within distance 2 in G).  Built
 // once on the device; the distance-1 rounds then colour it unchanged.
 //

@@ -354,7 +354,12 @@ __global__ __launch_bounds__(kBlock) void k_tail_seq(const SingleArgs *__restric
     }
     __syncthreads();
     if (tid < 3) S->cnt_out[tid] = cnt[tid];
-    if (tid == 0) S->inspected += (uint64_t)m;
+    if (tid == 0) {
+        S->inspected += (uint64_t)m;
+        unsigned long long rec = 0;
+        for (int i = 0; i < m; ++i) rec += recl[i];
+        S->acc[kAccAppended] += rec;
+    }
 }
 
 __global__ void k_tail_unmark(TailBuf t, int32_t *mark, int m) {

@@ -58,7 +58,10 @@ BIN_SPLITS = {"default": {}, "allbins": {"t_thread": 3, "t_wave": 8}, "wave_only
               "runs8": {"chunk": 8, "grid_thread": 5, "grid_list": 1}, "runs2": {"chunk": 2, "t_thread": 16},
               # optimistic ordered pass over small worklists: off, and at a
               # threshold of 4 with every degree bin in use
-              "notail": {"tail": -1}, "tail4": {"tail": 4, "t_thread": 3, "t_wave": 8}}
+              "notail": {"tail": -1}, "tail4": {"tail": 4, "t_thread": 3, "t_wave": 8},
+              # one workgroup per binning, sweep and worklist launch: its LDS
+              # queues fill and flush in the middle of their walks
+              "flush": {"grid_bin": 1, "grid_thread": 1, "grid_list": 1, "grid_wave": 1, "t_thread": 3, "t_wave": 8}}
 
 
 @pytest.mark.parametrize("split", sorted(BIN_SPLITS))
