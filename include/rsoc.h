@@ -55,10 +55,12 @@ typedef enum {
     RSOC_ENOCONV = -7,    /* the worklist was still non-empty after max_rounds passes */
     RSOC_EBUDGET = -8,    /* pool admission refused: HBM budget or slot table full */
     RSOC_ENOTFOUND = -9,  /* unknown or unfinished pool slot */
-    RSOC_EINTERNAL = -10  /* an internal consistency check failed on the device: a colour outside
+    RSOC_EINTERNAL = -10, /* an internal consistency check failed on the device: a colour outside
                              [0, degree], or a worklist / hub list whose size differs from an independent
                              count of the entries it must hold.  Never expected: it signals a defect of the
                              library, not of the input; the colours are then unspecified. */
+    RSOC_ESCRATCH = -11   /* the input needs more scratch than the fixed array of a no-allocation entry
+                             point holds (see rsoc_color_classes_noalloc); nothing was launched */
 } rsoc_status;
 
 typedef enum {
@@ -302,6 +304,25 @@ int32_t rsoc_recolor_device(rsoc_ctx *ctx, const int32_t *d_row_ptr, const int32
  */
 int32_t rsoc_color_classes(rsoc_ctx *ctx, const int32_t *d_colors, int32_t n, int32_t K, int32_t *d_class_ptr,
                            int32_t *d_class_vtx, void *hip_stream);
+
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the colour
+ * classes of rsoc_color_classes, with identical arguments and results, but
+ * without a context and without any allocation.  Its scratch is one fixed
+ * device array of 4,195,584 bytes per GPU (a count table of 2^20 entries, the
+ * scan sums and the state), created with the library and held until the
+ * process ends.  It runs on the current HIP device (hipSetDevice), on
+ * hip_stream, which must belong to that device and is synchronised before
+ * returning.  Every call on one GPU uses that GPU's array: calls that overlap
+ * on one GPU (other streams or host threads) race and must not be issued.
+ * Each call re-initialises what it reads, so consecutive calls need nothing
+ * cleared.  Returns RSOC_OK, RSOC_EINVAL as rsoc_color_classes, or
+ * RSOC_ESCRATCH when n > 2^30 (the count table must hold one colour's counts
+ * for every 1024 vertices); nothing is launched then.
+ */
+int32_t rsoc_color_classes_noalloc(const int32_t *d_colors, int32_t n, int32_t K, int32_t *d_class_ptr,
+                                   int32_t *d_class_vtx, void *hip_stream);
 
 /* Host-side CSR check (flags: RSOC_CHECK_*).  Returns RSOC_OK or the first error found. */
 int32_t rsoc_check_csr(const int32_t *row_ptr, const int32_t *col_idx, int32_t n, int32_t flags);

@@ -44,6 +44,7 @@ RSOC_ENOCONV = -7
 RSOC_EBUDGET = -8
 RSOC_ENOTFOUND = -9
 RSOC_EINTERNAL = -10
+RSOC_ESCRATCH = -11
 
 RSOC_MODE_OPTIMISTIC = 0
 RSOC_MODE_DETERMINISTIC = 1
@@ -100,6 +101,7 @@ _sig = {
     "rsoc_recolor_device": (_i32, [_p, _p, _p, _i32, _p, _p, _i32, ctypes.POINTER(rsoc_options),
                                    ctypes.POINTER(rsoc_stats), _p]),
     "rsoc_color_classes": (_i32, [_p, _p, _i32, _i32, _p, _p, _p]),
+    "rsoc_color_classes_noalloc": (_i32, [_p, _i32, _i32, _p, _p, _p]),
     "rsoc_check_csr": (_i32, [_p, _p, _i32, _i32]),
     "rsoc_strerror": (ctypes.c_char_p, [_i32]),
     "rsoc_last_error": (ctypes.c_char_p, []),
@@ -291,6 +293,13 @@ def rsoc_color_classes(ctx: Context, d_colors, n, K, d_class_ptr, d_class_vtx, s
     d_class_vtx (n); class k is d_class_vtx[d_class_ptr[k]:d_class_ptr[k+1]]."""
     _chk(_lib.rsoc_color_classes(ctx.h, _dev_ptr(d_colors), int(n), int(K), _dev_ptr(d_class_ptr),
                                  _dev_ptr(d_class_vtx), _stream_ptr(stream)), "rsoc_color_classes")
+
+
+def rsoc_color_classes_noalloc(d_colors, n, K, d_class_ptr, d_class_vtx, stream=None):
+    """rsoc_color_classes without a context and without allocating: runs on the
+    current device with the library's fixed per-GPU scratch (n <= 2^30)."""
+    _chk(_lib.rsoc_color_classes_noalloc(_dev_ptr(d_colors), int(n), int(K), _dev_ptr(d_class_ptr),
+                                         _dev_ptr(d_class_vtx), _stream_ptr(stream)), "rsoc_color_classes_noalloc")
 
 
 def rsoc_color_batch(ctx: Context, vtx_off, nnz_off, d_row_ptr_cat, d_col_idx_cat, d_colors_cat, options=None,

@@ -36,6 +36,7 @@ const char *rsoc_strerror(int32_t status) {
         case RSOC_ENOTFOUND: return "unknown or unfinished pool slot";
         case RSOC_EINTERNAL: return "internal consistency check failed (a colour outside [0, degree] or a list size "
                                     "that differs from its independent count): a library defect";
+        case RSOC_ESCRATCH: return "input larger than the fixed scratch of the no-allocation entry point allows";
         default: return status >= 0 ? "ok" : "unknown error";
     }
 }
@@ -164,6 +165,13 @@ int32_t rsoc_color_classes(rsoc_ctx *ctx, const int32_t *d_colors, int32_t n, in
         return RSOC_EINVAL;
     RSOC_HIP(hipSetDevice(ctx->device));
     return run_classes(ctx, d_colors, n, K, d_class_ptr, d_class_vtx, (hipStream_t)hip_stream);
+}
+
+int32_t rsoc_color_classes_noalloc(const int32_t *d_colors, int32_t n, int32_t K, int32_t *d_class_ptr,
+                                   int32_t *d_class_vtx, void *hip_stream) {
+    if (n < 0 || K < 0 || (n > 0 && K < 1) || !d_class_ptr || (n > 0 && (!d_colors || !d_class_vtx)))
+        return RSOC_EINVAL;
+    return run_classes_noalloc(d_colors, n, K, d_class_ptr, d_class_vtx, (hipStream_t)hip_stream);
 }
 
 static std::mutex g_default_mu;
