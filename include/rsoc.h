@@ -146,7 +146,20 @@ typedef struct {
      * fill and flush many times, which tests use to reach those flushes on
      * small graphs. */
     int32_t grid_bin;
-    int32_t reserved[1]; /* must be zero */
+    /* Optimistic mode, default round-0 flow, single-graph entry points: the
+     * vertices of degree above this threshold ("hubs"; 0 = library default,
+     * max(32, t_thread, max degree / 32); -1 = off; a value below t_thread
+     * counts as t_thread) are coloured first, one after another in tie
+     * order, each with the smallest colour absent among the hubs coloured
+     * before it; round 0 then colours every other vertex reading all of its
+     * neighbours, so that none takes a hub's colour and no hub is ever
+     * recoloured.  Without it, hubs are coloured at the start of round 0
+     * while their neighbours are still uncoloured, and recoloured later
+     * against all of them, which on power-law graphs costs hundreds of
+     * colours beyond sequential First-Fit.  Skipped (round 0 as without it)
+     * when more than 4096 vertices exceed the threshold. */
+    int32_t hub_first;
+    int32_t reserved[2]; /* must be zero */
 } rsoc_options;
 
 typedef struct {
@@ -168,7 +181,9 @@ typedef struct {
     int32_t per_round_cap;   /* its length */
     int32_t worklist0;       /* |U^0|: vertices round 1 inspects */
     int32_t chunk;           /* run length used by the sweeps */
-    int32_t reserved[3];
+    int32_t reserved[1];
+    int32_t *per_round_U;    /* optional caller array of per_round_cap entries: per_round_U[i] = |U| of
+                                inspection pass i+1 (U^0, then the previous round's L), for the passes run */
 } rsoc_stats;
 
 typedef struct rsoc_ctx rsoc_ctx;

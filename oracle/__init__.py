@@ -14,6 +14,10 @@ only marshals numpy arrays.  Functions:
   previous barrier; ties go to the lower id by default.
 * :func:`cat`    -- Algorithm 2 (Section 2.2) under the same reading.
 * :func:`check`  -- validity and the First-Fit bound c(v) <= deg(v).
+* :func:`omp_rsoc` -- Algorithm 3 as the paper runs it, on the host's cores
+  with OpenMP (``omp_rsoc.c``): live reads, thread-local parts of L.  A CPU
+  baseline, not a reference value: its result depends on the interleaving,
+  except with one thread, where it equals seq_ff.
 
 Parity status: seq_ff, rsync (both tie rules) and check are pinned by the
 ``-m "not gpu"`` tests (closed forms, hand-derived worked examples, networkx's
@@ -44,12 +48,22 @@ _TIES = {"lower": 0, "higher": 1, "none": 2, 0: 0, 1: 1, 2: 2}
 ENOCONV = -7
 
 
+_OMP_SRC = os.path.join(_HERE, "omp_rsoc.c")
+_OMP_LIB = os.path.join(_HERE, "libomprsoc.so")
+_omp = None
+
+
 def build(force: bool = True, src: str = _SRC, out: str = _LIB) -> str:
-    """Compile ``oracle.c`` (or another copy of it) into a shared library."""
+    """Compile ``oracle.c`` (or another copy of it) into a shared library; the
+    default build also compiles the OpenMP baseline ``omp_rsoc.c``."""
     if force or not os.path.exists(out):
         tmp = out + ".tmp%d" % os.getpid()
         subprocess.run(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-o", tmp, src], check=True)
         os.replace(tmp, out)
+    if src == _SRC and (force or not os.path.exists(_OMP_LIB)):
+        tmp = _OMP_LIB + ".tmp%d" % os.getpid()
+        subprocess.run(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-o", tmp, _OMP_SRC], check=True)
+        os.replace(tmp, _OMP_LIB)
     return out
 
 
@@ -235,6 +249,34 @@ def rsync_d2(row_ptr, col_idx, tie="lower", max_rounds=None, raise_on_noconv=Tru
 
 def recolor(row_ptr, col_idx, prev_colors, touched, tie="lower", max_rounds=None, raise_on_noconv=True):
     return default().recolor(row_ptr, col_idx, prev_colors, touched, tie, max_rounds, raise_on_noconv)
+
+
+def omp_rsoc(row_ptr, col_idx, tie="lower", threads=None, max_rounds=None):
+    """Algorithm 3 with OpenMP on `threads` host threads (default: the
+    OpenMP default).  Returns dict(colors, K, rounds, conflicts, threads)."""
+    global _omp
+    with _lock:
+        if _omp is None:
+            if not os.path.exists(_OMP_LIB) or os.path.getmtime(_OMP_LIB) < os.path.getmtime(_OMP_SRC):
+                build(force=True)
+            lib = ctypes.CDLL(_OMP_LIB)
+            p = ctypes.c_void_p
+            lib.omp_rsoc.argtypes = [ctypes.c_int32, p, p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, p,
+                                     ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)]
+            lib.omp_rsoc.restype = ctypes.c_int32
+            lib.omp_get_max_threads.restype = ctypes.c_int
+            _omp = lib
+    rp, ci, n = _csr(row_ptr, col_idx)
+    th = int(threads) if threads else int(_omp.omp_get_max_threads())
+    col = np.empty(max(n, 1), dtype=np.int32)
+    rounds = ctypes.c_int32(0)
+    conflicts = ctypes.c_int64(0)
+    k = _omp.omp_rsoc(n, rp.ctypes.data, ci.ctypes.data, _TIES[tie], th, int(max_rounds or 0), col.ctypes.data,
+                      ctypes.byref(rounds), ctypes.byref(conflicts))
+    if k < 0:
+        raise RuntimeError("omp_rsoc failed: %d" % k)
+    return {"colors": col[:n], "K": int(k), "rounds": int(rounds.value), "conflicts": int(conflicts.value),
+            "threads": th}
 
 
 def colour_count(colors) -> int:

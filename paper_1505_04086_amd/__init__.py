@@ -65,7 +65,8 @@ class rsoc_options(ctypes.Structure):
                 ("rounds_per_sync", ctypes.c_int32), ("small_cutoff", ctypes.c_int32),
                 ("timing", ctypes.c_int32), ("full_sweep", ctypes.c_int32), ("lookahead", ctypes.c_int32),
                 ("chunk", ctypes.c_int32), ("grid_list", ctypes.c_int32), ("tail", ctypes.c_int32),
-                ("distance", ctypes.c_int32), ("grid_bin", ctypes.c_int32), ("reserved", ctypes.c_int32 * 1)]
+                ("distance", ctypes.c_int32), ("grid_bin", ctypes.c_int32), ("hub_first", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 class rsoc_stats(ctypes.Structure):
@@ -75,7 +76,8 @@ class rsoc_stats(ctypes.Structure):
                 ("ms_round1", ctypes.c_double), ("bytes_round0", ctypes.c_int64), ("bytes_round1", ctypes.c_int64),
                 ("max_degree", ctypes.c_int32), ("bin_counts", ctypes.c_int32 * 3),
                 ("per_round_L", ctypes.POINTER(ctypes.c_int32)), ("per_round_cap", ctypes.c_int32),
-                ("worklist0", ctypes.c_int32), ("chunk", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("worklist0", ctypes.c_int32), ("chunk", ctypes.c_int32), ("reserved", ctypes.c_int32 * 1),
+                ("per_round_U", ctypes.POINTER(ctypes.c_int32))]
 
 
 _p = ctypes.c_void_p
@@ -150,11 +152,27 @@ def make_options(mode="optimistic", tie="lower", max_rounds=0, validate=0, **tun
     return o
 
 
-def stats_dict(st: rsoc_stats, L=None) -> dict:
-    d = {f: getattr(st, f) for f, _ in rsoc_stats._fields_ if f not in ("per_round_L", "reserved", "bin_counts")}
+def _per_round_arrays(st: rsoc_stats, cap: int):
+    """Caller arrays for |L| per round and |U| per pass (kept alive by the
+    returned pair), or None."""
+    if not cap:
+        return None
+    L = np.zeros(cap, dtype=np.int32)
+    U = np.zeros(cap, dtype=np.int32)
+    st.per_round_L = L.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    st.per_round_U = U.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    st.per_round_cap = cap
+    return L, U
+
+
+def stats_dict(st: rsoc_stats, LU=None) -> dict:
+    d = {f: getattr(st, f) for f, _ in rsoc_stats._fields_
+         if f not in ("per_round_L", "per_round_U", "reserved", "bin_counts")}
     d["bin_counts"] = list(st.bin_counts)
-    if L is not None:
+    if LU is not None:
+        L, U = LU
         d["L_sizes"] = L[:min(st.rounds, len(L))].copy()
+        d["U_sizes"] = U[:min(st.passes, len(U))].copy()
     return d
 
 
@@ -241,11 +259,7 @@ def rsoc_color_ex(ctx: Context, row_ptr, col_idx, n=None, colors_out=None, optio
     out = np.empty(max(n, 1), dtype=np.int32) if colors_out is None else colors_out
     o = options if options is not None else make_options()
     st = rsoc_stats()
-    L = None
-    if per_round_cap:
-        L = np.zeros(per_round_cap, dtype=np.int32)
-        st.per_round_L = L.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
-        st.per_round_cap = per_round_cap
+    L = _per_round_arrays(st, per_round_cap)
     k = _chk(_lib.rsoc_color_ex(ctx.h, rpp, cip, n, out.ctypes.data, ctypes.byref(o), ctypes.byref(st)),
              "rsoc_color_ex", ok_noconv=allow_noconv)
     return out[:n], k, stats_dict(st, L)
@@ -256,11 +270,7 @@ def rsoc_color_device(ctx: Context, d_row_ptr, d_col_idx, n, d_colors_out, optio
     """Device-tensor colouring.  Returns (K, stats dict)."""
     o = options if options is not None else make_options()
     st = rsoc_stats()
-    L = None
-    if per_round_cap:
-        L = np.zeros(per_round_cap, dtype=np.int32)
-        st.per_round_L = L.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
-        st.per_round_cap = per_round_cap
+    L = _per_round_arrays(st, per_round_cap)
     k = _chk(_lib.rsoc_color_device(ctx.h, _dev_ptr(d_row_ptr), _dev_ptr(d_col_idx), int(n), _dev_ptr(d_colors_out),
                                     ctypes.byref(o), ctypes.byref(st), _stream_ptr(stream)),
              "rsoc_color_device", ok_noconv=allow_noconv)
@@ -275,11 +285,7 @@ def rsoc_recolor_device(ctx: Context, d_row_ptr, d_col_idx, n, d_colors_inout, d
     Returns (K, stats dict)."""
     o = options if options is not None else make_options()
     st = rsoc_stats()
-    L = None
-    if per_round_cap:
-        L = np.zeros(per_round_cap, dtype=np.int32)
-        st.per_round_L = L.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
-        st.per_round_cap = per_round_cap
+    L = _per_round_arrays(st, per_round_cap)
     nt = 0 if d_touched is None else int(d_touched.numel())
     k = _chk(_lib.rsoc_recolor_device(ctx.h, _dev_ptr(d_row_ptr), _dev_ptr(d_col_idx), int(n),
                                       _dev_ptr(d_colors_inout), _dev_ptr(d_touched) if nt else None, nt,

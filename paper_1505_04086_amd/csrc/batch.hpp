@@ -121,10 +121,11 @@ inline int32_t run_batch(rsoc_ctx *c, int32_t G, const int64_t *vtx_off, const i
                          const int32_t *ci, int32_t *col, int32_t *counts_out, const Options &o, rsoc_stats *st,
                          hipStream_t s) {
     if (st) {
-        int32_t *keep = st->per_round_L;
+        int32_t *keep = st->per_round_L, *keepU = st->per_round_U;
         int32_t cap = st->per_round_cap;
         memset(st, 0, sizeof(*st));
         st->per_round_L = keep;
+        st->per_round_U = keepU;
         st->per_round_cap = cap;
     }
     if (vtx_off[0] != 0 || nnz_off[0] != 0) return RSOC_ECSR;

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_ext.h>
+#include <algorithm>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <stdio.h>
@@ -93,7 +94,7 @@ struct HostPinned {
 
 struct Options {
     int mode, tie, max_rounds, validate, t_thread, t_wave, grid_thread, grid_wave, rounds_per_sync, small_cutoff,
-        timing, full_sweep, lookahead, chunk, grid_list, tail, distance, grid_bin;
+        timing, full_sweep, lookahead, chunk, grid_list, tail, distance, grid_bin, hub_first;
 };
 
 inline int32_t resolve_options(const rsoc_options *o, int64_t n, Options &r) {
@@ -107,7 +108,8 @@ inline int32_t resolve_options(const rsoc_options *o, int64_t n, Options &r) {
     if (d.max_rounds < 0 || d.t_thread < 0 || d.t_thread > 32 || d.t_wave < 0 || d.grid_thread < 0 ||
         d.grid_wave < 0 || d.rounds_per_sync < 0 || d.validate < 0 || d.validate > 3 || d.grid_list < 0)
         return RSOC_EINVAL;
-    if (d.reserved[0] || d.grid_bin < 0) return RSOC_EINVAL;
+    if (d.reserved[0] || d.reserved[1] || d.grid_bin < 0) return RSOC_EINVAL;
+    if (d.hub_first < -1) return RSOC_EINVAL;
     r.grid_bin = d.grid_bin;  // 0: each launch site's own default
     if (d.distance < 0 || d.distance > 2) return RSOC_EINVAL;
     r.distance = d.distance == 2 ? 2 : 1;
@@ -131,6 +133,10 @@ inline int32_t resolve_options(const rsoc_options *o, int64_t n, Options &r) {
     if (r.rounds_per_sync & 1) r.rounds_per_sync += 1;  // worklist buffers alternate: keep it even
     r.small_cutoff = d.small_cutoff == 0 ? 4096 : (d.small_cutoff < 0 ? -1 : d.small_cutoff);
     r.timing = d.timing;
+    // hub threshold: 0 = off, -1 = automatic (from the max degree, on the
+    // device), else the degree given, never below the lane-group bin's limit,
+    // so that hubs are wavefront- or workgroup-bin vertices
+    r.hub_first = d.hub_first == -1 ? 0 : (d.hub_first == 0 ? -1 : std::max(d.hub_first, r.t_thread));
     return RSOC_OK;
 }
 

@@ -35,6 +35,7 @@ struct rsoc_pool {
     std::vector<char> pending;   // admitted, set-up enqueued, host fields not yet final
     hipEvent_t ev = nullptr;     // recorded after admission / release work on the context's stream
     rsoc::HostPinned stage;      // step download of all slots (copied into the mirror for active ones)
+    rsoc::DevBuf hub_args, hub_state, hubs;  // hub-first pass at admission (hub_kernels.hpp)
 };
 
 namespace rsoc {
@@ -155,7 +156,9 @@ void rsoc_pool_destroy(rsoc_pool *p) {
     for (auto &a : p->allocs)
         if (a.own) (void)hipFree(a.own);
     if (p->ev) (void)hipStreamSynchronize(p->ctx->own);
-    for (rsoc::DevBuf *b : {&p->slots_dev, &p->tasks_dev, &p->active_dev, &p->arena}) b->release();
+    for (rsoc::DevBuf *b : {&p->slots_dev, &p->tasks_dev, &p->active_dev, &p->arena, &p->hub_args, &p->hub_state,
+                            &p->hubs})
+        b->release();
     for (rsoc::HostPinned *b : {&p->mirror, &p->tasks_host, &p->active_host, &p->stage}) b->release();
     if (p->ev) (void)hipEventDestroy(p->ev);
     delete p;
@@ -227,11 +230,35 @@ inline int32_t pool_admit(rsoc_pool *p, const int32_t *d_row_ptr, const int32_t 
     m.recolor = recolor ? 1 : 0;
     m.touched = d_touched;
     m.nt = recolor ? nt : 0;
+    m.hub_opt = (o.mode == kOptimistic && !recolor) ? o.hub_first : 0;
+    if (m.hub_opt != 0 && n > 0) {
+        if ((r = p->hub_args.reserve(sizeof(SingleArgs))) < 0 || (r = p->hub_state.reserve(sizeof(SingleState))) < 0 ||
+            (r = p->hubs.reserve(kHubBytes)) < 0) {
+            pool_release(p, slot);
+            return r;
+        }
+    }
     p->reported[slot] = 0;
     if ((r = pool_upload_slot(p, slot, s)) < 0) { pool_release(p, slot); return r; }
     if (n > 0) {
         const int gbin = std::min(div_up(n, kBlock), o.grid_bin ? o.grid_bin : 1024);
         k_pinit<<<gbin, kBlock, 0, s>>>(p->slots_dev.as<PoolSlot>(), slot);
+        if (m.hub_opt != 0) {
+            SingleArgs *A = p->hub_args.as<SingleArgs>();
+            SingleState *S = p->hub_state.as<SingleState>();
+            int32_t *tables = p->hubs.as<int32_t>();
+            uint16_t *entries = reinterpret_cast<uint16_t *>(tables + 4 * kHubCap);
+            k_phub_setup<<<1, 64, 0, s>>>(p->slots_dev.as<PoolSlot>(), slot, A, S, tables, entries);
+            k_phub_collect<<<gbin, kBlock, 0, s>>>(A, S);
+            if (o.tie) {
+                k_hub_lists<kHigherKeeps><<<kHubListGrid, kBlock, 0, s>>>(A, S);
+                k_hub_ff<kHigherKeeps><<<1, kHubFfBlock, 0, s>>>(A, S);
+            } else {
+                k_hub_lists<kLowerKeeps><<<kHubListGrid, kBlock, 0, s>>>(A, S);
+                k_hub_ff<kLowerKeeps><<<1, kHubFfBlock, 0, s>>>(A, S);
+            }
+            k_phub_done<<<1, 64, 0, s>>>(p->slots_dev.as<PoolSlot>(), slot, S);
+        }
         if (recolor) {
             if (nt > 0) k_ptouch<<<std::min(div_up(nt, kBlock), 256), kBlock, 0, s>>>(p->slots_dev.as<PoolSlot>(), slot);
             k_plist<<<gbin, kBlock, 0, s>>>(p->slots_dev.as<PoolSlot>(), slot);
@@ -424,7 +451,11 @@ int32_t rsoc_pool_step(rsoc_pool *p, void *hip_stream, int32_t *finished_slots, 
         for (int k = 0; k < nact; ++k) {
             const int i = act[k];
             if (m[i].phase != kSlotDone) continue;
+            const bool wide = m[i].maxdeg >= 255 && m[i].n > 255;  // colours of 255 and more possible
+            if (wide) k_pflags_clear<<<std::min(div_up(m[i].maxdeg, kBlock), 64), kBlock, 0, s>>>(
+                p->slots_dev.as<PoolSlot>(), i);
             k_pcount<<<std::min(div_up(m[i].n, kBlock), 1024), kBlock, 0, s>>>(p->slots_dev.as<PoolSlot>(), i);
+            if (wide) k_pdistinct<<<1, kBlock, 0, s>>>(p->slots_dev.as<PoolSlot>(), i);
             RSOC_HIP(hipMemcpyAsync(st + i, p->slots_dev.as<PoolSlot>() + i, sizeof(PoolSlot), hipMemcpyDeviceToHost,
                                     s));
             counted = true;
@@ -464,15 +495,18 @@ int32_t rsoc_pool_result(rsoc_pool *p, int32_t slot, rsoc_stats *stats) {
     rsoc_ctx *c = p->ctx;
     RSOC_HIP(hipSetDevice(c->device));
     if (stats) {
-        int32_t *keep = stats->per_round_L;
+        int32_t *keep = stats->per_round_L, *keepU = stats->per_round_U;
         int32_t cap = stats->per_round_cap;
         memset(stats, 0, sizeof(*stats));
         stats->per_round_L = keep;
+        stats->per_round_U = keepU;
         stats->per_round_cap = cap;
         stats->rounds = m.rounds;
         stats->passes = m.passes;
         stats->colors = m.kmax;
-        stats->colors_distinct = -1;
+        int distinct = m.distinct;
+        for (uint32_t w : m.cbits) distinct += __builtin_popcount(w);
+        stats->colors_distinct = m.status < 0 ? 0 : distinct;
         stats->conflicts = m.conflicts;
         stats->max_degree = m.maxdeg;
         stats->bin_counts[0] = m.n - m.nW - m.nB;

@@ -7,6 +7,7 @@
 // older slots run a later worklist round.  Mode and tie rule are per slot.
 #pragma once
 
+#include "hub_kernels.hpp"
 #include "single_kernels.hpp"
 
 namespace rsoc {
@@ -40,7 +41,55 @@ struct PoolSlot {
     const int32_t *touched;  // recolouring after edits: the touched vertices (nt of them)
     int32_t nt, recolor;     // recolor: the slot starts from the colouring in col
     uint64_t near, sampled;  // id locality sample (admission)
+    uint32_t cbits[8];       // colours below 255 in use (k_pcount, once the slot is done)
+    int32_t distinct;        // distinct colours of 255 and more (k_pdistinct)
+    // hub-first round 0 (hub_kernels.hpp): hub_opt is the option (0 off, -1
+    // automatic threshold, else the threshold); nH hubs were coloured at
+    // admission, those above hub_t
+    int32_t hub_opt, nH, hub_t;
 };
+
+// Hub-first pass of an optimistic slot at admission, with the single-graph
+// kernels: k_phub_setup fills a SingleArgs / SingleState of the pool's (one
+// set, shared by the admissions, which run one after another on one stream)
+// from the slot, k_phub_collect collects the hubs, k_hub_lists and k_hub_ff
+// colour them, k_phub_done copies their number and threshold into the slot.
+__global__ void k_phub_setup(PoolSlot *slots, int slot, SingleArgs *A, SingleState *S, int32_t *hub_tables,
+                             uint16_t *hub_entries) {
+    if (threadIdx.x != 0) return;
+    const PoolSlot *sp = slots + slot;
+    SingleArgs a = {};
+    a.rp = sp->rp;
+    a.ci = sp->ci;
+    a.col = sp->col;
+    a.col8 = sp->col8;
+    a.col4 = sp->col4;
+    a.hubW = sp->hubW;
+    a.hubB = sp->hubB;
+    a.n = sp->n;
+    a.t_thread = sp->t_thread;
+    a.t_wave = sp->t_wave;
+    a.hub_t = sp->hub_opt;
+    a.hubC = hub_tables;
+    a.hubS = hub_tables + kHubCap;
+    a.hub_ls = hub_tables + 2 * kHubCap;
+    a.hub_ll = hub_tables + 3 * kHubCap;
+    a.hub_le = hub_entries;
+    *A = a;
+    S->nW = sp->nW;
+    S->nB = sp->nB;
+    S->maxdeg = sp->maxdeg;
+    S->err = sp->status < 0 ? kErrNoRun : 0;
+    S->nH = S->nHc = S->hub_t = S->hub_ecnt = 0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_phub_collect(const SingleArgs *A, SingleState *S) { hub_collect(A, S); }
+
+__global__ void k_phub_done(PoolSlot *slots, int slot, const SingleState *S) {
+    if (threadIdx.x != 0) return;
+    slots[slot].nH = S->nH;
+    slots[slot].hub_t = S->hub_t;
+}
 
 struct PoolTask {
     int32_t slot, kind, begin, end;
@@ -197,7 +246,9 @@ __device__ __forceinline__ void pool_thread_task(PoolSlot *sp, const PoolSlot &s
             const RSOC_GLOBAL uint32_t *c4s[kNV];
 #pragma unroll
             for (int i = 0; i < kNV; ++i) cis[i] = ci, c8s[i] = c8, c4s[i] = c4;
-            group_vertices<PHASE, TIE, kGroup, kGroupSlots, kWinOnly, kNV, kNib>(v, b, e, cis, c8s, cv, s.look, nc,
+            // after a hub-first pass round 0 reads all neighbours (hub colours)
+            const int look = (KIND == kAssignSweep && s.nH) ? INT_MAX : s.look;
+            group_vertices<PHASE, TIE, kGroup, kGroupSlots, kWinOnly, kNV, kNib>(v, b, e, cis, c8s, cv, look, nc,
                                                                                  act, unc, c4s, kNib ? keep : nullptr);
 #pragma unroll
             for (int i = 0; i < kNV; ++i) {
@@ -287,12 +338,15 @@ __device__ __forceinline__ void pool_wave_task(PoolSlot *sp, const PoolSlot &s, 
     int32_t *out = (s.parity ? s.wl[0] : s.wl[1]) + s.offW;
     if (lane_id() == 0) *wbn = 0;
     wave_lds_sync();
+    const bool hubs = KIND == kAssignSweep && s.nH > 0;  // hub-first: hubs done, all neighbours read
     for (int i = tk.begin + wv; i < tk.end; i += kWavesPerBlock) {
         const int v = in[i];
         const int b = s.rp[v], e = s.rp[v + 1];
+        if (hubs && e - b > s.hub_t) continue;  // a hub (wavefront-uniform)
         int nc = 0;
         bool unc = false;
-        const bool act = wave_vertex<PHASE, TIE, kWinOnly>(v, b, e, gro(s.ci), gro(s.col), gro(s.col8), bm, s.look, nc, unc);
+        const bool act = wave_vertex<PHASE, TIE, kWinOnly>(v, b, e, gro(s.ci), gro(s.col), gro(s.col8), bm,
+                                                           hubs ? INT_MAX : s.look, nc, unc, hubs);
         if (lane_id() == 0 && act) {
             (opt ? s.col : s.pend)[v] = nc;
             if (opt) s.col8[v] = shadow_of(nc);
@@ -311,13 +365,15 @@ __device__ __forceinline__ void pool_block_task(PoolSlot *sp, const PoolSlot &s,
     const bool opt = s.mode == kOptimistic;
     const int32_t *in = (KIND == kRecolorList) ? (s.parity ? s.wl[1] : s.wl[0]) + s.offB : s.hubB;
     int32_t *out = (s.parity ? s.wl[0] : s.wl[1]) + s.offB;
+    const bool hubs = KIND == kAssignSweep && s.nH > 0;  // hub-first: hubs done, all neighbours read
     for (int i = tk.begin; i < tk.end; ++i) {
         const int v = in[i];
         const int b = s.rp[v], e = s.rp[v + 1];
+        if (hubs && e - b > s.hub_t) continue;  // a hub (workgroup-uniform)
         int nc = 0;
         bool unc = false;
-        const bool act = block_vertex<PHASE, TIE, kWinOnly>(v, b, e, gro(s.ci), gro(s.col), gro(s.col8), lds, sh_min, s.look, nc,
-                                                              unc);
+        const bool act = block_vertex<PHASE, TIE, kWinOnly>(v, b, e, gro(s.ci), gro(s.col), gro(s.col8), lds, sh_min,
+                                                            hubs ? INT_MAX : s.look, nc, unc, hubs);
         if (threadIdx.x == 0) {
             if (act) {
                 (opt ? s.col : s.pend)[v] = nc;
@@ -422,19 +478,54 @@ __global__ void k_pround_end(PoolSlot *slots, const int32_t *__restrict__ active
     }
 }
 
+// Colour statistics of a finished slot: K (kmax), the colours below 255 in
+// use (cbits), and a flag per colour of 255 and more in the slot's first
+// worklist buffer (free once the slot is done; k_pflags_clear zeroed the
+// flags up to its max degree, which bounds every colour).
 __global__ __launch_bounds__(kBlock) void k_pcount(PoolSlot *slots, int slot) {
     __shared__ int sh[kWavesPerBlock];
+    __shared__ uint32_t bits[8];
     PoolSlot *sp = slots + slot;
+    if (threadIdx.x < 8) bits[threadIdx.x] = 0;
+    __syncthreads();
+    int32_t *flags = sp->wl[0];
     int m = -1;
     bool bad = false;
     for (int v = blockIdx.x * kBlock + threadIdx.x; v < sp->n; v += gridDim.x * kBlock) {
         const int c = sp->col[v];
         bad |= (c < 0 || c >= sp->n);
         m = max(m, c);
+        if (c >= 0 && c < 255) lds_or(&bits[c >> 5], 1u << (c & 31));
+        else if (c >= 255 && c < sp->n) flags[c] = 1;
     }
     if (ballot(bad) && lane_id() == 0) atomicOr(&sp->err, 4);
     m = block_max(m, sh);
     if (threadIdx.x == 0) atomicMax(&sp->kmax, m + 1);
+    if (threadIdx.x < 8 && bits[threadIdx.x]) atomicOr(&sp->cbits[threadIdx.x], bits[threadIdx.x]);
+}
+
+// Zeroes the flags k_pcount sets: colours 255 .. min(max degree, n - 1).
+__global__ __launch_bounds__(kBlock) void k_pflags_clear(PoolSlot *slots, int slot) {
+    PoolSlot *sp = slots + slot;
+    const int hi = min(sp->maxdeg, sp->n - 1);
+    for (int c = 255 + blockIdx.x * kBlock + threadIdx.x; c <= hi; c += gridDim.x * kBlock) sp->wl[0][c] = 0;
+}
+
+// Counts the flags of colours 255 .. kmax - 1 into sp->distinct.
+__global__ __launch_bounds__(kBlock) void k_pdistinct(PoolSlot *slots, int slot) {
+    __shared__ int sh[kWavesPerBlock];
+    PoolSlot *sp = slots + slot;
+    const int hi = min(sp->kmax, sp->n);
+    int cnt = 0;
+    for (int c = 255 + (int)threadIdx.x; c < hi; c += kBlock) cnt += sp->wl[0][c];
+    for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
+    if (lane_id() == 0) sh[threadIdx.x / kWave] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int t = 0;
+        for (int w = 0; w < kWavesPerBlock; ++w) t += sh[w];
+        sp->distinct = t;
+    }
 }
 
 }  // namespace rsoc

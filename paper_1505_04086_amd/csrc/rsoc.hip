@@ -116,10 +116,11 @@ int32_t rsoc_color_ex(rsoc_ctx *ctx, const int32_t *row_ptr, const int32_t *col_
     RSOC_TRY(resolve_options(opts, n, o));
     if (n == 0) {
         if (stats) {
-            int32_t *keep = stats->per_round_L;
+            int32_t *keep = stats->per_round_L, *keepU = stats->per_round_U;
             int32_t cap = stats->per_round_cap;
             memset(stats, 0, sizeof(*stats));
             stats->per_round_L = keep;
+            stats->per_round_U = keepU;
             stats->per_round_cap = cap;
         }
         return 0;

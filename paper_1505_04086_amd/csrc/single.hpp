@@ -15,9 +15,11 @@
 #pragma once
 
 #include <map>
+#include <vector>
 #include <tuple>
 
 #include "host_common.hpp"
+#include "hub_kernels.hpp"
 #include "single_kernels.hpp"
 #include "tail_kernels.hpp"
 
@@ -27,6 +29,7 @@ struct rsoc_ctx {
     hipStream_t cap = nullptr;    // capture stream
     rsoc::DevBuf wl0, wl1, hubW, hubB, pend, flags, col8, col4, aux;
     rsoc::DevBuf mark, tail;      // ordered pass over a small worklist (tail_kernels.hpp)
+    rsoc::DevBuf hubs;            // hub-first round 0: sorted hubs, their lists (hub_kernels.hpp)
     rsoc::DevBuf cls_h, cls_p, cls_st;  // colour classes (classes.hpp)
     rsoc::DevBuf sq_t, sq_rp, sq_ci, sq_misc, sq_big;  // G^2 for distance-2 colouring (square.hpp)
     rsoc::DevBuf args, state;     // SingleArgs, SingleState (fixed addresses: graphs point at them)
@@ -72,7 +75,7 @@ inline void ctx_free(rsoc_ctx *c) {
     c->graphs.clear();
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);
-    for (rsoc::DevBuf *b : {&c->col8, &c->col4, &c->aux, &c->mark, &c->tail, &c->cls_h, &c->cls_p, &c->cls_st,
+    for (rsoc::DevBuf *b : {&c->col8, &c->col4, &c->aux, &c->mark, &c->tail, &c->hubs, &c->cls_h, &c->cls_p, &c->cls_st,
                             &c->sq_t, &c->sq_rp, &c->sq_ci, &c->sq_misc, &c->sq_big, &c->wl0, &c->wl1, &c->hubW, &c->hubB, &c->pend, &c->flags, &c->args, &c->state, &c->drp,
                             &c->dci, &c->dcol, &c->b_desc, &c->b_wl0, &c->b_wl1, &c->b_pend, &c->b_flags,
                             &c->b_state, &c->b_hub, &c->b_kmax, &c->b_tasks, &c->b_args, &c->b_col8})
@@ -317,10 +320,11 @@ inline int32_t run_single(rsoc_ctx *c, const int32_t *rp, const int32_t *ci, int
     HostStaging *h = c->host.as<HostStaging>();
     SingleState *S = c->state.as<SingleState>();
     if (st) {
-        int32_t *keep = st->per_round_L;
+        int32_t *keep = st->per_round_L, *keepU = st->per_round_U;
         int32_t cap = st->per_round_cap;
         memset(st, 0, sizeof(*st));
         st->per_round_L = keep;
+        st->per_round_U = keepU;
         st->per_round_cap = cap;
     }
     if (n == 0) return 0;
@@ -350,6 +354,21 @@ inline int32_t run_single(rsoc_ctx *c, const int32_t *rp, const int32_t *ci, int
     a.look_auto = o.lookahead == 0 ? 1 : 0;
     a.chunk = inc ? 1 : o.chunk;  // 0: k_args picks it from the locality sample
     a.flags = c->flags.as<int32_t>();
+    // hub-first round 0: optimistic default flow only (the round-synchronous
+    // modes fix their result; the literal flow keeps the paper's round 0)
+    const bool hub_first = o.hub_first != 0 && o.mode == kOptimistic && !o.full_sweep && !inc;
+    a.hub_t = hub_first ? o.hub_first : 0;
+    a.hubC = a.hubS = a.hub_ls = a.hub_ll = nullptr;
+    a.hub_le = nullptr;
+    if (hub_first) {
+        RSOC_TRY(c->hubs.reserve(kHubBytes));
+        int32_t *hb = c->hubs.as<int32_t>();
+        a.hubC = hb;
+        a.hubS = hb + kHubCap;
+        a.hub_ls = hb + 2 * kHubCap;
+        a.hub_ll = hb + 3 * kHubCap;
+        a.hub_le = reinterpret_cast<uint16_t *>(hb + 4 * kHubCap);
+    }
     k_setup<<<1, kBlock, 0, s>>>(c->args.as<SingleArgs>(), a, S, (int)(kStateHeader / 4), 1);
     // binning: each workgroup ends with one global atomic per non-empty hub
     // queue, so fewer, longer-running workgroups (power-law graphs fill the
@@ -392,6 +411,17 @@ inline int32_t run_single(rsoc_ctx *c, const int32_t *rp, const int32_t *ci, int
                   opt ? c->col4.as<uint32_t>() : (uint32_t *)nullptr, (int64_t)(opt ? n / 8 + 1 : 0));
         RSOC_LAUNCH_CHECK();
         if (timing && !opt) RSOC_HIP(hipEventRecord(c->ev[3], s));
+        if (hub_first) {
+            const SingleArgs *A = c->args.as<SingleArgs>();
+            if (o.tie) {
+                k_hub_lists<kHigherKeeps><<<kHubListGrid, kBlock, 0, s>>>(A, S);
+                k_hub_ff<kHigherKeeps><<<1, kHubFfBlock, 0, s>>>(A, S);
+            } else {
+                k_hub_lists<kLowerKeeps><<<kHubListGrid, kBlock, 0, s>>>(A, S);
+                k_hub_ff<kLowerKeeps><<<1, kHubFfBlock, 0, s>>>(A, S);
+            }
+            RSOC_LAUNCH_CHECK();
+        }
         const int gB = validate ? std::min(h->head.nB, 1024) : std::min(n, 1024);
         const int gW = std::min(div_up(validate ? h->head.nW : n, kWavesPerBlock), o.grid_wave);
         masked = launch_sweep_dyn(c, s, o.mode, o.tie, col, n, gB, gW, gTs, timing, o.full_sweep != 0);
@@ -458,11 +488,22 @@ inline int32_t run_single(rsoc_ctx *c, const int32_t *rp, const int32_t *ci, int
             RSOC_LAUNCH_CHECK();
         }
     }
-    if (st && st->per_round_L && st->per_round_cap > 0) {
-        const int cnt = std::min(std::min(h->head.rounds, st->per_round_cap), kHistCap);
+    if (st && (st->per_round_L || st->per_round_U) && st->per_round_cap > 0) {
+        // |L| of round i+1 is the device history; |U| of pass i+1 is U^0 for
+        // the first pass and the previous round's |L| after it (U <- L)
+        const int cnt = std::min(std::min(std::max(h->head.rounds, h->head.passes), st->per_round_cap), kHistCap);
+        std::vector<int32_t> hist((size_t)std::max(cnt, 1), 0);
         if (cnt > 0) {
-            RSOC_HIP(hipMemcpyAsync(st->per_round_L, S->hist, sizeof(int32_t) * cnt, hipMemcpyDeviceToHost, s));
+            RSOC_HIP(hipMemcpyAsync(hist.data(), S->hist, sizeof(int32_t) * cnt, hipMemcpyDeviceToHost, s));
             RSOC_HIP(hipStreamSynchronize(s));
+        }
+        if (st->per_round_L)
+            for (int i = 0; i < std::min(h->head.rounds, cnt); ++i) st->per_round_L[i] = hist[i];
+        if (st->per_round_U) {
+            const bool sweep1u = !inc && !(o.mode == kOptimistic && !o.full_sweep);
+            const int np = std::min(h->head.passes, st->per_round_cap);
+            for (int i = 0; i < np; ++i)
+                st->per_round_U[i] = i == 0 ? (sweep1u ? n : h->head.u0) : (i - 1 < cnt ? hist[i - 1] : 0);
         }
     }
     if (h->head.err & (4 | kErrListCount)) return RSOC_EINTERNAL;  // never expected

@@ -37,7 +37,27 @@ struct SingleArgs {
     int32_t chunk;       // run of consecutive ids one lane group walks (1, 2, 4 or 8)
     int32_t look_auto;   // look is the default: k_args sets it to 0 once chunk turns out 1
     int32_t *flags;      // flags[c] for colours c >= 255 in use (zero between calls)
+    // hub-first round 0 (optimistic, default flow; hub_kernels.hpp): hub_t is
+    // the degree above which a vertex is a hub (0: off; -1: chosen from the
+    // max degree, see hub_threshold); hubC the hubs as binning's lists give
+    // them, hubS the same sorted by id; hub_ls / hub_ll / hub_le the list of
+    // each hub (by its position in tie order): the positions of the hubs it
+    // loses to
+    int32_t hub_t;
+    int32_t *hubC, *hubS;
+    int32_t *hub_ls, *hub_ll;
+    uint16_t *hub_le;
 };
+
+// Hub-first round 0: at most kHubCap hubs (else the pass is skipped); the
+// automatic threshold is max(t_thread, kHubMinDeg, max degree / kHubDiv).
+constexpr int kHubCap = 4096;
+constexpr int kHubMinDeg = 32;
+constexpr int kHubDiv = 32;
+
+__device__ __forceinline__ int hub_threshold(const SingleArgs &a, int maxdeg) {
+    return a.hub_t > 0 ? a.hub_t : max(max(a.t_thread, kHubMinDeg), maxdeg / kHubDiv);
+}
 
 constexpr int kAccSlots = 16;   // cache lines the inspection counts are spread over
 constexpr int kAccStride = 16;  // 64-bit words per line (128 bytes)
@@ -47,6 +67,7 @@ constexpr int kAccStride = 16;  // 64-bit words per line (128 bytes)
 // queues), and the rows binning found in the wavefront / workgroup ranges.
 enum AccWord : int { kAccItems = 0, kAccDegs = 1, kAccAppended = 2, kAccBinW = 3, kAccBinB = 4 };
 constexpr int kErrListCount = 32;
+constexpr int kErrNoRun = 1 | 8;  // err bits that keep the sweeps from running (bad row_ptr ends, no col_idx)
 
 // Device-side round state.
 struct SingleState {
@@ -72,6 +93,10 @@ struct SingleState {
     int32_t chunk;        // run length of the sweeps (k_args)
     uint64_t inspected1, deg_sum1;  // inspected / deg_sum as they stood after the first worklist round
     uint64_t near, sampled;  // id locality sample: row entries with |u - v| < kChunk, entries sampled
+    int32_t nH;           // hubs coloured before round 0 (0: none, or the hub-first pass is off)
+    int32_t nHc;          // vertices above the hub threshold (k_args; the pass is off above kHubCap)
+    int32_t hub_t;        // the hub threshold in use (k_args)
+    int32_t hub_ecnt;     // entries of the hub lists
     int32_t hist[kHistCap];  // |L| of recolouring round i+1
     // worklist rounds' inspection counts (inspected, degree sum), spread over
     // kAccSlots cache lines so that a round's workgroups do not all add to one
@@ -291,12 +316,37 @@ __device__ __forceinline__ unsigned long long acc_take(SingleState *S, int w) {
     return t;
 }
 
+// Hub-first round 0 (hub_kernels.hpp), called by a whole grid once binning is
+// done: every vertex above the hub threshold joins hubC (only the wavefront
+// and workgroup bins can hold one: the threshold is at least t_thread);
+// S->nHc counts them, also past kHubCap; S->hub_t = the threshold.
+__device__ __forceinline__ void hub_collect(const SingleArgs *A, SingleState *S) {
+    if (A->hub_t == 0 || (S->err & kErrNoRun)) return;
+    const int maxdeg = S->maxdeg;
+    const int T = hub_threshold(*A, maxdeg);
+    if (blockIdx.x == 0 && threadIdx.x == 0) S->hub_t = T;
+    if (maxdeg <= T) return;
+    const int nW = S->nW, nB = S->nB;
+    const int from = T >= A->t_wave ? nW : 0;  // rows above t_wave are all in the workgroup bin
+    const RSOC_GLOBAL int32_t *rp = gro(A->rp);
+    for (int64_t i = from + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (int64_t)nW + nB;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int v = i < nW ? A->hubW[i] : A->hubB[i - nW];
+        const bool hub = rp[v + 1] - rp[v] > T;
+        const uint64_t m = ballot(hub);
+        int slot = 0;
+        const int lead = m ? __ffsll((unsigned long long)m) - 1 : 0;
+        if (m && lane_id() == lead) slot = atomicAdd(&S->nHc, __popcll(m));
+        slot = __shfl(slot, lead) + lanes_below(m);
+        if (hub && slot < kHubCap) A->hubC[slot] = v;
+    }
+}
+
 // Completes the arguments once binning is done, on the device, so that the
 // rounds can be enqueued behind binning without the host waiting for it: the
 // worklists' bin segments, the run length (option 0: from the locality
 // sample), and bit 3 of err when there are edges but no col_idx.  The sweeps
 // do not run while err has bit 0 (row_ptr ends, from k_bin) or bit 3 set.
-constexpr int kErrNoRun = 1 | 8;
 // Workgroup 0 does that and then sends the header to the host's staging (dst)
 // as k_head_out does; the whole grid meanwhile fills the colours for round 0
 // (value, its byte shadow, and all-ones 4-bit shadow words p4[0, n4) if
@@ -324,6 +374,7 @@ __global__ void k_args(SingleArgs *A, SingleState *S, SingleState *dst, int32_t 
         int32_t *d = reinterpret_cast<int32_t *>(dst);
         for (int i = threadIdx.x; i < (int)(kStateHeader / 4); i += blockDim.x) d[i] = src[i];
     }
+    hub_collect(A, S);
     fill_colours(col, col8, n, value, col4, n4);
 }
 
@@ -539,6 +590,12 @@ __global__ __launch_bounds__(kBlock) void k_round(const SingleArgs *__restrict__
     const SingleArgs a = *A;
     if (!SWEEP && S->passes >= a.max_rounds) return;  // guard: the round may not run
     if (SWEEP && (S->err & kErrNoRun)) return;        // the input failed its checks
+    // hub-first round 0 (hub_kernels.hpp): the hubs already hold their
+    // colours; every other vertex reads all of its neighbours, upper ones
+    // exactly, so that none takes a hub's colour
+    const int nHub = kFlagAppend ? S->nH : 0;
+    const int hubT = nHub ? S->hub_t : INT_MAX;
+    const int look = nHub ? INT_MAX : a.look;
     const int cT = SWEEP ? a.n : S->cnt_in[kBinThread];
     const int cW = SWEEP ? S->nW : S->cnt_in[kBinWave];
     const int cB = SWEEP ? S->nB : S->cnt_in[kBinBlock];
@@ -583,9 +640,11 @@ __global__ __launch_bounds__(kBlock) void k_round(const SingleArgs *__restrict__
         for (int i = bid; i < cB; i += gB) {
             const int v = inB[i];
             const int b = rp[v], e = rp[v + 1];
+            if (nHub && e - b > hubT) continue;  // a hub: coloured before this round (workgroup-uniform)
             int nc = 0;
             bool unc = false;
-            const bool act = block_vertex<PHASE, TIE, kWinOnly>(v, b, e, ci, rcol, rcol8, lds, &sh_min, a.look, nc, unc);
+            const bool act = block_vertex<PHASE, TIE, kWinOnly>(v, b, e, ci, rcol, rcol8, lds, &sh_min, look, nc, unc,
+                                                                nHub > 0);
             const bool take = (kFlagAppend ? unc : act) && kAppend;
             if (threadIdx.x == 0) {
                 items += 1;
@@ -615,9 +674,10 @@ __global__ __launch_bounds__(kBlock) void k_round(const SingleArgs *__restrict__
         for (int i = w; i < cW; i += nw) {
             const int v = inW[i];
             const int b = rp[v], e = rp[v + 1];
+            if (nHub && e - b > hubT) continue;  // a hub (wavefront-uniform)
             int nc = 0;
             bool unc = false;
-            const bool act = wave_vertex<PHASE, TIE, kWinOnly>(v, b, e, ci, rcol, rcol8, bm, a.look, nc, unc);
+            const bool act = wave_vertex<PHASE, TIE, kWinOnly>(v, b, e, ci, rcol, rcol8, bm, look, nc, unc, nHub > 0);
             if (lane_id() == 0) {
                 items += 1;
                 degs += (uint64_t)(e - b);
@@ -751,7 +811,7 @@ __global__ __launch_bounds__(kBlock) void k_round(const SingleArgs *__restrict__
                 const RSOC_GLOBAL uint32_t *c4s[kNV];
 #pragma unroll
                 for (int i = 0; i < kNV; ++i) cis[i] = ci, c8s[i] = rcol8, c4s[i] = rcol4;
-                group_vertices<PHASE, TIE, kGroup, kGroupSlots, kWinOnly, kNV, kNibRead>(v, b, e, cis, c8s, cv, a.look, nc,
+                group_vertices<PHASE, TIE, kGroup, kGroupSlots, kWinOnly, kNV, kNibRead>(v, b, e, cis, c8s, cv, look, nc,
                                                                                      act, unc, c4s,
                                                                                      kFlagAppend ? keep : nullptr);
 #pragma unroll

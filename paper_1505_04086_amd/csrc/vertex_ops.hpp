@@ -258,6 +258,20 @@ __device__ __forceinline__ void hub_gather(const int (&u)[U], const bool (&take)
     for (int s = 0; s < U; ++s) x[s] = (y[s] == 255) ? (LOOSE ? -1 : col[u[s]]) : y[s];
 }
 
+// The same, except that entries with exact[s] are read from col directly (one
+// exact load, -1 when uncoloured), whatever LOOSE says: round 0 after the
+// hub-first pass must see every hub's colour, also one of 255 or more.
+template <bool LOOSE, int U>
+__device__ __forceinline__ void hub_gather(const int (&u)[U], const bool (&take)[U], const bool (&exact)[U],
+                                           const RSOC_GLOBAL int32_t *col, const RSOC_GLOBAL uint8_t *col8,
+                                           int (&x)[U]) {
+    int y[U];
+#pragma unroll
+    for (int s = 0; s < U; ++s) y[s] = take[s] ? (exact[s] ? col[u[s]] : (int)col8[u[s]]) : -1;
+#pragma unroll
+    for (int s = 0; s < U; ++s) x[s] = (!exact[s] && y[s] == 255) ? (LOOSE ? -1 : col[u[s]]) : y[s];
+}
+
 // Row entries each lane of a wavefront or workgroup holds per step: all the
 // loads of a step are in flight together, and so are its gathers.
 constexpr int kWaveSlots = 8;
@@ -273,7 +287,7 @@ constexpr int kBlockSlots = 8;
 template <int PHASE, int TIE, bool WIN_ONLY>
 __device__ __forceinline__ bool wave_vertex(int v, int b, int e, const RSOC_GLOBAL int32_t *ci,
                                             const RSOC_GLOBAL int32_t *col, const RSOC_GLOBAL uint8_t *col8,
-                                            uint32_t *bm, int look, int &newc, bool &unc_win) {
+                                            uint32_t *bm, int look, int &newc, bool &unc_win, bool exact_up = false) {
     const int lane = lane_id();
     constexpr int U = kWaveSlots;
     constexpr bool kLoose = PHASE == kAssign && WIN_ONLY;
@@ -306,13 +320,14 @@ __device__ __forceinline__ bool wave_vertex(int v, int b, int e, const RSOC_GLOB
             for (int s = 0; s < U; ++s)
                 if (r[s]) x[s] = x2[s];
         } else {
-            bool take[U];
+            bool take[U], ex[U];
 #pragma unroll
             for (int s = 0; s < U; ++s) {
                 const int dist = u[s] > v ? u[s] - v : v - u[s];
                 take[s] = WIN_ONLY ? (w[s] || (u[s] != v && dist < look)) : (u[s] != v);
+                ex[s] = exact_up && take[s] && !w[s];
             }
-            hub_gather<kLoose, U>(u, take, col, col8, x);
+            hub_gather<kLoose, U>(u, take, ex, col, col8, x);
             bool unc = false;
 #pragma unroll
             for (int s = 0; s < U; ++s) unc |= w[s] && x[s] < 0;
@@ -364,7 +379,7 @@ __device__ __forceinline__ bool wave_vertex(int v, int b, int e, const RSOC_GLOB
         wave_lds_sync();
         for (int j0 = b; j0 < e; j0 += U * kWave) {
             int u[U], x[U];
-            bool take[U], w[U];
+            bool take[U], w[U], ex[U];
 #pragma unroll
             for (int s = 0; s < U; ++s) {
                 const int j = j0 + s * kWave + lane;
@@ -375,8 +390,9 @@ __device__ __forceinline__ bool wave_vertex(int v, int b, int e, const RSOC_GLOB
                 w[s] = (u[s] != v) && loses<TIE>(v, u[s]);
                 const int dist = u[s] > v ? u[s] - v : v - u[s];
                 take[s] = (PHASE == kAssign && WIN_ONLY) ? (w[s] || (u[s] != v && dist < look)) : (u[s] != v);
+                ex[s] = PHASE == kAssign && exact_up && take[s] && !w[s];
             }
-            hub_gather<kLoose, U>(u, take, col, col8, x);
+            hub_gather<kLoose, U>(u, take, ex, col, col8, x);
 #pragma unroll
             for (int s = 0; s < U; ++s) {
                 if (PHASE == kAssign) unc |= w[s] && x[s] < 0;
@@ -410,7 +426,8 @@ __device__ __forceinline__ bool wave_vertex(int v, int b, int e, const RSOC_GLOB
 template <int PHASE, int TIE, bool WIN_ONLY>
 __device__ __forceinline__ bool block_vertex(int v, int b, int e, const RSOC_GLOBAL int32_t *ci,
                                              const RSOC_GLOBAL int32_t *col, const RSOC_GLOBAL uint8_t *col8,
-                                             uint32_t *bm, int *sh_min, int look, int &newc, bool &unc_win) {
+                                             uint32_t *bm, int *sh_min, int look, int &newc, bool &unc_win,
+                                             bool exact_up = false) {
     const int t = threadIdx.x;
     constexpr int U = kBlockSlots;
     constexpr bool kLoose = PHASE == kAssign && WIN_ONLY;
@@ -443,7 +460,7 @@ __device__ __forceinline__ bool block_vertex(int v, int b, int e, const RSOC_GLO
         __syncthreads();
         for (int j0 = b; j0 < e; j0 += kBlock * U) {
             int u[U], x[U];
-            bool take[U], w[U];
+            bool take[U], w[U], ex[U];
 #pragma unroll
             for (int s = 0; s < U; ++s) {
                 const int j = j0 + s * kBlock + t;
@@ -454,8 +471,9 @@ __device__ __forceinline__ bool block_vertex(int v, int b, int e, const RSOC_GLO
                 w[s] = (u[s] != v) && loses<TIE>(v, u[s]);
                 const int dist = u[s] > v ? u[s] - v : v - u[s];
                 take[s] = (PHASE == kAssign && WIN_ONLY) ? (w[s] || (u[s] != v && dist < look)) : (u[s] != v);
+                ex[s] = PHASE == kAssign && exact_up && take[s] && !w[s];
             }
-            hub_gather<kLoose, U>(u, take, col, col8, x);
+            hub_gather<kLoose, U>(u, take, ex, col, col8, x);
 #pragma unroll
             for (int s = 0; s < U; ++s) {
                 if (PHASE == kAssign) unc |= w[s] && x[s] < 0;

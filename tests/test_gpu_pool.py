@@ -28,14 +28,18 @@ def _dev(rp, ci):
 
 GRAPHS = [gg.path(9), gg.cycle(7), gg.complete(30), gg.star(500), gg.tri_grid(40, 23), gg.tri_grid(31, 31, permute_seed=8),
           gg.rmat(11, 8, seed=9, shuffle_seed=10), gg.rgg(4000, seed=11), (np.zeros(1, np.int32), np.zeros(0, np.int32)),
-          gg.complete_bipartite(33, 65), gg.grid4(50, 20)]
+          gg.complete_bipartite(33, 65), gg.grid4(50, 20),
+          # colours of 255 and more: the distinct count goes through per-colour flags
+          gg.complete(300)]
 MODES = [("deterministic", "lower"), ("optimistic", "lower"), ("deterministic", "higher"), ("optimistic", "higher")]
 
 
-def _check(lib, g, mode, tie, col, k):
+def _check(lib, g, mode, tie, col, k, st=None):
     rp, ci = GRAPHS[g]
     n = len(rp) - 1
     got = col.cpu().numpy()[:n]
+    if st is not None:
+        assert st["colors_distinct"] == len(np.unique(got)), (g, mode, tie)
     if mode == "deterministic":
         want = oracle.rsync(rp, ci, tie=tie)
         assert np.array_equal(got, want["colors"]) and k == want["K"], (g, mode, tie)
@@ -61,7 +65,7 @@ def test_pool_staggered_admission(lib, ctx, split):
         for slot in pool.step():
             g, mode, tie, d_rp, d_ci, d_col = live.pop(slot)
             k, st = pool.result(slot)
-            _check(lib, g, mode, tie, d_col, k)
+            _check(lib, g, mode, tie, d_col, k, st)
             done += 1
         steps += 1
         assert steps < 5000

@@ -82,6 +82,9 @@ def test_deterministic_matches_oracle(lib, ctx, name, tie, split):
     # round 1 sweeps V; every later pass inspects the list the pass before recoloured
     assert st["inspected"] == n + want["conflicts"]
     assert list(st["L_sizes"]) == list(want["L_sizes"])
+    # |U| per pass: V, then what each round recoloured (U <- L), for every pass run
+    assert st["passes"] == want["rounds"] + 1
+    assert list(st["U_sizes"]) == [n] + list(want["L_sizes"])
 
 
 @pytest.mark.parametrize("split", sorted(BIN_SPLITS))
@@ -107,9 +110,15 @@ def test_optimistic_valid(lib, ctx, name, tie, split, full_sweep):
     rp, ci = CASES[name]
     d_rp, d_ci, d_col, n = _dev(lib, rp, ci)
     o = lib.make_options("optimistic", tie, full_sweep=full_sweep, **BIN_SPLITS[split])
-    k, st = lib.rsoc_color_device(ctx, d_rp, d_ci, n, d_col, o)
+    k, st = lib.rsoc_color_device(ctx, d_rp, d_ci, n, d_col, o, per_round_cap=n + 2)
     got = d_col.cpu().numpy()[:n]
     assert oracle.check(rp, ci, got) == 0
+    # |U| per pass: U^0, then what each round recoloured (no pass at all when
+    # round 0 left nothing to inspect)
+    U = list(st["U_sizes"])
+    assert len(U) == st["passes"] and U[1:] == list(st["L_sizes"])[:max(len(U) - 1, 0)]
+    if U:
+        assert U[0] == st["worklist0"]
     assert k == oracle.colour_count(got)
     assert st["colors_distinct"] == len(np.unique(got))
     deg = np.diff(rp)
