@@ -64,14 +64,19 @@ def load_traffic(workload: str, kernel: str):
     return None if ent is None else ent.get("bytes_per_launch")
 
 
-def make_graph(workload: str, seed: int):
+def make_graph(workload: str, seed: int, sample: bool = False):
+    """The workload's graph; sample=True gives a smaller graph of the same
+    kind (the bounded sample of a CPU baseline that would take minutes on the
+    full graph)."""
     import graphgen as gg
     if workload == "mesh3d":
-        rp, ci = gg.lattice26(200, permute_seed=seed)
-        desc = "lattice26 200^3, ids permuted (seed %d)" % seed
+        S = 100 if sample else 200
+        rp, ci = gg.lattice26(S, permute_seed=seed)
+        desc = "lattice26 %d^3, ids permuted (seed %d)" % (S, seed)
     elif workload == "rmat":
-        rp, ci = gg.rmat(22, 16, 0.57, 0.19, 0.19, seed=seed, shuffle_seed=seed + 1)
-        desc = "rmat scale 22 ef 16 (.57,.19,.19,.05), symmetrised, ids shuffled (seed %d)" % seed
+        sc = 20 if sample else 22
+        rp, ci = gg.rmat(sc, 16, 0.57, 0.19, 0.19, seed=seed, shuffle_seed=seed + 1)
+        desc = "rmat scale %d ef 16 (.57,.19,.19,.05), symmetrised, ids shuffled (seed %d)" % (sc, seed)
     elif workload == "mesh2d":
         rp, ci = gg.tri_grid(100)
         desc = "triangulated grid 100x100, natural ids"
@@ -80,9 +85,21 @@ def make_graph(workload: str, seed: int):
     return rp, ci, desc
 
 
-def cpu_baseline(rp, ci, budget_s: float = 12.0):
-    """Oracle sequential First-Fit (Algorithm 1) on this host, one core, repeated
-    on the full graph until about budget_s seconds of CPU work."""
+def host_cores() -> int:
+    try:
+        return len(os.sched_getaffinity(0))
+    except Exception:
+        return os.cpu_count() or 1
+
+
+def cpu_baseline(rp, ci, budget_s: float = 12.0, workload: str = "mesh3d", seed: int = 1505, legs: bool = True):
+    """CPU baselines on this host, all from oracle/ (never tuned for this):
+    sequential First-Fit (Algorithm 1) on one core, repeated on the full graph
+    until about budget_s seconds; the round-synchronous Algorithm 3 schedule on
+    one core on a bounded sample of the workload; Algorithm 3 with OpenMP
+    (live reads, as the paper runs it) on every core this process may use, in
+    a child process started with OMP_PROC_BIND=close, on the full graph.
+    Returns (baseline dict, sequential First-Fit colour count)."""
     import oracle
     E = len(ci) // 2
     reps, t_total = 0, 0.0
@@ -91,8 +108,51 @@ def cpu_baseline(rp, ci, budget_s: float = 12.0):
         _, kseq = oracle.seq_ff(rp, ci)
         t_total += time.perf_counter() - t0
         reps += 1
-    return {"value": E * reps / t_total / 1e9, "unit": "GE/s", "cores": 1, "kind": "oracle",
-            "sample": "oracle sequential First-Fit (Algorithm 1) on the full graph, %d run(s), %.1f s" % (reps, t_total)}, kseq
+    out = {"value": E * reps / t_total / 1e9, "unit": "GE/s", "cores": 1, "kind": "oracle",
+           "sample": "oracle sequential First-Fit (Algorithm 1) on the full graph, %d run(s), %.1f s" % (reps, t_total),
+           "host_cores": host_cores()}
+    if not legs:
+        return out, kseq
+    # round-synchronous schedule on one core, on a smaller graph of the same kind
+    srp, sci, sdesc = make_graph(workload, seed, sample=True)
+    t0 = time.perf_counter()
+    r = oracle.rsync(srp, sci, tie="lower")
+    ts = time.perf_counter() - t0
+    out["rsync_1core"] = {"value": len(sci) // 2 / ts / 1e9, "unit": "GE/s", "cores": 1, "kind": "oracle",
+                          "sample": "oracle round-synchronous Algorithm 3 on %s, one run, %.1f s" % (sdesc, ts),
+                          "colors": r["K"], "rounds": r["rounds"], "conflicts": r["conflicts"]}
+    # OpenMP Algorithm 3 on all cores (a child process: the OpenMP runtime
+    # reads OMP_PROC_BIND when it starts)
+    env = dict(os.environ, OMP_PROC_BIND="close", OMP_PLACES="cores")
+    env.setdefault("OMP_NUM_THREADS", str(host_cores()))
+    import subprocess
+    cmd = [sys.executable, os.path.abspath(__file__), "--cpu-omp-leg", "--workload", workload, "--seed", str(seed),
+           "--cpu-budget", str(max(2.0, budget_s / 2))]
+    res = subprocess.run(cmd, capture_output=True, text=True, env=env, timeout=600)
+    if res.returncode == 0:
+        out["omp_rsoc"] = json.loads(res.stdout.strip().splitlines()[-1])
+    else:
+        out["omp_rsoc"] = {"error": (res.stderr or "")[-400:]}
+    return out, kseq
+
+
+def cpu_omp_leg(args):
+    """Child process of cpu_baseline: Algorithm 3 with OpenMP on the full
+    workload graph, repeated until about args.cpu_budget seconds."""
+    import oracle
+    rp, ci, desc = make_graph(args.workload, args.seed)
+    E = len(ci) // 2
+    reps, t_total, r = 0, 0.0, None
+    while t_total < args.cpu_budget and reps < 50:
+        t0 = time.perf_counter()
+        r = oracle.omp_rsoc(rp, ci, tie="lower")
+        t_total += time.perf_counter() - t0
+        reps += 1
+    valid = oracle.check(rp, ci, r["colors"]) == 0
+    print(json.dumps({"value": E * reps / t_total / 1e9, "unit": "GE/s", "cores": r["threads"], "kind": "oracle",
+                      "sample": "Algorithm 3 with OpenMP (oracle/omp_rsoc.c, live reads) on %s, %d run(s), %.1f s, "
+                                "OMP_PROC_BIND=%s" % (desc, reps, t_total, os.environ.get("OMP_PROC_BIND")),
+                      "colors": r["K"], "rounds": r["rounds"], "conflicts": r["conflicts"], "valid": valid}))
 
 
 def colouring_valid(rp, ci, col) -> bool:
@@ -350,11 +410,59 @@ def bench_single(args):
         out["deterministic"] = {"GEps": E / td / 1e9, "colors": kd, "rounds": sd["rounds"],
                                 "conflicts": sd["conflicts"], "device_ms": sd["ms"]}
     if not args.no_cpu:
-        cb, kseq = cpu_baseline(rp, ci, args.cpu_budget)
+        cb, kseq = cpu_baseline(rp, ci, args.cpu_budget, args.workload, args.seed)
         out["cpu_baseline"] = cb
         out["colors_seq_first_fit"] = kseq
     ctx.close()
     return out
+
+
+def bench_rmat_extra(args):
+    """The power-law workload beside the headline: R-MAT scale 22 (ids
+    shuffled), optimistic mode, throughput and colours against sequential
+    First-Fit (timed once on one core: the CPU leg of this workload), with
+    the hub-first round 0 (default) and without it."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_1505_04086_amd as rsoc
+
+    dev = torch.device("cuda:0")
+    rp, ci, desc = make_graph("rmat", args.seed)
+    n, E = len(rp) - 1, len(ci) // 2
+    d_rp, d_ci = torch.from_numpy(rp).to(dev), torch.from_numpy(ci).to(dev)
+    d_col = torch.empty(n, dtype=torch.int32, device=dev)
+    ctx = rsoc.Context(0)
+    stream = torch.cuda.current_stream()
+    res = {"workload": desc, "n": n, "edges": E}
+    for name, hf in (("hub_first", 0), ("hub_first_off", -1)):
+        opts = rsoc.make_options("optimistic", "lower", hub_first=hf)
+        for _ in range(2):
+            rsoc.rsoc_color_device(ctx, d_rp, d_ci, n, d_col, opts, stream=stream)
+        torch.cuda.synchronize()
+        reps, ks, sts = 5, [], []
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            k, st = rsoc.rsoc_color_device(ctx, d_rp, d_ci, n, d_col, opts, stream=stream)
+            ks.append(k)
+            sts.append(st)
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / reps
+        if not colouring_valid(rp, ci, d_col.cpu().numpy()):
+            raise SystemExit("bench: invalid R-MAT colouring (%s)" % name)
+        res[name] = {"GEps": E / el / 1e9, "ms": el * 1e3, "colors": ks, "colors_distinct": sts[-1]["colors_distinct"],
+                     "rounds": sts[-1]["rounds"], "conflicts": sts[-1]["conflicts"],
+                     "device_ms_median": float(np.median([x["ms"] for x in sts]))}
+    t0 = time.perf_counter()
+    _, kseq = oracle.seq_ff(rp, ci)
+    ts = time.perf_counter() - t0
+    res["colors_seq_first_fit"] = kseq
+    res["cpu_baseline"] = {"value": E / ts / 1e9, "unit": "GE/s", "cores": 1, "kind": "oracle",
+                           "sample": "oracle sequential First-Fit on the full graph, one run, %.1f s" % ts}
+    res["colors_within_seq_plus_1"] = max(res["hub_first"]["colors"]) <= kseq + 1
+    ctx.close()
+    return res
 
 
 def _pinned(a):
@@ -386,8 +494,16 @@ def bench_batched(args):
     ctx = rsoc.Context(0)
     stream = torch.cuda.current_stream()
     tune_info = None
+    tune_key = "batch-grids-rgg-1e3-1e6-deg12-%s" % args.mode
     if args.tune:
-        # autotune on a smaller batch drawn from the same distribution (another seed)
+        from paper_1505_04086_amd import tune
+        cached = tune.lookup(tune_key)
+        if cached is not None:
+            args.tuned = cached
+            tune_info = {"options": cached, "from_cache": tune.tune_file()}
+    if args.tune and tune_info is None:
+        # autotune on a smaller batch drawn from the same distribution (another
+        # seed); the result goes to the tuning cache, which later runs read
         from paper_1505_04086_amd import tune
         tb = gg.batch(args.tune_graphs, seed=args.seed + 1, nmin=1e3, nmax=1e6, mean_degree=12.0)
         t_rp = torch.from_numpy(tb["row_ptr_cat"]).to(dev)
@@ -399,9 +515,11 @@ def bench_batched(args):
             lambda o: tune._timer(lambda: rsoc.rsoc_color_batch(ctx, tb["vtx_off"], tb["nnz_off"], t_rp, t_ci, t_col,
                                                                 rsoc.make_options(args.mode, **o)), 3),
             space=space, sweeps=1)
-        args.tuned = best
+        tune.save(tune_key, best, best_t * 1e3)
+        args.tuned = tune.lookup(tune_key)
         tune_info = {"graphs": args.tune_graphs, "seconds": time.perf_counter() - tt, "trials": len(trials),
-                     "best_ms": best_t * 1e3, "default_ms": trials[0][1] * 1e3, "options": best}
+                     "best_ms": best_t * 1e3, "default_ms": trials[0][1] * 1e3, "options": args.tuned,
+                     "cache": tune.tune_file()}
         print("[bench] tuned %s" % json.dumps(tune_info), file=sys.stderr, flush=True)
         del t_rp, t_ci, t_col
     opts = rsoc.make_options(args.mode, "lower", timing=1, **(args.tuned or {}))
@@ -496,8 +614,13 @@ def make_requests(N: int, seed: int):
             return gg.lattice26(p, permute_seed=seed * 1000 + i)
         return gg.rmat(p, 16, seed=seed * 1000 + i, shuffle_seed=seed * 1000 + i + 7)
 
+    graphs = []
+    t0 = time.perf_counter()
     with cf.ThreadPoolExecutor(8) as ex:
-        graphs = list(ex.map(gen, specs))
+        for k in range(0, len(specs), 100):
+            graphs.extend(ex.map(gen, specs[k:k + 100]))
+            print("[bench] generated %d of %d requests (%.0f s)" % (len(graphs), len(specs), time.perf_counter() - t0),
+                  file=sys.stderr, flush=True)
     return specs, graphs
 
 
@@ -629,15 +752,19 @@ def main():
     ap.add_argument("--det-too", action="store_true", help="also time deterministic mode once")
     ap.add_argument("--batch-graphs", type=int, default=4096)
     ap.add_argument("--plain-reps", type=int, default=1)
-    ap.add_argument("--requests", type=int, default=160)
+    ap.add_argument("--requests", type=int, default=1000)
     ap.add_argument("--hbm-budget", type=int, default=16 << 30)
-    ap.add_argument("--rate-factors", type=float, nargs="*", default=[0.5, 1.0, 2.0])
+    ap.add_argument("--rate-factors", type=float, nargs="*", default=[0.5, 1.0, 2.0, 4.0])
     ap.add_argument("--tune", action="store_true", help="autotune launch options first (batched workload)")
     ap.add_argument("--tune-graphs", type=int, default=256)
+    ap.add_argument("--cpu-omp-leg", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates rocprofv3 FETCH_SIZE/WRITE_SIZE)")
     args = ap.parse_args()
     args.tuned = None
+    if args.cpu_omp_leg:
+        cpu_omp_leg(args)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build measures one GPU only (--gpus 1); multi-GPU runs are not supported",
               file=sys.stderr)
@@ -657,7 +784,62 @@ def main():
         out = bench_served(args)
     else:
         out = bench_single(args)
+        if args.workload == "mesh3d" and not args.no_extras:
+            default_extras(args, out)
     print(json.dumps(out), flush=True)
+
+
+def _free_device():
+    import gc
+
+    import torch
+    gc.collect()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+
+def _guarded(name, fn, *a):
+    """Runs one extra of the default benchmark; an extra that fails is
+    recorded with its error beside the headline figures, which are already
+    measured."""
+    t0 = time.perf_counter()
+    try:
+        r = fn(*a)
+    except Exception as e:  # noqa: BLE001 -- reported in the JSON line
+        print("[bench] %s failed: %r" % (name, e), file=sys.stderr, flush=True)
+        r = {"error": repr(e)}
+    _free_device()
+    r["wall_s"] = time.perf_counter() - t0
+    print("[bench] %s done in %.1f s" % (name, r["wall_s"]), file=sys.stderr, flush=True)
+    return r
+
+
+def default_extras(args, out):
+    """The rest of the metric beside the headline line: the power-law graph
+    (colours against sequential First-Fit), the batched form (4096 graphs,
+    autotuned on a 256-graph sample, against one call per graph) and the
+    served form (1000 Poisson requests at 0.5, 1, 2 and 4 times the plain
+    form's capacity plus saturation, against one call per request, p50/p99)."""
+    import copy
+    _free_device()
+    out["rmat_scale22"] = _guarded("rmat", bench_rmat_extra, args)
+    a = copy.copy(args)
+    a.steps, a.warmup, a.tune, a.tuned = 3, 1, True, None
+    b = _guarded("batched", bench_batched, a)
+    out["batched"] = b
+    a = copy.copy(args)
+    s = _guarded("served", bench_served, a)
+    out["served"] = s
+    out["batched_over_plain"] = b.get("batched_over_plain")
+    out["served_over_plain"] = s.get("saturation", {}).get("served_over_plain")
+    lat = {}
+    for key, rec in s.get("poisson", {}).items():
+        lat[key] = {side: {q: rec[side].get(q) for q in ("p50_ms", "p99_ms")} for side in ("plain", "served")}
+    if "saturation" in s:
+        lat["saturation"] = {"plain": {q: s["saturation"]["plain_latency"].get(q) for q in ("p50_ms", "p99_ms")},
+                             "served": {q: s["saturation"]["served_latency"].get(q) for q in ("p50_ms", "p99_ms")}}
+    out["latency_ms"] = lat
+    out["tuned_options"] = (b.get("autotune") or {}).get("options")
 
 
 if __name__ == "__main__":

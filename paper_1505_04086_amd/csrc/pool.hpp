@@ -5,11 +5,17 @@
 // RSOC_EBUDGET when it does not fit.
 //
 // The host waits on the device once or twice per step, never per request:
-// admission only enqueues the slot's set-up (k_pinit) on the context's own
-// stream and records p->ev; the next step waits for that event and finishes
-// the new slots' host fields with one look at their downloaded state; a step
-// in which slots finish enqueues their colour counts and downloads them once;
-// taking a result then needs no device work at all.
+// admission only enqueues the slot's set-up (k_pinit, and the hub-first pass
+// of an optimistic slot) on one of kAdmitStreams admission streams, in turn,
+// and records the slot's own event; a step takes in the new slots whose
+// set-up has completed (one look at their downloaded state) and leaves the
+// others for a later step, so a long set-up (the hub walk of a large
+// power-law graph is one workgroup's sequential work) neither holds up the
+// rounds of the slots already running nor the set-up of the next requests,
+// which proceed on the other streams; a step in which slots finish enqueues
+// their colour counts and downloads them once; taking a result then needs no
+// device work at all.  Releases go on the context's own stream and record
+// p->ev, which admissions and steps wait for before touching the slot table.
 #pragma once
 
 #include <map>
@@ -33,9 +39,15 @@ struct rsoc_pool {
     std::vector<Alloc> allocs;
     std::vector<char> reported;  // finished slot already returned by a step
     std::vector<char> pending;   // admitted, set-up enqueued, host fields not yet final
-    hipEvent_t ev = nullptr;     // recorded after admission / release work on the context's stream
+    hipEvent_t ev = nullptr;     // recorded after release work on the context's stream
     rsoc::HostPinned stage;      // step download of all slots (copied into the mirror for active ones)
-    rsoc::DevBuf hub_args, hub_state, hubs;  // hub-first pass at admission (hub_kernels.hpp)
+    // admission streams, each with the workspace of the hub-first pass it runs
+    // (hub_kernels.hpp; admissions on one stream run one after another)
+    static constexpr int kAdmitStreams = 8;
+    hipStream_t astream[kAdmitStreams] = {};
+    rsoc::DevBuf hub_args[kAdmitStreams], hub_state[kAdmitStreams], hubs[kAdmitStreams];
+    int next_astream = 0;
+    std::vector<hipEvent_t> slot_ev;  // recorded after a slot's set-up
 };
 
 namespace rsoc {
@@ -125,8 +137,14 @@ int32_t rsoc_pool_create(rsoc_ctx *ctx, int64_t hbm_budget_bytes, int32_t max_sl
     p->reported.assign((size_t)max_slots, 0);
     p->pending.assign((size_t)max_slots, 0);
     int32_t r = RSOC_OK;
-    if (hipEventCreateWithFlags(&p->ev, hipEventDisableTiming) != hipSuccess) {
-        p->ev = nullptr;
+    p->slot_ev.assign((size_t)max_slots, nullptr);
+    bool ok = hipEventCreateWithFlags(&p->ev, hipEventDisableTiming) == hipSuccess;
+    if (!ok) p->ev = nullptr;
+    for (auto &e : p->slot_ev)
+        if (ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) e = nullptr, ok = false;
+    for (auto &st : p->astream)
+        if (ok && hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) st = nullptr, ok = false;
+    if (!ok) {
         rsoc_pool_destroy(p);
         return RSOC_EHIP;
     }
@@ -156,11 +174,20 @@ void rsoc_pool_destroy(rsoc_pool *p) {
     for (auto &a : p->allocs)
         if (a.own) (void)hipFree(a.own);
     if (p->ev) (void)hipStreamSynchronize(p->ctx->own);
-    for (rsoc::DevBuf *b : {&p->slots_dev, &p->tasks_dev, &p->active_dev, &p->arena, &p->hub_args, &p->hub_state,
-                            &p->hubs})
-        b->release();
+    for (auto &st : p->astream)
+        if (st) (void)hipStreamSynchronize(st);
+    for (rsoc::DevBuf *b : {&p->slots_dev, &p->tasks_dev, &p->active_dev, &p->arena}) b->release();
+    for (int k = 0; k < rsoc_pool::kAdmitStreams; ++k) {
+        p->hub_args[k].release();
+        p->hub_state[k].release();
+        p->hubs[k].release();
+    }
     for (rsoc::HostPinned *b : {&p->mirror, &p->tasks_host, &p->active_host, &p->stage}) b->release();
     if (p->ev) (void)hipEventDestroy(p->ev);
+    for (auto &e : p->slot_ev)
+        if (e) (void)hipEventDestroy(e);
+    for (auto &st : p->astream)
+        if (st) (void)hipStreamDestroy(st);
     delete p;
 }
 
@@ -201,7 +228,15 @@ inline int32_t pool_admit(rsoc_pool *p, const int32_t *d_row_ptr, const int32_t 
     }
     p->allocs[slot] = al;
     p->reserved += bytes;
-    hipStream_t s = c->own;
+    // the slot's set-up runs on the next admission stream, after the release
+    // work on the context's stream (the slot table entry it overwrites)
+    const int as = p->next_astream;
+    p->next_astream = (p->next_astream + 1) % rsoc_pool::kAdmitStreams;
+    hipStream_t s = p->astream[as];
+    if (hipStreamWaitEvent(s, p->ev, 0) != hipSuccess) {
+        pool_release(p, slot);
+        return RSOC_EHIP;
+    }
     int32_t r = RSOC_OK;
     const int64_t l = align_up(4 * (int64_t)(n + 1), kPoolAlign);
     PoolSlot &m = pool_mirror(p)[slot];
@@ -232,10 +267,19 @@ inline int32_t pool_admit(rsoc_pool *p, const int32_t *d_row_ptr, const int32_t 
     m.nt = recolor ? nt : 0;
     m.hub_opt = (o.mode == kOptimistic && !recolor) ? o.hub_first : 0;
     if (m.hub_opt != 0 && n > 0) {
-        if ((r = p->hub_args.reserve(sizeof(SingleArgs))) < 0 || (r = p->hub_state.reserve(sizeof(SingleState))) < 0 ||
-            (r = p->hubs.reserve(kHubBytes)) < 0) {
+        const size_t had = p->hubs[as].bytes;
+        if ((r = p->hub_args[as].reserve(sizeof(SingleArgs))) < 0 ||
+            (r = p->hub_state[as].reserve(sizeof(SingleState))) < 0 || (r = p->hubs[as].reserve(kHubBytes)) < 0) {
             pool_release(p, slot);
             return r;
+        }
+        // the hub bit sets and the state's counts are zero between admissions
+        // (k_hub_ff clears what it reads and resets the counts)
+        if (p->hubs[as].bytes != had &&
+            (hipMemsetAsync(p->hubs[as].p, 0, p->hubs[as].bytes, s) != hipSuccess ||
+             hipMemsetAsync(p->hub_state[as].p, 0, p->hub_state[as].bytes, s) != hipSuccess)) {
+            pool_release(p, slot);
+            return RSOC_EHIP;
         }
     }
     p->reported[slot] = 0;
@@ -244,20 +288,19 @@ inline int32_t pool_admit(rsoc_pool *p, const int32_t *d_row_ptr, const int32_t 
         const int gbin = std::min(div_up(n, kBlock), o.grid_bin ? o.grid_bin : 1024);
         k_pinit<<<gbin, kBlock, 0, s>>>(p->slots_dev.as<PoolSlot>(), slot);
         if (m.hub_opt != 0) {
-            SingleArgs *A = p->hub_args.as<SingleArgs>();
-            SingleState *S = p->hub_state.as<SingleState>();
-            int32_t *tables = p->hubs.as<int32_t>();
-            uint16_t *entries = reinterpret_cast<uint16_t *>(tables + 4 * kHubCap);
-            k_phub_setup<<<1, 64, 0, s>>>(p->slots_dev.as<PoolSlot>(), slot, A, S, tables, entries);
-            k_phub_collect<<<gbin, kBlock, 0, s>>>(A, S);
+            SingleArgs *A = p->hub_args[as].as<SingleArgs>();
+            SingleState *S = p->hub_state[as].as<SingleState>();
+            PoolSlot *sd = p->slots_dev.as<PoolSlot>();
+            int32_t *done = &sd[slot].nH;  // nH, hub_t: adjacent fields of the slot
+            k_phub_collect<<<gbin, kBlock, 0, s>>>(sd, slot, A, S, p->hubs[as].as<int32_t>());
+            k_hub_sort<<<1, kHubSortBlock, 0, s>>>(A, S);
             if (o.tie) {
                 k_hub_lists<kHigherKeeps><<<kHubListGrid, kBlock, 0, s>>>(A, S);
-                k_hub_ff<kHigherKeeps><<<1, kHubFfBlock, 0, s>>>(A, S);
+                k_hub_ff<kHigherKeeps><<<1, kHubFfBlock, 0, s>>>(A, S, done);
             } else {
                 k_hub_lists<kLowerKeeps><<<kHubListGrid, kBlock, 0, s>>>(A, S);
-                k_hub_ff<kLowerKeeps><<<1, kHubFfBlock, 0, s>>>(A, S);
+                k_hub_ff<kLowerKeeps><<<1, kHubFfBlock, 0, s>>>(A, S, done);
             }
-            k_phub_done<<<1, 64, 0, s>>>(p->slots_dev.as<PoolSlot>(), slot, S);
         }
         if (recolor) {
             if (nt > 0) k_ptouch<<<std::min(div_up(nt, kBlock), 256), kBlock, 0, s>>>(p->slots_dev.as<PoolSlot>(), slot);
@@ -266,9 +309,10 @@ inline int32_t pool_admit(rsoc_pool *p, const int32_t *d_row_ptr, const int32_t 
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) { pool_release(p, slot); return hip_fail(e, "k_pinit", __FILE__, __LINE__); }
         if ((r = pool_download_slot(p, slot, s)) < 0) { pool_release(p, slot); return r; }
-        p->pending[slot] = 1;
     }
-    RSOC_HIP(hipEventRecord(p->ev, s));
+    // the slot is taken in by the first step that finds this event complete
+    p->pending[slot] = 1;
+    RSOC_HIP(hipEventRecord(p->slot_ev[slot], s));
     return slot;
 }
 
@@ -292,15 +336,26 @@ int32_t rsoc_pool_step(rsoc_pool *p, void *hip_stream, int32_t *finished_slots, 
     RSOC_HIP(hipSetDevice(c->device));
     hipStream_t s = (hipStream_t)hip_stream;
     PoolSlot *m = pool_mirror(p);
-    // admission and release work on the context's stream comes first
+    // release work on the context's stream comes first
     RSOC_HIP(hipStreamWaitEvent(s, p->ev, 0));
-    bool any_pending = false;
-    for (int i = 0; i < p->max_slots; ++i) any_pending |= p->pending[i] != 0;
-    if (any_pending) {
-        // the new slots' set-up is done and their state downloaded
-        RSOC_HIP(hipEventSynchronize(p->ev));
+    // new slots whose set-up has completed (their state downloaded) join this
+    // step; when no slot is running, the step waits for the earliest pending one
+    bool any_running = false;
+    int first_pending = -1;
+    for (int i = 0; i < p->max_slots; ++i) {
+        if (p->pending[i]) {
+            if (first_pending < 0) first_pending = i;
+        } else if (m[i].phase == kSlotNew || m[i].phase == kSlotRunning) {
+            any_running = true;
+        }
+    }
+    if (first_pending >= 0) {
+        if (!any_running) RSOC_HIP(hipEventSynchronize(p->slot_ev[first_pending]));
         for (int i = 0; i < p->max_slots; ++i) {
             if (!p->pending[i]) continue;
+            const hipError_t q = hipEventQuery(p->slot_ev[i]);
+            if (q == hipErrorNotReady) continue;
+            if (q != hipSuccess) return hip_fail(q, "hipEventQuery", __FILE__, __LINE__);
             p->pending[i] = 0;
             PoolSlot &ms = m[i];
             if (ms.status < 0) {
@@ -328,6 +383,7 @@ int32_t rsoc_pool_step(rsoc_pool *p, void *hip_stream, int32_t *finished_slots, 
     int32_t *act = p->active_host.as<int32_t>();
     for (int i = 0; i < p->max_slots; ++i) {
         const PoolSlot &sl = m[i];
+        if (p->pending[i]) continue;  // set-up still running (its mirror entry may be mid-download)
         if (sl.phase != kSlotNew && sl.phase != kSlotRunning) continue;
         int kind, cT, cW, cB;
         if (sl.phase == kSlotNew) {
@@ -469,7 +525,7 @@ int32_t rsoc_pool_step(rsoc_pool *p, void *hip_stream, int32_t *finished_slots, 
     }
     // report finished slots (including ones a previous step could not fit in `cap`)
     for (int i = 0; i < p->max_slots && nfin < cap; ++i) {
-        if (m[i].phase == kSlotDone && !p->reported[i]) {
+        if (m[i].phase == kSlotDone && !p->reported[i] && !p->pending[i]) {
             p->reported[i] = 1;
             finished_slots[nfin++] = i;
         }
@@ -481,7 +537,7 @@ int32_t rsoc_pool_live(const rsoc_pool *p) {
     if (!p) return RSOC_EINVAL;
     const rsoc::PoolSlot *m = p->mirror.as<rsoc::PoolSlot>();
     int live = 0;
-    for (int i = 0; i < p->max_slots; ++i) live += m[i].phase != rsoc::kSlotFree;
+    for (int i = 0; i < p->max_slots; ++i) live += p->pending[i] || m[i].phase != rsoc::kSlotFree;
     return live;
 }
 

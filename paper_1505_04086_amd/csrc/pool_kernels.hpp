@@ -45,18 +45,18 @@ struct PoolSlot {
     int32_t distinct;        // distinct colours of 255 and more (k_pdistinct)
     // hub-first round 0 (hub_kernels.hpp): hub_opt is the option (0 off, -1
     // automatic threshold, else the threshold); nH hubs were coloured at
-    // admission, those above hub_t
+    // admission, those above hub_t (written together by k_hub_ff)
     int32_t hub_opt, nH, hub_t;
 };
 
 // Hub-first pass of an optimistic slot at admission, with the single-graph
-// kernels: k_phub_setup fills a SingleArgs / SingleState of the pool's (one
-// set, shared by the admissions, which run one after another on one stream)
-// from the slot, k_phub_collect collects the hubs, k_hub_lists and k_hub_ff
-// colour them, k_phub_done copies their number and threshold into the slot.
-__global__ void k_phub_setup(PoolSlot *slots, int slot, SingleArgs *A, SingleState *S, int32_t *hub_tables,
-                             uint16_t *hub_entries) {
-    if (threadIdx.x != 0) return;
+// kernels and a SingleArgs / SingleState of the admission stream's own (the
+// admissions on one stream run one after another): k_phub_collect fills them
+// from the slot and collects the hubs, k_hub_lists and k_hub_ff colour them,
+// and k_hub_ff's last act copies their number and threshold into the slot
+// and clears the counts for the stream's next admission (they start zeroed).
+__global__ __launch_bounds__(kBlock) void k_phub_collect(PoolSlot *slots, int slot, SingleArgs *A, SingleState *S,
+                                                         int32_t *hub_tables) {
     const PoolSlot *sp = slots + slot;
     SingleArgs a = {};
     a.rp = sp->rp;
@@ -72,24 +72,41 @@ __global__ void k_phub_setup(PoolSlot *slots, int slot, SingleArgs *A, SingleSta
     a.hub_t = sp->hub_opt;
     a.hubC = hub_tables;
     a.hubS = hub_tables + kHubCap;
-    a.hub_ls = hub_tables + 2 * kHubCap;
-    a.hub_ll = hub_tables + 3 * kHubCap;
-    a.hub_le = hub_entries;
-    *A = a;
-    S->nW = sp->nW;
-    S->nB = sp->nB;
-    S->maxdeg = sp->maxdeg;
-    S->err = sp->status < 0 ? kErrNoRun : 0;
-    S->nH = S->nHc = S->hub_t = S->hub_ecnt = 0;
+    a.hub_cpre = hub_tables + 2 * kHubCap;
+    a.hub_bits = reinterpret_cast<uint32_t *>(hub_tables + kHubTablesInts);
+    a.pend = sp->wl[1];  // the hubs' position map (free until the slot's first round appends there)
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        *A = a;
+        S->nW = sp->nW;
+        S->nB = sp->nB;
+        S->maxdeg = sp->maxdeg;
+        S->err = sp->status < 0 ? kErrNoRun : 0;
+    }
+    if (sp->status < 0 || a.hub_t == 0) return;
+    // hub_collect with the slot's own sizes (S's are written by block 0 in
+    // this same launch)
+    const int maxdeg = sp->maxdeg;
+    const int T = hub_threshold(a, maxdeg);
+    if (blockIdx.x == 0 && threadIdx.x == 0) S->hub_t = T;
+    if (maxdeg <= T) return;
+    const int nW = sp->nW, nB = sp->nB;
+    const int from = T >= a.t_wave ? nW : 0;
+    const RSOC_GLOBAL int32_t *rp = gro(a.rp);
+    for (int64_t i = from + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (int64_t)nW + nB;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int v = i < nW ? a.hubW[i] : a.hubB[i - nW];
+        const bool hub = rp[v + 1] - rp[v] > T;
+        const uint64_t m = ballot(hub);
+        int at = 0;
+        const int lead = m ? __ffsll((unsigned long long)m) - 1 : 0;
+        if (m && lane_id() == lead) at = atomicAdd(&S->nHc, __popcll(m));
+        at = __shfl(at, lead) + lanes_below(m);
+        if (hub && at < kHubCap) a.hubC[at] = v;
+    }
 }
 
-__global__ __launch_bounds__(kBlock) void k_phub_collect(const SingleArgs *A, SingleState *S) { hub_collect(A, S); }
-
-__global__ void k_phub_done(PoolSlot *slots, int slot, const SingleState *S) {
-    if (threadIdx.x != 0) return;
-    slots[slot].nH = S->nH;
-    slots[slot].hub_t = S->hub_t;
-}
+static_assert(offsetof(PoolSlot, hub_t) == offsetof(PoolSlot, nH) + sizeof(int32_t),
+              "k_hub_ff writes nH and hub_t as two adjacent words");
 
 struct PoolTask {
     int32_t slot, kind, begin, end;

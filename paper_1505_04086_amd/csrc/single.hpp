@@ -358,16 +358,18 @@ inline int32_t run_single(rsoc_ctx *c, const int32_t *rp, const int32_t *ci, int
     // modes fix their result; the literal flow keeps the paper's round 0)
     const bool hub_first = o.hub_first != 0 && o.mode == kOptimistic && !o.full_sweep && !inc;
     a.hub_t = hub_first ? o.hub_first : 0;
-    a.hubC = a.hubS = a.hub_ls = a.hub_ll = nullptr;
-    a.hub_le = nullptr;
+    a.hubC = a.hubS = a.hub_cpre = nullptr;
+    a.hub_bits = nullptr;
     if (hub_first) {
+        const size_t had = c->hubs.bytes;
         RSOC_TRY(c->hubs.reserve(kHubBytes));
+        // the hub bit sets are zero between calls (k_hub_ff clears what it reads)
+        if (c->hubs.bytes != had) RSOC_HIP(hipMemsetAsync(c->hubs.p, 0, c->hubs.bytes, s));
         int32_t *hb = c->hubs.as<int32_t>();
         a.hubC = hb;
         a.hubS = hb + kHubCap;
-        a.hub_ls = hb + 2 * kHubCap;
-        a.hub_ll = hb + 3 * kHubCap;
-        a.hub_le = reinterpret_cast<uint16_t *>(hb + 4 * kHubCap);
+        a.hub_cpre = hb + 2 * kHubCap;
+        a.hub_bits = reinterpret_cast<uint32_t *>(hb + kHubTablesInts);
     }
     k_setup<<<1, kBlock, 0, s>>>(c->args.as<SingleArgs>(), a, S, (int)(kStateHeader / 4), 1);
     // binning: each workgroup ends with one global atomic per non-empty hub
@@ -413,6 +415,7 @@ inline int32_t run_single(rsoc_ctx *c, const int32_t *rp, const int32_t *ci, int
         if (timing && !opt) RSOC_HIP(hipEventRecord(c->ev[3], s));
         if (hub_first) {
             const SingleArgs *A = c->args.as<SingleArgs>();
+            k_hub_sort<<<1, kHubSortBlock, 0, s>>>(A, S);
             if (o.tie) {
                 k_hub_lists<kHigherKeeps><<<kHubListGrid, kBlock, 0, s>>>(A, S);
                 k_hub_ff<kHigherKeeps><<<1, kHubFfBlock, 0, s>>>(A, S);

@@ -40,13 +40,11 @@ struct SingleArgs {
     // hub-first round 0 (optimistic, default flow; hub_kernels.hpp): hub_t is
     // the degree above which a vertex is a hub (0: off; -1: chosen from the
     // max degree, see hub_threshold); hubC the hubs as binning's lists give
-    // them, hubS the same sorted by id; hub_ls / hub_ll / hub_le the list of
-    // each hub (by its position in tie order): the positions of the hubs it
-    // loses to
+    // them, hubS the same sorted by id; hub_bits per hub (by its position in
+    // tie order) the bit set of the positions of the hubs it loses to
     int32_t hub_t;
-    int32_t *hubC, *hubS;
-    int32_t *hub_ls, *hub_ll;
-    uint16_t *hub_le;
+    int32_t *hubC, *hubS, *hub_cpre;
+    uint32_t *hub_bits;
 };
 
 // Hub-first round 0: at most kHubCap hubs (else the pass is skipped); the
@@ -96,7 +94,6 @@ struct SingleState {
     int32_t nH;           // hubs coloured before round 0 (0: none, or the hub-first pass is off)
     int32_t nHc;          // vertices above the hub threshold (k_args; the pass is off above kHubCap)
     int32_t hub_t;        // the hub threshold in use (k_args)
-    int32_t hub_ecnt;     // entries of the hub lists
     int32_t hist[kHistCap];  // |L| of recolouring round i+1
     // worklist rounds' inspection counts (inspected, degree sum), spread over
     // kAccSlots cache lines so that a round's workgroups do not all add to one

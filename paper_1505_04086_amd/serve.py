@@ -142,7 +142,7 @@ class Server:
     """
 
     def __init__(self, ctx: rsoc.Context, hbm_budget: int = 16 << 30, scratch_share: float = 0.35,
-                 max_slots: int = 512, options=None, device: int = 0):
+                 max_slots: int = 512, options=None, device: int = 0, admit_per_poll: int = 32):
         self.ctx = ctx
         self.dev = torch.device("cuda", device)
         self.scratch_cap = int(hbm_budget * scratch_share)
@@ -157,6 +157,10 @@ class Server:
         self.draining = []         # (req, host colours, event, nbytes): D2H in flight
         self.finished = []
         self.steps = 0
+        # admissions per loop iteration: each costs host work (slot set-up
+        # launches), so a burst of arrivals is admitted a few dozen at a time
+        # between pool steps, which keeps the device busy with rounds meanwhile
+        self.admit_per_poll = admit_per_poll
 
     # -- admission ------------------------------------------------------
     def submit(self, req: Request):
@@ -165,6 +169,8 @@ class Server:
         self.queue.append(req)
 
     def _start_copies(self):
+        if len(self.staging) >= self.admit_per_poll:
+            return
         for req, nbytes in admit_fifo(self.queue, self.ledger, self.scratch_cap):
             if nbytes < 0:  # can never fit: complete it with the budget error
                 req.k, req.done = rsoc.RSOC_EBUDGET, time.monotonic()
@@ -182,11 +188,14 @@ class Server:
                 ev = torch.cuda.Event()
                 ev.record(self.copy)
             self.staging.append((req, (rp, ci, col, tch), ev, nbytes))
+            if len(self.staging) >= self.admit_per_poll:
+                break
 
     def _admit_copied(self):
         keep = []
+        admitted = 0
         for req, tens, ev, nbytes in self.staging:
-            if not ev.query():
+            if admitted >= self.admit_per_poll or not ev.query():
                 keep.append((req, tens, ev, nbytes))
                 continue
             rp, ci, col, tch = tens
@@ -199,6 +208,7 @@ class Server:
                 continue
             req.admitted = time.monotonic()
             self.live[slot] = (req, tens, nbytes)
+            admitted += 1
         self.staging = keep
 
     # -- completion -----------------------------------------------------
