@@ -314,8 +314,15 @@ def bench_single(args):
     st = stats[-1]
     if r1 >= r0 or args.mode != "optimistic":
         kname, kms, kbytes = "round1_detect_recolour", r1, st["bytes_round1"]
+        kbytes_lib = kbytes
     else:
-        kname, kms, kbytes = "round0_first_fit", r0, st["bytes_round0"]
+        kname, kms = "round0_first_fit", r0
+        # round-0 bytes as the method defines the round: row_ptr, every
+        # adjacency entry and the colour it names, one colour write per vertex
+        kbytes = 4 * (n + 1) + 8 * len(ci) + 4 * n
+        # the library's own count of what its pruned round 0 must move (each
+        # edge's colour read from one end only, plus the bins and U^0)
+        kbytes_lib = st["bytes_round0"]
     achieved = kbytes / (kms * 1e-3) / 1e9
     traffic = load_traffic(args.workload, kname)
 
@@ -345,7 +352,9 @@ def bench_single(args):
         "alg_bytes_per_step": st["alg_bytes"],
         "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic, "kernel_ms": kms, "alg_bytes_per_launch": kbytes},
+                     "traffic": traffic, "kernel_ms": kms, "alg_bytes_per_launch": kbytes,
+                     "library_bytes_per_launch": kbytes_lib,
+                     "frac_library_bytes": kbytes_lib / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS},
     }
     if not args.no_extras:
         # colour classes of the colouring just made (its independent sets, one per

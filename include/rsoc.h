@@ -97,7 +97,7 @@ typedef struct {
     int32_t grid_thread; /* workgroups given to the thread bin per round launch (default 1024) */
     int32_t grid_wave;   /* workgroups given to the wavefront bin (default 512) */
     int32_t rounds_per_sync; /* rounds enqueued (as one HIP graph) per host check of the worklist (default 4, even) */
-    int32_t small_cutoff;    /* batch: graphs with n <= this are coloured whole by one workgroup (default 4096; -1 disables) */
+    int32_t reserved_a;      /* must be zero */
     int32_t timing;      /* 1: record per-kernel HIP events (fills the ms_* fields of rsoc_stats) */
     /* Optimistic mode only.  0 (default): round 0 gives each vertex the smallest
      * colour absent among the neighbours it loses a tie to (the ones sequential
@@ -270,8 +270,23 @@ int32_t rsoc_pool_admit_recolor(rsoc_pool *pool, const int32_t *d_row_ptr, const
                                 const rsoc_options *opts);
 /* One fused round over all live slots on hip_stream (synchronised).  Writes up
  * to `cap` finished slot ids to finished_slots.  Returns the number finished
- * (they stay reserved until rsoc_pool_result). */
+ * (they stay reserved until rsoc_pool_result), or RSOC_EINVAL while a step
+ * launched by rsoc_pool_step_launch is not finished. */
 int32_t rsoc_pool_step(rsoc_pool *pool, void *hip_stream, int32_t *finished_slots, int32_t cap);
+/* rsoc_pool_step in two halves, for a caller that overlaps host work with the
+ * round (Section 3: one barrier per round is the method's synchronisation;
+ * here the host's wait for it is deferred).  rsoc_pool_step_launch enqueues
+ * the round on hip_stream and returns without waiting for it (it may wait for
+ * a pending admission's set-up when no slot is running).  Until
+ * rsoc_pool_step_finish, the pool accepts rsoc_pool_admit,
+ * rsoc_pool_admit_recolor, rsoc_pool_result (of slots reported by earlier
+ * steps), rsoc_pool_live and rsoc_pool_reserved_bytes; another launch or
+ * rsoc_pool_step returns RSOC_EINVAL.  Slots admitted meanwhile join a later
+ * step.  rsoc_pool_step_finish waits for the launched round and reports
+ * finished slots as rsoc_pool_step does; without a launched step it returns
+ * RSOC_EINVAL.  Both return RSOC_EHIP on a HIP failure. */
+int32_t rsoc_pool_step_launch(rsoc_pool *pool, void *hip_stream);
+int32_t rsoc_pool_step_finish(rsoc_pool *pool, int32_t *finished_slots, int32_t cap);
 /* Number of admitted slots that are not yet released. */
 int32_t rsoc_pool_live(const rsoc_pool *pool);
 /* Scratch bytes currently reserved by admitted slots. */

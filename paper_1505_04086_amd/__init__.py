@@ -62,7 +62,7 @@ class rsoc_options(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("tie", ctypes.c_int32), ("max_rounds", ctypes.c_int32),
                 ("validate", ctypes.c_int32), ("t_thread", ctypes.c_int32), ("t_wave", ctypes.c_int32),
                 ("grid_thread", ctypes.c_int32), ("grid_wave", ctypes.c_int32),
-                ("rounds_per_sync", ctypes.c_int32), ("small_cutoff", ctypes.c_int32),
+                ("rounds_per_sync", ctypes.c_int32), ("reserved_a", ctypes.c_int32),
                 ("timing", ctypes.c_int32), ("full_sweep", ctypes.c_int32), ("lookahead", ctypes.c_int32),
                 ("chunk", ctypes.c_int32), ("grid_list", ctypes.c_int32), ("tail", ctypes.c_int32),
                 ("distance", ctypes.c_int32), ("grid_bin", ctypes.c_int32), ("hub_first", ctypes.c_int32),
@@ -97,6 +97,8 @@ _sig = {
     "rsoc_pool_admit": (_i32, [_p, _p, _p, _i32, _p, ctypes.POINTER(rsoc_options)]),
     "rsoc_pool_admit_recolor": (_i32, [_p, _p, _p, _i32, _p, _p, _i32, ctypes.POINTER(rsoc_options)]),
     "rsoc_pool_step": (_i32, [_p, _p, _p, _i32]),
+    "rsoc_pool_step_launch": (_i32, [_p, _p]),
+    "rsoc_pool_step_finish": (_i32, [_p, _p, _i32]),
     "rsoc_pool_live": (_i32, [_p]),
     "rsoc_pool_reserved_bytes": (_i64, [_p]),
     "rsoc_pool_result": (_i32, [_p, _i32, ctypes.POINTER(rsoc_stats)]),
@@ -378,6 +380,16 @@ class Pool:
     def step(self, stream=None, cap=1024):
         buf = (ctypes.c_int32 * cap)()
         k = _chk(_lib.rsoc_pool_step(self.h, _stream_ptr(stream), buf, cap), "rsoc_pool_step")
+        return [buf[i] for i in range(k)]
+
+    def step_launch(self, stream=None):
+        """Enqueues one fused round without waiting for it (rsoc_pool_step_launch)."""
+        _chk(_lib.rsoc_pool_step_launch(self.h, _stream_ptr(stream)), "rsoc_pool_step_launch")
+
+    def step_finish(self, cap=1024):
+        """Waits for the launched round; returns the finished slots (rsoc_pool_step_finish)."""
+        buf = (ctypes.c_int32 * cap)()
+        k = _chk(_lib.rsoc_pool_step_finish(self.h, buf, cap), "rsoc_pool_step_finish")
         return [buf[i] for i in range(k)]
 
     def live(self) -> int:

@@ -93,7 +93,7 @@ struct HostPinned {
 };
 
 struct Options {
-    int mode, tie, max_rounds, validate, t_thread, t_wave, grid_thread, grid_wave, rounds_per_sync, small_cutoff,
+    int mode, tie, max_rounds, validate, t_thread, t_wave, grid_thread, grid_wave, rounds_per_sync,
         timing, full_sweep, lookahead, chunk, grid_list, tail, distance, grid_bin, hub_first;
 };
 
@@ -108,7 +108,7 @@ inline int32_t resolve_options(const rsoc_options *o, int64_t n, Options &r) {
     if (d.max_rounds < 0 || d.t_thread < 0 || d.t_thread > 32 || d.t_wave < 0 || d.grid_thread < 0 ||
         d.grid_wave < 0 || d.rounds_per_sync < 0 || d.validate < 0 || d.validate > 3 || d.grid_list < 0)
         return RSOC_EINVAL;
-    if (d.reserved[0] || d.reserved[1] || d.grid_bin < 0) return RSOC_EINVAL;
+    if (d.reserved_a || d.reserved[0] || d.reserved[1] || d.grid_bin < 0) return RSOC_EINVAL;
     if (d.hub_first < -1) return RSOC_EINVAL;
     r.grid_bin = d.grid_bin;  // 0: each launch site's own default
     if (d.distance < 0 || d.distance > 2) return RSOC_EINVAL;
@@ -131,7 +131,6 @@ inline int32_t resolve_options(const rsoc_options *o, int64_t n, Options &r) {
     r.grid_list = d.grid_list ? d.grid_list : 1024;
     r.rounds_per_sync = d.rounds_per_sync ? d.rounds_per_sync : 4;
     if (r.rounds_per_sync & 1) r.rounds_per_sync += 1;  // worklist buffers alternate: keep it even
-    r.small_cutoff = d.small_cutoff == 0 ? 4096 : (d.small_cutoff < 0 ? -1 : d.small_cutoff);
     r.timing = d.timing;
     // hub threshold: 0 = off, -1 = automatic (from the max degree, on the
     // device), else the degree given, never below the lane-group bin's limit,

@@ -4,7 +4,7 @@
 // from an arena sized by the HBM budget; admission is refused with
 // RSOC_EBUDGET when it does not fit.
 //
-// The host waits on the device once or twice per step, never per request:
+// The host waits on the device once per step, never per request:
 // admission only enqueues the slot's set-up (k_pinit, and the hub-first pass
 // of an optimistic slot) on one of kAdmitStreams admission streams, in turn,
 // and records the slot's own event; a step takes in the new slots whose
@@ -12,9 +12,12 @@
 // others for a later step, so a long set-up (the hub walk of a large
 // power-law graph is one workgroup's sequential work) neither holds up the
 // rounds of the slots already running nor the set-up of the next requests,
-// which proceed on the other streams; a step in which slots finish enqueues
-// their colour counts and downloads them once; taking a result then needs no
-// device work at all.  Releases go on the context's own stream and record
+// which proceed on the other streams.  A step enqueues, behind its round,
+// the colour counts of the slots the round finishes (kernels that skip the
+// others) and one download of the slot table; taking a result then needs no
+// device work at all.  The step is split in two (rsoc_pool_step_launch,
+// rsoc_pool_step_finish) so that a caller can admit the next graphs while
+// the round runs.  Releases go on the context's own stream and record
 // p->ev, which admissions and steps wait for before touching the slot table.
 #pragma once
 
@@ -30,7 +33,7 @@ struct rsoc_pool {
     int64_t reserved = 0;  // scratch bytes held by admitted slots
     int max_slots = 0;
     rsoc::DevBuf slots_dev, tasks_dev, active_dev, arena;
-    rsoc::HostPinned mirror, tasks_host, active_host;
+    rsoc::HostPinned mirror, active_host;
     std::map<int64_t, int64_t> free_blocks;  // arena offset -> size
     struct Alloc {
         int64_t off = -1, bytes = 0;
@@ -48,6 +51,14 @@ struct rsoc_pool {
     rsoc::DevBuf hub_args[kAdmitStreams], hub_state[kAdmitStreams], hubs[kAdmitStreams];
     int next_astream = 0;
     std::vector<hipEvent_t> slot_ev;  // recorded after a slot's set-up
+    // task-table descriptors of a step (PoolDeal[24], then the spans)
+    rsoc::DevBuf deal_dev;
+    rsoc::HostPinned deal_host;
+    // a step launched by rsoc_pool_step_launch and not yet finished: its
+    // stream and its number of active slots (listed in active_host)
+    bool inflight = false;
+    hipStream_t inflight_s = nullptr;
+    int inflight_nact = 0;
 };
 
 namespace rsoc {
@@ -176,13 +187,14 @@ void rsoc_pool_destroy(rsoc_pool *p) {
     if (p->ev) (void)hipStreamSynchronize(p->ctx->own);
     for (auto &st : p->astream)
         if (st) (void)hipStreamSynchronize(st);
-    for (rsoc::DevBuf *b : {&p->slots_dev, &p->tasks_dev, &p->active_dev, &p->arena}) b->release();
+    if (p->inflight && p->inflight_nact > 0) (void)hipStreamSynchronize(p->inflight_s);
+    for (rsoc::DevBuf *b : {&p->slots_dev, &p->tasks_dev, &p->active_dev, &p->deal_dev, &p->arena}) b->release();
     for (int k = 0; k < rsoc_pool::kAdmitStreams; ++k) {
         p->hub_args[k].release();
         p->hub_state[k].release();
         p->hubs[k].release();
     }
-    for (rsoc::HostPinned *b : {&p->mirror, &p->tasks_host, &p->active_host, &p->stage}) b->release();
+    for (rsoc::HostPinned *b : {&p->mirror, &p->deal_host, &p->active_host, &p->stage}) b->release();
     if (p->ev) (void)hipEventDestroy(p->ev);
     for (auto &e : p->slot_ev)
         if (e) (void)hipEventDestroy(e);
@@ -306,6 +318,7 @@ inline int32_t pool_admit(rsoc_pool *p, const int32_t *d_row_ptr, const int32_t 
             if (nt > 0) k_ptouch<<<std::min(div_up(nt, kBlock), 256), kBlock, 0, s>>>(p->slots_dev.as<PoolSlot>(), slot);
             k_plist<<<gbin, kBlock, 0, s>>>(p->slots_dev.as<PoolSlot>(), slot);
         }
+        k_pready<<<1, 1, 0, s>>>(p->slots_dev.as<PoolSlot>(), slot);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) { pool_release(p, slot); return hip_fail(e, "k_pinit", __FILE__, __LINE__); }
         if ((r = pool_download_slot(p, slot, s)) < 0) { pool_release(p, slot); return r; }
@@ -329,9 +342,9 @@ int32_t rsoc_pool_admit_recolor(rsoc_pool *p, const int32_t *d_row_ptr, const in
     return rsoc::pool_admit(p, d_row_ptr, d_col_idx, n, d_colors_inout, opts, true, d_touched, n_touched);
 }
 
-int32_t rsoc_pool_step(rsoc_pool *p, void *hip_stream, int32_t *finished_slots, int32_t cap) {
+int32_t rsoc_pool_step_launch(rsoc_pool *p, void *hip_stream) {
     using namespace rsoc;
-    if (!p || cap < 0 || (cap > 0 && !finished_slots)) return RSOC_EINVAL;
+    if (!p || p->inflight) return RSOC_EINVAL;
     rsoc_ctx *c = p->ctx;
     RSOC_HIP(hipSetDevice(c->device));
     hipStream_t s = (hipStream_t)hip_stream;
@@ -356,174 +369,148 @@ int32_t rsoc_pool_step(rsoc_pool *p, void *hip_stream, int32_t *finished_slots, 
             const hipError_t q = hipEventQuery(p->slot_ev[i]);
             if (q == hipErrorNotReady) continue;
             if (q != hipSuccess) return hip_fail(q, "hipEventQuery", __FILE__, __LINE__);
+            // the set-up finished the slot's state on the device (k_pready)
+            // and downloaded it: the mirror entry is final
             p->pending[i] = 0;
-            PoolSlot &ms = m[i];
-            if (ms.status < 0) {
-                ms.phase = kSlotDone;  // bad row_ptr ends, missing col_idx, touched id out of range
-            } else {
-                ms.offW = ms.n - ms.nW - ms.nB;
-                ms.offB = ms.n - ms.nB;
-                ms.chunk = pick_chunk(ms.chunk, ms.near, ms.sampled);
-                // an empty U^0 still takes one (empty) step, which ends the
-                // slot and counts its colours
-                if (ms.recolor) ms.u0 = ms.cnt_in[0] + ms.cnt_in[1] + ms.cnt_in[2];
-            }
-            RSOC_TRY(pool_upload_slot(p, i, s));
         }
     }
-    // task tables, one per (kind, tie rule): workgroup-bin tasks, then
-    // wavefront-bin, then thread-bin
+    // Spans of the task tables, one table per (kind, tie rule) and bin; a
+    // slot's thread-bin items may belong to another kind than its other bins
+    // (the masked first worklist round).  Tables are laid out by (kind, tie
+    // rule), each with its workgroup-bin tasks, then wavefront-bin, then
+    // thread-bin; k_pdeal fills them on the device.
     constexpr int kKinds = 8;  // kind * 2 + tie
-    std::vector<PoolTask> tb[kKinds], tw[kKinds], tt[kKinds];
-    struct SlotSpan {
-        int slot, kind, kindT, cT, cW, cB;  // kind / kindT: table index (task kind * 2 + tie)
-    };
-    std::vector<SlotSpan> spans;
-    int nact = 0;
+    constexpr int kPer[3] = {kPoolTaskB, kPoolTaskW, kPoolTaskT};
+    std::vector<PoolSpan> spans[kKinds][3];
+    int nact = 0, maxn = 0;
     int32_t *act = p->active_host.as<int32_t>();
     for (int i = 0; i < p->max_slots; ++i) {
         const PoolSlot &sl = m[i];
         if (p->pending[i]) continue;  // set-up still running (its mirror entry may be mid-download)
         if (sl.phase != kSlotNew && sl.phase != kSlotRunning) continue;
-        int kind, cT, cW, cB;
+        int kind, cnt[3];  // workgroup, wavefront, thread bin
         if (sl.phase == kSlotNew) {
             kind = sl.mode == kOptimistic ? kAssignSweep : kRecolorSweep;
-            cT = sl.n;  // the sweep skips the other bins' vertices
-            cW = sl.nW;
-            cB = sl.nB;
+            cnt[2] = sl.n;  // the sweep skips the other bins' vertices
+            cnt[1] = sl.nW;
+            cnt[0] = sl.nB;
         } else {
             kind = kRecolorList;
-            cT = sl.cnt_in[0];
-            cW = sl.cnt_in[1];
-            cB = sl.cnt_in[2];
+            cnt[2] = sl.cnt_in[0];
+            cnt[1] = sl.cnt_in[1];
+            cnt[0] = sl.cnt_in[2];
         }
         // the thread bin's part of the first worklist round after round 0
         const int kindT = (sl.phase == kSlotRunning && sl.masked) ? kRecolorMasked : kind;
-        spans.push_back({i, kind * 2 + sl.tie, kindT * 2 + sl.tie, cT, cW, cB});
+        for (int bin = 0; bin < 3; ++bin) {
+            if (cnt[bin] <= 0) continue;
+            const int k = (bin == 2 ? kindT : kind) * 2 + sl.tie;
+            spans[k][bin].push_back({i, cnt[bin], (int)((cnt[bin] + (int64_t)kPer[bin] - 1) / kPer[bin])});
+        }
         act[nact++] = i;
+        maxn = std::max(maxn, sl.n);
     }
-    // Each bin's tasks are dealt in proportion over the launch: task r of a
-    // slot with T tasks lands in bucket r * kDealBuckets / T, buckets in
-    // order.  The workgroups take the table in order, so every graph advances
-    // through its ids at the same relative pace and has about the same small
-    // fraction of them in flight at any time, as a single-graph sweep does;
-    // dealt slot by slot, a graph would have all its vertices coloured in the
-    // same instant (each reading its neighbours uncoloured: most would end
-    // round 0 defective), and the last graphs of the table would get the
-    // whole grid to themselves.
-    constexpr int kDealBuckets = 4096;
-    std::vector<int> fill(kDealBuckets + 1);
-    auto deal = [&](int which, int per) {
-        for (int k = 0; k < kKinds; ++k) {
-            std::vector<PoolTask> &out = which == 0 ? tt[k] : (which == 1 ? tw[k] : tb[k]);
-            std::fill(fill.begin(), fill.end(), 0);
-            size_t total = 0;
-            for (const SlotSpan &sp : spans) {
-                if ((which == 0 ? sp.kindT : sp.kind) != k) continue;
-                const int cnt = which == 0 ? sp.cT : (which == 1 ? sp.cW : sp.cB);
-                const int T = (cnt + per - 1) / per;
-                for (int r = 0; r < T; ++r) fill[(int)((int64_t)r * kDealBuckets / T) + 1] += 1;
-                total += (size_t)T;
-            }
-            if (!total) continue;
-            for (int b = 0; b < kDealBuckets; ++b) fill[b + 1] += fill[b];
-            out.resize(total);
-            for (const SlotSpan &sp : spans) {
-                if ((which == 0 ? sp.kindT : sp.kind) != k) continue;
-                const int cnt = which == 0 ? sp.cT : (which == 1 ? sp.cW : sp.cB);
-                const int T = (cnt + per - 1) / per;
-                for (int r = 0; r < T; ++r) {
-                    const int64_t b = (int64_t)r * per;
-                    out[fill[(int)((int64_t)r * kDealBuckets / T)]++] = {sp.slot, k / 2, (int)b,
-                                                                         (int)std::min<int64_t>(cnt, b + per)};
-                }
-            }
+    p->inflight_nact = nact;
+    p->inflight_s = s;
+    if (nact == 0) {
+        p->inflight = true;
+        return RSOC_OK;
+    }
+    int ndeal = 0, nspan = 0;
+    int64_t ntask = 0;
+    int tstart[kKinds], tcount[kKinds][3];
+    PoolDeal deals[kKinds * 3];
+    for (int k = 0; k < kKinds; ++k) {
+        tstart[k] = (int)ntask;
+        for (int bin = 0; bin < 3; ++bin) {
+            int64_t t = 0;
+            for (const PoolSpan &e : spans[k][bin]) t += e.ntask;
+            tcount[k][bin] = (int)t;
+            if (t) deals[ndeal++] = {nspan, (int)spans[k][bin].size(), kPer[bin], k / 2, (int)ntask, (int)t};
+            nspan += (int)spans[k][bin].size();
+            ntask += t;
         }
-    };
-    deal(2, kPoolTaskB);
-    deal(1, kPoolTaskW);
-    deal(0, kPoolTaskT);
-    int nfin = 0;
-    if (nact > 0) {
-        size_t ntask = 0;
-        for (int k = 0; k < kKinds; ++k) ntask += tb[k].size() + tw[k].size() + tt[k].size();
-        RSOC_TRY(p->tasks_dev.reserve(sizeof(PoolTask) * std::max<size_t>(ntask, 1)));
-        RSOC_TRY(p->tasks_host.reserve(sizeof(PoolTask) * std::max<size_t>(ntask, 1)));
-        PoolTask *th = p->tasks_host.as<PoolTask>();
-        size_t at = 0, start[kKinds];
-        for (int k = 0; k < kKinds; ++k) {
-            start[k] = at;
-            for (const auto *v : {&tb[k], &tw[k], &tt[k]}) {
-                std::copy(v->begin(), v->end(), th + at);
-                at += v->size();
-            }
+    }
+    if (ntask > INT32_MAX) return RSOC_EINVAL;  // more tasks than a table indexes (not reachable below 2^31 vertices)
+    const size_t deal_bytes = sizeof(PoolDeal) * kKinds * 3;
+    RSOC_TRY(p->tasks_dev.reserve(sizeof(PoolTask) * (size_t)std::max<int64_t>(ntask, 1)));
+    RSOC_TRY(p->deal_host.reserve(deal_bytes + sizeof(PoolSpan) * (size_t)nspan));
+    RSOC_TRY(p->deal_dev.reserve(deal_bytes + sizeof(PoolSpan) * (size_t)nspan));
+    char *dh = p->deal_host.as<char>();
+    memcpy(dh, deals, sizeof(PoolDeal) * ndeal);
+    PoolSpan *sh = reinterpret_cast<PoolSpan *>(dh + deal_bytes);
+    for (int k = 0; k < kKinds; ++k)
+        for (int bin = 0; bin < 3; ++bin) sh = std::copy(spans[k][bin].begin(), spans[k][bin].end(), sh);
+    RSOC_HIP(hipMemcpyAsync(p->deal_dev.p, dh, deal_bytes + sizeof(PoolSpan) * (size_t)nspan, hipMemcpyHostToDevice,
+                            s));
+    RSOC_HIP(hipMemcpyAsync(p->active_dev.p, act, sizeof(int32_t) * nact, hipMemcpyHostToDevice, s));
+    PoolTask *tasks = p->tasks_dev.as<PoolTask>();
+    k_pdeal<<<dim3(ndeal, kDealSplit), kDealBlock, 0, s>>>(p->deal_dev.as<PoolDeal>(),
+                                         reinterpret_cast<const PoolSpan *>(p->deal_dev.as<char>() + deal_bytes),
+                                         tasks);
+    // one launch per (kind, tie rule) present; a slot's tasks are all of one
+    // kind but the masked round's wavefront/workgroup-bin ones, whose launch
+    // comes first (the launches run in stream order; each hub recoloured
+    // first reads the thread-bin colours as they stand, so the masked test of
+    // those vertices stays sound)
+    PoolSlot *sd = p->slots_dev.as<PoolSlot>();
+    for (int k = 0; k < kKinds; ++k) {
+        const int nb = tcount[k][0], nw = tcount[k][1], nt = tcount[k][2];
+        const int gB = std::min(nb, 256);
+        const int gW = std::min(nw, 512);
+        // no more thread-bin workgroups than fit on the device at once: the
+        // grid-stride walk would otherwise leave the tasks of the ones that
+        // wait to the end, out of id order, and round 0 would read many more
+        // neighbours uncoloured
+        const int gT = std::min(nt, 1024);
+        if (gB + gW + gT == 0) continue;
+        PoolTask *tk = tasks + tstart[k];
+#define RSOC_PSTEP(KD, T) k_pstep<KD, T><<<gB + gW + gT, kBlock, 0, s>>>(sd, tk, nb, nw, nt, gB, gW, gT)
+        switch (k) {
+            case 0: RSOC_PSTEP(kAssignSweep, kLowerKeeps); break;
+            case 1: RSOC_PSTEP(kAssignSweep, kHigherKeeps); break;
+            case 2: RSOC_PSTEP(kRecolorSweep, kLowerKeeps); break;
+            case 3: RSOC_PSTEP(kRecolorSweep, kHigherKeeps); break;
+            case 4: RSOC_PSTEP(kRecolorList, kLowerKeeps); break;
+            case 5: RSOC_PSTEP(kRecolorList, kHigherKeeps); break;
+            case 6: RSOC_PSTEP(kRecolorMasked, kLowerKeeps); break;
+            default: RSOC_PSTEP(kRecolorMasked, kHigherKeeps); break;
         }
-        RSOC_HIP(hipMemcpyAsync(p->tasks_dev.p, th, sizeof(PoolTask) * ntask, hipMemcpyHostToDevice, s));
-        RSOC_HIP(hipMemcpyAsync(p->active_dev.p, act, sizeof(int32_t) * nact, hipMemcpyHostToDevice, s));
-        // one launch per (kind, tie rule) present; a slot's tasks are all of
-        // one kind but the masked round's wavefront/workgroup-bin ones, whose
-        // launch comes first (the launches run in stream order; each hub
-        // recoloured first reads the thread-bin colours as they stand, so
-        // the masked test of those vertices stays sound)
-        for (int k = 0; k < kKinds; ++k) {
-            const int gB = (int)std::min<size_t>(tb[k].size(), 256);
-            const int gW = (int)std::min<size_t>(tw[k].size(), 512);
-            // no more thread-bin workgroups than fit on the device at once: the
-            // grid-stride walk would otherwise leave the tasks of the ones
-            // that wait to the end, out of id order, and round 0 would read
-            // many more neighbours uncoloured
-            const int gT = (int)std::min<size_t>(tt[k].size(), 1024);
-            if (gB + gW + gT == 0) continue;
-            PoolTask *tk = p->tasks_dev.as<PoolTask>() + start[k];
-            PoolSlot *sl = p->slots_dev.as<PoolSlot>();
-            const int nb = (int)tb[k].size(), nw = (int)tw[k].size(), nt = (int)tt[k].size();
-#define RSOC_PSTEP(KD, T) k_pstep<KD, T><<<gB + gW + gT, kBlock, 0, s>>>(sl, tk, nb, nw, nt, gB, gW, gT)
-            switch (k) {
-                case 0: RSOC_PSTEP(kAssignSweep, kLowerKeeps); break;
-                case 1: RSOC_PSTEP(kAssignSweep, kHigherKeeps); break;
-                case 2: RSOC_PSTEP(kRecolorSweep, kLowerKeeps); break;
-                case 3: RSOC_PSTEP(kRecolorSweep, kHigherKeeps); break;
-                case 4: RSOC_PSTEP(kRecolorList, kLowerKeeps); break;
-                case 5: RSOC_PSTEP(kRecolorList, kHigherKeeps); break;
-                case 6: RSOC_PSTEP(kRecolorMasked, kLowerKeeps); break;
-                default: RSOC_PSTEP(kRecolorMasked, kHigherKeeps); break;
-            }
 #undef RSOC_PSTEP
-        }
-        bool any_staged = false;
-        for (int k = 0; k < nact; ++k) any_staged |= m[act[k]].mode != kOptimistic;
-        if (any_staged)
-            k_pscatter<<<dim3(64, std::min(nact, 64)), kBlock, 0, s>>>(p->slots_dev.as<PoolSlot>(),
-                                                                      p->active_dev.as<int32_t>(), nact);
-        k_pround_end<<<1, 256, 0, s>>>(p->slots_dev.as<PoolSlot>(), p->active_dev.as<int32_t>(), nact);
-        RSOC_LAUNCH_CHECK();
-        PoolSlot *st = p->stage.as<PoolSlot>();
-        RSOC_HIP(hipMemcpyAsync(st, p->slots_dev.p, sizeof(PoolSlot) * (size_t)p->max_slots, hipMemcpyDeviceToHost, s));
-        RSOC_HIP(hipStreamSynchronize(s));
+    }
+    const int32_t *ad = p->active_dev.as<int32_t>();
+    bool any_staged = false;
+    for (int k = 0; k < nact; ++k) any_staged |= m[act[k]].mode != kOptimistic;
+    if (any_staged) k_pscatter<<<dim3(64, std::min(nact, 64)), kBlock, 0, s>>>(sd, ad, nact);
+    k_pround_end<<<1, 256, 0, s>>>(sd, ad, nact);
+    // colour counts of the slots this round finished (the kernels skip the
+    // others), then one download of the slot table
+    const int gy = std::min(nact, 1024);
+    k_pflags_clear<<<dim3(16, gy), kBlock, 0, s>>>(sd, ad, nact);
+    k_pcount<<<dim3(std::max(1, std::min(div_up(maxn, kBlock), 128)), gy), kBlock, 0, s>>>(sd, ad, nact);
+    k_pdistinct<<<dim3(1, gy), kBlock, 0, s>>>(sd, ad, nact);
+    const hipError_t le = hipGetLastError();
+    if (le != hipSuccess) return hip_fail(le, "k_pstep", __FILE__, __LINE__);
+    RSOC_HIP(hipMemcpyAsync(p->stage.p, sd, sizeof(PoolSlot) * (size_t)p->max_slots, hipMemcpyDeviceToHost, s));
+    p->inflight = true;
+    return RSOC_OK;
+}
+
+int32_t rsoc_pool_step_finish(rsoc_pool *p, int32_t *finished_slots, int32_t cap) {
+    using namespace rsoc;
+    if (!p || !p->inflight || cap < 0 || (cap > 0 && !finished_slots)) return RSOC_EINVAL;
+    RSOC_HIP(hipSetDevice(p->ctx->device));
+    p->inflight = false;
+    PoolSlot *m = pool_mirror(p);
+    if (p->inflight_nact > 0) {
+        RSOC_HIP(hipStreamSynchronize(p->inflight_s));
         // only the slots of this step changed on the device
-        for (int k = 0; k < nact; ++k) m[act[k]] = st[act[k]];
-        // colour counts of the slots that finished, one download for all
-        bool counted = false;
-        for (int k = 0; k < nact; ++k) {
-            const int i = act[k];
-            if (m[i].phase != kSlotDone) continue;
-            const bool wide = m[i].maxdeg >= 255 && m[i].n > 255;  // colours of 255 and more possible
-            if (wide) k_pflags_clear<<<std::min(div_up(m[i].maxdeg, kBlock), 64), kBlock, 0, s>>>(
-                p->slots_dev.as<PoolSlot>(), i);
-            k_pcount<<<std::min(div_up(m[i].n, kBlock), 1024), kBlock, 0, s>>>(p->slots_dev.as<PoolSlot>(), i);
-            if (wide) k_pdistinct<<<1, kBlock, 0, s>>>(p->slots_dev.as<PoolSlot>(), i);
-            RSOC_HIP(hipMemcpyAsync(st + i, p->slots_dev.as<PoolSlot>() + i, sizeof(PoolSlot), hipMemcpyDeviceToHost,
-                                    s));
-            counted = true;
-        }
-        if (counted) {
-            RSOC_LAUNCH_CHECK();
-            RSOC_HIP(hipStreamSynchronize(s));
-            for (int k = 0; k < nact; ++k)
-                if (m[act[k]].phase == kSlotDone) m[act[k]] = st[act[k]];
-        }
+        const PoolSlot *st = p->stage.as<PoolSlot>();
+        const int32_t *act = p->active_host.as<int32_t>();
+        for (int k = 0; k < p->inflight_nact; ++k) m[act[k]] = st[act[k]];
     }
     // report finished slots (including ones a previous step could not fit in `cap`)
+    int nfin = 0;
     for (int i = 0; i < p->max_slots && nfin < cap; ++i) {
         if (m[i].phase == kSlotDone && !p->reported[i] && !p->pending[i]) {
             p->reported[i] = 1;
@@ -531,6 +518,12 @@ int32_t rsoc_pool_step(rsoc_pool *p, void *hip_stream, int32_t *finished_slots, 
         }
     }
     return nfin;
+}
+
+int32_t rsoc_pool_step(rsoc_pool *p, void *hip_stream, int32_t *finished_slots, int32_t cap) {
+    if (!p || p->inflight || cap < 0 || (cap > 0 && !finished_slots)) return RSOC_EINVAL;
+    RSOC_TRY(rsoc_pool_step_launch(p, hip_stream));
+    return rsoc_pool_step_finish(p, finished_slots, cap);
 }
 
 int32_t rsoc_pool_live(const rsoc_pool *p) {

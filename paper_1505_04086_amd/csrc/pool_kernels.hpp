@@ -112,6 +112,117 @@ struct PoolTask {
     int32_t slot, kind, begin, end;
 };
 
+// Task tables are dealt on the device.  A step's table of one (kind, tie
+// rule) and bin is described by one PoolDeal and its spans, one per slot in
+// the step: the slot's item count in that bin and its number of tasks
+// (ceil(items / per)).  Task r of a slot with T tasks goes to bucket
+// floor(r * kDealBuckets / T); the table lists the buckets in order, within a
+// bucket the slots in span order, within a slot its tasks in order.  The
+// workgroups take the table in order, so every graph advances through its
+// ids at the same relative pace and has about the same small fraction of
+// them in flight at any time, as a single-graph sweep does; dealt slot by
+// slot, a graph would have all its vertices coloured in the same instant
+// (each reading its neighbours uncoloured: most would end round 0
+// defective), and the last graphs of the table would get the whole grid to
+// themselves.
+struct PoolSpan {
+    int32_t slot, items, ntask;
+};
+struct PoolDeal {
+    int32_t span0, nspan, per, kind, at, ntask;  // at: the table's first entry in the task array
+};
+constexpr int kDealBuckets = 4096;
+constexpr int kDealBlock = 1024;
+
+// first task of bucket b among T: ceil(b * T / kDealBuckets)
+__device__ __forceinline__ int deal_first(int64_t T, int b) {
+    return (int)((T * b + kDealBuckets - 1) / kDealBuckets);
+}
+
+__device__ __forceinline__ int wave_incl_scan(int x) {
+    const int ln = lane_id();
+    for (int off = 1; off < kWave; off <<= 1) {
+        const int y = __shfl_up(x, off);
+        if (ln >= off) x += y;
+    }
+    return x;
+}
+
+// grid (tables, kDealSplit): every workgroup of a table computes the bucket
+// sizes and their exclusive scan in LDS, then its wavefronts write the tasks
+// of its share of the buckets, one bucket per wavefront at a time.  The spans
+// are staged in LDS (up to kDealLdsSpans; beyond that they are read from
+// global memory, in order).
+constexpr int kDealSplit = 8;
+constexpr int kDealLdsSpans = 2048;
+
+__global__ __launch_bounds__(kDealBlock) void k_pdeal(const PoolDeal *__restrict__ deals,
+                                                      const PoolSpan *__restrict__ spans,
+                                                      PoolTask *__restrict__ tasks) {
+    constexpr int kPer = kDealBuckets / kDealBlock;
+    constexpr int kWaves = kDealBlock / kWave;
+    __shared__ int first[kDealBuckets];
+    __shared__ int wsum[kWaves];
+    __shared__ PoolSpan lsp[kDealLdsSpans];
+    const PoolDeal d = deals[blockIdx.x];
+    const bool in_lds = d.nspan <= kDealLdsSpans;
+    for (int k = threadIdx.x; in_lds && k < d.nspan; k += kDealBlock) lsp[k] = spans[d.span0 + k];
+    __syncthreads();
+    const PoolSpan *sp = in_lds ? lsp : spans + d.span0;
+    const int b0 = threadIdx.x * kPer;
+    int c[kPer] = {};
+    for (int k = 0; k < d.nspan; ++k) {
+        const int64_t T = sp[k].ntask;
+        int lo = deal_first(T, b0);
+        for (int j = 0; j < kPer; ++j) {
+            const int hi = deal_first(T, b0 + j + 1);
+            c[j] += hi - lo;
+            lo = hi;
+        }
+    }
+    int mine = 0;
+    for (int j = 0; j < kPer; ++j) mine += c[j];
+    const int wv = threadIdx.x / kWave, ln = lane_id();
+    const int incl = wave_incl_scan(mine);
+    if (ln == kWave - 1) wsum[wv] = incl;
+    __syncthreads();
+    if (wv == 0) {
+        const int w = wave_incl_scan(ln < kWaves ? wsum[ln] : 0);
+        if (ln < kWaves) wsum[ln] = w;
+    }
+    __syncthreads();
+    int base = incl - mine + (wv > 0 ? wsum[wv - 1] : 0);
+    for (int j = 0; j < kPer; ++j) {
+        first[b0 + j] = base;
+        base += c[j];
+    }
+    __syncthreads();
+    PoolTask *out = tasks + d.at;
+    constexpr int kShare = kDealBuckets / kDealSplit;
+    const int bend = (blockIdx.y + 1) * kShare;
+    for (int b = blockIdx.y * kShare + wv; b < bend; b += kWaves) {
+        int run = first[b];
+        for (int k0 = 0; k0 < d.nspan; k0 += kWave) {
+            const int k = k0 + ln;
+            int lo = 0, cnt = 0, slot = 0, items = 0;
+            if (k < d.nspan) {
+                const PoolSpan e = sp[k];
+                slot = e.slot;
+                items = e.items;
+                lo = deal_first(e.ntask, b);
+                cnt = deal_first(e.ntask, b + 1) - lo;
+            }
+            const int x = wave_incl_scan(cnt);
+            PoolTask *o = out + run + x - cnt;
+            for (int j = 0; j < cnt; ++j) {
+                const int64_t beg = (int64_t)(lo + j) * d.per;
+                o[j] = {slot, d.kind, (int)beg, (int)min<int64_t>(items, beg + d.per)};
+            }
+            run += __shfl(x, kWave - 1);
+        }
+    }
+}
+
 // Admission: fills the colours (round 0 of the round-synchronous mode), bins
 // by degree, samples id locality, and checks the ends of row_ptr (status
 // RSOC_ECSR when row_ptr[0] != 0 or row_ptr[n] < 0, RSOC_EINVAL when edges
@@ -495,53 +606,91 @@ __global__ void k_pround_end(PoolSlot *slots, const int32_t *__restrict__ active
     }
 }
 
-// Colour statistics of a finished slot: K (kmax), the colours below 255 in
-// use (cbits), and a flag per colour of 255 and more in the slot's first
-// worklist buffer (free once the slot is done; k_pflags_clear zeroed the
-// flags up to its max degree, which bounds every colour).
-__global__ __launch_bounds__(kBlock) void k_pcount(PoolSlot *slots, int slot) {
+// Last act of a slot's set-up: the fields the rounds need that follow from
+// what the set-up found (bin offsets, the chunk from the locality sample,
+// |U^0| of a recolouring), or the end of a slot whose input was rejected.
+// The download that follows gives the host its final state.
+__global__ void k_pready(PoolSlot *slots, int slot) {
+    PoolSlot *sp = slots + slot;
+    if (sp->status < 0) {
+        sp->phase = kSlotDone;  // bad row_ptr ends, missing col_idx, touched id out of range
+        return;
+    }
+    sp->offW = sp->n - sp->nW - sp->nB;
+    sp->offB = sp->n - sp->nB;
+    sp->chunk = pick_chunk(sp->chunk, sp->near, sp->sampled);
+    // an empty U^0 still takes one (empty) step, which ends the slot and
+    // counts its colours
+    if (sp->recolor) sp->u0 = sp->cnt_in[0] + sp->cnt_in[1] + sp->cnt_in[2];
+}
+
+// Colour statistics of the slots that finished in this step, enqueued right
+// after the step's round (grid.y walks the step's active slots; the others
+// leave at once): K (kmax), the colours below 255 in use (cbits), and a flag
+// per colour of 255 and more in the slot's first worklist buffer (free once
+// the slot is done; k_pflags_clear zeroed the flags up to its max degree,
+// which bounds every colour), which k_pdistinct counts.
+__device__ __forceinline__ bool wide_colours(const PoolSlot *sp) { return sp->maxdeg >= 255 && sp->n > 255; }
+
+__global__ __launch_bounds__(kBlock) void k_pcount(PoolSlot *slots, const int32_t *__restrict__ active, int nact) {
     __shared__ int sh[kWavesPerBlock];
     __shared__ uint32_t bits[8];
-    PoolSlot *sp = slots + slot;
-    if (threadIdx.x < 8) bits[threadIdx.x] = 0;
-    __syncthreads();
-    int32_t *flags = sp->wl[0];
-    int m = -1;
-    bool bad = false;
-    for (int v = blockIdx.x * kBlock + threadIdx.x; v < sp->n; v += gridDim.x * kBlock) {
-        const int c = sp->col[v];
-        bad |= (c < 0 || c >= sp->n);
-        m = max(m, c);
-        if (c >= 0 && c < 255) lds_or(&bits[c >> 5], 1u << (c & 31));
-        else if (c >= 255 && c < sp->n) flags[c] = 1;
+    for (int k = blockIdx.y; k < nact; k += gridDim.y) {
+        PoolSlot *sp = slots + active[k];
+        if (sp->phase != kSlotDone) continue;  // uniform over the workgroup
+        const int n = sp->n;
+        if ((int64_t)blockIdx.x * kBlock >= n) continue;
+        __syncthreads();
+        if (threadIdx.x < 8) bits[threadIdx.x] = 0;
+        __syncthreads();
+        int32_t *flags = sp->wl[0];
+        const int32_t *col = sp->col;
+        int m = -1;
+        bool bad = false;
+        for (int v = blockIdx.x * kBlock + threadIdx.x; v < n; v += gridDim.x * kBlock) {
+            const int c = col[v];
+            bad |= (c < 0 || c >= n);
+            m = max(m, c);
+            if (c >= 0 && c < 255) lds_or(&bits[c >> 5], 1u << (c & 31));
+            else if (c >= 255 && c < n) flags[c] = 1;
+        }
+        if (ballot(bad) && lane_id() == 0) atomicOr(&sp->err, 4);
+        m = block_max(m, sh);
+        if (threadIdx.x == 0) atomicMax(&sp->kmax, m + 1);
+        if (threadIdx.x < 8 && bits[threadIdx.x]) atomicOr(&sp->cbits[threadIdx.x], bits[threadIdx.x]);
     }
-    if (ballot(bad) && lane_id() == 0) atomicOr(&sp->err, 4);
-    m = block_max(m, sh);
-    if (threadIdx.x == 0) atomicMax(&sp->kmax, m + 1);
-    if (threadIdx.x < 8 && bits[threadIdx.x]) atomicOr(&sp->cbits[threadIdx.x], bits[threadIdx.x]);
 }
 
 // Zeroes the flags k_pcount sets: colours 255 .. min(max degree, n - 1).
-__global__ __launch_bounds__(kBlock) void k_pflags_clear(PoolSlot *slots, int slot) {
-    PoolSlot *sp = slots + slot;
-    const int hi = min(sp->maxdeg, sp->n - 1);
-    for (int c = 255 + blockIdx.x * kBlock + threadIdx.x; c <= hi; c += gridDim.x * kBlock) sp->wl[0][c] = 0;
+__global__ __launch_bounds__(kBlock) void k_pflags_clear(PoolSlot *slots, const int32_t *__restrict__ active,
+                                                         int nact) {
+    for (int k = blockIdx.y; k < nact; k += gridDim.y) {
+        PoolSlot *sp = slots + active[k];
+        if (sp->phase != kSlotDone || !wide_colours(sp)) continue;
+        const int hi = min(sp->maxdeg, sp->n - 1);
+        for (int c = 255 + blockIdx.x * kBlock + threadIdx.x; c <= hi; c += gridDim.x * kBlock) sp->wl[0][c] = 0;
+    }
 }
 
-// Counts the flags of colours 255 .. kmax - 1 into sp->distinct.
-__global__ __launch_bounds__(kBlock) void k_pdistinct(PoolSlot *slots, int slot) {
+// Counts the flags of colours 255 .. kmax - 1 into sp->distinct (one
+// workgroup per slot).
+__global__ __launch_bounds__(kBlock) void k_pdistinct(PoolSlot *slots, const int32_t *__restrict__ active, int nact) {
     __shared__ int sh[kWavesPerBlock];
-    PoolSlot *sp = slots + slot;
-    const int hi = min(sp->kmax, sp->n);
-    int cnt = 0;
-    for (int c = 255 + (int)threadIdx.x; c < hi; c += kBlock) cnt += sp->wl[0][c];
-    for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
-    if (lane_id() == 0) sh[threadIdx.x / kWave] = cnt;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int t = 0;
-        for (int w = 0; w < kWavesPerBlock; ++w) t += sh[w];
-        sp->distinct = t;
+    for (int k = blockIdx.y; k < nact; k += gridDim.y) {
+        PoolSlot *sp = slots + active[k];
+        if (sp->phase != kSlotDone || !wide_colours(sp)) continue;
+        const int hi = min(sp->kmax, sp->n);
+        int cnt = 0;
+        for (int c = 255 + (int)threadIdx.x; c < hi; c += kBlock) cnt += sp->wl[0][c];
+        for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
+        __syncthreads();
+        if (lane_id() == 0) sh[threadIdx.x / kWave] = cnt;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int t = 0;
+            for (int w = 0; w < kWavesPerBlock; ++w) t += sh[w];
+            sp->distinct = t;
+        }
     }
 }
 

@@ -142,7 +142,8 @@ class Server:
     """
 
     def __init__(self, ctx: rsoc.Context, hbm_budget: int = 16 << 30, scratch_share: float = 0.35,
-                 max_slots: int = 512, options=None, device: int = 0, admit_per_poll: int = 32):
+                 max_slots: int = 512, options=None, device: int = 0, admit_per_poll: int = 32,
+                 solo_when_idle: bool = True):
         self.ctx = ctx
         self.dev = torch.device("cuda", device)
         self.scratch_cap = int(hbm_budget * scratch_share)
@@ -161,6 +162,11 @@ class Server:
         # launches), so a burst of arrivals is admitted a few dozen at a time
         # between pool steps, which keeps the device busy with rounds meanwhile
         self.admit_per_poll = admit_per_poll
+        # a request alone on an idle server goes straight to the single-graph
+        # entry point (_run_alone); solo counts those runs
+        self.solo_when_idle = solo_when_idle
+        self.solo = 0
+        self.inflight = False  # a pool round launched and not yet waited for
 
     # -- admission ------------------------------------------------------
     def submit(self, req: Request):
@@ -177,6 +183,15 @@ class Server:
                 self.finished.append(req)
                 continue
             self.ledger.take(nbytes)
+            if _on_device(req.row_ptr) and req.prev_colors is None:
+                # CSR already resident and no colouring to copy in: the request
+                # is ready at once (its colour array is only written by the
+                # library's kernels)
+                col = torch.empty(max(req.n, 1), dtype=torch.int32, device=self.dev)
+                self.staging.append((req, (req.row_ptr, req.col_idx, col, None), None, nbytes))
+                if len(self.staging) >= self.admit_per_poll:
+                    break
+                continue
             with torch.cuda.stream(self.copy):
                 if _on_device(req.row_ptr):  # CSR already resident: nothing to copy
                     rp, ci = req.row_ptr, req.col_idx
@@ -191,11 +206,43 @@ class Server:
             if len(self.staging) >= self.admit_per_poll:
                 break
 
+    def _run_alone(self):
+        """A request that finds the server otherwise idle (nothing running,
+        nothing else arrived) is coloured at once with the single-graph entry
+        point instead of through pool steps: the pool's per-round host
+        round trips only pay off when several graphs share them, and alone the
+        single-graph driver (captured rounds, one host check per few rounds)
+        has the lower latency.  Requests arriving meanwhile wait for it, as
+        they would behind one pool step."""
+        req, tens, ev, nbytes = self.staging.pop(0)
+        rp, ci, col, tch = tens
+        opts = req.options or self.options
+        req.admitted = time.monotonic()
+        try:
+            with torch.cuda.stream(self.compute):
+                if req.prev_colors is not None:
+                    req.k, req.stats = rsoc.rsoc_recolor_device(self.ctx, rp, ci, req.n, col, tch, opts,
+                                                                stream=self.compute)
+                else:
+                    req.k, req.stats = rsoc.rsoc_color_device(self.ctx, rp, ci, req.n, col, opts, stream=self.compute)
+        except rsoc.RsocError as e:
+            req.k, req.stats = e.code, {}
+        self.solo += 1
+        self.live[-1 - self.solo] = (req, tens, nbytes)
+        self._retire_result(-1 - self.solo, req.k, req.stats)
+
     def _admit_copied(self):
+        if not self.live and len(self.staging) == 1 and not self.queue and self.solo_when_idle:
+            ev = self.staging[0][2]
+            if ev is None or ev.query():
+                self._run_alone()
+            # else: its copy is still in flight; the loop waits for it and the
+            # next poll runs it alone
+            return
         keep = []
         admitted = 0
         for req, tens, ev, nbytes in self.staging:
-            if admitted >= self.admit_per_poll or not ev.query():
+            if admitted >= self.admit_per_poll or (ev is not None and not ev.query()):
                 keep.append((req, tens, ev, nbytes))
                 continue
             rp, ci, col, tch = tens
@@ -214,27 +261,32 @@ class Server:
     # -- completion -----------------------------------------------------
     def _retire(self, slots):
         for slot in slots:
-            req, (rp, ci, col, tch), nbytes = self.live.pop(slot)
             try:
-                req.k, req.stats = self.pool.result(slot)
+                k, stats = self.pool.result(slot)
             except rsoc.RsocError as e:
-                req.k, req.stats = e.code, {}
-            if _on_device(req.row_ptr):
-                # resident request: the colours stay on the device (the caller
-                # owns the result tensor; it stays accounted until dropped here)
-                req.colors = col[:req.n]
-                req.done = time.monotonic()
-                self.ledger.give(nbytes)
-                self.finished.append(req)
-                continue
-            with torch.cuda.stream(self.copy):
-                self.copy.wait_stream(self.compute)
-                host = torch.empty(max(req.n, 1), dtype=torch.int32, pin_memory=True)
-                host.copy_(col, non_blocking=True)
-                ev = torch.cuda.Event()
-                ev.record(self.copy)
-            # the device tensors stay referenced until the copy has completed
-            self.draining.append((req, host, ev, nbytes, (rp, ci, col, tch)))
+                k, stats = e.code, {}
+            self._retire_result(slot, k, stats)
+
+    def _retire_result(self, slot, k, stats):
+        req, (rp, ci, col, tch), nbytes = self.live.pop(slot)
+        req.k, req.stats = k, stats
+        if _on_device(req.row_ptr):
+            # resident request: the colours stay on the device (the caller
+            # owns the result tensor; it stays accounted until dropped here)
+            req.colors = col[:req.n]
+            req.done = time.monotonic()
+            self.ledger.give(nbytes)
+            self.finished.append(req)
+            return
+        # the colours are final: the pool step that finished the slot, or the
+        # single-graph call, has synchronised the compute stream
+        with torch.cuda.stream(self.copy):
+            host = torch.empty(max(req.n, 1), dtype=torch.int32, pin_memory=True)
+            host.copy_(col, non_blocking=True)
+            ev = torch.cuda.Event()
+            ev.record(self.copy)
+        # the device tensors stay referenced until the copy has completed
+        self.draining.append((req, host, ev, nbytes, (rp, ci, col, tch)))
 
     def _drain(self, block=False):
         keep = []
@@ -253,21 +305,28 @@ class Server:
 
     # -- loop -----------------------------------------------------------
     def idle(self) -> bool:
-        return not (self.queue or self.staging or self.live or self.draining)
+        return not (self.queue or self.staging or self.live or self.draining or self.inflight)
 
     def poll(self):
-        """One loop iteration: start copies, admit copied requests, run one
-        fused pool round, retire finished graphs."""
+        """One loop iteration: wait for the round launched by the previous
+        one, launch the next round at once, and, while it runs, hand out the
+        finished graphs, start copies and admit copied requests (they join a
+        later round)."""
+        fin = []
+        if self.inflight:
+            fin = self.pool.step_finish()
+            self.inflight = False
+            self.steps += 1
+        if len(self.live) > len(fin):  # slots still running or in set-up
+            self.pool.step_launch(stream=self.compute)
+            self.inflight = True
+        if fin:
+            self._retire(fin)
         self._start_copies()
         self._admit_copied()
-        if self.live:
-            fin = self.pool.step(stream=self.compute)
-            self.steps += 1
-            if fin:
-                self._retire(fin)
-        elif self.staging:
+        if not self.inflight and not self.live and self.staging and self.staging[0][2] is not None:
             self.staging[0][2].synchronize()
-        self._drain(block=not self.live and not self.staging and not self.queue)
+        self._drain(block=not self.inflight and not self.live and not self.staging and not self.queue)
 
     def run(self, requests, clock0=None):
         """Serve `requests` (sorted by arrival, offsets in seconds from clock0)."""

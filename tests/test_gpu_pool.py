@@ -224,3 +224,67 @@ def test_pool_recolour_requests(lib, ctx):
         pool.result(slot)
     assert e.value.code == lib.RSOC_EINVAL
     pool.close()
+
+
+def test_pool_split_step(lib, ctx):
+    """rsoc_pool_step_launch / rsoc_pool_step_finish: graphs admitted (and
+    earlier results taken) while a launched round runs join a later round;
+    every result is as with rsoc_pool_step.  A second launch, a plain step
+    while one is in flight, and a finish without a launch are refused."""
+    pool = lib.Pool(ctx, 0, 64)
+    pending = [(g, MODES[(g + i) % 4]) for i in range(2) for g in range(len(GRAPHS))]
+    live, ready = {}, []
+    done = steps = 0
+    with pytest.raises(lib.RsocError) as e:
+        pool.step_finish()
+    assert e.value.code == lib.RSOC_EINVAL
+    while pending or live:
+        pool.step_launch()
+        if steps == 0:
+            for bad in (pool.step_launch, pool.step):
+                with pytest.raises(lib.RsocError) as e:
+                    bad()
+                assert e.value.code == lib.RSOC_EINVAL
+        # results of the previous round, then new graphs, while this round runs
+        for slot in ready:
+            g, mode, tie, d_rp, d_ci, d_col = live.pop(slot)
+            k, st = pool.result(slot)
+            _check(lib, g, mode, tie, d_col, k, st)
+            done += 1
+        for _ in range(3):
+            if pending:
+                g, (mode, tie) = pending.pop(0)
+                d_rp, d_ci, d_col, n = _dev(*GRAPHS[g])
+                slot = pool.admit(d_rp, d_ci, n, d_col, lib.make_options(mode, tie))
+                live[slot] = (g, mode, tie, d_rp, d_ci, d_col)
+        ready = pool.step_finish()
+        steps += 1
+        assert steps < 5000
+    assert done == 2 * len(GRAPHS) and pool.live() == 0 and pool.reserved_bytes() == 0
+    pool.close()
+
+
+def test_pool_many_slots_one_step(lib, ctx):
+    """Many slots of very different sizes in the same rounds (the device deals
+    each table over its buckets): every result as alone."""
+    import torch
+    pool = lib.Pool(ctx, 0, 300)
+    live = {}
+    rng = np.random.default_rng(5)
+    for i in range(260):
+        g = int(rng.integers(len(GRAPHS)))
+        mode, tie = MODES[i % 4]
+        d_rp, d_ci, d_col, n = _dev(*GRAPHS[g])
+        live[pool.admit(d_rp, d_ci, n, d_col, lib.make_options(mode, tie))] = (g, mode, tie, d_rp, d_ci, d_col)
+    torch.cuda.synchronize()
+    done = steps = 0
+    while live:
+        for slot in pool.step():
+            g, mode, tie, d_rp, d_ci, d_col = live.pop(slot)
+            k, st = pool.result(slot)
+            _check(lib, g, mode, tie, d_col, k, st)
+            done += 1
+        steps += 1
+        assert steps < 5000
+    assert done == 260 and pool.live() == 0
+    pool.close()

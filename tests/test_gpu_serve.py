@@ -41,7 +41,9 @@ def test_alone_equals_mix(lib):
     alone = serve.PlainServer(ctx).run(make(np.zeros(len(reqs_spec))))
     # budget for roughly three of the larger graphs at a time: admission must wait for releases
     largest = max(serve.csr_bytes(len(rp) - 1, len(ci)) for rp, ci in GRAPHS)
-    sv = serve.Server(ctx, hbm_budget=int(3 * largest / 0.65), scratch_share=0.35, max_slots=8)
+    # every request through the pool (no single-graph runs on an idle server)
+    sv = serve.Server(ctx, hbm_budget=int(3 * largest / 0.65), scratch_share=0.35, max_slots=8,
+                      solo_when_idle=False)
     arrivals = np.cumsum(np.full(len(reqs_spec), 0.0005))
     mix = sv.run(make(arrivals))
     sv.close()
@@ -102,8 +104,10 @@ def test_recolour_requests_served(lib):
                               touched=touched) for k, (rp, ci, prev, touched, mode) in enumerate(specs)]
 
     largest = max(serve.csr_bytes(len(s[0]) - 1, len(s[1])) for s in specs)
-    sv = serve.Server(ctx, hbm_budget=int(3 * largest / 0.65), scratch_share=0.35, max_slots=8)
+    sv = serve.Server(ctx, hbm_budget=int(3 * largest / 0.65), scratch_share=0.35, max_slots=8,
+                      solo_when_idle=False)
     mix = sv.run(make())
+    assert sv.solo == 0
     sv.close()
     alone = serve.PlainServer(ctx).run(make())
     for out in (mix, alone):
@@ -116,4 +120,55 @@ def test_recolour_requests_served(lib):
             else:
                 assert oracle.check(rp, ci, r.colors) == 0 and r.k == oracle.colour_count(r.colors), r.rid
     assert sv.ledger.used == 0
+    ctx.close()
+
+
+def test_idle_server_runs_lone_requests_directly(lib):
+    """Requests spaced far apart each find the server idle and are coloured
+    with the single-graph entry point (host and device-resident CSR,
+    colourings and recolourings); the results are those of the plain path:
+    deterministic ones equal the oracle's, optimistic ones are valid."""
+    import torch
+    from paper_1505_04086_amd import serve
+    from tests.graph_edits import edit
+    ctx = lib.Context(0)
+    dev = torch.device("cuda:0")
+    specs = []
+    for i, (rp, ci) in enumerate(GRAPHS[:6]):
+        mode = "deterministic" if i % 2 == 0 else "optimistic"
+        specs.append((rp, ci, None, None, mode, i % 3 == 1))
+        if i < 3:
+            n = len(rp) - 1
+            prev, _ = oracle.seq_ff(rp, ci)
+            rp2, ci2, touched = edit(rp, ci, seed=200 + i, add=100, delete=50, new=5)
+            prev2 = np.concatenate([prev, np.full(len(rp2) - 1 - n, -1, np.int32)])
+            specs.append((rp2, ci2, prev2, touched, mode, False))
+
+    def make(rp, ci, resident):
+        if resident:
+            return torch.from_numpy(rp).to(dev), torch.from_numpy(ci if len(ci) else np.zeros(1, np.int32)).to(dev)
+        return rp, ci
+
+    def requests(gap):
+        reqs = []
+        for k, (rp, ci, prev, touched, mode, resident) in enumerate(specs):
+            a, b = make(rp, ci, resident)
+            reqs.append(serve.Request(k, a, b, gap * k, options=lib.make_options(mode), prev_colors=prev,
+                                      touched=touched))
+        return reqs
+
+    serve.PlainServer(ctx).run(requests(0.0))  # first-use set-up of the context, outside the spaced run
+    sv = serve.Server(ctx, hbm_budget=1 << 30, max_slots=8)
+    out = sv.run(requests(0.1))
+    sv.close()
+    assert len(out) == len(specs) and sv.ledger.used == 0
+    assert sv.solo == len(specs), "every request should have found the server idle"
+    for r in out:
+        rp, ci, prev, touched, mode, resident = specs[r.rid]
+        got = r.colors.cpu().numpy() if resident else r.colors
+        if mode == "deterministic":
+            want = oracle.recolor(rp, ci, prev, touched) if prev is not None else oracle.rsync(rp, ci)
+            assert np.array_equal(got, want["colors"]) and r.k == want["K"], r.rid
+        else:
+            assert oracle.check(rp, ci, got) == 0 and r.k == oracle.colour_count(got), r.rid
     ctx.close()
