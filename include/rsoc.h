@@ -95,7 +95,7 @@ typedef struct {
     int32_t t_thread;    /* max degree coloured by a group of 8 lanes (<= 32; default 32) */
     int32_t t_wave;      /* max degree coloured by one wavefront; larger rows use a workgroup (default 2048) */
     int32_t grid_thread; /* workgroups given to the thread bin per round launch (default 1024) */
-    int32_t grid_wave;   /* workgroups given to the wavefront bin (default 512) */
+    int32_t grid_wave;   /* workgroups given to the wavefront bin (default 2048) */
     int32_t rounds_per_sync; /* rounds enqueued (as one HIP graph) per host check of the worklist (default 4, even) */
     int32_t reserved_a;      /* must be zero */
     int32_t timing;      /* 1: record per-kernel HIP events (fills the ms_* fields of rsoc_stats) */

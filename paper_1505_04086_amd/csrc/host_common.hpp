@@ -127,7 +127,7 @@ inline int32_t resolve_options(const rsoc_options *o, int64_t n, Options &r) {
     r.t_wave = d.t_wave ? d.t_wave : 2048;
     if (r.t_wave < r.t_thread) r.t_wave = r.t_thread;
     r.grid_thread = d.grid_thread ? d.grid_thread : 1024;
-    r.grid_wave = d.grid_wave ? d.grid_wave : 512;
+    r.grid_wave = d.grid_wave ? d.grid_wave : 2048;
     r.grid_list = d.grid_list ? d.grid_list : 1024;
     r.rounds_per_sync = d.rounds_per_sync ? d.rounds_per_sync : 4;
     if (r.rounds_per_sync & 1) r.rounds_per_sync += 1;  // worklist buffers alternate: keep it even

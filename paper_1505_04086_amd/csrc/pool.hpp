@@ -457,7 +457,7 @@ int32_t rsoc_pool_step_launch(rsoc_pool *p, void *hip_stream) {
     for (int k = 0; k < kKinds; ++k) {
         const int nb = tcount[k][0], nw = tcount[k][1], nt = tcount[k][2];
         const int gB = std::min(nb, 256);
-        const int gW = std::min(nw, 512);
+        const int gW = std::min(nw, 2048);
         // no more thread-bin workgroups than fit on the device at once: the
         // grid-stride walk would otherwise leave the tasks of the ones that
         // wait to the end, out of id order, and round 0 would read many more

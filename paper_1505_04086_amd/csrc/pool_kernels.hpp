@@ -377,7 +377,8 @@ __device__ __forceinline__ void pool_thread_task(PoolSlot *sp, const PoolSlot &s
             // after a hub-first pass round 0 reads all neighbours (hub colours)
             const int look = (KIND == kAssignSweep && s.nH) ? INT_MAX : s.look;
             group_vertices<PHASE, TIE, kGroup, kGroupSlots, kWinOnly, kNV, kNib>(v, b, e, cis, c8s, cv, look, nc,
-                                                                                 act, unc, c4s, kNib ? keep : nullptr);
+                                                                                 act, unc, c4s, kNib ? keep : nullptr,
+                                                                                 KIND == kAssignSweep && s.nH > 0);
 #pragma unroll
             for (int i = 0; i < kNV; ++i) {
                 if (v[i] < 0) {
@@ -474,7 +475,7 @@ __device__ __forceinline__ void pool_wave_task(PoolSlot *sp, const PoolSlot &s, 
         int nc = 0;
         bool unc = false;
         const bool act = wave_vertex<PHASE, TIE, kWinOnly>(v, b, e, gro(s.ci), gro(s.col), gro(s.col8), bm,
-                                                           hubs ? INT_MAX : s.look, nc, unc, hubs);
+                                                           hubs ? INT_MAX : s.look, nc, unc, hubs, gro(s.col4));
         if (lane_id() == 0 && act) {
             (opt ? s.col : s.pend)[v] = nc;
             if (opt) s.col8[v] = shadow_of(nc);
@@ -501,7 +502,7 @@ __device__ __forceinline__ void pool_block_task(PoolSlot *sp, const PoolSlot &s,
         int nc = 0;
         bool unc = false;
         const bool act = block_vertex<PHASE, TIE, kWinOnly>(v, b, e, gro(s.ci), gro(s.col), gro(s.col8), lds, sh_min,
-                                                            hubs ? INT_MAX : s.look, nc, unc, hubs);
+                                                            hubs ? INT_MAX : s.look, nc, unc, hubs, gro(s.col4));
         if (threadIdx.x == 0) {
             if (act) {
                 (opt ? s.col : s.pend)[v] = nc;

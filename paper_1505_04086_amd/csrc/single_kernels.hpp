@@ -21,7 +21,7 @@ struct SingleArgs {
     const int32_t *ci;   // col_idx[nnz]
     int32_t *col;        // colours[n]
     uint8_t *col8;       // byte shadow of the colours: min(colour, 255), 255 when uncoloured
-    uint32_t *col4;      // 4-bit shadow (8 per word): min(colour, 15); 15 = consult col8 (optimistic mode)
+    uint32_t *col4;      // 4-bit shadow (8 per word): 0..13, 14 = 14 or more, 15 = consult col8 (optimistic mode)
     int32_t *pend;       // staged colours (round-synchronous modes), indexed by vertex
     int4 *aux;           // optimistic mode: what round 0 kept for U^0's thread-bin entries (parallel
                          // to that part of the list): up to three neighbour ids, position mask
@@ -153,12 +153,12 @@ __global__ __launch_bounds__(kHeadBlock) void k_head_out(const SingleArgs *__res
 __device__ __forceinline__ uint8_t shadow_of(int c) { return (uint8_t)((unsigned)c < 255u ? c : 255); }
 
 // Round 0 of the optimistic mode: v's nibble is 15 (nothing written since the
-// fill) and becomes min(c, 15) with one atomic AND, so that the colour is
+// fill) and becomes min(c, 14) with one atomic AND, so that the colour is
 // visible to the 4-bit gathers as soon as it is chosen (hub bins; the lane
 // groups combine the nibbles of one word first).
 __device__ __forceinline__ void publish_nibble(RSOC_GLOBAL uint32_t *col4, int v, int c) {
     const int sh = (v & 7) << 2;
-    atomicAnd((uint32_t *)&col4[v >> 3], ~(0xfu << sh) | ((uint32_t)min(c, 15) << sh));
+    atomicAnd((uint32_t *)&col4[v >> 3], ~(0xfu << sh) | ((uint32_t)min(c, 14) << sh));
 }
 
 // ------------------------------------------------------------------ fill --
@@ -538,7 +538,7 @@ __device__ __forceinline__ void publish_nibbles(const int (&ids)[NV], const int 
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
         const int key = ids[i] >= 0 ? (ids[i] >> 3) : -1 - g;
-        uint32_t clr = v[i] >= 0 ? (0xfu ^ (uint32_t)min(nc[i], 15)) << ((v[i] & 7) << 2) : 0u;
+        uint32_t clr = v[i] >= 0 ? (0xfu ^ (uint32_t)min(nc[i], 14)) << ((v[i] & 7) << 2) : 0u;
 #pragma unroll
         for (int d = 1; d < kWave / kGroup; d <<= 1) {
             const uint32_t oc = __shfl_up(clr, d * kGroup);
@@ -588,8 +588,10 @@ __global__ __launch_bounds__(kBlock) void k_round(const SingleArgs *__restrict__
     if (!SWEEP && S->passes >= a.max_rounds) return;  // guard: the round may not run
     if (SWEEP && (S->err & kErrNoRun)) return;        // the input failed its checks
     // hub-first round 0 (hub_kernels.hpp): the hubs already hold their
-    // colours; every other vertex reads all of its neighbours, upper ones
-    // exactly, so that none takes a hub's colour
+    // colours; every other vertex reads all of its neighbours, those it wins
+    // against through the 4-bit shadow first (a hub's nibble is its colour,
+    // or 14 for 14 and more, settled exactly), so that none takes a hub's
+    // colour
     const int nHub = kFlagAppend ? S->nH : 0;
     const int hubT = nHub ? S->hub_t : INT_MAX;
     const int look = nHub ? INT_MAX : a.look;
@@ -641,7 +643,7 @@ __global__ __launch_bounds__(kBlock) void k_round(const SingleArgs *__restrict__
             int nc = 0;
             bool unc = false;
             const bool act = block_vertex<PHASE, TIE, kWinOnly>(v, b, e, ci, rcol, rcol8, lds, &sh_min, look, nc, unc,
-                                                                nHub > 0);
+                                                                nHub > 0, rcol4);
             const bool take = (kFlagAppend ? unc : act) && kAppend;
             if (threadIdx.x == 0) {
                 items += 1;
@@ -674,7 +676,8 @@ __global__ __launch_bounds__(kBlock) void k_round(const SingleArgs *__restrict__
             if (nHub && e - b > hubT) continue;  // a hub (wavefront-uniform)
             int nc = 0;
             bool unc = false;
-            const bool act = wave_vertex<PHASE, TIE, kWinOnly>(v, b, e, ci, rcol, rcol8, bm, look, nc, unc, nHub > 0);
+            const bool act =
+                wave_vertex<PHASE, TIE, kWinOnly>(v, b, e, ci, rcol, rcol8, bm, look, nc, unc, nHub > 0, rcol4);
             if (lane_id() == 0) {
                 items += 1;
                 degs += (uint64_t)(e - b);
@@ -810,7 +813,8 @@ __global__ __launch_bounds__(kBlock) void k_round(const SingleArgs *__restrict__
                 for (int i = 0; i < kNV; ++i) cis[i] = ci, c8s[i] = rcol8, c4s[i] = rcol4;
                 group_vertices<PHASE, TIE, kGroup, kGroupSlots, kWinOnly, kNV, kNibRead>(v, b, e, cis, c8s, cv, look, nc,
                                                                                      act, unc, c4s,
-                                                                                     kFlagAppend ? keep : nullptr);
+                                                                                     kFlagAppend ? keep : nullptr,
+                                                                                     nHub > 0);
 #pragma unroll
                 for (int i = 0; i < kNV; ++i) {
                     if (v[i] < 0) {
@@ -939,7 +943,7 @@ __global__ __launch_bounds__(kBlock) void k_inc_shadow(const SingleArgs *__restr
             for (int k = 0; k < 8; ++k) {
                 const int64_t v = w * 8 + k;
                 const int c = v < a.n ? col[v] : -1;
-                word |= ((c < 0 || c > 15) ? 15u : (uint32_t)c) << (4 * k);
+                word |= (c < 0 ? 15u : (uint32_t)min(c, 14)) << (4 * k);
             }
             a.col4[w] = word;
         }

@@ -40,10 +40,14 @@ namespace rsoc {
 // ci[i] / col8[i] / col4[i] are the (per-graph) bases vertex i's ids refer to.
 //
 // NIB: colours are first read from a 4-bit shadow (eight vertices per 32-bit
-// word, value min(colour, 15)); a nibble of 15 ("15 or more, or uncoloured")
-// falls back to the byte shadow where exact[s] is set, and reads as
-// uncoloured (255) elsewhere.  The 4-bit array is half the size of the byte
-// one, so far more of it stays in each XCD's L2 under random gathers.
+// word): 0..13 are the colour, 14 means "coloured, 14 or more", 15 "not
+// coloured yet" in round 0 and "consult the byte shadow" after it (a vertex
+// recoloured later gets 15 back).  Where exact[s] is set, 14 and 15 fall back
+// to the byte shadow; elsewhere they read as uncoloured (255), except that
+// with `big` a 14 is settled from the byte shadow too (round 0 after the
+// hub-first pass: a hub among the neighbours v wins against must be seen).
+// The 4-bit array is half the size of the byte one, so far more of it stays
+// in each XCD's L2 under random gathers.
 // Colour reads are agent-scope relaxed loads: a kernel that colours in place
 // must not be served a line its compute unit's L1 cached before another
 // compute unit wrote the colour (a stale "uncoloured" costs conflicts).
@@ -57,7 +61,7 @@ __device__ __forceinline__ int colour_byte(const RSOC_GLOBAL uint8_t *p) {
 template <bool NIB, int S>
 __device__ __forceinline__ void gather_colours(const int (&u)[S], const bool (&take)[S], const bool (&exact)[S],
                                                const RSOC_GLOBAL uint8_t *col8, const RSOC_GLOBAL uint32_t *col4,
-                                               int (&out)[S]) {
+                                               int (&out)[S], bool big = false) {
     if (!NIB) {
 #pragma unroll
         for (int s = 0; s < S; ++s) out[s] = take[s] ? colour_byte(col8 + u[s]) : 255;
@@ -70,7 +74,7 @@ __device__ __forceinline__ void gather_colours(const int (&u)[S], const bool (&t
     for (int s = 0; s < S; ++s) out[s] = (int)((w[s] >> ((u[s] & 7) << 2)) & 15u);
 #pragma unroll
     for (int s = 0; s < S; ++s)
-        if (out[s] == 15) out[s] = (take[s] && exact[s]) ? colour_byte(col8 + u[s]) : 255;
+        if (out[s] >= 14) out[s] = (take[s] && (exact[s] || (big && out[s] == 14))) ? colour_byte(col8 + u[s]) : 255;
 #pragma unroll
     for (int s = 0; s < S; ++s)
         if (!take[s]) out[s] = 255;
@@ -122,7 +126,7 @@ __device__ __forceinline__ void group_vertices(const int (&v)[NV], const int (&b
                                                const RSOC_GLOBAL uint8_t *const (&col8)[NV], const int (&cv)[NV],
                                                int look, int (&newc)[NV], bool (&act)[NV], uint32_t (&unc)[NV],
                                                const RSOC_GLOBAL uint32_t *const *col4 = nullptr,
-                                               int (*keep)[4] = nullptr) {
+                                               int (*keep)[4] = nullptr, bool big = false) {
     static_assert(G == 8 && S == 4, "rows of at most 32 entries over 8 lanes");
     constexpr int T = kRowSlots;
     int u[NV][T], pos[NV][T], off[NV];
@@ -171,13 +175,18 @@ __device__ __forceinline__ void group_vertices(const int (&v)[NV], const int (&b
                 const int dist = u[i][s] > v[i] ? u[i][s] - v[i] : v[i] - u[i][s];
                 take[s] = WIN_ONLY ? (win[s] || (u[i][s] != v[i] && dist < look)) : (u[i][s] != v[i]);
             }
-            // a nibble of 15 (colour 15 or more, or none yet) is settled from
-            // the byte shadow: otherwise every neighbour v loses to with a
-            // colour of 15 or more would look uncoloured and send v to U^0
+            // a nibble of 14 or 15 is settled from the byte shadow for every
+            // neighbour of a First-Fit over all of them, and in round 0
+            // (WIN_ONLY) for the neighbours v loses to: otherwise every such
+            // neighbour with a colour of 14 or more, or coloured but not yet
+            // published, would look uncoloured and send v to U^0.  Round 0
+            // reads the others only as far as the nibble tells (their colours
+            // are optional to it; after the hub-first pass a 14 is settled,
+            // for the hubs)
             bool exact[T];
 #pragma unroll
-            for (int s = 0; s < T; ++s) exact[s] = take[s];
-            gather_colours<NIB, T>(u[i], take, exact, col8[i], NIB ? col4[i] : nullptr, cu[i]);
+            for (int s = 0; s < T; ++s) exact[s] = WIN_ONLY ? win[s] : take[s];
+            gather_colours<NIB, T>(u[i], take, exact, col8[i], NIB ? col4[i] : nullptr, cu[i], big);
             uint32_t bits = 0;
 #pragma unroll
             for (int s = 0; s < T; ++s)
@@ -272,6 +281,31 @@ __device__ __forceinline__ void hub_gather(const int (&u)[U], const bool (&take)
     for (int s = 0; s < U; ++s) x[s] = (!exact[s] && y[s] == 255) ? (LOOSE ? -1 : col[u[s]]) : y[s];
 }
 
+// Round 0 after the hub-first pass (optimistic): entries with up[s] (the
+// neighbours v wins against, which round 0 reads only for the hubs' sake) are
+// read from the 4-bit shadow first: 15 (not coloured yet) reads as
+// uncoloured, 0..13 are the colour, and 14 (14 or more: every hub of such a
+// colour) is settled from the byte shadow and, where that saturates, from
+// col.  The other taken entries are read as hub_gather<LOOSE> reads them.
+template <bool LOOSE, int U>
+__device__ __forceinline__ void hub_gather_up(const int (&u)[U], const bool (&take)[U], const bool (&up)[U],
+                                              const RSOC_GLOBAL int32_t *col, const RSOC_GLOBAL uint8_t *col8,
+                                              const RSOC_GLOBAL uint32_t *col4, int (&x)[U]) {
+    int y[U];
+#pragma unroll
+    for (int s = 0; s < U; ++s)
+        y[s] = take[s] ? (up[s] ? (int)((colour_word(col4 + (u[s] >> 3)) >> ((u[s] & 7) << 2)) & 15u)
+                                : (int)col8[u[s]])
+                       : -1;
+#pragma unroll
+    for (int s = 0; s < U; ++s) {
+        if (up[s] && take[s]) y[s] = y[s] == 15 ? -1 : (y[s] == 14 ? (int)col8[u[s]] : y[s]);
+        else if (take[s] && y[s] == 255) y[s] = LOOSE ? -1 : 255;
+    }
+#pragma unroll
+    for (int s = 0; s < U; ++s) x[s] = (take[s] && y[s] == 255) ? col[u[s]] : y[s];
+}
+
 // Row entries each lane of a wavefront or workgroup holds per step: all the
 // loads of a step are in flight together, and so are its gathers.
 constexpr int kWaveSlots = 8;
@@ -287,7 +321,8 @@ constexpr int kBlockSlots = 8;
 template <int PHASE, int TIE, bool WIN_ONLY>
 __device__ __forceinline__ bool wave_vertex(int v, int b, int e, const RSOC_GLOBAL int32_t *ci,
                                             const RSOC_GLOBAL int32_t *col, const RSOC_GLOBAL uint8_t *col8,
-                                            uint32_t *bm, int look, int &newc, bool &unc_win, bool exact_up = false) {
+                                            uint32_t *bm, int look, int &newc, bool &unc_win, bool exact_up = false,
+                                            const RSOC_GLOBAL uint32_t *col4 = nullptr) {
     const int lane = lane_id();
     constexpr int U = kWaveSlots;
     constexpr bool kLoose = PHASE == kAssign && WIN_ONLY;
@@ -327,7 +362,8 @@ __device__ __forceinline__ bool wave_vertex(int v, int b, int e, const RSOC_GLOB
                 take[s] = WIN_ONLY ? (w[s] || (u[s] != v && dist < look)) : (u[s] != v);
                 ex[s] = exact_up && take[s] && !w[s];
             }
-            hub_gather<kLoose, U>(u, take, ex, col, col8, x);
+            if (exact_up) hub_gather_up<kLoose, U>(u, take, ex, col, col8, col4, x);
+            else hub_gather<kLoose, U>(u, take, col, col8, x);
             bool unc = false;
 #pragma unroll
             for (int s = 0; s < U; ++s) unc |= w[s] && x[s] < 0;
@@ -392,7 +428,8 @@ __device__ __forceinline__ bool wave_vertex(int v, int b, int e, const RSOC_GLOB
                 take[s] = (PHASE == kAssign && WIN_ONLY) ? (w[s] || (u[s] != v && dist < look)) : (u[s] != v);
                 ex[s] = PHASE == kAssign && exact_up && take[s] && !w[s];
             }
-            hub_gather<kLoose, U>(u, take, ex, col, col8, x);
+            if (PHASE == kAssign && exact_up) hub_gather_up<kLoose, U>(u, take, ex, col, col8, col4, x);
+            else hub_gather<kLoose, U>(u, take, col, col8, x);
 #pragma unroll
             for (int s = 0; s < U; ++s) {
                 if (PHASE == kAssign) unc |= w[s] && x[s] < 0;
@@ -427,7 +464,7 @@ template <int PHASE, int TIE, bool WIN_ONLY>
 __device__ __forceinline__ bool block_vertex(int v, int b, int e, const RSOC_GLOBAL int32_t *ci,
                                              const RSOC_GLOBAL int32_t *col, const RSOC_GLOBAL uint8_t *col8,
                                              uint32_t *bm, int *sh_min, int look, int &newc, bool &unc_win,
-                                             bool exact_up = false) {
+                                             bool exact_up = false, const RSOC_GLOBAL uint32_t *col4 = nullptr) {
     const int t = threadIdx.x;
     constexpr int U = kBlockSlots;
     constexpr bool kLoose = PHASE == kAssign && WIN_ONLY;
@@ -473,7 +510,8 @@ __device__ __forceinline__ bool block_vertex(int v, int b, int e, const RSOC_GLO
                 take[s] = (PHASE == kAssign && WIN_ONLY) ? (w[s] || (u[s] != v && dist < look)) : (u[s] != v);
                 ex[s] = PHASE == kAssign && exact_up && take[s] && !w[s];
             }
-            hub_gather<kLoose, U>(u, take, ex, col, col8, x);
+            if (PHASE == kAssign && exact_up) hub_gather_up<kLoose, U>(u, take, ex, col, col8, col4, x);
+            else hub_gather<kLoose, U>(u, take, col, col8, x);
 #pragma unroll
             for (int s = 0; s < U; ++s) {
                 if (PHASE == kAssign) unc |= w[s] && x[s] < 0;

@@ -34,7 +34,7 @@ SPACE = {
     "t_thread": [8, 16, 24, 32],
     "t_wave": [256, 1024, 2048, 8192],
     "grid_thread": [512, 1024, 2048, 4096],
-    "grid_wave": [128, 512, 1024],
+    "grid_wave": [512, 1024, 2048],
     "grid_list": [1024, 2048, 4096, 8192],
     "chunk": [1, 2, 4, 8],
     "lookahead": [-1, 1 << 18, 1 << 20, 1 << 22],
