@@ -355,6 +355,10 @@ def bench_single(args):
                      "traffic": traffic, "kernel_ms": kms, "alg_bytes_per_launch": kbytes,
                      "library_bytes_per_launch": kbytes_lib,
                      "frac_library_bytes": kbytes_lib / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS},
+        # the launch after round 0 (the masked first worklist round by default),
+        # with the library's count of the bytes it must move
+        "round1": {"kernel_ms": r1, "alg_bytes_per_launch": st["bytes_round1"],
+                   "traffic": load_traffic(args.workload, "round1_detect_recolour")},
     }
     if not args.no_extras:
         # colour classes of the colouring just made (its independent sets, one per
