@@ -17,7 +17,7 @@ enum PoolPhase : int { kSlotFree = 0, kSlotNew = 1, kSlotRunning = 2, kSlotDone 
 // round, whose entries carry what round 0 kept for them (see k_round's ROUND0)
 enum PoolTaskKind : int { kAssignSweep = 0, kRecolorSweep = 1, kRecolorList = 2, kRecolorMasked = 3 };
 constexpr int kPoolAuxCap = 256;     // round-0 queue length when entries carry their kept neighbours
-constexpr int kPoolMaskedBuf = 128;  // per-wavefront append buffer of the masked round
+constexpr int kPoolMaskedBuf = 512;  // per-wavefront append buffer of the masked round
 constexpr int kPoolTaskT = kStep;  // thread-bin items per task (one workgroup step)
 constexpr int kPoolTaskW = 32;   // wavefront-bin items per task
 constexpr int kPoolTaskB = 2;    // workgroup-bin items per task
@@ -331,7 +331,7 @@ __global__ __launch_bounds__(kBlock) void k_plist(PoolSlot *slots, int slot) {
 
 template <int TIE, int KIND>
 __device__ __forceinline__ void pool_thread_task(PoolSlot *sp, const PoolSlot &s, const PoolTask &tk, int *q, int *qn,
-                                                 int *qbase, int4 *qa) {
+                                                 int *qbase, int4 *qa, bool flush) {
     constexpr int PHASE = KIND == kAssignSweep ? kAssign : kRecolor;
     constexpr bool SWEEP = KIND != kRecolorList;
     constexpr bool kWinOnly = KIND == kAssignSweep;
@@ -409,7 +409,7 @@ __device__ __forceinline__ void pool_thread_task(PoolSlot *sp, const PoolSlot &s
                 queue_flush_n<int4>(cq, q, qn, qbase, &sp->cnt_out[kBinThread], out, kNib ? qa : nullptr, s.aux);
         }
     }
-    queue_flush<int4>(q, qn, qbase, &sp->cnt_out[kBinThread], out, kNib ? qa : nullptr, s.aux);
+    if (flush) queue_flush<int4>(q, qn, qbase, &sp->cnt_out[kBinThread], out, kNib ? qa : nullptr, s.aux);
 }
 
 // The first worklist round after round 0, thread-bin entries: one lane per
@@ -418,7 +418,7 @@ __device__ __forceinline__ void pool_thread_task(PoolSlot *sp, const PoolSlot &s
 // groups (wave_recolour_selected); appends gather in the wavefront's buffer.
 template <int TIE>
 __device__ __forceinline__ void pool_masked_task(PoolSlot *sp, const PoolSlot &s, const PoolTask &tk, int *ms,
-                                                 int *mb, int *mbn) {
+                                                 int *mb, int *mbn, bool flush) {
     typedef int v4i __attribute__((ext_vector_type(4)));
     const int32_t *in = s.parity ? s.wl[1] : s.wl[0];
     int32_t *out = s.parity ? s.wl[0] : s.wl[1];
@@ -430,8 +430,6 @@ __device__ __forceinline__ void pool_masked_task(PoolSlot *sp, const PoolSlot &s
     RSOC_GLOBAL uint8_t *wcol8 = grw(s.col8);
     const int wv = threadIdx.x / kWave;
     uint64_t degs = 0, apps = 0;
-    if (lane_id() == 0) *mbn = 0;
-    wave_lds_sync();
     for (int base = tk.begin + wv * kWave; base < tk.end; base += kWavesPerBlock * kWave) {
         const int idx = base + lane_id();
         int v = -1, cv = 255;
@@ -452,12 +450,12 @@ __device__ __forceinline__ void pool_masked_task(PoolSlot *sp, const PoolSlot &s
                                                          nullptr, s.look, degs, apps);
         if (*mbn >= kPoolMaskedBuf - kWave) wave_buf_flush(mb, mbn, &sp->cnt_out[kBinThread], out);
     }
-    wave_buf_flush(mb, mbn, &sp->cnt_out[kBinThread], out);
+    if (flush) wave_buf_flush(mb, mbn, &sp->cnt_out[kBinThread], out);
 }
 
 template <int TIE, int KIND>
 __device__ __forceinline__ void pool_wave_task(PoolSlot *sp, const PoolSlot &s, const PoolTask &tk, uint32_t *lds,
-                                               int *wbuf, int *wbn) {
+                                               int *wbuf, int *wbn, bool flush) {
     constexpr int PHASE = KIND == kAssignSweep ? kAssign : kRecolor;
     constexpr bool kWinOnly = KIND == kAssignSweep;
     const int wv = threadIdx.x / kWave;
@@ -465,8 +463,6 @@ __device__ __forceinline__ void pool_wave_task(PoolSlot *sp, const PoolSlot &s, 
     const bool opt = s.mode == kOptimistic;
     const int32_t *in = (KIND == kRecolorList) ? (s.parity ? s.wl[1] : s.wl[0]) + s.offW : s.hubW;
     int32_t *out = (s.parity ? s.wl[0] : s.wl[1]) + s.offW;
-    if (lane_id() == 0) *wbn = 0;
-    wave_lds_sync();
     const bool hubs = KIND == kAssignSweep && s.nH > 0;  // hub-first: hubs done, all neighbours read
     for (int i = tk.begin + wv; i < tk.end; i += kWavesPerBlock) {
         const int v = in[i];
@@ -483,7 +479,7 @@ __device__ __forceinline__ void pool_wave_task(PoolSlot *sp, const PoolSlot &s, 
         }
         wave_buf_push(KIND == kAssignSweep ? unc : act, v, wbuf, wbn, &sp->cnt_out[kBinWave], out);
     }
-    wave_buf_flush(wbuf, wbn, &sp->cnt_out[kBinWave], out);
+    if (flush) wave_buf_flush(wbuf, wbn, &sp->cnt_out[kBinWave], out);
 }
 
 template <int TIE, int KIND>
@@ -534,6 +530,7 @@ __global__ __launch_bounds__(kBlock) void k_pstep(PoolSlot *slots, const PoolTas
     __shared__ int mbuf[kWavesPerBlock][kMasked ? kPoolMaskedBuf : 1];
     const int bid = blockIdx.x;
     if (threadIdx.x == 0) qn = 0;
+    if (threadIdx.x < kWavesPerBlock) wbn[threadIdx.x] = 0;
     __syncthreads();
     // thread-bin workgroups come first in the grid, so they are dispatched
     // first: the order in which round 0 walks the ids must not wait behind
@@ -548,10 +545,16 @@ __global__ __launch_bounds__(kBlock) void k_pstep(PoolSlot *slots, const PoolTas
         const PoolTask tk = tasks[first + t];
         PoolSlot *sp = slots + tk.slot;
         const PoolSlot s = *sp;
-        if (kMasked) pool_masked_task<TIE>(sp, s, tk, mstage[wv], mbuf[wv], &wbn[wv]);
+        // what a task appends stays in the LDS buffers while the workgroup's
+        // next task belongs to the same slot (same lists, same counter): one
+        // global atomic per buffer-full, not per task -- with one or two
+        // large slots every flush hits the same counter, and 1024 workgroups'
+        // per-task atomics on it serialised the round
+        const bool flush = t + stride >= count || tasks[first + t + stride].slot != tk.slot;
+        if (kMasked) pool_masked_task<TIE>(sp, s, tk, mstage[wv], mbuf[wv], &wbn[wv], flush);
         else if (sec == 2) pool_block_task<TIE, KIND>(sp, s, tk, lds, &sh_min);
-        else if (sec == 1) pool_wave_task<TIE, KIND>(sp, s, tk, lds, wbuf[wv], &wbn[wv]);
-        else pool_thread_task<TIE, KIND>(sp, s, tk, q, &qn, &qbase, qa);
+        else if (sec == 1) pool_wave_task<TIE, KIND>(sp, s, tk, lds, wbuf[wv], &wbn[wv], flush);
+        else pool_thread_task<TIE, KIND>(sp, s, tk, q, &qn, &qbase, qa, flush);
     }
 }
 

@@ -143,7 +143,7 @@ class Server:
 
     def __init__(self, ctx: rsoc.Context, hbm_budget: int = 16 << 30, scratch_share: float = 0.35,
                  max_slots: int = 512, options=None, device: int = 0, admit_per_poll: int = 32,
-                 solo_when_idle: bool = True):
+                 solo_when_idle: bool = True, solo_backlog: int = 2):
         self.ctx = ctx
         self.dev = torch.device("cuda", device)
         self.scratch_cap = int(hbm_budget * scratch_share)
@@ -162,9 +162,11 @@ class Server:
         # launches), so a burst of arrivals is admitted a few dozen at a time
         # between pool steps, which keeps the device busy with rounds meanwhile
         self.admit_per_poll = admit_per_poll
-        # a request alone on an idle server goes straight to the single-graph
-        # entry point (_run_alone); solo counts those runs
+        # while the pool holds nothing and at most solo_backlog requests wait,
+        # the first goes straight to the single-graph entry point (_run_alone);
+        # solo counts those runs
         self.solo_when_idle = solo_when_idle
+        self.solo_backlog = solo_backlog
         self.solo = 0
         self.inflight = False  # a pool round launched and not yet waited for
 
@@ -207,13 +209,13 @@ class Server:
                 break
 
     def _run_alone(self):
-        """A request that finds the server otherwise idle (nothing running,
-        nothing else arrived) is coloured at once with the single-graph entry
-        point instead of through pool steps: the pool's per-round host
-        round trips only pay off when several graphs share them, and alone the
-        single-graph driver (captured rounds, one host check per few rounds)
-        has the lower latency.  Requests arriving meanwhile wait for it, as
-        they would behind one pool step."""
+        """The first waiting request, when the pool holds nothing and at most
+        solo_backlog requests wait, is coloured at once with the single-graph
+        entry point instead of through pool steps: the pool's per-round host
+        round trips only pay off when several graphs share them, and for one
+        or two graphs the single-graph driver (captured rounds, one host check
+        per few rounds) has the lower latency.  Requests arriving meanwhile
+        wait for it, as they would in the one-call-per-request form."""
         req, tens, ev, nbytes = self.staging.pop(0)
         rp, ci, col, tch = tens
         opts = req.options or self.options
@@ -232,7 +234,8 @@ class Server:
         self._retire_result(-1 - self.solo, req.k, req.stats)
 
     def _admit_copied(self):
-        if not self.live and len(self.staging) == 1 and not self.queue and self.solo_when_idle:
+        if (self.solo_when_idle and not self.live and self.staging
+                and len(self.staging) + len(self.queue) <= self.solo_backlog):
             ev = self.staging[0][2]
             if ev is None or ev.query():
                 self._run_alone()
