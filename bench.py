@@ -412,16 +412,27 @@ def bench_single(args):
                                  "ms_round0": sf["ms_round0"], "ms_round1": sf["ms_round1"]}
             if not colouring_valid(rp, ci, d_col.cpu().numpy()):
                 raise SystemExit("bench: invalid colouring produced (full sweep)")
-    if args.det_too and args.mode == "optimistic":
-        o2 = rsoc.make_options("deterministic", "lower", timing=0)
-        rsoc.rsoc_color_device(ctx, d_rp, d_ci, n, d_col, o2, stream=stream)
-        torch.cuda.synchronize()
-        td = time.perf_counter()
-        kd, sd = rsoc.rsoc_color_device(ctx, d_rp, d_ci, n, d_col, o2, stream=stream)
-        torch.cuda.synchronize()
-        td = time.perf_counter() - td
-        out["deterministic"] = {"GEps": E / td / 1e9, "colors": kd, "rounds": sd["rounds"],
-                                "conflicts": sd["conflicts"], "device_ms": sd["ms"]}
+    if (args.det_too or not args.no_extras) and args.mode == "optimistic":
+        # the paper's comparison (Section 4, Table 1): Algorithm 3 read
+        # round-synchronously (R) and its predecessor Algorithm 2 (C) on the
+        # same graph -- recolouring rounds ("iterations"), conflicts, colours
+        comp = {}
+        for name in ("deterministic", "two_phase"):
+            o2 = rsoc.make_options(name, "lower", timing=0)
+            rsoc.rsoc_color_device(ctx, d_rp, d_ci, n, d_col, o2, stream=stream)
+            torch.cuda.synchronize()
+            reps = 3
+            td = time.perf_counter()
+            for _ in range(reps):
+                kd, sd = rsoc.rsoc_color_device(ctx, d_rp, d_ci, n, d_col, o2, stream=stream)
+            torch.cuda.synchronize()
+            td = (time.perf_counter() - td) / reps
+            if not colouring_valid(rp, ci, d_col.cpu().numpy()):
+                raise SystemExit("bench: invalid colouring produced (%s)" % name)
+            comp[name] = {"GEps": E / td / 1e9, "ms": td * 1e3, "colors": kd, "rounds": sd["rounds"],
+                          "passes": sd["passes"], "conflicts": sd["conflicts"], "device_ms": sd["ms"]}
+        out["deterministic"] = comp["deterministic"]
+        out["two_phase"] = comp["two_phase"]
     if not args.no_cpu:
         cb, kseq = cpu_baseline(rp, ci, args.cpu_budget, args.workload, args.seed)
         out["cpu_baseline"] = cb
@@ -523,7 +534,8 @@ def bench_batched(args):
         t_ci = torch.from_numpy(tb["col_idx_cat"]).to(dev)
         t_col = torch.empty(int(tb["vtx_off"][-1]), dtype=torch.int32, device=dev)
         tt = time.perf_counter()
-        space = {k: tune.SPACE[k] for k in ("chunk", "grid_thread", "t_thread", "lookahead", "rounds_per_sync")}
+        space = {k: tune.SPACE[k] for k in ("chunk", "grid_thread", "t_thread", "lookahead", "rounds_per_sync",
+                                             "small_cutoff")}
         best, best_t, trials = tune.coordinate_descent(
             lambda o: tune._timer(lambda: rsoc.rsoc_color_batch(ctx, tb["vtx_off"], tb["nnz_off"], t_rp, t_ci, t_col,
                                                                 rsoc.make_options(args.mode, **o)), 3),

@@ -97,7 +97,16 @@ typedef struct {
     int32_t grid_thread; /* workgroups given to the thread bin per round launch (default 1024) */
     int32_t grid_wave;   /* workgroups given to the wavefront bin (default 2048) */
     int32_t rounds_per_sync; /* rounds enqueued (as one HIP graph) per host check of the worklist (default 4, even) */
-    int32_t reserved_a;      /* must be zero */
+    /* rsoc_color_batch: graphs of at most this many vertices (at most 2048;
+     * 0 = library default 2048, -1 = none) are coloured by one workgroup each,
+     * every round inside it with the workgroup barrier as the round barrier and
+     * the colours in LDS, beside the fused launches that take the larger graphs
+     * (optimistic and round-synchronous modes; two-phase graphs always take the
+     * fused launches).  Round-synchronous results are unchanged (the same
+     * schedule); optimistic graphs so coloured run Algorithm 3 as written:
+     * round 0 over all neighbours as they stand, round 1 over all of V.
+     * Ignored by the other entry points. */
+    int32_t small_cutoff;
     int32_t timing;      /* 1: record per-kernel HIP events (fills the ms_* fields of rsoc_stats) */
     /* Optimistic mode only.  0 (default): round 0 gives each vertex the smallest
      * colour absent among the neighbours it loses a tie to (the ones sequential
@@ -181,7 +190,7 @@ typedef struct {
     int32_t per_round_cap;   /* its length */
     int32_t worklist0;       /* |U^0|: vertices round 1 inspects */
     int32_t chunk;           /* run length used by the sweeps */
-    int32_t reserved[1];
+    int32_t small_graphs;    /* rsoc_color_batch: graphs coloured by one workgroup each (small_cutoff) */
     int32_t *per_round_U;    /* optional caller array of per_round_cap entries: per_round_U[i] = |U| of
                                 inspection pass i+1 (U^0, then the previous round's L), for the passes run */
 } rsoc_stats;

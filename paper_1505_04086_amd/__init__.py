@@ -62,7 +62,7 @@ class rsoc_options(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("tie", ctypes.c_int32), ("max_rounds", ctypes.c_int32),
                 ("validate", ctypes.c_int32), ("t_thread", ctypes.c_int32), ("t_wave", ctypes.c_int32),
                 ("grid_thread", ctypes.c_int32), ("grid_wave", ctypes.c_int32),
-                ("rounds_per_sync", ctypes.c_int32), ("reserved_a", ctypes.c_int32),
+                ("rounds_per_sync", ctypes.c_int32), ("small_cutoff", ctypes.c_int32),
                 ("timing", ctypes.c_int32), ("full_sweep", ctypes.c_int32), ("lookahead", ctypes.c_int32),
                 ("chunk", ctypes.c_int32), ("grid_list", ctypes.c_int32), ("tail", ctypes.c_int32),
                 ("distance", ctypes.c_int32), ("grid_bin", ctypes.c_int32), ("hub_first", ctypes.c_int32),
@@ -76,7 +76,7 @@ class rsoc_stats(ctypes.Structure):
                 ("ms_round1", ctypes.c_double), ("bytes_round0", ctypes.c_int64), ("bytes_round1", ctypes.c_int64),
                 ("max_degree", ctypes.c_int32), ("bin_counts", ctypes.c_int32 * 3),
                 ("per_round_L", ctypes.POINTER(ctypes.c_int32)), ("per_round_cap", ctypes.c_int32),
-                ("worklist0", ctypes.c_int32), ("chunk", ctypes.c_int32), ("reserved", ctypes.c_int32 * 1),
+                ("worklist0", ctypes.c_int32), ("chunk", ctypes.c_int32), ("small_graphs", ctypes.c_int32),
                 ("per_round_U", ctypes.POINTER(ctypes.c_int32))]
 
 
@@ -311,19 +311,23 @@ def rsoc_color_classes_noalloc(d_colors, n, K, d_class_ptr, d_class_vtx, stream=
 
 
 def rsoc_color_batch(ctx: Context, vtx_off, nnz_off, d_row_ptr_cat, d_col_idx_cat, d_colors_cat, options=None,
-                     stream=None):
+                     stream=None, per_round_cap=0):
     """Batched colouring.  vtx_off/nnz_off are host int64 arrays (G+1).
-    Returns (counts int32[G], max K, stats dict)."""
+    Returns (counts int32[G], max K, stats dict); with per_round_cap the stats
+    carry L_sizes, |L| per recolouring round summed over the graphs."""
     vo = np.ascontiguousarray(vtx_off, dtype=np.int64)
     no = np.ascontiguousarray(nnz_off, dtype=np.int64)
     G = len(vo) - 1
     counts = np.zeros(max(G, 1), dtype=np.int32)
     o = options if options is not None else make_options()
     st = rsoc_stats()
+    L = _per_round_arrays(st, per_round_cap)
     k = _chk(_lib.rsoc_color_batch(ctx.h, G, vo.ctypes.data, no.ctypes.data, _dev_ptr(d_row_ptr_cat),
                                    _dev_ptr(d_col_idx_cat), _dev_ptr(d_colors_cat), counts.ctypes.data,
                                    ctypes.byref(o), ctypes.byref(st), _stream_ptr(stream)), "rsoc_color_batch")
-    return counts[:G], k, stats_dict(st)
+    d = stats_dict(st, L)
+    d.pop("U_sizes", None)  # the batch reports |L| per round only
+    return counts[:G], k, d
 
 
 def rsoc_check_csr(row_ptr, col_idx, n=None, flags=RSOC_CHECK_CSR) -> int:

@@ -140,27 +140,54 @@ inline int32_t run_batch(rsoc_ctx *c, int32_t G, const int64_t *vtx_off, const i
             if (counts_out) counts_out[g] = 0;
         return 0;
     }
-    // sweep tasks: (graph, first vertex) chunks of kTaskLen vertices, in graph order
+    // graphs of at most small_cutoff vertices are coloured by one workgroup
+    // each (k_bsmall); the others by the fused launches
+    const bool small_ok = o.small_cutoff > 0 && o.mode != kTwoPhase;
+    auto is_small = [&](int g) {
+        const int64_t n = vtx_off[g + 1] - vtx_off[g];
+        return small_ok && n > 0 && n <= o.small_cutoff;
+    };
+    std::vector<int32_t> small;
+    // sweep tasks: (graph, first vertex) chunks of kTaskLen vertices, in graph
+    // order; the fused launches' graphs first, then the small graphs' (which
+    // only validation and the colour count walk)
     std::vector<int64_t> tasks;
     tasks.reserve((size_t)(nV / kTaskLen + G + 1));
-    for (int g = 0; g < G; ++g)
-        for (int64_t st0 = 0; st0 < vtx_off[g + 1] - vtx_off[g]; st0 += kTaskLen)
-            tasks.push_back(((int64_t)g << 32) | (uint32_t)st0);
+    int64_t nVL = 0;
+    for (int pass = 0; pass < 2; ++pass)
+        for (int g = 0; g < G; ++g) {
+            if (is_small(g) != (pass == 1)) continue;
+            if (pass == 1) small.push_back(g);
+            else nVL += vtx_off[g + 1] - vtx_off[g];
+            for (int64_t st0 = 0; st0 < vtx_off[g + 1] - vtx_off[g]; st0 += kTaskLen)
+                tasks.push_back(((int64_t)g << 32) | (uint32_t)st0);
+        }
     if (tasks.size() > (size_t)INT32_MAX) return RSOC_EINVAL;
-    const int ntasks = (int)tasks.size();
+    const int ntasks_all = (int)tasks.size();
+    int ntasks = 0;
+    for (int64_t x : tasks) ntasks += !is_small((int)(x >> 32));
+    const int nsmall = (int)small.size();
+    constexpr int kSmallStatInts = kSmallStatHist + kSmallMax + 2;
     RSOC_TRY(c->b_desc.reserve(sizeof(int64_t) * 2 * (size_t)(G + 1)));
-    RSOC_TRY(c->b_tasks.reserve(sizeof(int64_t) * (size_t)ntasks));
+    RSOC_TRY(c->b_tasks.reserve(sizeof(int64_t) * (size_t)std::max(ntasks_all, 1)));
     RSOC_TRY(c->b_col8.reserve((size_t)nV + 64));
     if (o.mode != kOptimistic) RSOC_TRY(c->b_pend.reserve(sizeof(int32_t) * (size_t)nV));
     RSOC_TRY(c->b_wl0.reserve(sizeof(int64_t) * (size_t)(nV + 1)));
     RSOC_TRY(c->b_wl1.reserve(sizeof(int64_t) * (size_t)(nV + 1)));
     RSOC_TRY(c->b_hub.reserve(sizeof(int64_t) * (size_t)(nV + 1)));
     RSOC_TRY(c->b_kmax.reserve(sizeof(int32_t) * (size_t)G));
+    RSOC_TRY(c->b_small.reserve(sizeof(int32_t) * (size_t)(kSmallStatInts + nsmall)));
+    int32_t *d_small_stat = c->b_small.as<int32_t>();
+    int32_t *d_small = d_small_stat + kSmallStatInts;
     int64_t *d_voff = c->b_desc.as<int64_t>();
     int64_t *d_noff = d_voff + (G + 1);
     RSOC_HIP(hipMemcpyAsync(d_voff, vtx_off, sizeof(int64_t) * (size_t)(G + 1), hipMemcpyHostToDevice, s));
     RSOC_HIP(hipMemcpyAsync(d_noff, nnz_off, sizeof(int64_t) * (size_t)(G + 1), hipMemcpyHostToDevice, s));
-    RSOC_HIP(hipMemcpyAsync(c->b_tasks.p, tasks.data(), sizeof(int64_t) * (size_t)ntasks, hipMemcpyHostToDevice, s));
+    RSOC_HIP(hipMemcpyAsync(c->b_tasks.p, tasks.data(), sizeof(int64_t) * (size_t)ntasks_all, hipMemcpyHostToDevice,
+                            s));
+    if (nsmall)
+        RSOC_HIP(hipMemcpyAsync(d_small, small.data(), sizeof(int32_t) * (size_t)nsmall, hipMemcpyHostToDevice, s));
+    RSOC_HIP(hipMemsetAsync(d_small_stat, 0, sizeof(int32_t) * kSmallStatInts, s));
     c->b_colp = col;
 
     BatchHost *h = c->host.as<BatchHost>();
@@ -182,6 +209,10 @@ inline int32_t run_batch(rsoc_ctx *c, int32_t G, const int64_t *vtx_off, const i
     a.offW = a.offB = 0;
     a.G = G;
     a.ntasks = ntasks;
+    a.ntasks_all = ntasks_all;
+    a.small = d_small;
+    a.small_stat = d_small_stat;
+    a.nsmall = nsmall;
     a.t_thread = o.t_thread;
     a.t_wave = o.t_wave;
     a.max_rounds = o.max_rounds;
@@ -192,12 +223,13 @@ inline int32_t run_batch(rsoc_ctx *c, int32_t G, const int64_t *vtx_off, const i
     RSOC_HIP(hipMemsetAsync(S, 0, kStateHeader, s));
     RSOC_HIP(hipMemsetAsync(c->b_kmax.p, 0, sizeof(int32_t) * (size_t)G, s));
     const int tgrid = std::min(ntasks, o.grid_bin ? o.grid_bin : 8192);
+    const int tgrid_all = std::max(1, std::min(ntasks_all, o.grid_bin ? o.grid_bin : 8192));
     if (o.validate & RSOC_CHECK_CSR) {
-        k_bvalidate<<<tgrid, kBlock, 0, s>>>(c->b_args.as<BatchArgs>(), &S->err);
+        k_bvalidate<<<tgrid_all, kBlock, 0, s>>>(c->b_args.as<BatchArgs>(), &S->err);
         RSOC_LAUNCH_CHECK();
     }
-    k_bbin<<<tgrid, kBlock, 0, s>>>(c->b_args.as<BatchArgs>(), S);
-    if (o.chunk == 0) {
+    if (ntasks > 0) k_bbin<<<tgrid, kBlock, 0, s>>>(c->b_args.as<BatchArgs>(), S);
+    if (o.chunk == 0 && ntasks > 0) {
         const int ns = std::min(ntasks, 16384);
         k_blocality<<<div_up(ns, kBlock), kBlock, 0, s>>>(c->b_args.as<BatchArgs>(), ns, S);
     }
@@ -206,48 +238,75 @@ inline int32_t run_batch(rsoc_ctx *c, int32_t G, const int64_t *vtx_off, const i
     RSOC_HIP(hipStreamSynchronize(s));
     RSOC_TRY(status_from_err(h->head.err));
     const int nW = h->head.nW, nB = h->head.nB;
-    const int64_t nT = nV - nW - nB;
-    a.offW = nT;
-    a.offB = nT + nW;
-    const int gB = std::min(nB, 1024);
-    const int gW = std::min(div_up(nW, kWavesPerBlock), o.grid_wave);
-    const int gTs = std::max(1, std::min(ntasks, o.grid_thread));
-    const int64_t look = o.lookahead == -1 ? 0 : (o.lookahead > 0 ? o.lookahead : 2ll * gTs * kStep);
-    a.look = (int)std::min<int64_t>(look, INT32_MAX);
-    a.chunk = pick_chunk(o.chunk, h->head.near, h->head.sampled);
-    RSOC_HIP(hipMemcpyAsync(c->b_args.p, &a, sizeof(a), hipMemcpyHostToDevice, s));
-    const int gBl = std::min(nB, 256);
-    const int gWl = std::min(div_up(nW, kWavesPerBlock), o.grid_wave);
-    const int gTl = (int)std::max<int64_t>(1, std::min<int64_t>(div_up(nT, kStep), o.grid_list));
-    hipGraphExec_t gexec = nullptr;
-    RSOC_TRY(get_batch_graph(c, o.mode, o.tie, o.rounds_per_sync, gBl, gWl, gTl, &gexec));
-
-    RSOC_HIP(hipEventRecord(c->ev[0], s));
+    const int64_t nT = nVL - nW - nB;
     const bool timing = o.timing && o.mode == kOptimistic;
-    launch_bsweep_dyn(c, s, o.mode, o.tie, nV, gB, gW, gTs, o.full_sweep != 0, timing);
-    RSOC_LAUNCH_CHECK();
     int32_t status = RSOC_OK;
-    for (;;) {
-        RSOC_HIP(hipGraphLaunch(gexec, s));
-        RSOC_HIP(hipEventRecord(c->ev[1], s));
-        RSOC_HIP(hipMemcpyAsync(&h->head, S, kStateHeader, hipMemcpyDeviceToHost, s));
-        RSOC_HIP(hipStreamSynchronize(s));
-        const int left = h->head.cnt_in[0] + h->head.cnt_in[1] + h->head.cnt_in[2];
-        if (left == 0) break;
-        if (h->head.passes >= o.max_rounds) { status = RSOC_ENOCONV; break; }
+    RSOC_HIP(hipEventRecord(c->ev[0], s));
+    if (ntasks > 0) {
+        a.offW = nT;
+        a.offB = nT + nW;
+        const int gB = std::min(nB, 1024);
+        const int gW = std::min(div_up(nW, kWavesPerBlock), o.grid_wave);
+        const int gTs = std::max(1, std::min(ntasks, o.grid_thread));
+        const int64_t look = o.lookahead == -1 ? 0 : (o.lookahead > 0 ? o.lookahead : 2ll * gTs * kStep);
+        a.look = (int)std::min<int64_t>(look, INT32_MAX);
+        a.chunk = pick_chunk(o.chunk, h->head.near, h->head.sampled);
+        RSOC_HIP(hipMemcpyAsync(c->b_args.p, &a, sizeof(a), hipMemcpyHostToDevice, s));
+        const int gBl = std::min(nB, 256);
+        const int gWl = std::min(div_up(nW, kWavesPerBlock), o.grid_wave);
+        const int gTl = (int)std::max<int64_t>(1, std::min<int64_t>(div_up(nT, kStep), o.grid_list));
+        hipGraphExec_t gexec = nullptr;
+        RSOC_TRY(get_batch_graph(c, o.mode, o.tie, o.rounds_per_sync, gBl, gWl, gTl, &gexec));
+        launch_bsweep_dyn(c, s, o.mode, o.tie, nV, gB, gW, gTs, o.full_sweep != 0, timing);
+        RSOC_LAUNCH_CHECK();
+        for (;;) {
+            RSOC_HIP(hipGraphLaunch(gexec, s));
+            RSOC_HIP(hipMemcpyAsync(&h->head, S, kStateHeader, hipMemcpyDeviceToHost, s));
+            RSOC_HIP(hipStreamSynchronize(s));
+            const int left = h->head.cnt_in[0] + h->head.cnt_in[1] + h->head.cnt_in[2];
+            if (left == 0) break;
+            if (h->head.passes >= o.max_rounds) { status = RSOC_ENOCONV; break; }
+        }
     }
-    k_bcount<<<tgrid, kBlock, 0, s>>>(c->b_args.as<BatchArgs>(), &S->err);
+    // the small graphs, one workgroup each, after the fused launches (whose
+    // colour fill covers the whole batch)
+    if (nsmall > 0) {
+        const int sgrid = std::min(nsmall, 8192);
+        const BatchArgs *A = c->b_args.as<BatchArgs>();
+        if (o.mode == kOptimistic)
+            o.tie ? k_bsmall<kOptimistic, kHigherKeeps><<<sgrid, kBlock, 0, s>>>(A)
+                  : k_bsmall<kOptimistic, kLowerKeeps><<<sgrid, kBlock, 0, s>>>(A);
+        else
+            o.tie ? k_bsmall<kDeterministic, kHigherKeeps><<<sgrid, kBlock, 0, s>>>(A)
+                  : k_bsmall<kDeterministic, kLowerKeeps><<<sgrid, kBlock, 0, s>>>(A);
+        RSOC_LAUNCH_CHECK();
+    }
+    RSOC_HIP(hipEventRecord(c->ev[1], s));
+    k_bcount<<<tgrid_all, kBlock, 0, s>>>(c->b_args.as<BatchArgs>(), &S->err);
     RSOC_LAUNCH_CHECK();
     RSOC_HIP(hipMemcpyAsync(&h->head, S, kStateHeader, hipMemcpyDeviceToHost, s));
     std::vector<int32_t> kg((size_t)G);
     RSOC_HIP(hipMemcpyAsync(kg.data(), c->b_kmax.p, sizeof(int32_t) * (size_t)G, hipMemcpyDeviceToHost, s));
-    if (st && st->per_round_L && st->per_round_cap > 0) {
-        RSOC_HIP(hipStreamSynchronize(s));
-        const int cnt = std::min(std::min(h->head.rounds, st->per_round_cap), kHistCap);
-        if (cnt > 0)
-            RSOC_HIP(hipMemcpyAsync(st->per_round_L, S->hist, sizeof(int32_t) * cnt, hipMemcpyDeviceToHost, s));
-    }
+    const bool want_hist = st && st->per_round_L && st->per_round_cap > 0;
+    std::vector<int32_t> sstat((size_t)kSmallStatInts, 0);
+    if (nsmall > 0)
+        RSOC_HIP(hipMemcpyAsync(sstat.data(), d_small_stat,
+                                sizeof(int32_t) * (size_t)(want_hist ? kSmallStatInts : kSmallStatHist),
+                                hipMemcpyDeviceToHost, s));
     RSOC_HIP(hipStreamSynchronize(s));
+    if (sstat[2]) status = RSOC_ENOCONV;
+    int64_t small_conf = 0;
+    memcpy(&small_conf, &sstat[4], sizeof(small_conf));
+    const int rounds_all = std::max(ntasks > 0 ? h->head.rounds : 0, sstat[1]);
+    if (want_hist) {
+        const int cnt = std::min(std::min(rounds_all, st->per_round_cap), kHistCap);
+        const int cf = std::min(ntasks > 0 ? h->head.rounds : 0, cnt);
+        if (cf > 0)
+            RSOC_HIP(hipMemcpyAsync(st->per_round_L, S->hist, sizeof(int32_t) * cf, hipMemcpyDeviceToHost, s));
+        RSOC_HIP(hipStreamSynchronize(s));
+        for (int r = cf; r < cnt; ++r) st->per_round_L[r] = 0;
+        for (int r = 0; r < cnt && r < kSmallMax + 2; ++r) st->per_round_L[r] += sstat[kSmallStatHist + r];
+    }
     if (h->head.err & (4 | kErrListCount)) return RSOC_EINTERNAL;  // never expected
     int32_t kmax = 0;
     for (int g = 0; g < G; ++g) {
@@ -255,11 +314,11 @@ inline int32_t run_batch(rsoc_ctx *c, int32_t G, const int64_t *vtx_off, const i
         kmax = std::max(kmax, kg[g]);
     }
     if (st) {
-        st->rounds = h->head.rounds;
-        st->passes = h->head.passes;
+        st->rounds = rounds_all;
+        st->passes = std::max(ntasks > 0 ? h->head.passes : 0, sstat[0]);
         st->colors = kmax;
         st->colors_distinct = -1;
-        st->conflicts = h->head.conflicts;
+        st->conflicts = (ntasks > 0 ? h->head.conflicts : 0) + small_conf;
         st->inspected = (int64_t)h->head.inspected;
         st->max_degree = h->head.maxdeg;
         st->bin_counts[0] = (int32_t)nT;
@@ -267,22 +326,30 @@ inline int32_t run_batch(rsoc_ctx *c, int32_t G, const int64_t *vtx_off, const i
         st->bin_counts[2] = nB;
         st->worklist0 = h->head.u0;
         st->chunk = a.chunk;
+        st->small_graphs = nsmall;
         float ms = 0;
         RSOC_HIP(hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
         st->ms = ms;
         const int64_t nnzT = nnz_off[G];
-        if (timing) {
+        if (timing && ntasks > 0) {
             float m0 = 0;
             RSOC_HIP(hipEventElapsedTime(&m0, c->ev[2], c->ev[3]));
             st->ms_round0 = m0;
         }
         // round 0 (optimistic): task table 8/task, row_ptr 4(n+G), col_idx 4 nnz,
         // colours of the neighbours a vertex loses to (4 nnz/2), colour
-        // writes 4n, hub lists 8(nW+nB), U^0 appends 8|U^0|
-        if (o.mode == kOptimistic)
-            st->bytes_round0 = 8 * (int64_t)ntasks + 4 * (nV + G) + 4 * nnzT +
-                               (o.full_sweep ? 4 * nnzT : 4 * (nnzT / 2)) + 4 * nV + 8 * (int64_t)(nW + nB) +
+        // writes 4n, hub lists 8(nW+nB), U^0 appends 8|U^0| (the fused
+        // launches' graphs)
+        if (o.mode == kOptimistic && ntasks > 0) {
+            int64_t nnzL = 0;
+            int GL = 0;
+            for (int g = 0; g < G; ++g)
+                if (!is_small(g)) nnzL += nnz_off[g + 1] - nnz_off[g], ++GL;
+            st->bytes_round0 = 8 * (int64_t)ntasks + 4 * (nVL + GL) + 4 * nnzL +
+                               (o.full_sweep ? 4 * nnzL : 4 * (nnzL / 2)) + 4 * nVL + 8 * (int64_t)(nW + nB) +
                                (o.full_sweep ? 0 : 8 * (int64_t)h->head.u0);
+        }
+        (void)nnzT;
     }
     if (status < 0) return status;
     return kmax;

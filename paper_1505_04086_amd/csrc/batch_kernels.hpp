@@ -34,7 +34,10 @@ struct BatchArgs {
     int32_t G, ntasks;
     int32_t t_thread, t_wave, max_rounds, look;
     int32_t chunk;        // run of consecutive ids one lane group walks
-    int32_t pad;
+    int32_t ntasks_all;   // tasks of every graph (the first ntasks are the fused launches' graphs)
+    const int32_t *small; // graphs coloured by one workgroup each (k_bsmall)
+    int32_t *small_stat;  // their statistics: see k_bsmall
+    int32_t nsmall, pad;
 };
 
 __device__ __forceinline__ int64_t pack_item(int g, int v) { return ((int64_t)g << 32) | (uint32_t)v; }
@@ -158,7 +161,7 @@ __global__ __launch_bounds__(kBlock) void k_blocality(const BatchArgs *__restric
 __global__ __launch_bounds__(kBlock) void k_bvalidate(const BatchArgs *__restrict__ A, int32_t *err) {
     const BatchArgs a = *A;
     int flags = 0;
-    for (int t = blockIdx.x; t < a.ntasks; t += gridDim.x) {
+    for (int t = blockIdx.x; t < a.ntasks_all; t += gridDim.x) {
         const int64_t task = a.tasks[t];
         const int g = item_graph(task), start = item_vertex(task);
         const GraphView w = graph_view(a, g);
@@ -464,7 +467,7 @@ __global__ void k_bround_end(const BatchArgs *__restrict__ A, SingleState *S) {
 __global__ __launch_bounds__(kBlock) void k_bcount(const BatchArgs *__restrict__ A, int32_t *err) {
     __shared__ int sh[kWavesPerBlock];
     const BatchArgs a = *A;
-    for (int t = blockIdx.x; t < a.ntasks; t += gridDim.x) {
+    for (int t = blockIdx.x; t < a.ntasks_all; t += gridDim.x) {
         const int64_t task = a.tasks[t];
         const int g = item_graph(task), start = item_vertex(task);
         const GraphView w = graph_view(a, g);
@@ -481,6 +484,135 @@ __global__ __launch_bounds__(kBlock) void k_bcount(const BatchArgs *__restrict__
         if (threadIdx.x == 0 && m + 1 > __hip_atomic_load(&a.kg[g], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
             atomicMax(&a.kg[g], m + 1);
         __syncthreads();
+    }
+}
+
+// ------------------------------------------------------ small graphs --
+// Graphs of at most kSmallMaxVertices vertices, one workgroup each: all of
+// Algorithm 3 (Section 3) inside the workgroup, with __syncthreads() as the
+// round barrier and the colours, staged colours and worklists in LDS; one
+// thread per vertex (v = t, t + 256, ...).  MODE kDeterministic is the
+// round-synchronous reading (round 0 colours every vertex 0, U^0 = V; a round
+// tests and recolours from the colours of the previous barrier and publishes
+// the staged colours after it), so each graph comes out as the oracle's
+// schedule colours it.  MODE kOptimistic reads the colours as they stand:
+// round 0 gives every vertex the smallest colour absent among its neighbours
+// coloured at that moment, then rounds over U^0 = V detect (a neighbour the
+// vertex loses to holds its colour) and recolour in place.  Row bounds are
+// clamped into the graph's own adjacency and neighbour ids outside [0, n)
+// are skipped, so unchecked input cannot reach outside it.
+// small_stat: [0] most passes, [1] most recolouring rounds, [2] 1 if a graph
+// hit max_rounds, [4..5] conflicts (64-bit), from [8] |L| per round summed
+// over the graphs.
+constexpr int kSmallMax = kSmallMaxVertices;
+constexpr int kSmallStatHist = 8;
+
+// smallest colour absent among v's neighbours whose colours are >= 0 (colours
+// below 64 at a time: a colour is at most the degree, so the windows end)
+__device__ __forceinline__ int small_first_fit(int v, int b, int e, const RSOC_GLOBAL int32_t *ci, int n,
+                                               const volatile int *c) {
+    for (int base = 0;; base += 64) {
+        uint64_t used = 0;
+        for (int j = b; j < e; ++j) {
+            const int u = ci[j];
+            if ((unsigned)u >= (unsigned)n || u == v) continue;
+            const int x = c[u] - base;
+            if (x >= 0 && x < 64) used |= 1ull << x;
+        }
+        if (~used) return base + __builtin_ctzll(~used);
+    }
+}
+
+template <int MODE, int TIE>
+__global__ __launch_bounds__(kBlock) void k_bsmall(const BatchArgs *__restrict__ A) {
+    __shared__ int c[kSmallMax];
+    __shared__ int p[MODE == kDeterministic ? kSmallMax : 1];
+    __shared__ int lst[2][kSmallMax];
+    __shared__ int nU, nL;
+    const BatchArgs a = *A;
+    const int t = threadIdx.x;
+    int32_t *stat = a.small_stat;
+    volatile int *cv = c;
+    for (int k = blockIdx.x; k < a.nsmall; k += gridDim.x) {
+        const int g = a.small[k];
+        const GraphView w = graph_view(a, g);
+        const int n = min(w.n, kSmallMax);
+        const int nnz = (int)(a.noff[g + 1] - a.noff[g]);
+        auto row = [&](int v, int &b, int &e) {
+            b = min(max(w.rp[v], 0), nnz);
+            e = min(max(w.rp[v + 1], b), nnz);
+        };
+        for (int v = t; v < n; v += kBlock) {
+            c[v] = MODE == kDeterministic ? 0 : -1;
+            lst[0][v] = v;
+        }
+        if (t == 0) {
+            nU = n;
+            nL = 0;
+        }
+        __syncthreads();
+        if (MODE == kOptimistic) {
+            for (int v = t; v < n; v += kBlock) {
+                int b, e;
+                row(v, b, e);
+                cv[v] = small_first_fit(v, b, e, w.ci, n, cv);
+            }
+            __syncthreads();
+        }
+        int passes = 0, rounds = 0, par = 0;
+        int64_t conf = 0;
+        for (;;) {
+            const int m = nU;
+            if (m == 0) break;
+            if (passes >= a.max_rounds) {
+                if (t == 0) atomicOr(stat + 2, 1);
+                break;
+            }
+            const int *U = lst[par];
+            int *L = lst[par ^ 1];
+            for (int i = t; i < m; i += kBlock) {
+                const int v = U[i];
+                int b, e;
+                row(v, b, e);
+                const int mine = cv[v];
+                bool def = false;
+                for (int j = b; j < e && !def; ++j) {
+                    const int u = w.ci[j];
+                    if ((unsigned)u >= (unsigned)n || u == v) continue;
+                    def = loses<TIE>(v, u) && cv[u] == mine;
+                }
+                if (!def) continue;
+                const int nc = small_first_fit(v, b, e, w.ci, n, cv);
+                if (MODE == kDeterministic) p[v] = nc;
+                else cv[v] = nc;
+                L[atomicAdd(&nL, 1)] = v;
+            }
+            __syncthreads();
+            const int l = nL;
+            if (MODE == kDeterministic)
+                for (int i = t; i < l; i += kBlock) c[L[i]] = p[L[i]];
+            __syncthreads();
+            ++passes;
+            if (l) {
+                ++rounds;
+                conf += l;
+                if (t == 0 && rounds <= kSmallMax + 1) atomicAdd(stat + kSmallStatHist + rounds - 1, l);
+            }
+            if (t == 0) {
+                nU = l;
+                nL = 0;
+            }
+            par ^= 1;
+            __syncthreads();
+        }
+        int32_t *out = a.col + w.voff;
+        for (int v = t; v < n; v += kBlock) out[v] = c[v];
+        if (t == 0) {
+            atomicMax(stat + 0, passes);
+            atomicMax(stat + 1, rounds);
+            atomicAdd(reinterpret_cast<unsigned long long *>(stat + 4), (unsigned long long)conf);
+        }
+        __syncthreads();  // the LDS arrays are the next graph's
     }
 }
 

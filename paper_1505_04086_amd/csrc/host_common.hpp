@@ -92,9 +92,13 @@ struct HostPinned {
     T *as() const { return static_cast<T *>(p); }
 };
 
+// Largest graph of a batch coloured by one workgroup (colours and worklists in
+// LDS; the option small_cutoff).
+constexpr int kSmallMaxVertices = 2048;
+
 struct Options {
     int mode, tie, max_rounds, validate, t_thread, t_wave, grid_thread, grid_wave, rounds_per_sync,
-        timing, full_sweep, lookahead, chunk, grid_list, tail, distance, grid_bin, hub_first;
+        timing, full_sweep, lookahead, chunk, grid_list, tail, distance, grid_bin, hub_first, small_cutoff;
 };
 
 inline int32_t resolve_options(const rsoc_options *o, int64_t n, Options &r) {
@@ -108,7 +112,8 @@ inline int32_t resolve_options(const rsoc_options *o, int64_t n, Options &r) {
     if (d.max_rounds < 0 || d.t_thread < 0 || d.t_thread > 32 || d.t_wave < 0 || d.grid_thread < 0 ||
         d.grid_wave < 0 || d.rounds_per_sync < 0 || d.validate < 0 || d.validate > 3 || d.grid_list < 0)
         return RSOC_EINVAL;
-    if (d.reserved_a || d.reserved[0] || d.reserved[1] || d.grid_bin < 0) return RSOC_EINVAL;
+    if (d.reserved[0] || d.reserved[1] || d.grid_bin < 0) return RSOC_EINVAL;
+    if (d.small_cutoff < -1 || d.small_cutoff > kSmallMaxVertices) return RSOC_EINVAL;
     if (d.hub_first < -1) return RSOC_EINVAL;
     r.grid_bin = d.grid_bin;  // 0: each launch site's own default
     if (d.distance < 0 || d.distance > 2) return RSOC_EINVAL;
@@ -136,6 +141,7 @@ inline int32_t resolve_options(const rsoc_options *o, int64_t n, Options &r) {
     // device), else the degree given, never below the lane-group bin's limit,
     // so that hubs are wavefront- or workgroup-bin vertices
     r.hub_first = d.hub_first == -1 ? 0 : (d.hub_first == 0 ? -1 : std::max(d.hub_first, r.t_thread));
+    r.small_cutoff = d.small_cutoff == -1 ? 0 : (d.small_cutoff == 0 ? kSmallMaxVertices : d.small_cutoff);
     return RSOC_OK;
 }
 

@@ -39,6 +39,7 @@ SPACE = {
     "chunk": [1, 2, 4, 8],
     "lookahead": [-1, 1 << 18, 1 << 20, 1 << 22],
     "rounds_per_sync": [4, 8, 16],
+    "small_cutoff": [-1, 256, 1024, 2048],
 }
 
 

@@ -29,8 +29,17 @@ def _mixed_batch():
 
 GRAPHS = _mixed_batch()
 BATCH = gg.concat(GRAPHS)
-SPLITS = {"default": {}, "allbins": {"t_thread": 3, "t_wave": 8}, "runs1": {"chunk": 1, "grid_thread": 7, "grid_list": 2},
-          "runs8": {"chunk": 8, "grid_thread": 3}}
+# "default" sends the graphs of at most 2048 vertices to the workgroup-resident
+# path (one workgroup per graph, every round inside it); the launch splits of
+# the fused launches run with that path off, and "small64" divides the batch
+SPLITS = {"default": {}, "allbins": {"t_thread": 3, "t_wave": 8, "small_cutoff": -1},
+          "runs1": {"chunk": 1, "grid_thread": 7, "grid_list": 2, "small_cutoff": -1},
+          "runs8": {"chunk": 8, "grid_thread": 3, "small_cutoff": -1}, "small64": {"small_cutoff": 64}}
+
+
+def _n_small(opts):
+    cut = {-1: 0, 0: 2048}.get(opts.get("small_cutoff", 0), opts.get("small_cutoff", 0))
+    return sum(1 for rp, _ in GRAPHS if 0 < len(rp) - 1 <= cut)
 
 
 def _upload(lib, b):
@@ -52,14 +61,25 @@ def _member_colours(col, b, g):
 def test_batch_round_synchronous_matches_oracle(lib, ctx, mode, tie, split):
     rp, ci, col = _upload(lib, BATCH)
     counts, kmax, st = lib.rsoc_color_batch(ctx, BATCH["vtx_off"], BATCH["nnz_off"], rp, ci, col,
-                                            lib.make_options(mode, tie, **SPLITS[split]))
+                                            lib.make_options(mode, tie, **SPLITS[split]), per_round_cap=4096)
     got = col.cpu().numpy()
     fn = oracle.rsync if mode == "deterministic" else oracle.cat
+    L_total = np.zeros(4096, np.int64)
+    conflicts = rounds = 0
     for g, (grp, gci) in enumerate(GRAPHS):
         want = fn(grp, gci, tie=tie)
         assert np.array_equal(_member_colours(got, BATCH, g), want["colors"]), (mode, tie, g)
         assert counts[g] == want["K"], g
+        L_total[:len(want["L_sizes"])] += want["L_sizes"]
+        conflicts += want["conflicts"]
+        rounds = max(rounds, want["rounds"])
     assert kmax == max(counts)
+    assert st["small_graphs"] == (_n_small(SPLITS[split]) if mode == "deterministic" else 0)
+    # the per-round |L| of the batch is the graphs' summed round by round,
+    # whichever path coloured them
+    if mode == "deterministic":
+        assert st["rounds"] == rounds and st["conflicts"] == conflicts
+        assert np.array_equal(st["L_sizes"], L_total[:rounds])
 
 
 @pytest.mark.parametrize("split", sorted(SPLITS))
@@ -75,6 +95,7 @@ def test_batch_optimistic_valid(lib, ctx, tie, full_sweep, split):
         c = _member_colours(got, BATCH, g)
         assert oracle.check(grp, gci, c) == 0, g
         assert counts[g] == oracle.colour_count(c)
+    assert st["small_graphs"] == _n_small(SPLITS[split])
 
 
 def test_batch_equals_single_calls(lib, ctx):
@@ -110,3 +131,36 @@ def test_batch_validation_and_empty(lib, ctx):
     with pytest.raises(lib.RsocError) as e:
         lib.rsoc_color_batch(ctx, b["vtx_off"], b["nnz_off"], rp, ci, col, lib.make_options(validate=1))
     assert e.value.code == lib.RSOC_ECSR
+
+
+@pytest.mark.parametrize("cutoff", [0, 64, -1])
+def test_batch_pass_bound(lib, ctx, cutoff):
+    """A pass bound below what a path needs (n - 1 rounds, round-synchronous)
+    ends the batch with RSOC_ENOCONV on either path."""
+    b = gg.concat([gg.path(300), gg.cycle(6)])
+    rp, ci, col = _upload(lib, b)
+    with pytest.raises(lib.RsocError) as e:
+        lib.rsoc_color_batch(ctx, b["vtx_off"], b["nnz_off"], rp, ci, col,
+                             lib.make_options("deterministic", max_rounds=5, small_cutoff=cutoff))
+    assert e.value.code == lib.RSOC_ENOCONV
+
+
+def test_batch_small_graphs_only_and_option_checked(lib, ctx):
+    """A batch of small graphs only (no fused launch at all), optimistic and
+    round-synchronous; cutoffs beyond 2048 are refused."""
+    graphs = [gg.complete(12), gg.star(50), gg.tri_grid(20, 9, permute_seed=2), gg.rmat(8, 8, seed=3, shuffle_seed=4)]
+    b = gg.concat(graphs)
+    rp, ci, col = _upload(lib, b)
+    for mode in ("optimistic", "deterministic"):
+        counts, kmax, st = lib.rsoc_color_batch(ctx, b["vtx_off"], b["nnz_off"], rp, ci, col, lib.make_options(mode))
+        assert st["small_graphs"] == len(graphs)
+        got = col.cpu().numpy()
+        for g, (grp, gci) in enumerate(graphs):
+            c = _member_colours(got, b, g)
+            if mode == "deterministic":
+                assert np.array_equal(c, oracle.rsync(grp, gci)["colors"]), g
+            else:
+                assert oracle.check(grp, gci, c) == 0 and counts[g] == oracle.colour_count(c), g
+    with pytest.raises(lib.RsocError) as e:
+        lib.rsoc_color_batch(ctx, b["vtx_off"], b["nnz_off"], rp, ci, col, lib.make_options(small_cutoff=2049))
+    assert e.value.code == lib.RSOC_EINVAL
