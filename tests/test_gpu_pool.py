@@ -288,3 +288,36 @@ def test_pool_many_slots_one_step(lib, ctx):
         assert steps < 5000
     assert done == 260 and pool.live() == 0
     pool.close()
+
+
+@pytest.mark.parametrize("mode", ["deterministic", "optimistic"])
+def test_pool_one_large_slot(lib, ctx, mode):
+    """One large graph alone in the pool: every workgroup takes many tasks of
+    the same slot, so its append buffers carry over from task to task and fill
+    up several times (flushed when full, when the slot changes and at the end
+    of the launch).  Deterministic: equal to the oracle; optimistic: valid."""
+    import torch
+    rp, ci = gg.lattice26(128, permute_seed=17)  # 2.1 M vertices: about four tasks per workgroup
+    n = len(rp) - 1
+    d = torch.device("cuda:0")
+    d_rp, d_ci = torch.from_numpy(rp).to(d), torch.from_numpy(ci).to(d)
+    d_col = torch.full((n,), -5, dtype=torch.int32, device=d)
+    pool = lib.Pool(ctx, 0, 8)
+    slot = pool.admit(d_rp, d_ci, n, d_col, lib.make_options(mode))
+    steps = 0
+    while True:
+        fin = pool.step()
+        steps += 1
+        assert steps < 1000
+        if slot in fin:
+            break
+    k, st = pool.result(slot)
+    got = d_col.cpu().numpy()
+    if mode == "deterministic":
+        want = oracle.rsync(rp, ci)
+        assert np.array_equal(got, want["colors"]) and k == want["K"]
+        assert st["rounds"] == want["rounds"] and st["conflicts"] == want["conflicts"]
+    else:
+        assert oracle.check(rp, ci, got) == 0 and k == oracle.colour_count(got)
+    assert st["colors_distinct"] == len(np.unique(got))
+    pool.close()
