@@ -785,6 +785,9 @@ def main():
     ap.add_argument("--cpu-omp-leg", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates rocprofv3 FETCH_SIZE/WRITE_SIZE)")
+    ap.add_argument("--gather-probe", action="store_true",
+                    help="only time random 4-byte gathers from a 4 MB table (the access pattern of round 0's "
+                         "colour reads, without the rest of the round)")
     args = ap.parse_args()
     args.tuned = None
     if args.cpu_omp_leg:
@@ -794,6 +797,28 @@ def main():
         print("bench.py: this build measures one GPU only (--gpus 1); multi-GPU runs are not supported",
               file=sys.stderr)
         sys.exit(2)
+    if args.gather_probe:
+        # 2^27 random indices into a 2^20-entry int32 table (4 MB, the size of
+        # the 8 M-vertex lattice's nibble shadow), gathered with torch.take:
+        # besides the gathers it streams the indices in and the values out
+        import torch
+        g = torch.Generator(device="cuda:0")
+        g.manual_seed(args.seed)
+        table = torch.arange(1 << 20, dtype=torch.int32, device="cuda:0")
+        idx = torch.randint(0, 1 << 20, (1 << 27,), dtype=torch.int64, device="cuda:0", generator=g)
+        out = torch.take(table, idx)
+        torch.cuda.synchronize()
+        reps = 5
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            out = torch.take(table, idx)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        ok = bool((out[:1000] == idx[:1000].to(torch.int32)).all())
+        print(json.dumps({"gather_probe": {"gathers": 1 << 27, "table_bytes": 4 << 20, "ms": dt * 1e3,
+                                           "G_gathers_per_s": (1 << 27) / dt / 1e9,
+                                           "stream_bytes": (1 << 27) * (8 + 4), "checked": ok}}), flush=True)
+        return
     if args.copy_probe:
         import torch
         x = torch.ones(1 << 28, dtype=torch.int32, device="cuda:0")
