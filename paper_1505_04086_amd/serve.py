@@ -143,7 +143,7 @@ class Server:
 
     def __init__(self, ctx: rsoc.Context, hbm_budget: int = 16 << 30, scratch_share: float = 0.35,
                  max_slots: int = 512, options=None, device: int = 0, admit_per_poll: int = 32,
-                 solo_when_idle: bool = True, solo_backlog: int = 6):
+                 solo_when_idle: bool = True, solo_backlog: int = 32):
         self.ctx = ctx
         self.dev = torch.device("cuda", device)
         self.scratch_cap = int(hbm_budget * scratch_share)
@@ -164,10 +164,11 @@ class Server:
         self.admit_per_poll = admit_per_poll
         # while the pool holds nothing and at most solo_backlog requests wait,
         # the first goes straight to the single-graph entry point (_run_alone);
-        # solo counts those runs.  Measured on the served workload at half the
-        # plain capacity (p50 / p99 ms; plain 0.97 / 4.15): backlog 2 1.00 /
-        # 5.61, 4 0.95 / 4.81, 6 0.96 / 4.30; at the plain capacity the pool
-        # stays 4x better at p50 with any of them
+        # solo counts those runs.  Measured on the served workload (p50 / p99
+        # ms): at half the plain capacity plain 0.94 / 4.09, backlog 2 1.00 /
+        # 5.61, 6 1.00 / 4.49, 16 0.97 / 4.12, 32 0.95 / 3.98; at the plain
+        # capacity plain 8.1 / 17.8, backlog 6 2.3 / 15.4, 32 5.5 / 12.3; at
+        # twice it plain 155 / 315, backlog 32 10.7 / 23.3
         self.solo_when_idle = solo_when_idle
         self.solo_backlog = solo_backlog
         self.solo = 0
@@ -215,9 +216,9 @@ class Server:
         """The first waiting request, when the pool holds nothing and at most
         solo_backlog requests wait, is coloured at once with the single-graph
         entry point instead of through pool steps: the pool's per-round host
-        round trips only pay off when several graphs share them, and for one
-        or two graphs the single-graph driver (captured rounds, one host check
-        per few rounds) has the lower latency.  Requests arriving meanwhile
+        round trips only pay off when many graphs share them, and for a few
+        graphs the single-graph driver (captured rounds, one host check per
+        few rounds) has the lower latency.  Requests arriving meanwhile
         wait for it, as they would in the one-call-per-request form."""
         req, tens, ev, nbytes = self.staging.pop(0)
         rp, ci, col, tch = tens
