@@ -413,11 +413,12 @@ def bench_single(args):
             if not colouring_valid(rp, ci, d_col.cpu().numpy()):
                 raise SystemExit("bench: invalid colouring produced (full sweep)")
     if (args.det_too or not args.no_extras) and args.mode == "optimistic":
-        # the paper's comparison (Section 4, Table 1): Algorithm 3 read
-        # round-synchronously (R) and its predecessor Algorithm 2 (C) on the
-        # same graph -- recolouring rounds ("iterations"), conflicts, colours
+        # the paper's comparison (Section 4, Table 1): Algorithm 3 (R) and its
+        # predecessor Algorithm 2 (C) on the same graph, round-synchronously
+        # and with live reads -- recolouring rounds ("iterations"), conflicts,
+        # colours
         comp = {}
-        for name in ("deterministic", "two_phase"):
+        for name in ("deterministic", "two_phase", "two_phase_live"):
             o2 = rsoc.make_options(name, "lower", timing=0)
             rsoc.rsoc_color_device(ctx, d_rp, d_ci, n, d_col, o2, stream=stream)
             torch.cuda.synchronize()
@@ -433,6 +434,9 @@ def bench_single(args):
                           "passes": sd["passes"], "conflicts": sd["conflicts"], "device_ms": sd["ms"]}
         out["deterministic"] = comp["deterministic"]
         out["two_phase"] = comp["two_phase"]
+        # with live reads, beside Algorithm 3's literal flow (full_sweep) and
+        # its default flow: the paper's own comparison
+        out["two_phase_live"] = comp["two_phase_live"]
     if not args.no_cpu:
         cb, kseq = cpu_baseline(rp, ci, args.cpu_budget, args.workload, args.seed)
         out["cpu_baseline"] = cb

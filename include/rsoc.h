@@ -76,7 +76,14 @@ typedef enum {
     /* Algorithm 2 (Section 2.2, the predecessor scheme): per round a tentative
      * First-Fit over U, a barrier, conflict detection over U into L, a barrier,
      * U <- L.  Round-synchronous reads, so the result is unique. */
-    RSOC_MODE_TWO_PHASE = 2
+    RSOC_MODE_TWO_PHASE = 2,
+    /* Algorithm 2 as the paper runs it beside Algorithm 3 (Section 4): the
+     * same two phases per round, with live reads and writes straight to the
+     * colour array, as RSOC_MODE_OPTIMISTIC does for Algorithm 3; the first
+     * round colours all of V, reading every neighbour.  Any valid colouring
+     * is a correct result.  rsoc_color_ex / rsoc_color_device only (the
+     * batch, the pool and the recolouring return RSOC_EINVAL). */
+    RSOC_MODE_TWO_PHASE_LIVE = 3
 } rsoc_mode;
 
 typedef enum {

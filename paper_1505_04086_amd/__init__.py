@@ -49,12 +49,14 @@ RSOC_ESCRATCH = -11
 RSOC_MODE_OPTIMISTIC = 0
 RSOC_MODE_DETERMINISTIC = 1
 RSOC_MODE_TWO_PHASE = 2
+RSOC_MODE_TWO_PHASE_LIVE = 3
 RSOC_TIE_LOWER_KEEPS = 0
 RSOC_TIE_HIGHER_KEEPS = 1
 RSOC_CHECK_CSR = 1
 RSOC_CHECK_SYMMETRY = 2
 
-_MODES = {"optimistic": 0, "opt": 0, "deterministic": 1, "det": 1, "two_phase": 2, 0: 0, 1: 1, 2: 2}
+_MODES = {"optimistic": 0, "opt": 0, "deterministic": 1, "det": 1, "two_phase": 2, "two_phase_live": 3,
+          0: 0, 1: 1, 2: 2, 3: 3}
 _TIES = {"lower": 0, "higher": 1, 0: 0, 1: 1}
 
 

@@ -368,6 +368,7 @@ extern "C" int32_t rsoc_color_batch(rsoc_ctx *ctx, int32_t G, const int64_t *vtx
     Options o;
     RSOC_TRY(resolve_options(opts, G > 0 ? vtx_off[G] : 0, o));
     if (o.distance == 2) return RSOC_EINVAL;  // distance 2: single-graph entry points only
+    if (o.mode == kTwoPhaseLive) return RSOC_EINVAL;  // single-graph entry points only
     RSOC_HIP(hipSetDevice(ctx->device));
     return run_batch(ctx, G, vtx_off, nnz_off, d_row_ptr_cat, d_col_idx_cat, d_colors_cat, counts_out, o, stats,
                      (hipStream_t)hip_stream);

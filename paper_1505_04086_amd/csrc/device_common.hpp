@@ -59,7 +59,10 @@ __host__ __device__ constexpr int step_offset(int r, int i, int gi, int c) {
 }
 
 enum Phase : int { kAssign = 0, kRecolor = 1, kDetect = 2 };
-enum Mode : int { kOptimistic = 0, kDeterministic = 1, kTwoPhase = 2 };
+enum Mode : int { kOptimistic = 0, kDeterministic = 1, kTwoPhase = 2, kTwoPhaseLive = 3 };
+// modes that write colours in place and read them live
+__host__ __device__ constexpr bool live_mode(int m) { return m == kOptimistic || m == kTwoPhaseLive; }
+__host__ __device__ constexpr bool two_phase_mode(int m) { return m == kTwoPhase || m == kTwoPhaseLive; }
 enum Tie : int { kLowerKeeps = 0, kHigherKeeps = 1 };
 enum Bin : int { kBinThread = 0, kBinWave = 1, kBinBlock = 2 };
 

@@ -107,7 +107,7 @@ inline int32_t resolve_options(const rsoc_options *o, int64_t n, Options &r) {
     if (o) d = *o;
     r.mode = d.mode;
     r.tie = d.tie;
-    if (r.mode < RSOC_MODE_OPTIMISTIC || r.mode > RSOC_MODE_TWO_PHASE) return RSOC_EINVAL;
+    if (r.mode < RSOC_MODE_OPTIMISTIC || r.mode > RSOC_MODE_TWO_PHASE_LIVE) return RSOC_EINVAL;
     if (r.tie != RSOC_TIE_LOWER_KEEPS && r.tie != RSOC_TIE_HIGHER_KEEPS) return RSOC_EINVAL;
     if (d.max_rounds < 0 || d.t_thread < 0 || d.t_thread > 32 || d.t_wave < 0 || d.grid_thread < 0 ||
         d.grid_wave < 0 || d.rounds_per_sync < 0 || d.validate < 0 || d.validate > 3 || d.grid_list < 0)

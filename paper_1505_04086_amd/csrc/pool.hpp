@@ -216,7 +216,7 @@ inline int32_t pool_admit(rsoc_pool *p, const int32_t *d_row_ptr, const int32_t 
         return RSOC_EINVAL;
     Options o;
     RSOC_TRY(resolve_options(opts, n, o));
-    if (o.mode == RSOC_MODE_TWO_PHASE) return RSOC_EINVAL;  // the pool runs Algorithm 3 only
+    if (two_phase_mode(o.mode)) return RSOC_EINVAL;  // the pool runs Algorithm 3 only
     if (o.distance == 2) return RSOC_EINVAL;                // distance 2: single-graph entry points only
     rsoc_ctx *c = p->ctx;
     RSOC_HIP(hipSetDevice(c->device));

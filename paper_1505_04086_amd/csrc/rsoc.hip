@@ -153,7 +153,7 @@ int32_t rsoc_recolor_device(rsoc_ctx *ctx, const int32_t *d_row_ptr, const int32
         return RSOC_EINVAL;
     Options o;
     RSOC_TRY(resolve_options(opts, n, o));
-    if (o.mode == kTwoPhase) return RSOC_EINVAL;  // Algorithm 2 recolours all of U: no incremental reading
+    if (two_phase_mode(o.mode)) return RSOC_EINVAL;  // Algorithm 2 recolours all of U: no incremental reading
     if (o.distance == 2) return RSOC_EINVAL;
     RSOC_HIP(hipSetDevice(ctx->device));
     return run_single(ctx, d_row_ptr, d_col_idx, n, d_colors_inout, o, stats, (hipStream_t)hip_stream, d_touched,

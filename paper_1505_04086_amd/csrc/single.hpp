@@ -91,10 +91,10 @@ inline void launch_list_round(rsoc_ctx *c, hipStream_t s, int parity, int gB, in
     const SingleArgs *A = c->args.as<SingleArgs>();
     SingleState *S = c->state.as<SingleState>();
     const int grid = gB + gW + gT;
-    if (MODE == kTwoPhase) {
-        k_round<kAssign, kTwoPhase, TIE, false><<<grid, kBlock, 0, s>>>(A, S, parity, gB, gW, gT);
-        k_scatter<false, true><<<gT, kBlock, 0, s>>>(A, S, parity);
-        k_round<kDetect, kTwoPhase, TIE, false><<<grid, kBlock, 0, s>>>(A, S, parity, gB, gW, gT);
+    if (two_phase_mode(MODE)) {
+        k_round<kAssign, MODE, TIE, false><<<grid, kBlock, 0, s>>>(A, S, parity, gB, gW, gT);
+        if (MODE == kTwoPhase) k_scatter<false, true><<<gT, kBlock, 0, s>>>(A, S, parity);
+        k_round<kDetect, MODE, TIE, false><<<grid, kBlock, 0, s>>>(A, S, parity, gB, gW, gT);
     } else {
         k_round<kRecolor, MODE, TIE, false><<<grid, kBlock, 0, s>>>(A, S, parity, gB, gW, gT);
         if (MODE == kDeterministic) k_scatter<false, false><<<gT, kBlock, 0, s>>>(A, S, parity);
@@ -114,9 +114,12 @@ inline void launch_list_rounds_dyn(rsoc_ctx *c, hipStream_t s, int mode, int tie
     else if (mode == kDeterministic)
         tie ? launch_list_rounds<kDeterministic, kHigherKeeps>(c, s, K, gB, gW, gT)
             : launch_list_rounds<kDeterministic, kLowerKeeps>(c, s, K, gB, gW, gT);
-    else
+    else if (mode == kTwoPhase)
         tie ? launch_list_rounds<kTwoPhase, kHigherKeeps>(c, s, K, gB, gW, gT)
             : launch_list_rounds<kTwoPhase, kLowerKeeps>(c, s, K, gB, gW, gT);
+    else
+        tie ? launch_list_rounds<kTwoPhaseLive, kHigherKeeps>(c, s, K, gB, gW, gT)
+            : launch_list_rounds<kTwoPhaseLive, kLowerKeeps>(c, s, K, gB, gW, gT);
 }
 
 // Captured graph of K worklist rounds followed by the colour statistics and
@@ -180,12 +183,15 @@ inline bool launch_sweep_rounds(rsoc_ctx *c, hipStream_t s, int32_t *col, int n,
         launch_ev(k_round<kAssign, kOptimistic, TIE, true, 0>, grid, kBlock, s, timing ? ev[2] : nullptr,
                   timing ? ev[3] : nullptr, A, S, 1, gB, gW, gT);
     }
-    if (MODE == kTwoPhase) {
-        // Algorithm 2, first round: tentative colouring of V, publish, detect
-        k_round<kAssign, kTwoPhase, TIE, true><<<grid, kBlock, 0, s>>>(A, S, 1, gB, gW, gT);
-        k_scatter<true, false><<<fill_grid, kBlock, 0, s>>>(A, S, 1);
+    if (two_phase_mode(MODE)) {
+        // Algorithm 2, first round: tentative colouring of V (published by
+        // the scatter, or in place with live reads), detect
+        if (MODE == kTwoPhaseLive && timing) (void)hipEventRecord(c->ev[2], s);
+        k_round<kAssign, MODE, TIE, true><<<grid, kBlock, 0, s>>>(A, S, 1, gB, gW, gT);
+        if (MODE == kTwoPhase) k_scatter<true, false><<<fill_grid, kBlock, 0, s>>>(A, S, 1);
+        else if (timing) (void)hipEventRecord(c->ev[3], s);
         if (timing) (void)hipEventRecord(c->ev[4], s);
-        k_round<kDetect, kTwoPhase, TIE, true><<<grid, kBlock, 0, s>>>(A, S, 1, gB, gW, gT);
+        k_round<kDetect, MODE, TIE, true><<<grid, kBlock, 0, s>>>(A, S, 1, gB, gW, gT);
         if (timing) (void)hipEventRecord(c->ev[5], s);
     } else {
         if (timing) (void)hipEventRecord(c->ev[4], s);
@@ -216,7 +222,9 @@ inline bool launch_sweep_dyn(rsoc_ctx *c, hipStream_t s, int mode, int tie, int3
         return tie ? RSOC_SWEEP(kOptimistic, kHigherKeeps) : RSOC_SWEEP(kOptimistic, kLowerKeeps);
     if (mode == kDeterministic)
         return tie ? RSOC_SWEEP(kDeterministic, kHigherKeeps) : RSOC_SWEEP(kDeterministic, kLowerKeeps);
-    return tie ? RSOC_SWEEP(kTwoPhase, kHigherKeeps) : RSOC_SWEEP(kTwoPhase, kLowerKeeps);
+    if (mode == kTwoPhase)
+        return tie ? RSOC_SWEEP(kTwoPhase, kHigherKeeps) : RSOC_SWEEP(kTwoPhase, kLowerKeeps);
+    return tie ? RSOC_SWEEP(kTwoPhaseLive, kHigherKeeps) : RSOC_SWEEP(kTwoPhaseLive, kLowerKeeps);
 #undef RSOC_SWEEP
 }
 
@@ -289,7 +297,7 @@ inline void alg_bytes(int mode, bool full_sweep, int64_t n, int64_t nnz, int64_t
                       int64_t L1, int64_t conflicts, uint64_t inspected, uint64_t deg_sum, uint64_t inspected1,
                       uint64_t deg_sum1, int64_t &b0, int64_t &b1, int64_t &total) {
     const int64_t per_rec = (mode == kOptimistic) ? 8 : 20;
-    if (mode == kTwoPhase) {
+    if (two_phase_mode(mode)) {
         b0 = 4 * n;
         b1 = (4 * (n + 1) + 8 * nnz + 4 * n + 4 * (nW + nB)) + 12 * n + (4 * (n + 1) + 4 * n + 8 * nnz + 4 * (nW + nB)) +
              4 * L1;

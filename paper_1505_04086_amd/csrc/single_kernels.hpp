@@ -607,7 +607,7 @@ __global__ __launch_bounds__(kBlock) void k_round(const SingleArgs *__restrict__
     const RSOC_GLOBAL int32_t *ci = gro(a.ci);
     const RSOC_GLOBAL int32_t *rcol = gro(a.col);
     const RSOC_GLOBAL uint8_t *rcol8 = gro(a.col8);
-    RSOC_GLOBAL int32_t *wcol = grw((MODE == kOptimistic) ? a.col : a.pend);
+    RSOC_GLOBAL int32_t *wcol = grw(live_mode(MODE) ? a.col : a.pend);
     RSOC_GLOBAL uint8_t *wcol8 = grw(a.col8);
     // The 4-bit shadow is kept in optimistic mode (colours change in place):
     // round 0 publishes each colour into it as soon as it is chosen
@@ -650,7 +650,7 @@ __global__ __launch_bounds__(kBlock) void k_round(const SingleArgs *__restrict__
                 degs += (uint64_t)(e - b);
                 if (act && kWrite) {
                     wcol[v] = nc;
-                    if (MODE == kOptimistic) wcol8[v] = shadow_of(nc);
+                    if (live_mode(MODE)) wcol8[v] = shadow_of(nc);
                     if (kPublish) publish_nibble(wcol4, v, nc);
                     else if (kNib) atomicOr((uint32_t *)&wcol4[v >> 3], 0xfu << ((v & 7) << 2));
                 }
@@ -683,7 +683,7 @@ __global__ __launch_bounds__(kBlock) void k_round(const SingleArgs *__restrict__
                 degs += (uint64_t)(e - b);
                 if (act && kWrite) {
                     wcol[v] = nc;
-                    if (MODE == kOptimistic) wcol8[v] = shadow_of(nc);
+                    if (live_mode(MODE)) wcol8[v] = shadow_of(nc);
                     if (kPublish) publish_nibble(wcol4, v, nc);
                     else if (kNib) atomicOr((uint32_t *)&wcol4[v >> 3], 0xfu << ((v & 7) << 2));
                 }
@@ -826,7 +826,7 @@ __global__ __launch_bounds__(kBlock) void k_round(const SingleArgs *__restrict__
                         degs += (uint64_t)(e[i] - b[i]);
                         if (act[i] && kWrite) {
                             wcol[v[i]] = nc[i];
-                            if (MODE == kOptimistic) wcol8[v[i]] = (uint8_t)nc[i];
+                            if (live_mode(MODE)) wcol8[v[i]] = (uint8_t)nc[i];
                             // a recoloured vertex's nibble becomes 15: readers then use col8
                             // (round 0 publishes nibbles below, one atomic per word)
                             if (kNib && !kPublish) atomicOr((uint32_t *)&wcol4[v[i] >> 3], 0xfu << ((v[i] & 7) << 2));
@@ -1032,7 +1032,7 @@ __global__ void k_round_end(const SingleArgs *__restrict__ A, SingleState *S) {
             S->inspected1 = S->inspected;
             S->deg_sum1 = S->deg_sum;
         }
-        if (MODE == kTwoPhase) {
+        if (two_phase_mode(MODE)) {
             if (S->rounds < kHistCap) S->hist[S->rounds] = out_total;
             S->rounds += 1;
             S->conflicts += out_total;

@@ -251,3 +251,45 @@ def test_config1_full(lib, ctx):
             assert list(st["L_sizes"]) == list(want["L_sizes"])
             k, st = lib.rsoc_color_device(ctx, d_rp, d_ci, n, d_col, lib.make_options("optimistic", tie))
             assert oracle.check(rp, ci, d_col.cpu().numpy()) == 0
+
+
+@pytest.mark.parametrize("split", ["default", "allbins", "wave_only", "block_only", "runs1"])
+@pytest.mark.parametrize("tie", ["lower", "higher"])
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_two_phase_live_valid(lib, ctx, name, tie, split):
+    """Algorithm 2 with live reads (the paper's "C" as it runs beside
+    Algorithm 3): any valid colouring with 0 <= c(v) <= deg(v) is correct; the
+    one-sided test still lets the lowest vertex of U leave it in every round,
+    so at most n rounds; every round recolours all of U, so its |L| is the
+    next round's |U|."""
+    rp, ci = CASES[name]
+    d_rp, d_ci, d_col, n = _dev(lib, rp, ci)
+    o = lib.make_options("two_phase_live", tie, **BIN_SPLITS[split])
+    k, st = lib.rsoc_color_device(ctx, d_rp, d_ci, n, d_col, o, per_round_cap=n + 2)
+    got = d_col.cpu().numpy()[:n]
+    assert oracle.check(rp, ci, got) == 0
+    assert k == oracle.colour_count(got) and st["colors_distinct"] == len(np.unique(got))
+    deg = np.diff(rp)
+    assert k <= (deg.max() + 1 if n else 0)
+    assert st["rounds"] <= max(n, 1)
+
+
+def test_two_phase_live_single_graph_only(lib, ctx):
+    """The live two-phase mode is refused where only Algorithm 3 runs (the
+    pool, the recolouring) and by the batch."""
+    import torch
+    rp, ci = gg.tri_grid(20, 20)
+    d_rp, d_ci, d_col, n = _dev(lib, rp, ci)
+    o = lib.make_options("two_phase_live")
+    b = gg.concat([(rp, ci)])
+    with pytest.raises(lib.RsocError) as e:
+        lib.rsoc_color_batch(ctx, b["vtx_off"], b["nnz_off"], d_rp, d_ci, d_col, o)
+    assert e.value.code == lib.RSOC_EINVAL
+    pool = lib.Pool(ctx, 0, 4)
+    with pytest.raises(lib.RsocError) as e:
+        pool.admit(d_rp, d_ci, n, d_col, o)
+    assert e.value.code == lib.RSOC_EINVAL
+    pool.close()
+    with pytest.raises(lib.RsocError) as e:
+        lib.rsoc_recolor_device(ctx, d_rp, d_ci, n, d_col, torch.zeros(1, dtype=torch.int32, device=d_col.device), o)
+    assert e.value.code == lib.RSOC_EINVAL
