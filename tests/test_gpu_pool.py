@@ -321,3 +321,36 @@ def test_pool_one_large_slot(lib, ctx, mode):
         assert oracle.check(rp, ci, got) == 0 and k == oracle.colour_count(got)
     assert st["colors_distinct"] == len(np.unique(got))
     pool.close()
+
+
+def test_pool_more_spans_than_lds_holds(lib, ctx):
+    """2100 slots in the same rounds: a task table's spans (one per slot)
+    exceed what the dealing kernel stages in LDS (2048), so it reads them from
+    memory; every result as alone."""
+    import torch
+    small = [gg.path(9), gg.cycle(7), gg.complete(6), gg.star(20), gg.tri_grid(5, 4)]
+    pool = lib.Pool(ctx, 0, 2200)
+    live = {}
+    d = torch.device("cuda:0")
+    dev = [(torch.from_numpy(rp).to(d), torch.from_numpy(ci).to(d)) for rp, ci in small]
+    for i in range(2100):
+        g = i % len(small)
+        mode, tie = MODES[i % 4]
+        n = len(small[g][0]) - 1
+        col = torch.full((n,), -5, dtype=torch.int32, device=d)
+        live[pool.admit(dev[g][0], dev[g][1], n, col, lib.make_options(mode, tie))] = (g, mode, tie, col)
+    torch.cuda.synchronize()
+    steps = 0
+    while live:
+        for slot in pool.step(cap=4096):
+            g, mode, tie, col = live.pop(slot)
+            k, st = pool.result(slot)
+            rp, ci = small[g]
+            got = col.cpu().numpy()
+            if mode == "deterministic":
+                assert np.array_equal(got, oracle.rsync(rp, ci, tie=tie)["colors"]), g
+            else:
+                assert oracle.check(rp, ci, got) == 0, g
+        steps += 1
+        assert steps < 1000
+    pool.close()
