@@ -199,6 +199,9 @@ __global__ __launch_bounds__(kBlock) void k_hub_lists(const SingleArgs *__restri
 // The walk over the hubs in tie order (one workgroup), then the colours out.
 // The bit sets of a block of consecutive hubs are copied into LDS at once (one
 // memory round trip per block); a hub then costs LDS work and two barriers.
+// Each thread keeps the colours of its 8 hub positions in registers (set as
+// the walk settles them), and the smallest-colour search reads only colours
+// up to one above the largest given so far.
 // Its forbidden colours (those of the hubs it loses to; each thread takes 8
 // bits of one word of its bit set) are marked in an LDS array by writing the
 // hub's stamp (position + 1) at each colour -- plain writes, so the many
@@ -244,7 +247,12 @@ __global__ __launch_bounds__(kHubFfBlock) void k_hub_ff(const SingleArgs *__rest
     const RSOC_GLOBAL uint32_t *gb = gro(a.hub_bits);
     const int word = t >> 2, sub = (t & 3) * 8;  // this thread's 8 bits of a bit set
     const int wv = t / kWave;
-    int prev = -1;                               // colour of the hub settled last
+    // the colours of this thread's 8 hub positions, kept in registers as the
+    // walk settles them (a position's bit is set only for hubs after it)
+    int own[8];
+#pragma unroll
+    for (int b = 0; b < 8; ++b) own[b] = 0;
+    int maxc = -1;                               // largest colour given so far
     for (int i0 = 0; i0 < nH; i0 += B) {
         const int nb = min(B, nH - i0);
         constexpr int kLoads = kHubBufWords / kHubFfBlock;
@@ -270,23 +278,16 @@ __global__ __launch_bounds__(kHubFfBlock) void k_hub_ff(const SingleArgs *__rest
             // unset bit's write goes to the lane's own spare word
             if (word < W) {
                 const uint32_t byte = (bits[h * W + word] >> sub) & 0xffu;
-                int c[8];
 #pragma unroll
-                for (int b = 0; b < 8; ++b) c[b] = hc[word * 32 + sub + b];
-#pragma unroll
-                for (int b = 0; b < 8; ++b) {
-                    // hub i - 1 was settled in the previous step: its colour is in
-                    // every thread's register, not yet behind a barrier in LDS
-                    const int cb = (word * 32 + sub + b == i - 1) ? prev : c[b];
-                    mark[((byte >> b) & 1u) ? cb : kHubCap + lane_id()] = stamp;
-                }
+                for (int b = 0; b < 8; ++b) mark[((byte >> b) & 1u) ? own[b] : kHubCap + lane_id()] = stamp;
             }
             __syncthreads();
             // the smallest colour not marked for hub i: hub i loses to at most
-            // i hubs, so it is at most i; thread t looks at colours 8t .. 8t + 7
+            // i hubs and every colour given so far is at most maxc, so it is at
+            // most min(i, maxc + 1); thread t looks at colours 8t .. 8t + 7
             const int c0 = t * kHubColPerThread;
             int first = INT_MAX;
-            if (c0 <= i) {
+            if (c0 <= min(i, maxc + 1)) {
                 int m8[kHubColPerThread];
 #pragma unroll
                 for (int k = 0; k < kHubColPerThread; ++k) m8[k] = mark[c0 + k];
@@ -302,7 +303,9 @@ __global__ __launch_bounds__(kHubFfBlock) void k_hub_ff(const SingleArgs *__rest
 #pragma unroll
             for (int w = 0; w < kHubFfWaves; ++w) cc = min(cc, wmin[i & 1][w]);
             if (t == 0) hc[i] = (uint16_t)cc;
-            prev = cc;
+            maxc = max(maxc, cc);
+#pragma unroll
+            for (int b = 0; b < 8; ++b) own[b] = (word * 32 + sub + b == i) ? cc : own[b];
         }
         // the last hub's barriers also end every read of `bits` of this block
     }
