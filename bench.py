@@ -35,9 +35,10 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak
 
 
-# sources the single-graph round kernels and their launch shapes are built
-# from (the figures in profiles/traffic.json stay valid while these are unchanged)
-ROUND_KERNEL_SOURCES = ("device_common.hpp", "vertex_ops.hpp", "single_kernels.hpp", "single.hpp", "host_common.hpp")
+# sources the round kernels and their launch shapes are built from (the
+# figures in profiles/traffic.json stay valid while these are unchanged)
+ROUND_KERNEL_SOURCES = ("device_common.hpp", "vertex_ops.hpp", "single_kernels.hpp", "single.hpp", "host_common.hpp",
+                        "hub_kernels.hpp", "batch_kernels.hpp", "batch.hpp")
 
 
 def kernel_source_hash() -> str:
@@ -48,9 +49,10 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic(workload: str, kernel: str):
+def load_traffic(workload: str, kernel: str, options=None):
     """HBM traffic per launch measured with rocprofv3 counters, if it was taken
-    for the current kernel sources (else None)."""
+    for the current kernel sources (and, where recorded, the same launch
+    options), else None."""
     p = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(p):
         return None
@@ -61,7 +63,9 @@ def load_traffic(workload: str, kernel: str):
     if rec.get("source_hash") != kernel_source_hash():
         return None
     ent = rec.get("workloads", {}).get(workload, {}).get(kernel)
-    return None if ent is None else ent.get("bytes_per_launch")
+    if ent is None or ("options" in ent and ent["options"] != (options or {})):
+        return None
+    return ent.get("bytes_per_launch")
 
 
 def make_graph(workload: str, seed: int, sample: bool = False):
@@ -607,7 +611,7 @@ def bench_batched(args):
         "batched_over_plain": value / (E / tp / 1e9),
         "roofline": {"bound": "hbm", "kernel": "batched_round0_first_fit", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": None if achieved is None else achieved / HBM_PEAK_GBS,
-                     "traffic": load_traffic("batched", "batched_round0_first_fit"), "kernel_ms": kms,
+                     "traffic": load_traffic("batched", "batched_round0_first_fit", args.tuned), "kernel_ms": kms,
                      "alg_bytes_per_launch": kbytes},
     }
     ctx.close()
