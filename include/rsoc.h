@@ -175,7 +175,17 @@ typedef struct {
      * colours beyond sequential First-Fit.  Skipped (round 0 as without it)
      * when more than 4096 vertices exceed the threshold. */
     int32_t hub_first;
-    int32_t reserved[2]; /* must be zero */
+    /* rsoc_color_batch, optimistic round 0: sweep bands per XCD (1 .. 16; 0 =
+     * library default).  The fused launches' tasks are cut into 8 x bands
+     * ranges of about equal work; each is handed out in order from its own
+     * counter, each XCD's workgroups start on its own ranges, and a workgroup
+     * whose range is exhausted helps the next ones.  More bands spread the
+     * vertices coloured at one instant over more graphs (fewer neighbours
+     * read before they are coloured, a shorter round-1 list); fewer keep
+     * fewer graphs' colours in each XCD's L2.  Ignored by the other entry
+     * points and modes. */
+    int32_t bands;
+    int32_t reserved; /* must be zero */
 } rsoc_options;
 
 typedef struct {

@@ -68,7 +68,7 @@ class rsoc_options(ctypes.Structure):
                 ("timing", ctypes.c_int32), ("full_sweep", ctypes.c_int32), ("lookahead", ctypes.c_int32),
                 ("chunk", ctypes.c_int32), ("grid_list", ctypes.c_int32), ("tail", ctypes.c_int32),
                 ("distance", ctypes.c_int32), ("grid_bin", ctypes.c_int32), ("hub_first", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("bands", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class rsoc_stats(ctypes.Structure):

@@ -218,6 +218,26 @@ inline int32_t run_batch(rsoc_ctx *c, int32_t G, const int64_t *vtx_off, const i
     a.max_rounds = o.max_rounds;
     a.look = 0;
     a.chunk = 1;
+    // round 0's bands (claim_task): ranges of the fused launches' tasks of
+    // about equal work, a task's work taken as its vertices times one plus
+    // its graph's mean degree
+    a.nbands = kXcds * o.bands;
+    {
+        std::vector<double> work((size_t)ntasks + 1, 0.0);
+        for (int t = 0; t < ntasks; ++t) {
+            const int g = (int)(tasks[(size_t)t] >> 32);
+            const int64_t ng = vtx_off[g + 1] - vtx_off[g];
+            const int64_t len = std::min<int64_t>(kTaskLen, ng - (int64_t)(uint32_t)tasks[(size_t)t]);
+            const double deg = ng > 0 ? (double)(nnz_off[g + 1] - nnz_off[g]) / (double)ng : 0.0;
+            work[(size_t)t + 1] = work[(size_t)t] + (double)len * (1.0 + deg);
+        }
+        int t = 0;
+        for (int x = 0; x <= a.nbands; ++x) {
+            const double target = work[(size_t)ntasks] * x / a.nbands;
+            while (t < ntasks && work[(size_t)t] < target) ++t;
+            a.band[x] = x == a.nbands ? ntasks : t;
+        }
+    }
     SingleState *S = c->b_state.as<SingleState>();
     RSOC_HIP(hipMemcpyAsync(c->b_args.p, &a, sizeof(a), hipMemcpyHostToDevice, s));
     RSOC_HIP(hipMemsetAsync(S, 0, kStateHeader, s));

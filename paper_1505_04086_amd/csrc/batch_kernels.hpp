@@ -37,7 +37,9 @@ struct BatchArgs {
     int32_t ntasks_all;   // tasks of every graph (the first ntasks are the fused launches' graphs)
     const int32_t *small; // graphs coloured by one workgroup each (k_bsmall)
     int32_t *small_stat;  // their statistics: see k_bsmall
-    int32_t nsmall, pad;
+    int32_t nsmall;
+    int32_t nbands;              // optimistic round 0: sweep bands, kXcds per band index of an XCD
+    int32_t band[kMaxBands + 1]; // band b is tasks [band[b], band[b+1]) (about equal work)
 };
 
 __device__ __forceinline__ int64_t pack_item(int g, int v) { return ((int64_t)g << 32) | (uint32_t)v; }
@@ -78,6 +80,34 @@ __device__ __forceinline__ void wave_append64(bool take, int64_t x, int *counter
         const int64_t pos = base + lanes_below(m);
         list[from_back ? cap - 1 - pos : pos] = x;
     }
+}
+
+// Optimistic round 0 of the batch sweeps its tasks in nbands = kXcds * B
+// bands of about equal work, B of them per XCD, the XCD's bands one
+// contiguous part of the batch: each band is handed out in order from its own
+// counter, so the tasks in flight on one XCD form B narrow ranges of its part
+// (a few graphs) and those graphs' colours stay in the XCD's L2 while the
+// ranges cross them.  A workgroup starts on a band of its own XCD (hardware
+// deals consecutive workgroups round-robin over the XCDs) and, once that band
+// is exhausted, helps the following ones, so every task is claimed exactly
+// once whatever the grid and however unequal the bands turn out.
+__device__ __forceinline__ int home_band(const BatchArgs &a, int bid) {
+    const int per = a.nbands / kXcds;
+    return (bid % kXcds) * per + (bid / kXcds) % per;
+}
+// Returns the next task, or -1 when every band is exhausted; *k counts the
+// bands this workgroup has finished with (start at 0).  Thread 0 only.
+__device__ __forceinline__ int claim_task(const BatchArgs &a, SingleState *S, int home, int *k) {
+    while (*k < a.nbands) {
+        const int x = (home + *k) % a.nbands;
+        const int lo = a.band[x], hi = a.band[x + 1];
+        if (lo < hi) {
+            const int i = atomicAdd(&S->next_task[x], 1);
+            if (i < hi - lo) return lo + i;
+        }
+        ++*k;
+    }
+    return -1;
 }
 
 // --------------------------------------------------------------- binning --
@@ -219,7 +249,7 @@ __global__ __launch_bounds__(kBlock) void k_bround(const BatchArgs *__restrict__
                                                    int gB, int gW, int gT) {
     __shared__ uint32_t lds[kLdsWords];
     __shared__ int64_t q[kQueueCap];
-    __shared__ int sh_min, qn, qbase;
+    __shared__ int sh_min, qn, qbase, sh_step;
     __shared__ unsigned long long sh_acc[2];
     __shared__ int64_t wbuf[kWavesPerBlock][kWaveBuf];
     __shared__ int wbn[kWavesPerBlock];
@@ -301,8 +331,25 @@ __global__ __launch_bounds__(kBlock) void k_bround(const BatchArgs *__restrict__
         }
         // SWEEP: one task (a chunk of one graph) per workgroup step;
         // worklist rounds: kStep packed items per step.
+        // Optimistic round 0 claims its tasks band by band (claim_task).  A
+        // fixed stride over the task table instead lets workgroups drift apart
+        // over a long sweep: the tasks in flight then span many graphs at once,
+        // whose colour gathers (random ids in a geometric graph) evict one
+        // another from L2, and the rounds read several times the bytes.
+        constexpr bool kClaim = SWEEP && ROUND0 == 1;
         const int64_t nsteps = SWEEP ? (int64_t)cT : ((int64_t)cT + kStep - 1) / kStep;
-        for (int64_t step = tb; step < nsteps; step += gT) {
+        int64_t step = tb;
+        int bands_done = 0;
+        if (kClaim) {
+            if (threadIdx.x == 0) sh_step = claim_task(a, S, home_band(a, bid), &bands_done);
+            __syncthreads();
+            step = sh_step < 0 ? nsteps : sh_step;
+        }
+        while (step < nsteps) {
+            // the next task is claimed when this one starts (the claim's round
+            // trip overlaps this task's loads)
+            int next = 0;
+            if (kClaim && threadIdx.x == 0) next = claim_task(a, S, home_band(a, bid), &bands_done);
             int tg = 0, tstart = 0, tlen = 0;
             GraphView tw = {};
             if (SWEEP) {
@@ -380,6 +427,14 @@ __global__ __launch_bounds__(kBlock) void k_bround(const BatchArgs *__restrict__
                     const int cq = queue_size(&qn);
                     if (cq > kQueueCap - kSub) queue_flush64_n(cq, q, &qn, &qbase, &S->cnt_out[kBinThread], out);
                 }
+            }
+            if (kClaim) {
+                __syncthreads();  // every thread has read sh_step
+                if (threadIdx.x == 0) sh_step = next;
+                __syncthreads();
+                step = sh_step < 0 ? nsteps : sh_step;
+            } else {
+                step += gT;
             }
         }
         if (kAppend) queue_flush64(q, &qn, &qbase, &S->cnt_out[kBinThread], out);

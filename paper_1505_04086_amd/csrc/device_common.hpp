@@ -26,6 +26,8 @@ constexpr int kLdsWords = (kBlockWindowWords > kWavesPerBlock * kWaveWindowWords
                                                                                   : kWavesPerBlock * kWaveWindowWords;
 constexpr int kHistCap = 1 << 16;         // per-round |L| history kept on the device
 constexpr int kXcds = 8;                  // MI355X: 8 accelerator complex dies, 32 CUs each
+constexpr int kMaxBandsPerXcd = 16;      // sweep bands per XCD of a batch's optimistic round 0
+constexpr int kMaxBands = kXcds * kMaxBandsPerXcd;
 constexpr int kGroup = 8;                 // lanes per vertex in the thread bin
 constexpr int kGroupSlots = 4;            // row entries each lane holds: thread-bin degree <= 32
 constexpr int kThreadBinMax = kGroup * kGroupSlots;

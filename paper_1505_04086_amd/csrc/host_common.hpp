@@ -8,6 +8,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include "device_common.hpp"
 #include "rsoc.h"
 
 namespace rsoc {
@@ -95,10 +96,13 @@ struct HostPinned {
 // Largest graph of a batch coloured by one workgroup (colours and worklists in
 // LDS; the option small_cutoff).
 constexpr int kSmallMaxVertices = 2048;
+// Sweep bands per XCD of a batch's optimistic round 0 (the option bands;
+// at most kMaxBandsPerXcd).
+constexpr int kDefaultBandsPerXcd = 4;
 
 struct Options {
     int mode, tie, max_rounds, validate, t_thread, t_wave, grid_thread, grid_wave, rounds_per_sync,
-        timing, full_sweep, lookahead, chunk, grid_list, tail, distance, grid_bin, hub_first, small_cutoff;
+        timing, full_sweep, lookahead, chunk, grid_list, tail, distance, grid_bin, hub_first, small_cutoff, bands;
 };
 
 inline int32_t resolve_options(const rsoc_options *o, int64_t n, Options &r) {
@@ -112,7 +116,9 @@ inline int32_t resolve_options(const rsoc_options *o, int64_t n, Options &r) {
     if (d.max_rounds < 0 || d.t_thread < 0 || d.t_thread > 32 || d.t_wave < 0 || d.grid_thread < 0 ||
         d.grid_wave < 0 || d.rounds_per_sync < 0 || d.validate < 0 || d.validate > 3 || d.grid_list < 0)
         return RSOC_EINVAL;
-    if (d.reserved[0] || d.reserved[1] || d.grid_bin < 0) return RSOC_EINVAL;
+    if (d.reserved || d.grid_bin < 0) return RSOC_EINVAL;
+    if (d.bands < 0 || d.bands > kMaxBandsPerXcd) return RSOC_EINVAL;
+    r.bands = d.bands ? d.bands : kDefaultBandsPerXcd;
     if (d.small_cutoff < -1 || d.small_cutoff > kSmallMaxVertices) return RSOC_EINVAL;
     if (d.hub_first < -1) return RSOC_EINVAL;
     r.grid_bin = d.grid_bin;  // 0: each launch site's own default
