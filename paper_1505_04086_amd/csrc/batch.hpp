@@ -61,9 +61,10 @@ inline int32_t get_batch_graph(rsoc_ctx *c, int mode, int tie, int K, int gB, in
     return RSOC_OK;
 }
 
+// gB/gW/gT: the sweep's grid; gBl/gWl/gTl: the list rounds' grid.
 template <int MODE, int TIE>
 inline void launch_bsweep(rsoc_ctx *c, hipStream_t s, int64_t nV, int gB, int gW, int gT, bool full_sweep,
-                          bool timing) {
+                          bool timing, int gBl, int gWl, int gTl) {
     const BatchArgs *A = c->b_args.as<BatchArgs>();
     SingleState *S = c->b_state.as<SingleState>();
     const int grid = gB + gW + gT;
@@ -80,6 +81,13 @@ inline void launch_bsweep(rsoc_ctx *c, hipStream_t s, int64_t nV, int gB, int gW
                 k_bround<kAssign, kOptimistic, TIE, true, 1><<<grid, kBlock, 0, s>>>(A, S, 1, gB, gW, gT);
                 if (timing) (void)hipEventRecord(c->ev[3], s);
                 k_bround_end<MODE, true, true><<<1, 64, 0, s>>>(A, S);
+                // round 1 over U^0, its thread-bin part walked task by task from
+                // round 0's masks with the sweep's grid, then one list round at
+                // parity 1, so that the captured rounds find their list at parity 0
+                k_bround<kRecolor, kOptimistic, TIE, false, 2><<<gBl + gWl + gT, kBlock, 0, s>>>(A, S, 0, gBl, gWl,
+                                                                                             gT);
+                k_bround_end<MODE, false><<<1, 64, 0, s>>>(A, S);
+                launch_blist_round<kOptimistic, TIE>(c, s, 1, gBl, gWl, gTl);
                 return;
             }
             k_bround<kAssign, kOptimistic, TIE, true, 0><<<grid, kBlock, 0, s>>>(A, S, 1, gB, gW, gT);
@@ -98,16 +106,16 @@ inline void launch_bsweep(rsoc_ctx *c, hipStream_t s, int64_t nV, int gB, int gW
 }
 
 inline void launch_bsweep_dyn(rsoc_ctx *c, hipStream_t s, int mode, int tie, int64_t nV, int gB, int gW, int gT,
-                              bool full, bool timing) {
+                              bool full, bool timing, int gBl, int gWl, int gTl) {
     if (mode == kOptimistic)
-        tie ? launch_bsweep<kOptimistic, kHigherKeeps>(c, s, nV, gB, gW, gT, full, timing)
-            : launch_bsweep<kOptimistic, kLowerKeeps>(c, s, nV, gB, gW, gT, full, timing);
+        tie ? launch_bsweep<kOptimistic, kHigherKeeps>(c, s, nV, gB, gW, gT, full, timing, gBl, gWl, gTl)
+            : launch_bsweep<kOptimistic, kLowerKeeps>(c, s, nV, gB, gW, gT, full, timing, gBl, gWl, gTl);
     else if (mode == kDeterministic)
-        tie ? launch_bsweep<kDeterministic, kHigherKeeps>(c, s, nV, gB, gW, gT, full, timing)
-            : launch_bsweep<kDeterministic, kLowerKeeps>(c, s, nV, gB, gW, gT, full, timing);
+        tie ? launch_bsweep<kDeterministic, kHigherKeeps>(c, s, nV, gB, gW, gT, full, timing, gBl, gWl, gTl)
+            : launch_bsweep<kDeterministic, kLowerKeeps>(c, s, nV, gB, gW, gT, full, timing, gBl, gWl, gTl);
     else
-        tie ? launch_bsweep<kTwoPhase, kHigherKeeps>(c, s, nV, gB, gW, gT, full, timing)
-            : launch_bsweep<kTwoPhase, kLowerKeeps>(c, s, nV, gB, gW, gT, full, timing);
+        tie ? launch_bsweep<kTwoPhase, kHigherKeeps>(c, s, nV, gB, gW, gT, full, timing, gBl, gWl, gTl)
+            : launch_bsweep<kTwoPhase, kLowerKeeps>(c, s, nV, gB, gW, gT, full, timing, gBl, gWl, gTl);
 }
 
 struct BatchHost {
@@ -172,6 +180,7 @@ inline int32_t run_batch(rsoc_ctx *c, int32_t G, const int64_t *vtx_off, const i
     RSOC_TRY(c->b_tasks.reserve(sizeof(int64_t) * (size_t)std::max(ntasks_all, 1)));
     RSOC_TRY(c->b_col8.reserve((size_t)nV + 64));
     if (o.mode != kOptimistic) RSOC_TRY(c->b_pend.reserve(sizeof(int32_t) * (size_t)nV));
+    else RSOC_TRY(c->b_u0mask.reserve(sizeof(uint32_t) * kTaskWords * (size_t)std::max(ntasks, 1)));
     RSOC_TRY(c->b_wl0.reserve(sizeof(int64_t) * (size_t)(nV + 1)));
     RSOC_TRY(c->b_wl1.reserve(sizeof(int64_t) * (size_t)(nV + 1)));
     RSOC_TRY(c->b_hub.reserve(sizeof(int64_t) * (size_t)(nV + 1)));
@@ -203,6 +212,7 @@ inline int32_t run_batch(rsoc_ctx *c, int32_t G, const int64_t *vtx_off, const i
     a.wl[1] = c->b_wl1.as<int64_t>();
     a.hub = c->b_hub.as<int64_t>();
     a.tasks = c->b_tasks.as<int64_t>();
+    a.u0mask = c->b_u0mask.as<uint32_t>();
     a.kg = c->b_kmax.as<int32_t>();
     a.nV = nV;
     a.hub_cap = nV + 1;
@@ -277,7 +287,7 @@ inline int32_t run_batch(rsoc_ctx *c, int32_t G, const int64_t *vtx_off, const i
         const int gTl = (int)std::max<int64_t>(1, std::min<int64_t>(div_up(nT, kStep), o.grid_list));
         hipGraphExec_t gexec = nullptr;
         RSOC_TRY(get_batch_graph(c, o.mode, o.tie, o.rounds_per_sync, gBl, gWl, gTl, &gexec));
-        launch_bsweep_dyn(c, s, o.mode, o.tie, nV, gB, gW, gTs, o.full_sweep != 0, timing);
+        launch_bsweep_dyn(c, s, o.mode, o.tie, nV, gB, gW, gTs, o.full_sweep != 0, timing, gBl, gWl, gTl);
         RSOC_LAUNCH_CHECK();
         for (;;) {
             RSOC_HIP(hipGraphLaunch(gexec, s));
@@ -358,7 +368,8 @@ inline int32_t run_batch(rsoc_ctx *c, int32_t G, const int64_t *vtx_off, const i
         }
         // round 0 (optimistic): task table 8/task, row_ptr 4(n+G), col_idx 4 nnz,
         // colours of the neighbours a vertex loses to (4 nnz/2), colour
-        // writes 4n, hub lists 8(nW+nB), U^0 appends 8|U^0| (the fused
+        // writes 4n, hub lists 8(nW+nB), U^0: a 64-byte mask per task plus
+        // 8 per listed entry of the wavefront and workgroup bins (the fused
         // launches' graphs)
         if (o.mode == kOptimistic && ntasks > 0) {
             int64_t nnzL = 0;
@@ -367,7 +378,7 @@ inline int32_t run_batch(rsoc_ctx *c, int32_t G, const int64_t *vtx_off, const i
                 if (!is_small(g)) nnzL += nnz_off[g + 1] - nnz_off[g], ++GL;
             st->bytes_round0 = 8 * (int64_t)ntasks + 4 * (nVL + GL) + 4 * nnzL +
                                (o.full_sweep ? 4 * nnzL : 4 * (nnzL / 2)) + 4 * nVL + 8 * (int64_t)(nW + nB) +
-                               (o.full_sweep ? 0 : 8 * (int64_t)h->head.u0);
+                               (o.full_sweep ? 0 : 8 * (int64_t)h->head.u0_listed + 4 * kTaskWords * (int64_t)ntasks);
         }
         (void)nnzT;
     }

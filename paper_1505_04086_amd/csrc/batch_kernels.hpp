@@ -15,6 +15,7 @@
 namespace rsoc {
 
 constexpr int kTaskLen = kStep;  // vertices per sweep task (one workgroup step)
+constexpr int kTaskWords = kTaskLen / 32;  // 32-bit words of a task's U^0 mask
 
 struct BatchArgs {
     const int64_t *voff;  // [G+1] vertex offsets of the graphs
@@ -38,6 +39,7 @@ struct BatchArgs {
     const int32_t *small; // graphs coloured by one workgroup each (k_bsmall)
     int32_t *small_stat;  // their statistics: see k_bsmall
     int32_t nsmall;
+    uint32_t *u0mask;            // optimistic round 0: per task, bit l = its l-th vertex is in U^0 (thread bin)
     int32_t nbands;              // optimistic round 0: sweep bands, kXcds per band index of an XCD
     int32_t band[kMaxBands + 1]; // band b is tasks [band[b], band[b+1]) (about equal work)
 };
@@ -249,12 +251,22 @@ __global__ __launch_bounds__(kBlock) void k_bround(const BatchArgs *__restrict__
                                                    int gB, int gW, int gT) {
     __shared__ uint32_t lds[kLdsWords];
     __shared__ int64_t q[kQueueCap];
-    __shared__ int sh_min, qn, qbase, sh_step;
+    __shared__ int sh_min, qn, qbase, sh_step, tcount;
     __shared__ unsigned long long sh_acc[2];
     __shared__ int64_t wbuf[kWavesPerBlock][kWaveBuf];
     __shared__ int wbn[kWavesPerBlock];
     const BatchArgs a = *A;
     if (!SWEEP && S->passes >= a.max_rounds) return;
+    // Optimistic round 0 records the thread-bin part of U^0 as one bit mask
+    // per task (kMaskU0) and round 1 walks those masks (kTaskList), claiming
+    // the tasks band by band as round 0 did: it then meets each graph in the
+    // same narrow ranges, on the same XCD, with the colours it reads in L2
+    // (a packed list in append order would send each XCD's round 1 to every
+    // graph of every band at once).
+    constexpr bool kMaskU0 = PHASE == kAssign && ROUND0 == 1;
+    constexpr bool kTaskList = PHASE == kRecolor && ROUND0 == 2 && !SWEEP && MODE == kOptimistic;
+    __shared__ uint32_t tmask[kMaskU0 ? kTaskWords : 1];
+    __shared__ int16_t tpos[kTaskList ? kTaskLen : 1];
     const int cT = SWEEP ? a.ntasks : S->cnt_in[kBinThread];
     const int cW = SWEEP ? S->nW : S->cnt_in[kBinWave];
     const int cB = SWEEP ? S->nB : S->cnt_in[kBinBlock];
@@ -265,9 +277,10 @@ __global__ __launch_bounds__(kBlock) void k_bround(const BatchArgs *__restrict__
     constexpr bool kAppend = PHASE != kAssign || kFlagAppend;
     constexpr bool kWrite = PHASE != kDetect;
     constexpr bool kAcct = PHASE != kAssign && !SWEEP;
+    constexpr bool kQueueT = kAppend && !kMaskU0;  // thread-bin appends go through the LDS queue
     RSOC_GLOBAL int32_t *wcolg = grw((MODE == kOptimistic) ? a.col : a.pend);
     RSOC_GLOBAL uint8_t *wcol8g = grw(a.col8);
-    uint64_t items = 0, degs = 0;
+    uint64_t items = 0, degs = 0, flagged = 0;
     const int bid = blockIdx.x;
     if (bid < gB) {
         if (threadIdx.x == 0) qn = 0;
@@ -325,10 +338,11 @@ __global__ __launch_bounds__(kBlock) void k_bround(const BatchArgs *__restrict__
         const int tb = bid - gB - gW;
         const int gi = threadIdx.x / kGroup;
         const bool leader = (threadIdx.x & (kGroup - 1)) == 0;
-        if (kAppend) {
+        if (kQueueT) {
             if (threadIdx.x == 0) qn = 0;
             __syncthreads();
         }
+        if (kMaskU0 && threadIdx.x < kTaskWords) tmask[threadIdx.x] = 0;
         // SWEEP: one task (a chunk of one graph) per workgroup step;
         // worklist rounds: kStep packed items per step.
         // Optimistic round 0 claims its tasks band by band (claim_task).  A
@@ -336,8 +350,10 @@ __global__ __launch_bounds__(kBlock) void k_bround(const BatchArgs *__restrict__
         // over a long sweep: the tasks in flight then span many graphs at once,
         // whose colour gathers (random ids in a geometric graph) evict one
         // another from L2, and the rounds read several times the bytes.
-        constexpr bool kClaim = SWEEP && ROUND0 == 1;
-        const int64_t nsteps = SWEEP ? (int64_t)cT : ((int64_t)cT + kStep - 1) / kStep;
+        constexpr bool kClaim = (SWEEP && ROUND0 == 1) || kTaskList;
+        const int64_t nsteps = SWEEP       ? (int64_t)a.ntasks
+                               : kTaskList ? (cT > 0 ? (int64_t)a.ntasks : 0)
+                                           : ((int64_t)cT + kStep - 1) / kStep;
         int64_t step = tb;
         int bands_done = 0;
         if (kClaim) {
@@ -350,17 +366,75 @@ __global__ __launch_bounds__(kBlock) void k_bround(const BatchArgs *__restrict__
             // trip overlaps this task's loads)
             int next = 0;
             if (kClaim && threadIdx.x == 0) next = claim_task(a, S, home_band(a, bid), &bands_done);
-            int tg = 0, tstart = 0, tlen = 0;
+            int tg = 0, tstart = 0, tlen = 0, tcur = 0;
             GraphView tw = {};
-            if (SWEEP) {
-                const int t = (kFlagAppend && TIE == kHigherKeeps) ? (int)(nsteps - 1 - step) : (int)step;
-                const int64_t task = a.tasks[t];
+            if (SWEEP || kTaskList) {
+                tcur = ((kFlagAppend || kTaskList) && TIE == kHigherKeeps) ? (int)(nsteps - 1 - step) : (int)step;
+                const int64_t task = a.tasks[tcur];
                 tg = item_graph(task);
                 tstart = item_vertex(task);
                 tw = graph_view(a, tg);
                 tlen = min(kTaskLen, tw.n - tstart);
             }
-            for (int r = 0; r < kChunk; ++r) {
+            if (kTaskList) {
+                // the task's U^0 positions, compacted in LDS by the first wavefront
+                if (threadIdx.x < kWave) {
+                    const uint32_t m = threadIdx.x < kTaskWords
+                                           ? gro(a.u0mask)[(int64_t)tcur * kTaskWords + threadIdx.x] : 0u;
+                    int incl = __popc(m);
+#pragma unroll
+                    for (int d = 1; d < kTaskWords; d <<= 1) {
+                        const int o = __shfl_up(incl, d);
+                        if (lane_id() >= d) incl += o;
+                    }
+                    int k = incl - __popc(m);
+                    for (uint32_t mm = m; mm; mm &= mm - 1) tpos[k++] = (int16_t)(threadIdx.x * 32 + __builtin_ctz(mm));
+                    if (threadIdx.x == kTaskWords - 1) tcount = incl;
+                }
+                __syncthreads();
+                const int cnt = tcount;
+                for (int base = 0; base < cnt; base += kSub) {
+                    int v[kNV], b[kNV], e[kNV], cv[kNV], nc[kNV];
+                    bool act[kNV];
+                    uint32_t unc[kNV] = {};
+                    const RSOC_GLOBAL int32_t *cis[kNV];
+                    const RSOC_GLOBAL uint8_t *c8s[kNV];
+#pragma unroll
+                    for (int i = 0; i < kNV; ++i) {
+                        const int idx = base + i * kGpb + gi;
+                        v[i] = -1;
+                        b[i] = e[i] = 0;
+                        cis[i] = tw.ci;
+                        c8s[i] = tw.col8;
+                        if (idx < cnt) {
+                            const int li = tpos[idx];
+                            v[i] = TIE == kHigherKeeps ? tstart + tlen - 1 - li : tstart + li;
+                            b[i] = tw.rp[v[i]];
+                            e[i] = tw.rp[v[i] + 1];
+                        }
+                        cv[i] = v[i] >= 0 ? (int)tw.col8[v[i]] : 255;
+                    }
+                    group_vertices<kRecolor, TIE, kGroup, kGroupSlots, false, kNV>(v, b, e, cis, c8s, cv, a.look, nc,
+                                                                                   act, unc);
+#pragma unroll
+                    for (int i = 0; i < kNV; ++i) {
+                        if (v[i] < 0) act[i] = false;
+                        if (leader && v[i] >= 0) {
+                            items += 1;
+                            degs += (uint64_t)(e[i] - b[i]);
+                            if (act[i]) {
+                                wcolg[tw.voff + v[i]] = nc[i];
+                                wcol8g[tw.voff + v[i]] = (uint8_t)nc[i];
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int i = 0; i < kNV; ++i) queue_push64(act[i] && leader, pack_item(tg, v[i]), q, &qn);
+                    const int cq = queue_size(&qn);
+                    if (cq > kQueueCap - kSub) queue_flush64_n(cq, q, &qn, &qbase, &S->cnt_out[kBinThread], out);
+                }
+            }
+            for (int r = 0; r < (kTaskList ? 0 : kChunk); ++r) {
                 int v[kNV], b[kNV], e[kNV], cv[kNV], nc[kNV], gg[kNV];
                 bool act[kNV];
                 uint32_t unc[kNV] = {};
@@ -420,7 +494,16 @@ __global__ __launch_bounds__(kBlock) void k_bround(const BatchArgs *__restrict__
                         }
                     }
                 }
-                if (kAppend) {
+                if (kMaskU0) {
+#pragma unroll
+                    for (int i = 0; i < kNV; ++i)
+                        if (leader && unc[i] != 0) {
+                            const int li = step_offset(r, i, gi, a.chunk);
+                            atomicOr(&tmask[li >> 5], 1u << (li & 31));
+                            flagged += 1;
+                        }
+                }
+                if (kQueueT) {
 #pragma unroll
                     for (int i = 0; i < kNV; ++i)
                         queue_push64((kFlagAppend ? unc[i] != 0 : act[i]) && leader, pack_item(gg[i], v[i]), q, &qn);
@@ -429,15 +512,24 @@ __global__ __launch_bounds__(kBlock) void k_bround(const BatchArgs *__restrict__
                 }
             }
             if (kClaim) {
-                __syncthreads();  // every thread has read sh_step
+                __syncthreads();  // every thread has read sh_step (and set its flags in tmask)
                 if (threadIdx.x == 0) sh_step = next;
+                if (kMaskU0 && threadIdx.x < kTaskWords) {
+                    a.u0mask[(int64_t)tcur * kTaskWords + threadIdx.x] = tmask[threadIdx.x];
+                    tmask[threadIdx.x] = 0;  // cleared before the barrier that opens the next task
+                }
                 __syncthreads();
                 step = sh_step < 0 ? nsteps : sh_step;
             } else {
                 step += gT;
             }
         }
-        if (kAppend) queue_flush64(q, &qn, &qbase, &S->cnt_out[kBinThread], out);
+        if (kQueueT) queue_flush64(q, &qn, &qbase, &S->cnt_out[kBinThread], out);
+    }
+    if (kMaskU0) {
+        // |U^0|'s thread-bin part (the masks hold the entries themselves)
+        flagged = wave_sum_u64(flagged);
+        if (lane_id() == 0 && flagged) atomicAdd(&S->cnt_out[kBinThread], (int)flagged);
     }
     if (kAcct) {
         if (threadIdx.x == 0) { sh_acc[0] = 0; sh_acc[1] = 0; }
@@ -495,6 +587,8 @@ __global__ void k_bround_end(const BatchArgs *__restrict__ A, SingleState *S) {
     if (threadIdx.x != 0) return;
     if (PUBLISH_ONLY) {
         S->u0 = S->cnt_out[0] + S->cnt_out[1] + S->cnt_out[2];
+        S->u0_listed = S->cnt_out[1] + S->cnt_out[2];
+        for (int x = 0; x < kMaxBands; ++x) S->next_task[x] = 0;  // round 1 claims the tasks again
         for (int b = 0; b < 3; ++b) {
             S->cnt_in[b] = S->cnt_out[b];
             S->cnt_out[b] = 0;

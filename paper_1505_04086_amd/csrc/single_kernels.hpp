@@ -94,7 +94,8 @@ struct SingleState {
     int32_t nH;           // hubs coloured before round 0 (0: none, or the hub-first pass is off)
     int32_t nHc;          // vertices above the hub threshold (k_args; the pass is off above kHubCap)
     int32_t hub_t;        // the hub threshold in use (k_args)
-    int32_t next_task[kMaxBands];  // tasks handed out so far per band (batched optimistic round 0)
+    int32_t next_task[kMaxBands];  // tasks handed out so far per band (batched optimistic rounds 0 and 1)
+    int32_t u0_listed;    // batched: the part of |U^0| kept as list entries (wavefront and workgroup bins)
     int32_t hist[kHistCap];  // |L| of recolouring round i+1
     // worklist rounds' inspection counts (inspected, degree sum), spread over
     // kAccSlots cache lines so that a round's workgroups do not all add to one

@@ -34,7 +34,10 @@ BATCH = gg.concat(GRAPHS)
 # the fused launches run with that path off, and "small64" divides the batch
 SPLITS = {"default": {}, "allbins": {"t_thread": 3, "t_wave": 8, "small_cutoff": -1},
           "runs1": {"chunk": 1, "grid_thread": 7, "grid_list": 2, "small_cutoff": -1},
-          "runs8": {"chunk": 8, "grid_thread": 3, "small_cutoff": -1}, "small64": {"small_cutoff": 64}}
+          "runs8": {"chunk": 8, "grid_thread": 3, "small_cutoff": -1}, "small64": {"small_cutoff": 64},
+          # optimistic round 0's task bands: one per XCD; 128 bands over a grid
+          # of 5 workgroups (most bands start with no workgroup of their own)
+          "bands1": {"bands": 1, "small_cutoff": -1}, "bands16": {"bands": 16, "grid_thread": 5, "small_cutoff": -1}}
 
 
 def _n_small(opts):
@@ -96,6 +99,16 @@ def test_batch_optimistic_valid(lib, ctx, tie, full_sweep, split):
         assert oracle.check(grp, gci, c) == 0, g
         assert counts[g] == oracle.colour_count(c)
     assert st["small_graphs"] == _n_small(SPLITS[split])
+    if not full_sweep:
+        # round 1 inspects every vertex of U^0 (its thread-bin part walked from
+        # round 0's per-task masks), and U^0 only holds vertices of the fused
+        # launches' graphs
+        n_fused = sum(len(grp) - 1 for grp, _ in GRAPHS) - sum(
+            len(grp) - 1 for grp, _ in GRAPHS if 0 < len(grp) - 1 <= {-1: 0, 0: 2048}.get(
+                SPLITS[split].get("small_cutoff", 0), SPLITS[split].get("small_cutoff", 0)))
+        assert 0 <= st["worklist0"] <= n_fused
+        if st["worklist0"]:
+            assert st["inspected"] >= st["worklist0"]
 
 
 def test_batch_equals_single_calls(lib, ctx):
@@ -147,7 +160,8 @@ def test_batch_pass_bound(lib, ctx, cutoff):
 
 def test_batch_small_graphs_only_and_option_checked(lib, ctx):
     """A batch of small graphs only (no fused launch at all), optimistic and
-    round-synchronous; cutoffs beyond 2048 are refused."""
+    round-synchronous; cutoffs beyond 2048 and band counts outside 1..16 are
+    refused."""
     graphs = [gg.complete(12), gg.star(50), gg.tri_grid(20, 9, permute_seed=2), gg.rmat(8, 8, seed=3, shuffle_seed=4)]
     b = gg.concat(graphs)
     rp, ci, col = _upload(lib, b)
@@ -161,6 +175,7 @@ def test_batch_small_graphs_only_and_option_checked(lib, ctx):
                 assert np.array_equal(c, oracle.rsync(grp, gci)["colors"]), g
             else:
                 assert oracle.check(grp, gci, c) == 0 and counts[g] == oracle.colour_count(c), g
-    with pytest.raises(lib.RsocError) as e:
-        lib.rsoc_color_batch(ctx, b["vtx_off"], b["nnz_off"], rp, ci, col, lib.make_options(small_cutoff=2049))
-    assert e.value.code == lib.RSOC_EINVAL
+    for bad in ({"small_cutoff": 2049}, {"bands": 17}, {"bands": -1}):
+        with pytest.raises(lib.RsocError) as e:
+            lib.rsoc_color_batch(ctx, b["vtx_off"], b["nnz_off"], rp, ci, col, lib.make_options(**bad))
+        assert e.value.code == lib.RSOC_EINVAL, bad
