@@ -101,7 +101,9 @@ typedef struct {
     /* tuning; 0 selects the library default (or the tuned value) */
     int32_t t_thread;    /* max degree coloured by a group of 8 lanes (<= 32; default 32) */
     int32_t t_wave;      /* max degree coloured by one wavefront; larger rows use a workgroup (default 2048) */
-    int32_t grid_thread; /* workgroups given to the thread bin per round launch (default 1024) */
+    int32_t grid_thread; /* workgroups given to the thread bin per round launch (default 1024; 4096 for
+                          * rsoc_color_batch's optimistic rounds 0 and 1, whose workgroups claim tasks
+                          * from counters, so that extra ones only wait) */
     int32_t grid_wave;   /* workgroups given to the wavefront bin (default 2048) */
     int32_t rounds_per_sync; /* rounds enqueued (as one HIP graph) per host check of the worklist (default 4, even) */
     /* rsoc_color_batch: graphs of at most this many vertices (at most 2048;

@@ -3,6 +3,7 @@
 // with the same round structure as the single-graph driver.
 #pragma once
 
+#include <cmath>
 #include <vector>
 
 #include "batch_kernels.hpp"
@@ -158,22 +159,32 @@ inline int32_t run_batch(rsoc_ctx *c, int32_t G, const int64_t *vtx_off, const i
     std::vector<int32_t> small;
     // sweep tasks: (graph, first vertex) chunks of kTaskLen vertices, in graph
     // order; the fused launches' graphs first, then the small graphs' (which
-    // only validation and the colour count walk)
-    std::vector<int64_t> tasks;
-    tasks.reserve((size_t)(nV / kTaskLen + G + 1));
-    int64_t nVL = 0;
-    for (int pass = 0; pass < 2; ++pass)
-        for (int g = 0; g < G; ++g) {
-            if (is_small(g) != (pass == 1)) continue;
-            if (pass == 1) small.push_back(g);
-            else nVL += vtx_off[g + 1] - vtx_off[g];
-            for (int64_t st0 = 0; st0 < vtx_off[g + 1] - vtx_off[g]; st0 += kTaskLen)
-                tasks.push_back(((int64_t)g << 32) | (uint32_t)st0);
+    // only validation and the colour count walk).  Written straight into
+    // pinned memory, so that the upload is one DMA.
+    int64_t nVL = 0, nt_large = 0, nt_small = 0;
+    for (int g = 0; g < G; ++g) {
+        const int64_t k = (vtx_off[g + 1] - vtx_off[g] + kTaskLen - 1) / kTaskLen;
+        if (is_small(g)) {
+            small.push_back(g);
+            nt_small += k;
+        } else {
+            nVL += vtx_off[g + 1] - vtx_off[g];
+            nt_large += k;
         }
-    if (tasks.size() > (size_t)INT32_MAX) return RSOC_EINVAL;
-    const int ntasks_all = (int)tasks.size();
-    int ntasks = 0;
-    for (int64_t x : tasks) ntasks += !is_small((int)(x >> 32));
+    }
+    if (nt_large + nt_small > INT32_MAX) return RSOC_EINVAL;
+    const int ntasks = (int)nt_large;
+    const int ntasks_all = (int)(nt_large + nt_small);
+    RSOC_TRY(c->b_tasks_host.reserve(sizeof(int64_t) * (size_t)std::max(ntasks_all, 1)));
+    int64_t *const tasks = c->b_tasks_host.as<int64_t>();
+    {
+        int64_t wl = 0, ws = nt_large;
+        for (int g = 0; g < G; ++g) {
+            int64_t &w = is_small(g) ? ws : wl;
+            for (int64_t st0 = 0; st0 < vtx_off[g + 1] - vtx_off[g]; st0 += kTaskLen)
+                tasks[w++] = ((int64_t)g << 32) | (uint32_t)st0;
+        }
+    }
     const int nsmall = (int)small.size();
     constexpr int kSmallStatInts = kSmallStatHist + kSmallMax + 2;
     RSOC_TRY(c->b_desc.reserve(sizeof(int64_t) * 2 * (size_t)(G + 1)));
@@ -192,7 +203,7 @@ inline int32_t run_batch(rsoc_ctx *c, int32_t G, const int64_t *vtx_off, const i
     int64_t *d_noff = d_voff + (G + 1);
     RSOC_HIP(hipMemcpyAsync(d_voff, vtx_off, sizeof(int64_t) * (size_t)(G + 1), hipMemcpyHostToDevice, s));
     RSOC_HIP(hipMemcpyAsync(d_noff, nnz_off, sizeof(int64_t) * (size_t)(G + 1), hipMemcpyHostToDevice, s));
-    RSOC_HIP(hipMemcpyAsync(c->b_tasks.p, tasks.data(), sizeof(int64_t) * (size_t)ntasks_all, hipMemcpyHostToDevice,
+    RSOC_HIP(hipMemcpyAsync(c->b_tasks.p, tasks, sizeof(int64_t) * (size_t)ntasks_all, hipMemcpyHostToDevice,
                             s));
     if (nsmall)
         RSOC_HIP(hipMemcpyAsync(d_small, small.data(), sizeof(int32_t) * (size_t)nsmall, hipMemcpyHostToDevice, s));
@@ -230,23 +241,33 @@ inline int32_t run_batch(rsoc_ctx *c, int32_t G, const int64_t *vtx_off, const i
     a.chunk = 1;
     // round 0's bands (claim_task): ranges of the fused launches' tasks of
     // about equal work, a task's work taken as its vertices times one plus
-    // its graph's mean degree
+    // its graph's mean degree (a graph's tasks then weigh n_g + nnz_g in all);
+    // band x starts at the first task with at least x/nbands of the work
+    // before it
     a.nbands = kXcds * o.bands;
     {
-        std::vector<double> work((size_t)ntasks + 1, 0.0);
-        for (int t = 0; t < ntasks; ++t) {
-            const int g = (int)(tasks[(size_t)t] >> 32);
-            const int64_t ng = vtx_off[g + 1] - vtx_off[g];
-            const int64_t len = std::min<int64_t>(kTaskLen, ng - (int64_t)(uint32_t)tasks[(size_t)t]);
-            const double deg = ng > 0 ? (double)(nnz_off[g + 1] - nnz_off[g]) / (double)ng : 0.0;
-            work[(size_t)t + 1] = work[(size_t)t] + (double)len * (1.0 + deg);
+        double total = 0;
+        for (int g = 0; g < G; ++g)
+            if (!is_small(g)) total += (double)(vtx_off[g + 1] - vtx_off[g] + nnz_off[g + 1] - nnz_off[g]);
+        int x = 1;
+        double before = 0;  // work of the graphs before g
+        int64_t t0 = 0;     // their tasks
+        a.band[0] = 0;
+        for (int g = 0; g < G && x < a.nbands; ++g) {
+            if (is_small(g)) continue;
+            const int64_t n = vtx_off[g + 1] - vtx_off[g];
+            const int64_t k = (n + kTaskLen - 1) / kTaskLen;
+            const double gw = (double)(n + nnz_off[g + 1] - nnz_off[g]);
+            const double per_task = n > 0 ? kTaskLen * gw / (double)n : 0.0;
+            for (; x < a.nbands && total * x / a.nbands <= before + gw; ++x) {
+                const double need = total * x / a.nbands - before;
+                int64_t j = per_task > 0 ? (int64_t)std::ceil(need / per_task) : 0;
+                a.band[x] = (int)(t0 + std::min(std::max<int64_t>(j, 0), k));
+            }
+            before += gw;
+            t0 += k;
         }
-        int t = 0;
-        for (int x = 0; x <= a.nbands; ++x) {
-            const double target = work[(size_t)ntasks] * x / a.nbands;
-            while (t < ntasks && work[(size_t)t] < target) ++t;
-            a.band[x] = x == a.nbands ? ntasks : t;
-        }
+        for (; x <= a.nbands; ++x) a.band[x] = ntasks;
     }
     SingleState *S = c->b_state.as<SingleState>();
     RSOC_HIP(hipMemcpyAsync(c->b_args.p, &a, sizeof(a), hipMemcpyHostToDevice, s));
@@ -277,7 +298,10 @@ inline int32_t run_batch(rsoc_ctx *c, int32_t G, const int64_t *vtx_off, const i
         a.offB = nT + nW;
         const int gB = std::min(nB, 1024);
         const int gW = std::min(div_up(nW, kWavesPerBlock), o.grid_wave);
-        const int gTs = std::max(1, std::min(ntasks, o.grid_thread));
+        // the optimistic default flow's sweeps claim their tasks (claim_task):
+        // a grid beyond the resident workgroups costs nothing there
+        const bool claims = o.mode == kOptimistic && !o.full_sweep;
+        const int gTs = std::max(1, std::min(ntasks, (claims && !o.grid_thread_given) ? 4096 : o.grid_thread));
         const int64_t look = o.lookahead == -1 ? 0 : (o.lookahead > 0 ? o.lookahead : 2ll * gTs * kStep);
         a.look = (int)std::min<int64_t>(look, INT32_MAX);
         a.chunk = pick_chunk(o.chunk, h->head.near, h->head.sampled);

@@ -103,6 +103,7 @@ constexpr int kDefaultBandsPerXcd = 4;
 struct Options {
     int mode, tie, max_rounds, validate, t_thread, t_wave, grid_thread, grid_wave, rounds_per_sync,
         timing, full_sweep, lookahead, chunk, grid_list, tail, distance, grid_bin, hub_first, small_cutoff, bands;
+    bool grid_thread_given;  // grid_thread came from the caller (not the default)
 };
 
 inline int32_t resolve_options(const rsoc_options *o, int64_t n, Options &r) {
@@ -138,6 +139,7 @@ inline int32_t resolve_options(const rsoc_options *o, int64_t n, Options &r) {
     r.t_wave = d.t_wave ? d.t_wave : 2048;
     if (r.t_wave < r.t_thread) r.t_wave = r.t_thread;
     r.grid_thread = d.grid_thread ? d.grid_thread : 1024;
+    r.grid_thread_given = d.grid_thread != 0;
     r.grid_wave = d.grid_wave ? d.grid_wave : 2048;
     r.grid_list = d.grid_list ? d.grid_list : 1024;
     r.rounds_per_sync = d.rounds_per_sync ? d.rounds_per_sync : 4;

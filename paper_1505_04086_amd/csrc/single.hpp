@@ -34,6 +34,7 @@ struct rsoc_ctx {
     rsoc::DevBuf sq_t, sq_rp, sq_ci, sq_misc, sq_big;  // G^2 for distance-2 colouring (square.hpp)
     rsoc::DevBuf args, state;     // SingleArgs, SingleState (fixed addresses: graphs point at them)
     rsoc::HostPinned host;        // pinned staging for small copies
+    rsoc::HostPinned b_tasks_host;  // a batch's task table on its way to the device
     rsoc::DevBuf drp, dci, dcol;  // device copies for host-pointer calls
     std::map<std::tuple<int, int, int, int, int, int, int>, hipGraphExec_t> graphs;
     hipEvent_t ev[8] = {};
@@ -81,6 +82,7 @@ inline void ctx_free(rsoc_ctx *c) {
                             &c->b_state, &c->b_hub, &c->b_kmax, &c->b_tasks, &c->b_args, &c->b_col8, &c->b_small})
         b->release();
     c->host.release();
+    c->b_tasks_host.release();
     if (c->own) (void)hipStreamDestroy(c->own);
     if (c->cap) (void)hipStreamDestroy(c->cap);
 }
