@@ -143,7 +143,7 @@ class Server:
 
     def __init__(self, ctx: rsoc.Context, hbm_budget: int = 16 << 30, scratch_share: float = 0.35,
                  max_slots: int = 512, options=None, device: int = 0, admit_per_poll: int = 32,
-                 solo_when_idle: bool = True, solo_backlog: int = 32):
+                 solo_when_idle: bool = True, solo_backlog: int = 32, idle_spin_s: float = 2e-4):
         self.ctx = ctx
         self.dev = torch.device("cuda", device)
         self.scratch_cap = int(hbm_budget * scratch_share)
@@ -172,6 +172,10 @@ class Server:
         self.solo_when_idle = solo_when_idle
         self.solo_backlog = solo_backlog
         self.solo = 0
+        # an idle server sleeps until idle_spin_s before the next arrival and
+        # polls from there on: a sleep ends tens of microseconds past its
+        # deadline, which a request arriving at the deadline would wait out
+        self.idle_spin_s = idle_spin_s
         self.inflight = False  # a pool round launched and not yet waited for
 
     # -- admission ------------------------------------------------------
@@ -346,7 +350,9 @@ class Server:
             while pending and pending[0].arrival <= now:
                 self.submit(pending.popleft())
             if self.idle() and pending:
-                time.sleep(max(0.0, min(pending[0].arrival - now, 0.001)))
+                wait = pending[0].arrival - now
+                if wait > self.idle_spin_s:
+                    time.sleep(min(wait - self.idle_spin_s, 0.001))
                 continue
             self.poll()
         return self.finished
