@@ -597,6 +597,9 @@ def bench_batched(args):
     tp = (time.perf_counter() - tp) / args.plain_reps
     st = stats[-1]
     kms = float(np.mean([x["ms_round0"] for x in stats]))
+    # the launch options in effect (the run length as the library chose it
+    # when the options leave it open), which the counters are keyed by
+    launch = dict(args.tuned or {}, chunk=st["chunk"])
     kbytes = st["bytes_round0"]
     achieved = kbytes / (kms * 1e-3) / 1e9 if kms > 0 else None
     value = E * args.steps / elapsed / 1e9
@@ -615,7 +618,7 @@ def bench_batched(args):
         "batched_over_plain": value / (E / tp / 1e9),
         "roofline": {"bound": "hbm", "kernel": "batched_round0_first_fit", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": None if achieved is None else achieved / HBM_PEAK_GBS,
-                     "traffic": load_traffic("batched", "batched_round0_first_fit", args.tuned), "kernel_ms": kms,
+                     "traffic": load_traffic("batched", "batched_round0_first_fit", launch), "kernel_ms": kms,
                      "alg_bytes_per_launch": kbytes},
     }
     ctx.close()
