@@ -208,7 +208,7 @@ typedef struct {
     int32_t *per_round_L;    /* optional caller array: per_round_L[i] = |L| of recolouring round i+1 */
     int32_t per_round_cap;   /* its length */
     int32_t worklist0;       /* |U^0|: vertices round 1 inspects */
-    int32_t chunk;           /* run length used by the sweeps */
+    int32_t chunk;           /* run length used by the sweeps (rsoc_color_batch: 0 when chosen per graph) */
     int32_t small_graphs;    /* rsoc_color_batch: graphs coloured by one workgroup each (small_cutoff) */
     int32_t *per_round_U;    /* optional caller array of per_round_cap entries: per_round_U[i] = |U| of
                                 inspection pass i+1 (U^0, then the previous round's L), for the passes run */

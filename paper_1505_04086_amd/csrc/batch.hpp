@@ -239,6 +239,18 @@ inline int32_t run_batch(rsoc_ctx *c, int32_t G, const int64_t *vtx_off, const i
     a.max_rounds = o.max_rounds;
     a.look = 0;
     a.chunk = 1;
+    // run length: the option's for every graph, else each sweep task takes
+    // its graph's, chosen on the device (k_bchunk), and the worklist rounds
+    // walk their lists in runs of kChunk: a list keeps the order in which a
+    // grid's vertices were appended, and neighbouring groups taking
+    // consecutive entries would recolour adjacent vertices at the same
+    // instant (25 rounds instead of 7 on the 4096-graph batch)
+    if (o.chunk == 0) {
+        RSOC_TRY(c->b_gchunk.reserve((size_t)std::max(G, 1)));
+        a.gchunk = c->b_gchunk.as<uint8_t>();
+    } else {
+        a.gchunk = nullptr;
+    }
     // round 0's bands (claim_task): ranges of the fused launches' tasks of
     // about equal work, a task's work taken as its vertices times one plus
     // its graph's mean degree (a graph's tasks then weigh n_g + nnz_g in all);
@@ -280,10 +292,7 @@ inline int32_t run_batch(rsoc_ctx *c, int32_t G, const int64_t *vtx_off, const i
         RSOC_LAUNCH_CHECK();
     }
     if (ntasks > 0) k_bbin<<<tgrid, kBlock, 0, s>>>(c->b_args.as<BatchArgs>(), S);
-    if (o.chunk == 0 && ntasks > 0) {
-        const int ns = std::min(ntasks, 16384);
-        k_blocality<<<div_up(ns, kBlock), kBlock, 0, s>>>(c->b_args.as<BatchArgs>(), ns, S);
-    }
+    if (o.chunk == 0 && ntasks > 0) k_bchunk<<<div_up(G, kWavesPerBlock), kBlock, 0, s>>>(c->b_args.as<BatchArgs>());
     RSOC_LAUNCH_CHECK();
     RSOC_HIP(hipMemcpyAsync(&h->head, S, kStateHeader, hipMemcpyDeviceToHost, s));
     RSOC_HIP(hipStreamSynchronize(s));
@@ -304,7 +313,7 @@ inline int32_t run_batch(rsoc_ctx *c, int32_t G, const int64_t *vtx_off, const i
         const int gTs = std::max(1, std::min(ntasks, (claims && !o.grid_thread_given) ? 4096 : o.grid_thread));
         const int64_t look = o.lookahead == -1 ? 0 : (o.lookahead > 0 ? o.lookahead : 2ll * gTs * kStep);
         a.look = (int)std::min<int64_t>(look, INT32_MAX);
-        a.chunk = pick_chunk(o.chunk, h->head.near, h->head.sampled);
+        a.chunk = o.chunk ? o.chunk : kChunk;
         RSOC_HIP(hipMemcpyAsync(c->b_args.p, &a, sizeof(a), hipMemcpyHostToDevice, s));
         const int gBl = std::min(nB, 256);
         const int gWl = std::min(div_up(nW, kWavesPerBlock), o.grid_wave);
@@ -379,7 +388,7 @@ inline int32_t run_batch(rsoc_ctx *c, int32_t G, const int64_t *vtx_off, const i
         st->bin_counts[1] = nW;
         st->bin_counts[2] = nB;
         st->worklist0 = h->head.u0;
-        st->chunk = a.chunk;
+        st->chunk = a.gchunk ? 0 : a.chunk;
         st->small_graphs = nsmall;
         float ms = 0;
         RSOC_HIP(hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));

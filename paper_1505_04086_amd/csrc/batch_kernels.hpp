@@ -40,6 +40,7 @@ struct BatchArgs {
     int32_t *small_stat;  // their statistics: see k_bsmall
     int32_t nsmall;
     uint32_t *u0mask;            // optimistic round 0: per task, bit l = its l-th vertex is in U^0 (thread bin)
+    uint8_t *gchunk;             // [G] run length of each graph's sweeps, when the option leaves it open (else null)
     int32_t nbands;              // optimistic round 0: sweep bands, kXcds per band index of an XCD
     int32_t band[kMaxBands + 1]; // band b is tasks [band[b], band[b+1]) (about equal work)
 };
@@ -171,23 +172,22 @@ __global__ __launch_bounds__(kBlock) void k_bbin(const BatchArgs *__restrict__ A
         atomicMax(&S->maxdeg, md);
 }
 
-// Id-locality sample over the batch: the first vertex of ns tasks spread
-// evenly over the task table.
-__global__ __launch_bounds__(kBlock) void k_blocality(const BatchArgs *__restrict__ A, int ns, SingleState *S) {
+// Run length per graph (the option chunk = 0): one wavefront per graph reads
+// up to 64 rows spread over the graph and picks kChunk when at least 2 % of
+// their entries join ids less than kChunk apart (a grid in natural order),
+// else 1 (random ids, where runs only spread a wavefront's rows and writes
+// over more cache lines).
+__global__ __launch_bounds__(kBlock) void k_bchunk(const BatchArgs *__restrict__ A) {
     const BatchArgs a = *A;
+    const int g = (int)(blockIdx.x * kWavesPerBlock + threadIdx.x / kWave);
+    if (g >= a.G) return;
+    const GraphView w = graph_view(a, g);
     uint64_t near = 0, sampled = 0;
-    const int k = blockIdx.x * kBlock + threadIdx.x;
-    if (k < ns) {
-        const int64_t task = a.tasks[(int)((int64_t)k * a.ntasks / ns)];
-        const GraphView w = graph_view(a, item_graph(task));
-        locality_row(w.rp, w.ci, item_vertex(task), w.rp[w.n], near, sampled);
-    }
+    const int ns = min(w.n, kWave);
+    if (lane_id() < ns) locality_row(w.rp, w.ci, (int)((int64_t)lane_id() * w.n / ns), w.rp[w.n], near, sampled);
     near = wave_sum_u64(near);
     sampled = wave_sum_u64(sampled);
-    if (lane_id() == 0 && sampled) {
-        atomicAdd((unsigned long long *)&S->near, (unsigned long long)near);
-        atomicAdd((unsigned long long *)&S->sampled, (unsigned long long)sampled);
-    }
+    if (lane_id() == 0) a.gchunk[g] = (uint8_t)pick_chunk(0, near, sampled);
 }
 
 __global__ __launch_bounds__(kBlock) void k_bvalidate(const BatchArgs *__restrict__ A, int32_t *err) {
@@ -376,6 +376,7 @@ __global__ __launch_bounds__(kBlock) void k_bround(const BatchArgs *__restrict__
                 tw = graph_view(a, tg);
                 tlen = min(kTaskLen, tw.n - tstart);
             }
+            const int tchunk = (SWEEP && a.gchunk) ? (int)a.gchunk[tg] : a.chunk;
             if (kTaskList) {
                 // the task's U^0 positions, compacted in LDS by the first wavefront
                 if (threadIdx.x < kWave) {
@@ -446,7 +447,7 @@ __global__ __launch_bounds__(kBlock) void k_bround(const BatchArgs *__restrict__
                     v[i] = -1;
                     b[i] = e[i] = 0;
                     gg[i] = 0;
-                    const int li = step_offset(r, i, gi, a.chunk);
+                    const int li = step_offset(r, i, gi, tchunk);
                     if (SWEEP) {
                         if (li < tlen) v[i] = (kFlagAppend && TIE == kHigherKeeps) ? tstart + tlen - 1 - li : tstart + li;
                         gg[i] = tg;
@@ -498,7 +499,7 @@ __global__ __launch_bounds__(kBlock) void k_bround(const BatchArgs *__restrict__
 #pragma unroll
                     for (int i = 0; i < kNV; ++i)
                         if (leader && unc[i] != 0) {
-                            const int li = step_offset(r, i, gi, a.chunk);
+                            const int li = step_offset(r, i, gi, tchunk);
                             atomicOr(&tmask[li >> 5], 1u << (li & 31));
                             flagged += 1;
                         }

@@ -39,7 +39,7 @@ struct rsoc_ctx {
     std::map<std::tuple<int, int, int, int, int, int, int>, hipGraphExec_t> graphs;
     hipEvent_t ev[8] = {};
     // batched path scratch (batch.hpp)
-    rsoc::DevBuf b_desc, b_wl0, b_wl1, b_pend, b_u0mask, b_state, b_hub, b_kmax, b_tasks, b_args, b_col8, b_small;
+    rsoc::DevBuf b_desc, b_wl0, b_wl1, b_pend, b_u0mask, b_gchunk, b_state, b_hub, b_kmax, b_tasks, b_args, b_col8, b_small;
     int32_t *b_colp = nullptr;
 };
 
@@ -78,7 +78,7 @@ inline void ctx_free(rsoc_ctx *c) {
         if (e) (void)hipEventDestroy(e);
     for (rsoc::DevBuf *b : {&c->col8, &c->col4, &c->aux, &c->mark, &c->tail, &c->hubs, &c->cls_h, &c->cls_p, &c->cls_st,
                             &c->sq_t, &c->sq_rp, &c->sq_ci, &c->sq_misc, &c->sq_big, &c->wl0, &c->wl1, &c->hubW, &c->hubB, &c->pend, &c->flags, &c->args, &c->state, &c->drp,
-                            &c->dci, &c->dcol, &c->b_desc, &c->b_wl0, &c->b_wl1, &c->b_pend, &c->b_u0mask,
+                            &c->dci, &c->dcol, &c->b_desc, &c->b_wl0, &c->b_wl1, &c->b_pend, &c->b_u0mask, &c->b_gchunk,
                             &c->b_state, &c->b_hub, &c->b_kmax, &c->b_tasks, &c->b_args, &c->b_col8, &c->b_small})
         b->release();
     c->host.release();

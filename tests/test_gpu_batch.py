@@ -99,6 +99,8 @@ def test_batch_optimistic_valid(lib, ctx, tie, full_sweep, split):
         assert oracle.check(grp, gci, c) == 0, g
         assert counts[g] == oracle.colour_count(c)
     assert st["small_graphs"] == _n_small(SPLITS[split])
+    # the run length: the option's, or 0 when each graph's is chosen on the device
+    assert st["chunk"] == SPLITS[split].get("chunk", 0)
     if not full_sweep:
         # round 1 inspects every vertex of U^0 (its thread-bin part walked from
         # round 0's per-task masks), and U^0 only holds vertices of the fused
