@@ -160,9 +160,9 @@ typedef struct {
      * list-shaped inputs (a recolouring's first worklist): 0 = library
      * default (1024 for a single graph and a pool slot, up to 8192 for a
      * batch).  Each such workgroup walks its share of the ids and appends to
-     * workgroup queues in LDS; a small value makes every workgroup's queue
-     * fill and flush many times, which tests use to reach those flushes on
-     * small graphs. */
+     * queues in LDS (one per workgroup; one per wavefront in a batch); a small
+     * value makes every queue fill and flush many times, which tests use to
+     * reach those flushes on small graphs. */
     int32_t grid_bin;
     /* Optimistic mode, default round-0 flow, single-graph entry points: the
      * vertices of degree above this threshold ("hubs"; 0 = library default,

@@ -114,61 +114,75 @@ __device__ __forceinline__ int claim_task(const BatchArgs &a, SingleState *S, in
 }
 
 // --------------------------------------------------------------- binning --
-__device__ __forceinline__ void queue_push64(bool take, int64_t x, int64_t *q, int *qn);
-
-// Flushes a workgroup queue into the static hub list (workgroup bin: written
-// from the back of the list).
-// cnt: the queue size every wavefront agreed on (see queue_flush_n).
-__device__ __forceinline__ void hub_flush_n(int cnt, int64_t *q, int *qn, int *qbase, int *counter, int64_t *hub,
-                                            bool from_back, int64_t cap) {
+// Appends x for every lane with `take` to the wavefront's LDS buffer buf
+// (*bn entries, at most kWave); when the ballot would overflow it, the buffer
+// first goes to the static hub list (one global atomic per flush).  Called by
+// the whole wavefront in lockstep.
+__device__ __forceinline__ void wave_hub_flush(int64_t *buf, int *bn, int *counter, int64_t *hub, bool from_back,
+                                               int64_t cap) {
+    const int cnt = *bn;
     if (cnt == 0) return;
-    if (threadIdx.x == 0) {
-        *qbase = atomicAdd(counter, cnt);
-        *qn = 0;
+    int base = 0;
+    if (lane_id() == 0) base = atomicAdd(counter, cnt);
+    base = __shfl(base, 0);
+    if (lane_id() < cnt) {
+        const int64_t pos = (int64_t)base + lane_id();
+        hub[from_back ? cap - 1 - pos : pos] = buf[lane_id()];
     }
-    __syncthreads();
-    const int base = *qbase;
-    for (int i = threadIdx.x; i < cnt; i += kBlock) {
-        const int64_t pos = base + i;
-        hub[from_back ? cap - 1 - pos : pos] = q[i];
-    }
-    __syncthreads();
+    wave_lds_sync();
+    if (lane_id() == 0) *bn = 0;
+    wave_lds_sync();
 }
-__device__ __forceinline__ void hub_flush(int64_t *q, int *qn, int *qbase, int *counter, int64_t *hub, bool from_back,
-                                          int64_t cap) {
-    hub_flush_n(queue_size(qn), q, qn, qbase, counter, hub, from_back, cap);
+__device__ __forceinline__ void wave_hub_push(bool take, int64_t x, int64_t *buf, int *bn, int *counter, int64_t *hub,
+                                              bool from_back, int64_t cap) {
+    const uint64_t m = ballot(take);
+    if (m == 0) return;
+    if (*bn + __popcll(m) > kWave) wave_hub_flush(buf, bn, counter, hub, from_back, cap);
+    if (take) buf[*bn + lanes_below(m)] = x;
+    wave_lds_sync();
+    if (lane_id() == 0) *bn += __popcll(m);
+    wave_lds_sync();
 }
 
+// Degree bins of the fused launches' graphs: one wavefront per task (no
+// workgroup barrier), rows above t_wave to the workgroup hub list (from the
+// back of `hub`), rows above t_thread to the wavefront list (from the front);
+// the lane-group bin needs no list (the sweeps walk the tasks).
 __global__ __launch_bounds__(kBlock) void k_bbin(const BatchArgs *__restrict__ A, SingleState *S) {
-    __shared__ int sh[kWavesPerBlock];
-    __shared__ int64_t qW[kQueueCap / 2], qB[kQueueCap / 2];
-    __shared__ int nqW, nqB, qbase;
+    __shared__ int64_t qW[kWavesPerBlock][kWave], qB[kWavesPerBlock][kWave];
+    __shared__ int nqW[kWavesPerBlock], nqB[kWavesPerBlock];
     const BatchArgs a = *A;
+    const int wv = threadIdx.x / kWave;
+    const int nwv = (int)gridDim.x * kWavesPerBlock;
+    if (lane_id() == 0) nqW[wv] = nqB[wv] = 0;
+    wave_lds_sync();
     int md = 0;
-    if (threadIdx.x == 0) nqW = nqB = 0;
-    __syncthreads();
-    for (int t = blockIdx.x; t < a.ntasks; t += gridDim.x) {
+    for (int t = (int)blockIdx.x * kWavesPerBlock + wv; t < a.ntasks; t += nwv) {
         const int64_t task = a.tasks[t];
         const int g = item_graph(task), start = item_vertex(task);
         const GraphView w = graph_view(a, g);
         const int end = min(w.n, start + kTaskLen);
-        for (int base = start; base < end; base += kBlock) {
-            const int v = base + threadIdx.x;
-            int d = -1;
-            if (v < end) d = w.rp[v + 1] - w.rp[v];
-            md = max(md, d);
-            queue_push64(d > a.t_wave, pack_item(g, v), qB, &nqB);
-            queue_push64(d > a.t_thread && d <= a.t_wave, pack_item(g, v), qW, &nqW);
-            int cB, cW;
-            queue_sizes(&nqB, &nqW, cB, cW);
-            if (cB > kQueueCap / 2 - kBlock) hub_flush_n(cB, qB, &nqB, &qbase, &S->nB, a.hub, true, a.hub_cap);
-            if (cW > kQueueCap / 2 - kBlock) hub_flush_n(cW, qW, &nqW, &qbase, &S->nW, a.hub, false, a.hub_cap);
+        // every row_ptr pair of the task in flight at once, then the appends
+        constexpr int kPer = kTaskLen / kWave;
+        int d[kPer];
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const int v = start + k * kWave + lane_id();
+            d[k] = v < end ? w.rp[v + 1] - w.rp[v] : -1;
+        }
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const int v = start + k * kWave + lane_id();
+            md = max(md, d[k]);
+            wave_hub_push(d[k] > a.t_wave, pack_item(g, v), qB[wv], &nqB[wv], &S->nB, a.hub, true, a.hub_cap);
+            wave_hub_push(d[k] > a.t_thread && d[k] <= a.t_wave, pack_item(g, v), qW[wv], &nqW[wv], &S->nW, a.hub,
+                          false, a.hub_cap);
         }
     }
-    hub_flush(qB, &nqB, &qbase, &S->nB, a.hub, true, a.hub_cap);
-    hub_flush(qW, &nqW, &qbase, &S->nW, a.hub, false, a.hub_cap);
-    md = block_max(md, sh);
-    if (threadIdx.x == 0 && md > __hip_atomic_load(&S->maxdeg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+    wave_hub_flush(qB[wv], &nqB[wv], &S->nB, a.hub, true, a.hub_cap);
+    wave_hub_flush(qW[wv], &nqW[wv], &S->nW, a.hub, false, a.hub_cap);
+    md = wave_max_i32(md);
+    if (lane_id() == 0 && md > __hip_atomic_load(&S->maxdeg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
         atomicMax(&S->maxdeg, md);
 }
 
@@ -615,25 +629,34 @@ __global__ void k_bround_end(const BatchArgs *__restrict__ A, SingleState *S) {
 
 // Per-graph colour count: kg[g] = max colour + 1; flags colours outside [0, n_g).
 __global__ __launch_bounds__(kBlock) void k_bcount(const BatchArgs *__restrict__ A, int32_t *err) {
-    __shared__ int sh[kWavesPerBlock];
+    // one wavefront per task, no workgroup barrier
     const BatchArgs a = *A;
-    for (int t = blockIdx.x; t < a.ntasks_all; t += gridDim.x) {
+    const int nwv = (int)gridDim.x * kWavesPerBlock;
+    for (int t = (int)blockIdx.x * kWavesPerBlock + (int)threadIdx.x / kWave; t < a.ntasks_all; t += nwv) {
         const int64_t task = a.tasks[t];
         const int g = item_graph(task), start = item_vertex(task);
         const GraphView w = graph_view(a, g);
         const int end = min(w.n, start + kTaskLen);
+        // the task's colours, all loads in flight at once
+        constexpr int kPer = kTaskLen / kWave;
+        int c[kPer];
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const int v = start + k * kWave + lane_id();
+            c[k] = v < end ? w.col[v] : -1;
+        }
         int m = -1;
         bool bad = false;
-        for (int v = start + threadIdx.x; v < end; v += kBlock) {
-            const int c = w.col[v];
-            bad |= (c < 0 || c >= w.n);
-            m = max(m, c);
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const bool in = start + k * kWave + lane_id() < end;
+            bad |= in && (c[k] < 0 || c[k] >= w.n);
+            m = max(m, c[k]);
         }
         if (ballot(bad) && lane_id() == 0) atomicOr(err, 4);
-        m = block_max(m, sh);
-        if (threadIdx.x == 0 && m + 1 > __hip_atomic_load(&a.kg[g], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+        m = wave_max_i32(m);
+        if (lane_id() == 0 && m + 1 > __hip_atomic_load(&a.kg[g], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
             atomicMax(&a.kg[g], m + 1);
-        __syncthreads();
     }
 }
 
