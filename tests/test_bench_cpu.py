@@ -1,0 +1,84 @@
+"""bench.py's host-side helpers (no GPU): the lookup of counter traffic.
+
+`roofline.traffic` may only carry a figure taken on the kernel sources being
+measured and, where the record names them, with the same launch options."""
+import json
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+@pytest.fixture
+def traffic_root(tmp_path, monkeypatch):
+    """A copy of the repository layout that bench.py reads: the kernel sources
+    (for the hash) and a profiles/traffic.json the test writes."""
+    csrc = tmp_path / "paper_1505_04086_amd" / "csrc"
+    csrc.mkdir(parents=True)
+    for f in bench.ROUND_KERNEL_SOURCES:
+        (csrc / f).write_bytes(open(os.path.join(ROOT, "paper_1505_04086_amd", "csrc", f), "rb").read())
+    (tmp_path / "profiles").mkdir()
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+
+    def write(rec):
+        (tmp_path / "profiles" / "traffic.json").write_text(json.dumps(rec))
+    return tmp_path, write
+
+
+def _record(source_hash):
+    return {"source_hash": source_hash,
+            "workloads": {
+                "mesh3d": {"round0_first_fit": {"bytes_per_launch": 111}},
+                "batched": {"batched_round0_first_fit": [
+                    {"bytes_per_launch": 222, "options": {"chunk": 0, "small_cutoff": -1}},
+                    {"bytes_per_launch": 333, "options": {"chunk": 4, "small_cutoff": -1}}]}}}
+
+
+def test_traffic_for_current_sources(traffic_root):
+    root, write = traffic_root
+    write(_record(bench.kernel_source_hash()))
+    assert bench.load_traffic("mesh3d", "round0_first_fit") == 111
+    # an entry without options matches whatever options the run used
+    assert bench.load_traffic("mesh3d", "round0_first_fit", {"chunk": 2}) == 111
+    # entries with options match only the same options
+    assert bench.load_traffic("batched", "batched_round0_first_fit", {"small_cutoff": -1, "chunk": 0}) == 222
+    assert bench.load_traffic("batched", "batched_round0_first_fit", {"chunk": 4, "small_cutoff": -1}) == 333
+    assert bench.load_traffic("batched", "batched_round0_first_fit", {"chunk": 8, "small_cutoff": -1}) is None
+    assert bench.load_traffic("batched", "batched_round0_first_fit", None) is None
+    assert bench.load_traffic("rmat", "round0_first_fit") is None
+
+
+def test_traffic_dropped_when_sources_change(traffic_root):
+    root, write = traffic_root
+    write(_record(bench.kernel_source_hash()))
+    f = root / "paper_1505_04086_amd" / "csrc" / bench.ROUND_KERNEL_SOURCES[0]
+    f.write_bytes(f.read_bytes() + b"\n// edited\n")
+    assert bench.load_traffic("mesh3d", "round0_first_fit") is None
+
+
+def test_traffic_missing_or_unreadable(traffic_root):
+    root, write = traffic_root
+    assert bench.load_traffic("mesh3d", "round0_first_fit") is None
+    (root / "profiles" / "traffic.json").write_text("{not json")
+    assert bench.load_traffic("mesh3d", "round0_first_fit") is None
+
+
+def test_committed_traffic_record_shape():
+    """The committed record: per-launch byte counts that follow from its own
+    counters and calibration (FETCH_SIZE x fetch factor + WRITE_SIZE x write
+    factor, in KiB)."""
+    rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))
+    cal = rec["calibration"]
+    n = 0
+    for kernels in rec["workloads"].values():
+        for ent in kernels.values():
+            for e in (ent if isinstance(ent, list) else [ent]):
+                want = e["fetch_kib"] * 1024 * cal["fetch_factor"] + e["write_kib"] * 1024 * cal["write_factor"]
+                assert abs(e["bytes_per_launch"] - want) <= 1024 * (cal["fetch_factor"] + cal["write_factor"])
+                n += 1
+    assert n >= 5
