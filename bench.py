@@ -41,11 +41,34 @@ ROUND_KERNEL_SOURCES = ("device_common.hpp", "vertex_ops.hpp", "single_kernels.h
                         "hub_kernels.hpp", "batch_kernels.hpp", "batch.hpp")
 
 
+def _code_only(text: bytes) -> bytes:
+    """C++ source without its comments and blank lines (what the compiler
+    sees): a comment edit does not invalidate counters taken on the code."""
+    out, i, n = bytearray(), 0, len(text)
+    while i < n:
+        if text.startswith(b"//", i):
+            j = text.find(b"\n", i)
+            i = n if j < 0 else j
+        elif text.startswith(b"/*", i):
+            j = text.find(b"*/", i + 2)
+            i = n if j < 0 else j + 2
+        elif text[i:i + 1] == b'"':  # string literal, copied whole
+            j = i + 1
+            while j < n and text[j:j + 1] != b'"':
+                j += 2 if text[j:j + 1] == b"\\" else 1
+            out += text[i:j + 1]
+            i = j + 1
+        else:
+            out += text[i:i + 1]
+            i += 1
+    return b"\n".join(ln.rstrip() for ln in bytes(out).splitlines() if ln.strip())
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha1()
     d = os.path.join(ROOT, "paper_1505_04086_amd", "csrc")
     for f in ROUND_KERNEL_SOURCES:
-        h.update(open(os.path.join(d, f), "rb").read())
+        h.update(_code_only(open(os.path.join(d, f), "rb").read()))
     return h.hexdigest()[:16]
 
 

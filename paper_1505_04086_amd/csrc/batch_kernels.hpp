@@ -85,8 +85,8 @@ __device__ __forceinline__ void wave_append64(bool take, int64_t x, int *counter
     }
 }
 
-// Optimistic round 0 of the batch sweeps its tasks in nbands = kXcds * B
-// bands of about equal work, B of them per XCD, the XCD's bands one
+// The batch's optimistic rounds 0 and 1 sweep their tasks in nbands =
+// kXcds * B bands of about equal work, B of them per XCD, the XCD's bands one
 // contiguous part of the batch: each band is handed out in order from its own
 // counter, so the tasks in flight on one XCD form B narrow ranges of its part
 // (a few graphs) and those graphs' colours stay in the XCD's L2 while the

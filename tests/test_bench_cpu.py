@@ -53,12 +53,20 @@ def test_traffic_for_current_sources(traffic_root):
     assert bench.load_traffic("rmat", "round0_first_fit") is None
 
 
-def test_traffic_dropped_when_sources_change(traffic_root):
+def test_traffic_dropped_when_code_changes(traffic_root):
     root, write = traffic_root
     write(_record(bench.kernel_source_hash()))
     f = root / "paper_1505_04086_amd" / "csrc" / bench.ROUND_KERNEL_SOURCES[0]
-    f.write_bytes(f.read_bytes() + b"\n// edited\n")
+    # comments and blank lines are not code: the counters stay valid
+    f.write_bytes(f.read_bytes() + b"\n// a comment\n/* another\n one */\n\n")
+    assert bench.load_traffic("mesh3d", "round0_first_fit") == 111
+    f.write_bytes(f.read_bytes() + b"static int edited_probe;\n")
     assert bench.load_traffic("mesh3d", "round0_first_fit") is None
+
+
+def test_code_only_keeps_strings():
+    src = b'int a; // c1\n/* block\n comment */ const char *s = "x//y /* z */";\n\n  // only\nint c;\n'
+    assert bench._code_only(src) == b'int a;\n const char *s = "x//y /* z */";\nint c;'
 
 
 def test_traffic_missing_or_unreadable(traffic_root):
