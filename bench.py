@@ -35,10 +35,12 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak
 
 
-# sources the round kernels and their launch shapes are built from (the
-# figures in profiles/traffic.json stay valid while these are unchanged)
-ROUND_KERNEL_SOURCES = ("device_common.hpp", "vertex_ops.hpp", "single_kernels.hpp", "single.hpp", "host_common.hpp",
-                        "hub_kernels.hpp", "batch_kernels.hpp", "batch.hpp")
+# sources the round kernels and their launch shapes are built from, for the
+# single-graph workloads and for the batch (the figures in
+# profiles/traffic.json stay valid while the code in these is unchanged)
+SINGLE_KERNEL_SOURCES = ("device_common.hpp", "vertex_ops.hpp", "single_kernels.hpp", "single.hpp", "host_common.hpp",
+                         "hub_kernels.hpp")
+ROUND_KERNEL_SOURCES = SINGLE_KERNEL_SOURCES + ("batch_kernels.hpp", "batch.hpp")
 
 
 def _code_only(text: bytes) -> bytes:
@@ -64,10 +66,12 @@ def _code_only(text: bytes) -> bytes:
     return b"\n".join(ln.rstrip() for ln in bytes(out).splitlines() if ln.strip())
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(workload: str = "mesh3d") -> str:
+    """Hash of the code (comments and blank lines left out) the workload's
+    round kernels are built from."""
     h = hashlib.sha1()
     d = os.path.join(ROOT, "paper_1505_04086_amd", "csrc")
-    for f in ROUND_KERNEL_SOURCES:
+    for f in (ROUND_KERNEL_SOURCES if workload == "batched" else SINGLE_KERNEL_SOURCES):
         h.update(_code_only(open(os.path.join(d, f), "rb").read()))
     return h.hexdigest()[:16]
 
@@ -83,7 +87,7 @@ def load_traffic(workload: str, kernel: str, options=None):
         rec = json.load(open(p))
     except Exception:
         return None
-    if rec.get("source_hash") != kernel_source_hash():
+    if rec.get("source_hashes", {}).get(workload) != kernel_source_hash(workload):
         return None
     ent = rec.get("workloads", {}).get(workload, {}).get(kernel)
     # one entry, or a list of entries taken with different launch options

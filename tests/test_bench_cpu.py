@@ -30,8 +30,8 @@ def traffic_root(tmp_path, monkeypatch):
     return tmp_path, write
 
 
-def _record(source_hash):
-    return {"source_hash": source_hash,
+def _record(single_hash, batched_hash):
+    return {"source_hashes": {"mesh3d": single_hash, "batched": batched_hash},
             "workloads": {
                 "mesh3d": {"round0_first_fit": {"bytes_per_launch": 111}},
                 "batched": {"batched_round0_first_fit": [
@@ -41,7 +41,7 @@ def _record(source_hash):
 
 def test_traffic_for_current_sources(traffic_root):
     root, write = traffic_root
-    write(_record(bench.kernel_source_hash()))
+    write(_record(bench.kernel_source_hash("mesh3d"), bench.kernel_source_hash("batched")))
     assert bench.load_traffic("mesh3d", "round0_first_fit") == 111
     # an entry without options matches whatever options the run used
     assert bench.load_traffic("mesh3d", "round0_first_fit", {"chunk": 2}) == 111
@@ -55,11 +55,19 @@ def test_traffic_for_current_sources(traffic_root):
 
 def test_traffic_dropped_when_code_changes(traffic_root):
     root, write = traffic_root
-    write(_record(bench.kernel_source_hash()))
-    f = root / "paper_1505_04086_amd" / "csrc" / bench.ROUND_KERNEL_SOURCES[0]
+    write(_record(bench.kernel_source_hash("mesh3d"), bench.kernel_source_hash("batched")))
+    opts = {"chunk": 4, "small_cutoff": -1}
+    csrc = root / "paper_1505_04086_amd" / "csrc"
     # comments and blank lines are not code: the counters stay valid
+    f = csrc / bench.SINGLE_KERNEL_SOURCES[0]
     f.write_bytes(f.read_bytes() + b"\n// a comment\n/* another\n one */\n\n")
     assert bench.load_traffic("mesh3d", "round0_first_fit") == 111
+    # a batch-only source: the batch's counters go, the single graph's stay
+    b = csrc / "batch.hpp"
+    b.write_bytes(b.read_bytes() + b"static int batch_probe;\n")
+    assert bench.load_traffic("batched", "batched_round0_first_fit", opts) is None
+    assert bench.load_traffic("mesh3d", "round0_first_fit") == 111
+    # a shared source: both go
     f.write_bytes(f.read_bytes() + b"static int edited_probe;\n")
     assert bench.load_traffic("mesh3d", "round0_first_fit") is None
 
