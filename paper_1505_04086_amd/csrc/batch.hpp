@@ -191,7 +191,12 @@ inline int32_t run_batch(rsoc_ctx *c, int32_t G, const int64_t *vtx_off, const i
     RSOC_TRY(c->b_tasks.reserve(sizeof(int64_t) * (size_t)std::max(ntasks_all, 1)));
     RSOC_TRY(c->b_col8.reserve((size_t)nV + 64));
     if (o.mode != kOptimistic) RSOC_TRY(c->b_pend.reserve(sizeof(int32_t) * (size_t)nV));
-    else RSOC_TRY(c->b_u0mask.reserve(sizeof(uint32_t) * kTaskWords * (size_t)std::max(ntasks, 1)));
+    else {
+        // optimistic mode stages no colours: the staging buffer holds, for
+        // U^0's lane-group entries, the row positions round 0 read uncoloured
+        RSOC_TRY(c->b_u0mask.reserve(sizeof(uint32_t) * kTaskWords * (size_t)std::max(ntasks, 1)));
+        RSOC_TRY(c->b_pend.reserve(sizeof(uint32_t) * (size_t)nV));
+    }
     RSOC_TRY(c->b_wl0.reserve(sizeof(int64_t) * (size_t)(nV + 1)));
     RSOC_TRY(c->b_wl1.reserve(sizeof(int64_t) * (size_t)(nV + 1)));
     RSOC_TRY(c->b_hub.reserve(sizeof(int64_t) * (size_t)(nV + 1)));
@@ -224,6 +229,7 @@ inline int32_t run_batch(rsoc_ctx *c, int32_t G, const int64_t *vtx_off, const i
     a.hub = c->b_hub.as<int64_t>();
     a.tasks = c->b_tasks.as<int64_t>();
     a.u0mask = c->b_u0mask.as<uint32_t>();
+    a.u0pos = o.mode == kOptimistic ? c->b_pend.as<uint32_t>() : nullptr;
     a.kg = c->b_kmax.as<int32_t>();
     a.nV = nV;
     a.hub_cap = nV + 1;
@@ -401,9 +407,9 @@ inline int32_t run_batch(rsoc_ctx *c, int32_t G, const int64_t *vtx_off, const i
         }
         // round 0 (optimistic): task table 8/task, row_ptr 4(n+G), col_idx 4 nnz,
         // colours of the neighbours a vertex loses to (4 nnz/2), colour
-        // writes 4n, hub lists 8(nW+nB), U^0: a 64-byte mask per task plus
-        // 8 per listed entry of the wavefront and workgroup bins (the fused
-        // launches' graphs)
+        // writes 4n, hub lists 8(nW+nB), U^0: a 64-byte mask per task, 4 per
+        // lane-group entry (its row positions read uncoloured) and 8 per listed
+        // entry of the wavefront and workgroup bins (the fused launches' graphs)
         if (o.mode == kOptimistic && ntasks > 0) {
             int64_t nnzL = 0;
             int GL = 0;
@@ -411,7 +417,9 @@ inline int32_t run_batch(rsoc_ctx *c, int32_t G, const int64_t *vtx_off, const i
                 if (!is_small(g)) nnzL += nnz_off[g + 1] - nnz_off[g], ++GL;
             st->bytes_round0 = 8 * (int64_t)ntasks + 4 * (nVL + GL) + 4 * nnzL +
                                (o.full_sweep ? 4 * nnzL : 4 * (nnzL / 2)) + 4 * nVL + 8 * (int64_t)(nW + nB) +
-                               (o.full_sweep ? 0 : 8 * (int64_t)h->head.u0_listed + 4 * kTaskWords * (int64_t)ntasks);
+                               (o.full_sweep ? 0
+                                             : 8 * (int64_t)h->head.u0_listed + 4 * kTaskWords * (int64_t)ntasks +
+                                                   4 * (int64_t)(h->head.u0 - h->head.u0_listed));
         }
         (void)nnzT;
     }

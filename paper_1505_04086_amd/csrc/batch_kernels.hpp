@@ -40,6 +40,8 @@ struct BatchArgs {
     int32_t *small_stat;  // their statistics: see k_bsmall
     int32_t nsmall;
     uint32_t *u0mask;            // optimistic round 0: per task, bit l = its l-th vertex is in U^0 (thread bin)
+    uint32_t *u0pos;             // [nV] for those vertices: the row positions of the neighbours round 0 read
+                                 // uncoloured (group_vertices' unc)
     uint8_t *gchunk;             // [G] run length of each graph's sweeps, when the option leaves it open (else null)
     int32_t nbands;              // optimistic round 0: sweep bands, kXcds per band index of an XCD
     int32_t band[kMaxBands + 1]; // band b is tasks [band[b], band[b+1]) (about equal work)
@@ -260,6 +262,55 @@ __device__ __forceinline__ void queue_flush64(int64_t *q, int *qn, int *qbase, i
 
 // ----------------------------------------------------------------- round --
 // Same contract as k_round (PHASE, MODE, TIE, SWEEP, ROUND0), over the batch.
+// Batched round 1, lane groups: the vertices of `list` (n entries, ids of the
+// task's graph tw) recoloured kGroup lanes each -- PH = kAssign gives a vertex
+// known to be defective First-Fit over all its neighbours, PH = kRecolor
+// detects first -- written in place and appended to the next list.  Called by
+// the whole workgroup (n is the same for every thread).
+template <int PH, int TIE>
+__device__ __forceinline__ void task_recolour(const int *list, int n, const GraphView &tw, int tg, int look,
+                                              RSOC_GLOBAL int32_t *wcol, RSOC_GLOBAL uint8_t *wcol8, int64_t *q,
+                                              int *qn, int *qbase, int *counter, int64_t *out, uint64_t &degs) {
+    const int gi = threadIdx.x / kGroup;
+    const bool leader = (threadIdx.x & (kGroup - 1)) == 0;
+    for (int base = 0; base < n; base += kSub) {
+        int v[kNV], b[kNV], e[kNV], cv[kNV], nc[kNV];
+        bool act[kNV];
+        uint32_t unc[kNV] = {};
+        const RSOC_GLOBAL int32_t *cis[kNV];
+        const RSOC_GLOBAL uint8_t *c8s[kNV];
+#pragma unroll
+        for (int i = 0; i < kNV; ++i) {
+            const int idx = base + i * kGpb + gi;
+            v[i] = idx < n ? list[idx] : -1;
+            b[i] = e[i] = 0;
+            cis[i] = tw.ci;
+            c8s[i] = tw.col8;
+            if (v[i] >= 0) {
+                b[i] = tw.rp[v[i]];
+                e[i] = tw.rp[v[i] + 1];
+            }
+            cv[i] = (PH != kAssign && v[i] >= 0) ? (int)tw.col8[v[i]] : 255;
+        }
+        group_vertices<PH, TIE, kGroup, kGroupSlots, false, kNV>(v, b, e, cis, c8s, cv, look, nc, act, unc);
+#pragma unroll
+        for (int i = 0; i < kNV; ++i) {
+            if (v[i] < 0) act[i] = false;
+            if (leader && v[i] >= 0) {
+                degs += (uint64_t)(e[i] - b[i]);
+                if (act[i]) {
+                    wcol[tw.voff + v[i]] = nc[i];
+                    wcol8[tw.voff + v[i]] = (uint8_t)nc[i];
+                }
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < kNV; ++i) queue_push64(act[i] && leader, pack_item(tg, v[i]), q, qn);
+        const int cq = queue_size(qn);
+        if (cq > kQueueCap - kSub) queue_flush64_n(cq, q, qn, qbase, counter, out);
+    }
+}
+
 template <int PHASE, int MODE, int TIE, bool SWEEP, int ROUND0 = 0>
 __global__ __launch_bounds__(kBlock) void k_bround(const BatchArgs *__restrict__ A, SingleState *S, int parity,
                                                    int gB, int gW, int gT) {
@@ -281,6 +332,8 @@ __global__ __launch_bounds__(kBlock) void k_bround(const BatchArgs *__restrict__
     constexpr bool kTaskList = PHASE == kRecolor && ROUND0 == 2 && !SWEEP && MODE == kOptimistic;
     __shared__ uint32_t tmask[kMaskU0 ? kTaskWords : 1];
     __shared__ int16_t tpos[kTaskList ? kTaskLen : 1];
+    __shared__ int tdef[kTaskList ? kTaskLen : 1], tover[kTaskList ? kTaskLen : 1];
+    __shared__ int ndef, nover;
     const int cT = SWEEP ? a.ntasks : S->cnt_in[kBinThread];
     const int cW = SWEEP ? S->nW : S->cnt_in[kBinWave];
     const int cB = SWEEP ? S->nB : S->cnt_in[kBinBlock];
@@ -405,49 +458,40 @@ __global__ __launch_bounds__(kBlock) void k_bround(const BatchArgs *__restrict__
                     int k = incl - __popc(m);
                     for (uint32_t mm = m; mm; mm &= mm - 1) tpos[k++] = (int16_t)(threadIdx.x * 32 + __builtin_ctz(mm));
                     if (threadIdx.x == kTaskWords - 1) tcount = incl;
+                    if (threadIdx.x == 0) ndef = nover = 0;
                 }
                 __syncthreads();
                 const int cnt = tcount;
-                for (int base = 0; base < cnt; base += kSub) {
-                    int v[kNV], b[kNV], e[kNV], cv[kNV], nc[kNV];
-                    bool act[kNV];
-                    uint32_t unc[kNV] = {};
-                    const RSOC_GLOBAL int32_t *cis[kNV];
-                    const RSOC_GLOBAL uint8_t *c8s[kNV];
-#pragma unroll
-                    for (int i = 0; i < kNV; ++i) {
-                        const int idx = base + i * kGpb + gi;
-                        v[i] = -1;
-                        b[i] = e[i] = 0;
-                        cis[i] = tw.ci;
-                        c8s[i] = tw.col8;
-                        if (idx < cnt) {
-                            const int li = tpos[idx];
-                            v[i] = TIE == kHigherKeeps ? tstart + tlen - 1 - li : tstart + li;
-                            b[i] = tw.rp[v[i]];
-                            e[i] = tw.rp[v[i] + 1];
-                        }
-                        cv[i] = v[i] >= 0 ? (int)tw.col8[v[i]] : 255;
+                // one thread per vertex of U^0: only the neighbours round 0 read
+                // uncoloured (at most three, at the row positions it recorded)
+                // can hold its colour; a defective vertex, and one with more
+                // than three such neighbours, goes to the lane groups below (as
+                // the single-graph masked round)
+                for (int idx = threadIdx.x; idx < cnt; idx += kBlock) {
+                    const int li = tpos[idx];
+                    const int v = TIE == kHigherKeeps ? tstart + tlen - 1 - li : tstart + li;
+                    const uint32_t pm = gro(a.u0pos)[tw.voff + v];
+                    const int cv = tw.col8[v];
+                    const bool over = __popc(pm) > 3;
+                    int4 x = make_int4(-1, -1, -1, (int)pm);
+                    if (!over) {
+                        const int b = tw.rp[v];
+                        uint32_t mm = pm;
+                        if (mm) { x.x = tw.ci[b + __builtin_ctz(mm)]; mm &= mm - 1; }
+                        if (mm) { x.y = tw.ci[b + __builtin_ctz(mm)]; mm &= mm - 1; }
+                        if (mm) x.z = tw.ci[b + __builtin_ctz(mm)];
                     }
-                    group_vertices<kRecolor, TIE, kGroup, kGroupSlots, false, kNV>(v, b, e, cis, c8s, cv, a.look, nc,
-                                                                                   act, unc);
-#pragma unroll
-                    for (int i = 0; i < kNV; ++i) {
-                        if (v[i] < 0) act[i] = false;
-                        if (leader && v[i] >= 0) {
-                            items += 1;
-                            degs += (uint64_t)(e[i] - b[i]);
-                            if (act[i]) {
-                                wcolg[tw.voff + v[i]] = nc[i];
-                                wcol8g[tw.voff + v[i]] = (uint8_t)nc[i];
-                            }
-                        }
-                    }
-#pragma unroll
-                    for (int i = 0; i < kNV; ++i) queue_push64(act[i] && leader, pack_item(tg, v[i]), q, &qn);
-                    const int cq = queue_size(&qn);
-                    if (cq > kQueueCap - kSub) queue_flush64_n(cq, q, &qn, &qbase, &S->cnt_out[kBinThread], out);
+                    const bool def = !over && lane_detect_kept<false>(v, x, cv, tw.col8, nullptr);
+                    items += 1;
+                    degs += (uint64_t)__popc(pm);
+                    if (def) tdef[atomicAdd(&ndef, 1)] = v;
+                    if (over) tover[atomicAdd(&nover, 1)] = v;
                 }
+                __syncthreads();
+                task_recolour<kAssign, TIE>(tdef, ndef, tw, tg, a.look, wcolg, wcol8g, q, &qn, &qbase,
+                                            &S->cnt_out[kBinThread], out, degs);
+                task_recolour<kRecolor, TIE>(tover, nover, tw, tg, a.look, wcolg, wcol8g, q, &qn, &qbase,
+                                             &S->cnt_out[kBinThread], out, degs);
             }
             for (int r = 0; r < (kTaskList ? 0 : kChunk); ++r) {
                 int v[kNV], b[kNV], e[kNV], cv[kNV], nc[kNV], gg[kNV];
@@ -515,6 +559,7 @@ __global__ __launch_bounds__(kBlock) void k_bround(const BatchArgs *__restrict__
                         if (leader && unc[i] != 0) {
                             const int li = step_offset(r, i, gi, tchunk);
                             atomicOr(&tmask[li >> 5], 1u << (li & 31));
+                            a.u0pos[vo[i] + v[i]] = unc[i];
                             flagged += 1;
                         }
                 }
